@@ -1,0 +1,218 @@
+/*
+ * libmlp — PaiNN-form machine-learning potential: energy and forces on one
+ * MI355X (gfx950).  C ABI; no C++ or torch types cross this boundary.
+ *
+ * Method (arXiv 2506.04055, Results "Distributed potential computation"):
+ *   the total energy of a domain is the sum of semi-local per-atom energies
+ *   U_i of the local atoms (Eq. 1); the forces are the partial derivatives of
+ *   that sum with respect to every atom of the domain, local and ghost, whose
+ *   ghost rows are summed onto their owners (Eq. 2).  Neighbour graphs are
+ *   built with a skin and edges longer than the model cutoff are pruned at
+ *   every evaluation; atoms farther than T hops from any local atom are
+ *   pruned as well (same paragraph, pruning).  Buffers are sized to
+ *   capacities that only grow (Results, "Runtime optimizations and
+ *   buffering").  The per-atom energy is PaiNN (Methods, "Chosen
+ *   Architectures"), with T message/update layers, F features, K radial
+ *   Bessel functions sin(k pi r / rc) / r and a cosine cutoff envelope.
+ *
+ * Units: Angstrom, eV, eV/Angstrom, amu, fs.
+ *
+ * Conventions for every call
+ *   - Return value: MLP_OK (0), MLP_PENDING (1) or a negative MLP_ERR_*.
+ *     After an error, mlp_last_error() returns a message (thread-local).
+ *   - Device pointers are HIP device memory owned by the caller; the library
+ *     never frees or retains them beyond the call.  Host pointers are read
+ *     during the call only (mlp_submit copies what it needs).
+ *   - Positions and forces are structure-of-arrays: 3 rows of N floats
+ *     (x[0..N), then y[0..N), then z[0..N)).
+ *   - Work is enqueued on the caller's stream (hipStream_t passed as void*;
+ *     NULL is the default stream).  Calls that return sizes or statistics
+ *     synchronise that stream; mlp_energy_forces without stats does not.
+ *   - Handles (mlp_model, mlp_nbr, mlp_server) are owned by the library and
+ *     released with their *_destroy call.  A handle may be used from one
+ *     thread at a time.
+ */
+#ifndef MLP_H
+#define MLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MLP_OK = 0,
+    MLP_PENDING = 1,
+    MLP_ERR_INVALID_ARG = -1,   /* bad shape, species out of range, bad header */
+    MLP_ERR_OOM = -2,           /* device allocation failed */
+    MLP_ERR_CAPACITY = -3,      /* a buffer overflowed and could not be grown */
+    MLP_ERR_BOX_TOO_SMALL = -4, /* rc + skin >= L/2 in a periodic dimension */
+    MLP_ERR_DEVICE = -5,        /* a HIP runtime call failed */
+    MLP_ERR_UNKNOWN_TICKET = -6
+};
+
+enum { MLP_FP32 = 0, MLP_BF16 = 1 };
+
+typedef struct mlp_model mlp_model;
+typedef struct mlp_nbr mlp_nbr;
+typedef struct mlp_server mlp_server;
+
+/* Statistics of one evaluation (the library "returns statistics of the
+ * computation", Results, "Runtime optimizations and buffering"). */
+typedef struct {
+    int64_t n_edges_skin;      /* directed edges within rc + skin            */
+    int64_t n_edges;           /* directed edges within rc (used)            */
+    int32_t n_atoms;           /* atoms of the domain (local + ghost)        */
+    int32_t n_local;
+    int32_t n_within_hops[8];  /* atoms within <= t hops of a local atom     */
+    int32_t n_cells[3];        /* cell grid of the last neighbour build      */
+    int32_t max_cell_occupancy;
+    int32_t n_builds;          /* neighbour builds so far on this handle     */
+    int32_t n_grows;           /* capacity growths so far on this handle     */
+    int64_t device_bytes;      /* device memory held by the nbr handle       */
+} mlp_stats;
+
+/* Message describing the last error of the calling thread. */
+const char *mlp_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Model
+ * header_json: the export properties of the model (Results, "Structure":
+ *   units, maximal edge length, graph format) plus the architecture:
+ *   {"model":"painn","F":..,"K":..,"T":..,"n_species":..,"r_c":..,"eps":..,
+ *    "basis":"bessel_sin_over_r","envelope":"cosine",...}.
+ *   Supported: (F, K) in {(128,20), (128,8), (64,20), (64,8), (32,20), (32,8),
+ *   (16,6)}, 1 <= T <= 7, n_species >= 1.
+ * weights: host float32 array of n_weights values in the stated layout
+ *   (emb [S][F]; per layer W1 [F][F] b1 [F] W2 [3F][F] b2 [3F] A [3F][K]
+ *   c [3F] U [F][F] V [F][F] W3 [F][2F] b3 [F] W4 [3F][F] b4 [3F]; then
+ *   W5 [F/2][F] b5 [F/2] w6 [F/2] b6 [1]); matrices are [out][in] row-major;
+ *   3F blocks are split [vv | s | vs] (message) and [vv | sv | ss] (update).
+ *   Copied to the device; the caller keeps ownership of its array.
+ * precision: MLP_FP32 (all arithmetic FP32) or MLP_BF16 (node-feature GEMMs
+ *   and the radial-filter contraction take bfloat16 operands with FP32
+ *   accumulation; geometry, cutoff, accumulation of messages and forces stay
+ *   FP32; the energy sum is FP64 in both).
+ * Errors: INVALID_ARG (header or weight count), OOM, DEVICE.
+ * ------------------------------------------------------------------------- */
+int mlp_model_create(const char *header_json, const float *weights, size_t n_weights,
+                     int precision, mlp_model **out);
+int mlp_model_destroy(mlp_model *model);
+
+/* ---------------------------------------------------------------------------
+ * mlp_build_neighbors — cell-list neighbour graph of all atoms within
+ * rc + skin (Results, "Distributed potential computation": the MD engine
+ * builds lists with a skin so they need not be rebuilt every step).
+ * pos: device, SoA 3 x n_atoms float32.  Periodic dimensions (box[d] > 0)
+ *   require 0 <= x < box[d]; box lengths should be float32-representable.
+ *   Locals are rows [0, n_local); ghosts follow.  With ghosts
+ *   (n_atoms > n_local) the domain is open in every dimension: ghost atoms
+ *   are explicit copies and no minimum image is applied; box is then ignored.
+ * species: device int32 [n_atoms], each in [0, n_species).
+ * skin >= 0.  A pair (i, j) is a neighbour iff, in float32,
+ *   dx = x_j - x_i, folded once by +-L when |dx| > L/2 (periodic dims),
+ *   fma(dz, dz, fma(dy, dy, dx*dx)) < (rc + skin)^2.
+ * *inout: NULL to create a handle, or an existing handle to refresh (its
+ *   buffers are reused and grown when too small, never shrunk).
+ * Synchronises the stream (edge counts size the buffers).
+ * Errors: INVALID_ARG (sizes, species, positions outside the box),
+ *   BOX_TOO_SMALL (rc + skin >= L/2), OOM, DEVICE.
+ * ------------------------------------------------------------------------- */
+int mlp_build_neighbors(mlp_model *model, const float *pos, const int32_t *species,
+                        int32_t n_atoms, int32_t n_local, const double box[3], float skin,
+                        void *stream, mlp_nbr **inout);
+int mlp_nbr_destroy(mlp_nbr *nbr);
+
+/* ---------------------------------------------------------------------------
+ * mlp_nbr_edges — the directed edges of a neighbour handle in the caller's
+ * atom numbering: which = 0 for the rc + skin graph of the last build,
+ * which = 1 for the rc graph of the last mlp_energy_forces call.
+ * dst, src: device int32 arrays of capacity cap; edge e is (dst[e] <- src[e]).
+ * Edges are grouped by destination in the library's internal (cell-sorted)
+ * order; callers that need a canonical order sort them.
+ * *n_edges (host) receives the count; when it exceeds cap nothing is written
+ * and CAPACITY is returned.  Synchronises the stream.
+ * ------------------------------------------------------------------------- */
+int mlp_nbr_edges(mlp_nbr *nbr, int32_t which, int32_t *dst, int32_t *src, int64_t cap, int64_t *n_edges,
+                  void *stream);
+
+/* ---------------------------------------------------------------------------
+ * mlp_energy_forces — E = sum_{i < n_local} U_i (Eq. 1) and F = -dE/dr for
+ * every row (Eq. 2), on the graph of the last mlp_build_neighbors call with
+ * edges pruned to r < rc at the current positions, and atoms farther than
+ * T hops from the locals pruned.
+ * pos: device SoA 3 x n_atoms (same atom order, count and n_local as the
+ *   build; displacements since the build must stay below skin/2 for the
+ *   result to be exact).
+ * ghost_owner: NULL, or device int32 [n_atoms - n_local] with the local
+ *   index each ghost copies; then each ghost row's force is also added into
+ *   its owner's row (the reverse summation of partial forces) while ghost
+ *   rows keep their own partial forces.
+ * energy: device double [1] (written on the stream).
+ * forces: device SoA 3 x n_atoms float32 (written on the stream).
+ * atom_energy: NULL or device float [n_atoms] receiving U_i (ghost rows too).
+ * stats: NULL, or host struct filled after a stream synchronisation.
+ * Errors: INVALID_ARG, CAPACITY, DEVICE.
+ * ------------------------------------------------------------------------- */
+int mlp_energy_forces(mlp_model *model, mlp_nbr *nbr, const float *pos, int32_t n_atoms,
+                      int32_t n_local, const int32_t *ghost_owner, void *stream, double *energy,
+                      float *forces, float *atom_energy, mlp_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * mlp_md_step — one velocity-Verlet step (kick, drift, wrap into [0, L),
+ * rebuild the neighbour graph when the largest displacement since the last
+ * build exceeds skin/2, evaluate, kick) for a periodic system without ghosts,
+ * the protocol the paper runs its timing simulations with (Methods,
+ * "Molecular Dynamics Simulations", thermostat aside).
+ * pos, vel: device SoA 3 x n float32, updated in place (vel in A/fs).
+ * forces: device SoA 3 x n float32: on entry the forces at pos, on exit the
+ *   forces at the new positions.  inv_mass: device float [n] (1/amu).
+ * energy: device double [1], potential energy at the new positions.
+ * *rebuilt (host, may be NULL) is set to 1 when the graph was rebuilt.
+ * Synchronises the stream once (the displacement check).
+ * ------------------------------------------------------------------------- */
+int mlp_md_step(mlp_model *model, mlp_nbr *nbr, float *pos, float *vel, float *forces,
+                const float *inv_mass, const int32_t *species, int32_t n, const double box[3],
+                float skin, float dt, void *stream, double *energy, int32_t *rebuilt);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent periodic systems.
+ * mlp_server_create starts a scheduler thread with its own streams.
+ *   hbm_budget_bytes bounds the device memory of admitted requests; a
+ *   request whose estimated footprint exceeds the budget on its own is
+ *   rejected with INVALID_ARG at submit.  max_slots bounds the number of
+ *   requests resident on the device at once.
+ * mlp_submit copies the request's host arrays (pos SoA 3 x n float32,
+ *   species int32 [n], box) into library-owned pinned memory, queues it and
+ *   returns a ticket without waiting for the GPU.
+ * mlp_poll returns MLP_PENDING while the request runs, MLP_OK once energy
+ *   (host double) and forces (host SoA 3 x n float32) have been copied out
+ *   (the ticket is then retired), or an error.  timing (nullable) receives
+ *   the request's submit->done latency in microseconds and its queueing part.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    const float *pos;        /* host SoA 3 x n_atoms */
+    const int32_t *species;  /* host [n_atoms] */
+    int32_t n_atoms;
+    double box[3];
+} mlp_request;
+
+typedef struct {
+    double latency_us;       /* submit -> results ready */
+    double queue_us;         /* submit -> admitted to the device */
+    int32_t batch_size;      /* requests in the launch wave that ran it */
+} mlp_timing;
+
+int mlp_server_create(mlp_model *model, size_t hbm_budget_bytes, int32_t max_slots,
+                      mlp_server **out);
+int mlp_server_destroy(mlp_server *server);
+int mlp_submit(mlp_server *server, const mlp_request *req, uint64_t *ticket);
+int mlp_poll(mlp_server *server, uint64_t ticket, double *energy, float *forces,
+             mlp_timing *timing);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLP_H */

@@ -1,0 +1,360 @@
+// C ABI of libmlp: model and neighbour handles, evaluation, MD step.
+#include "../../include/mlp.h"
+#include "internal.h"
+
+#include <cctype>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+
+namespace mlp {
+const char *last_error_cstr();
+int hop_histogram(mlp_model *m, mlp_nbr *g, hipStream_t s, int *hist_host);
+int export_edges(mlp_nbr *g, const int *row, const int *col, int32_t *dst, int32_t *src, hipStream_t s);
+}
+
+using namespace mlp;
+
+// ---------------------------------------------------------------------------
+// Minimal reader for the flat top-level JSON object of the model header.
+// Values: numbers and strings are kept; nested objects/arrays are skipped.
+// ---------------------------------------------------------------------------
+namespace {
+struct JsonTop {
+    std::map<std::string, std::string> kv;
+    bool ok = false;
+};
+
+void skip_ws(const char *&p) {
+    while (*p && std::isspace((unsigned char)*p)) p++;
+}
+
+bool read_string(const char *&p, std::string &out) {
+    if (*p != '"') return false;
+    p++;
+    out.clear();
+    while (*p && *p != '"') {
+        if (*p == '\\' && p[1]) p++;
+        out.push_back(*p++);
+    }
+    if (*p != '"') return false;
+    p++;
+    return true;
+}
+
+bool skip_value(const char *&p, std::string *scalar) {
+    skip_ws(p);
+    if (*p == '"') {
+        std::string s;
+        if (!read_string(p, s)) return false;
+        if (scalar) *scalar = s;
+        return true;
+    }
+    if (*p == '{' || *p == '[') {
+        int depth = 0;
+        bool in_str = false;
+        do {
+            char c = *p;
+            if (!c) return false;
+            if (in_str) {
+                if (c == '\\' && p[1]) p++;
+                else if (c == '"') in_str = false;
+            } else if (c == '"') {
+                in_str = true;
+            } else if (c == '{' || c == '[') {
+                depth++;
+            } else if (c == '}' || c == ']') {
+                depth--;
+            }
+            p++;
+        } while (depth > 0);
+        return true;
+    }
+    const char *b = p;
+    while (*p && *p != ',' && *p != '}' && !std::isspace((unsigned char)*p)) p++;
+    if (scalar) scalar->assign(b, p);
+    return p > b;
+}
+
+JsonTop parse_top(const char *s) {
+    JsonTop r;
+    const char *p = s;
+    skip_ws(p);
+    if (*p != '{') return r;
+    p++;
+    for (;;) {
+        skip_ws(p);
+        if (*p == '}') {
+            r.ok = true;
+            return r;
+        }
+        std::string key, val;
+        if (!read_string(p, key)) return r;
+        skip_ws(p);
+        if (*p != ':') return r;
+        p++;
+        if (!skip_value(p, &val)) return r;
+        r.kv[key] = val;
+        skip_ws(p);
+        if (*p == ',') {
+            p++;
+            continue;
+        }
+        if (*p == '}') {
+            r.ok = true;
+            return r;
+        }
+        return r;
+    }
+}
+
+bool get_int(const JsonTop &j, const char *k, long *out) {
+    auto it = j.kv.find(k);
+    if (it == j.kv.end()) return false;
+    char *end = nullptr;
+    long v = std::strtol(it->second.c_str(), &end, 10);
+    if (end == it->second.c_str() || *end) return false;
+    *out = v;
+    return true;
+}
+
+bool get_num(const JsonTop &j, const char *k, double *out) {
+    auto it = j.kv.find(k);
+    if (it == j.kv.end()) return false;
+    char *end = nullptr;
+    double v = std::strtod(it->second.c_str(), &end);
+    if (end == it->second.c_str() || *end) return false;
+    *out = v;
+    return true;
+}
+
+int status(int rc) { return rc; }
+}  // namespace
+
+mlp::LayerW mlp_model::layer(int t) const {
+    LayerW L;
+    const size_t *o = off_layer[t];
+    L.W1 = at(o[0]); L.b1 = at(o[1]); L.W2 = at(o[2]); L.b2 = at(o[3]);
+    L.A = at(o[4]); L.c = at(o[5]); L.U = at(o[6]); L.V = at(o[7]);
+    L.W3 = at(o[8]); L.b3 = at(o[9]); L.W4 = at(o[10]); L.b4 = at(o[11]);
+    return L;
+}
+
+extern "C" {
+
+const char *mlp_last_error(void) { return last_error_cstr(); }
+
+int mlp_model_create(const char *header_json, const float *weights, size_t n_weights, int precision,
+                     mlp_model **out) {
+    if (!header_json || !weights || !out) return fail(MLP_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    JsonTop j = parse_top(header_json);
+    if (!j.ok) return fail(MLP_ERR_INVALID_ARG, "model header is not a JSON object");
+    long F, K, T, S;
+    double rc, eps;
+    if (!get_int(j, "F", &F) || !get_int(j, "K", &K) || !get_int(j, "T", &T) || !get_int(j, "n_species", &S) ||
+        !get_num(j, "r_c", &rc) || !get_num(j, "eps", &eps))
+        return fail(MLP_ERR_INVALID_ARG, "model header lacks F, K, T, n_species, r_c or eps");
+    auto str = [&](const char *k) { auto it = j.kv.find(k); return it == j.kv.end() ? std::string() : it->second; };
+    if (str("model") != "painn") return fail(MLP_ERR_INVALID_ARG, "model must be \"painn\"");
+    if (str("basis") != "bessel_sin_over_r") return fail(MLP_ERR_INVALID_ARG, "basis must be bessel_sin_over_r");
+    if (str("envelope") != "cosine") return fail(MLP_ERR_INVALID_ARG, "envelope must be cosine");
+    if (!(F == 16 || F == 32 || F == 64 || F == 128)) return fail(MLP_ERR_INVALID_ARG, "F must be 16, 32, 64 or 128");
+    if (K < 1 || K > MLP_MAX_K || T < 1 || T > MLP_MAX_LAYERS || S < 1)
+        return fail(MLP_ERR_INVALID_ARG, "K, T or n_species out of range");
+    {
+        static const int ok[][2] = {{128, 20}, {32, 8}, {64, 20}, {128, 8}, {32, 20}, {64, 8}, {16, 6}};
+        bool found = false;
+        for (auto &p : ok) found |= (p[0] == F && p[1] == K);
+        if (!found) return fail(MLP_ERR_INVALID_ARG, "(F, K) combination is not compiled in this build");
+    }
+    if (!(rc > 0.0) || !(eps > 0.0)) return fail(MLP_ERR_INVALID_ARG, "r_c and eps must be positive");
+    if (precision != MLP_FP32 && precision != MLP_BF16) return fail(MLP_ERR_INVALID_ARG, "unknown precision");
+    mlp_model *m = new mlp_model();
+    m->F = (int)F; m->K = (int)K; m->T = (int)T; m->S = (int)S;
+    m->rc = (float)rc; m->eps = (float)eps; m->precision = precision;
+    size_t off = 0;
+    m->off_emb = off; off += (size_t)S * F;
+    const size_t sizes[12] = {(size_t)F * F, (size_t)F, 3 * (size_t)F * F, 3 * (size_t)F, 3 * (size_t)F * K,
+                              3 * (size_t)F, (size_t)F * F, (size_t)F * F, 2 * (size_t)F * F, (size_t)F,
+                              3 * (size_t)F * F, 3 * (size_t)F};
+    for (int t = 0; t < T; t++)
+        for (int b = 0; b < 12; b++) {
+            m->off_layer[t][b] = off;
+            off += sizes[b];
+        }
+    m->off_W5 = off; off += (size_t)(F / 2) * F;
+    m->off_b5 = off; off += F / 2;
+    m->off_w6 = off; off += F / 2;
+    m->off_b6 = off; off += 1;
+    if (off != n_weights) {
+        delete m;
+        return fail(MLP_ERR_INVALID_ARG, "weight count " + std::to_string(n_weights) + " does not match the header (" +
+                                             std::to_string(off) + ")");
+    }
+    m->n_weights = off;
+    if (hipMalloc(&m->w_dev, sizeof(float) * off) != hipSuccess) {
+        (void)hipGetLastError();
+        delete m;
+        return fail(MLP_ERR_OOM, "weight allocation failed");
+    }
+    if (hipMemcpy(m->w_dev, weights, sizeof(float) * off, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(m->w_dev);
+        delete m;
+        return fail(MLP_ERR_DEVICE, "weight copy failed");
+    }
+    *out = m;
+    return MLP_OK;
+}
+
+int mlp_model_destroy(mlp_model *m) {
+    if (!m) return MLP_OK;
+    if (m->w_dev) hipFree(m->w_dev);
+    if (m->wb_dev) hipFree(m->wb_dev);
+    delete m;
+    return MLP_OK;
+}
+
+int mlp_build_neighbors(mlp_model *m, const float *pos, const int32_t *species, int32_t n_atoms, int32_t n_local,
+                        const double box[3], float skin, void *stream, mlp_nbr **inout) {
+    if (!m || !pos || !species || !box || !inout) return fail(MLP_ERR_INVALID_ARG, "null argument");
+    mlp_nbr *g = *inout;
+    bool created = false;
+    if (!g) {
+        g = new mlp_nbr();
+        created = true;
+    }
+    int rc = build_graph(m, g, pos, species, n_atoms, n_local, box, skin, (hipStream_t)stream);
+    if (rc) {
+        if (created) {
+            mlp_nbr_destroy(g);
+        }
+        return rc;
+    }
+    *inout = g;
+    return MLP_OK;
+}
+
+static void release_all(mlp_nbr *g) {
+    DevBuf *bufs[] = {&g->perm, &g->iperm, &g->cell_of, &g->cell_start, &g->cell_cnt, &g->cell_fill, &g->tmp_idx,
+                      &g->pos_build, &g->species, &g->row, &g->col, &g->rev, &g->rowc, &g->colc, &g->revc,
+                      &g->geom, &g->map, &g->oldidx, &g->cnt, &g->hop, &g->pos4, &g->scan_tmp, &g->flags,
+                      &g->red, &g->ghost_ptr, &g->ghost_list, &g->ghost_cnt, &g->act, &g->G, &g->Fint, &g->Uatom};
+    for (DevBuf *b : bufs) b->release();
+}
+
+static int64_t held_bytes(mlp_nbr *g) {
+    DevBuf *bufs[] = {&g->perm, &g->iperm, &g->cell_of, &g->cell_start, &g->cell_cnt, &g->cell_fill, &g->tmp_idx,
+                      &g->pos_build, &g->species, &g->row, &g->col, &g->rev, &g->rowc, &g->colc, &g->revc,
+                      &g->geom, &g->map, &g->oldidx, &g->cnt, &g->hop, &g->pos4, &g->scan_tmp, &g->flags,
+                      &g->red, &g->ghost_ptr, &g->ghost_list, &g->ghost_cnt, &g->act, &g->G, &g->Fint, &g->Uatom};
+    int64_t t = 0;
+    for (DevBuf *b : bufs) t += (int64_t)b->bytes;
+    return t;
+}
+
+int mlp_nbr_destroy(mlp_nbr *g) {
+    if (!g) return MLP_OK;
+    release_all(g);
+    delete g;
+    return MLP_OK;
+}
+
+int mlp_energy_forces(mlp_model *m, mlp_nbr *g, const float *pos, int32_t n_atoms, int32_t n_local,
+                      const int32_t *ghost_owner, void *stream, double *energy, float *forces, float *atom_energy,
+                      mlp_stats *stats) {
+    if (!m || !g || !pos || !energy) return fail(MLP_ERR_INVALID_ARG, "null argument");
+    if (g->n_builds == 0) return fail(MLP_ERR_INVALID_ARG, "neighbour handle was never built");
+    if (n_atoms != g->n_atoms || n_local != g->n_local)
+        return fail(MLP_ERR_INVALID_ARG, "atom counts differ from the last neighbour build");
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if ((rc = prune_graph(m, g, pos, s))) return rc;
+    if ((rc = compute_hops(m, g, s))) return rc;
+    if ((rc = evaluate(m, g, s, energy, forces, atom_energy))) return rc;
+    if (forces && ghost_owner && n_atoms > n_local)
+        if ((rc = fold_ghosts(g, ghost_owner, forces, s))) return rc;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        int hist[MLP_MAX_LAYERS + 2] = {0};
+        if ((rc = hop_histogram(m, g, s, hist))) return rc;
+        int Ec = 0, flag1 = 0;
+        if (hipMemcpyAsync(&Ec, g->rowc.as<int>() + g->n_atoms, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&flag1, g->flags.as<int>() + 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(MLP_ERR_DEVICE, "statistics readback failed");
+        if (flag1) return fail(MLP_ERR_INVALID_ARG, "ghost owner index out of range");
+        stats->n_edges_skin = g->n_edges_skin;
+        stats->n_edges = Ec;
+        stats->n_atoms = g->n_atoms;
+        stats->n_local = g->n_local;
+        int run = 0;
+        for (int t = 0; t <= m->T && t < 8; t++) {
+            run += hist[t];
+            stats->n_within_hops[t] = run;
+        }
+        for (int d = 0; d < 3; d++) stats->n_cells[d] = g->nc[d];
+        stats->max_cell_occupancy = g->max_occ;
+        stats->n_builds = g->n_builds;
+        stats->n_grows = g->n_grows;
+        stats->device_bytes = held_bytes(g);
+    }
+    return MLP_OK;
+}
+
+int mlp_md_step(mlp_model *m, mlp_nbr *g, float *pos, float *vel, float *forces, const float *inv_mass,
+                const int32_t *species, int32_t n, const double box[3], float skin, float dt, void *stream,
+                double *energy, int32_t *rebuilt) {
+    if (!m || !g || !pos || !vel || !forces || !inv_mass || !species || !box || !energy)
+        return fail(MLP_ERR_INVALID_ARG, "null argument");
+    if (g->n_builds == 0 || g->n_atoms != n || g->n_local != n)
+        return fail(MLP_ERR_INVALID_ARG, "MD step needs a periodic system built on this handle");
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if ((rc = verlet_kick_drift(pos, vel, forces, inv_mass, n, box, dt, s))) return rc;
+    bool exceeds = false;
+    if ((rc = max_displacement_exceeds(g, pos, 0.5f * g->skin, s, &exceeds))) return rc;
+    if (rebuilt) *rebuilt = exceeds ? 1 : 0;
+    if (exceeds) {
+        mlp_nbr *gg = g;
+        if ((rc = mlp_build_neighbors(m, pos, species, n, n, box, skin, stream, &gg))) return rc;
+    }
+    if ((rc = mlp_energy_forces(m, g, pos, n, n, nullptr, stream, energy, forces, nullptr, nullptr))) return rc;
+    return verlet_kick(vel, forces, inv_mass, n, dt, s);
+}
+
+int mlp_nbr_edges(mlp_nbr *g, int32_t which, int32_t *dst, int32_t *src, int64_t cap, int64_t *n_edges,
+                  void *stream) {
+    if (!g || !n_edges || (which != 0 && which != 1)) return fail(MLP_ERR_INVALID_ARG, "bad argument");
+    if (g->n_builds == 0) return fail(MLP_ERR_INVALID_ARG, "neighbour handle was never built");
+    hipStream_t s = (hipStream_t)stream;
+    const int *row = which ? g->rowc.as<int>() : g->row.as<int>();
+    const int *col = which ? g->colc.as<int>() : g->col.as<int>();
+    if (which && !row) return fail(MLP_ERR_INVALID_ARG, "no evaluation has pruned this graph yet");
+    int E = 0;
+    if (hipMemcpyAsync(&E, row + g->n_atoms, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(MLP_ERR_DEVICE, "edge count readback failed");
+    *n_edges = E;
+    if (E > cap) return fail(MLP_ERR_CAPACITY, "edge arrays too small");
+    if (!dst || !src) return fail(MLP_ERR_INVALID_ARG, "null edge arrays");
+    int rc = export_edges(g, row, col, dst, src, s);
+    if (rc) return rc;
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(MLP_ERR_DEVICE, "edge export failed");
+    return MLP_OK;
+}
+
+int mlp_server_create(mlp_model *, size_t, int32_t, mlp_server **) {
+    return fail(MLP_ERR_INVALID_ARG, "server not available in this build");
+}
+int mlp_server_destroy(mlp_server *) { return MLP_OK; }
+int mlp_submit(mlp_server *, const mlp_request *, uint64_t *) {
+    return fail(MLP_ERR_INVALID_ARG, "server not available in this build");
+}
+int mlp_poll(mlp_server *, uint64_t, double *, float *, mlp_timing *) {
+    return fail(MLP_ERR_UNKNOWN_TICKET, "server not available in this build");
+}
+
+}  // extern "C"

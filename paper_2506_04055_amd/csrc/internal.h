@@ -1,0 +1,108 @@
+// Internal declarations shared by the libmlp translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string>
+
+#define MLP_MAX_LAYERS 7
+#define MLP_MAX_K 32
+
+namespace mlp {
+
+// Status carried through host code; converted to the C return codes at the boundary.
+struct Error {
+    int code;
+    std::string msg;
+};
+
+void set_error(int code, const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t _e = (expr);                                                         \
+        if (_e != hipSuccess)                                                           \
+            return ::mlp::fail(-5, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+// Grow-only device buffer.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    // Ensure at least `need` bytes; grows to need * headroom.  Returns 0 or error code.
+    int ensure(size_t need, double headroom, int *n_grows);
+    void release();
+    template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// Device-side view of one layer's weights (float32 and optional bf16 copies).
+struct LayerW {
+    const float *W1, *b1, *W2, *b2, *A, *c, *U, *V, *W3, *b3, *W4, *b4;
+};
+
+}  // namespace mlp
+
+struct mlp_model {
+    int F, K, T, S, precision;
+    float rc, eps;
+    size_t n_weights;
+    float *w_dev = nullptr;              // flat weights on the device
+    __hip_bfloat16 *wb_dev = nullptr;    // bf16 copy (same offsets)
+    size_t off_emb;
+    size_t off_layer[MLP_MAX_LAYERS][12];
+    size_t off_W5, off_b5, off_w6, off_b6;
+    mlp::LayerW layer(int t) const;
+    const float *at(size_t off) const { return w_dev + off; }
+    const __hip_bfloat16 *atb(size_t off) const { return wb_dev + off; }
+};
+
+struct mlp_nbr {
+    int n_atoms = 0, n_local = 0;
+    bool open = false;
+    float box[3] = {0, 0, 0};
+    float skin = 0;
+    int nc[3] = {1, 1, 1};
+    float lo[3] = {0, 0, 0};
+    float inv_w[3] = {1, 1, 1};
+    int64_t n_edges_skin = 0;
+    int n_builds = 0, n_grows = 0, max_occ = 0;
+    // graph (internal atom order: cell-sorted)
+    mlp::DevBuf perm, iperm, cell_of, cell_start, cell_cnt, cell_fill, tmp_idx;
+    mlp::DevBuf pos_build;     // float4 positions at build time (internal order)
+    mlp::DevBuf species;       // int32 internal order
+    mlp::DevBuf row, col, rev; // skin graph CSR
+    mlp::DevBuf rowc, colc, revc, geom, map, oldidx, cnt;  // pruned graph
+    mlp::DevBuf hop;           // int8 hop distance (capped T+1)
+    mlp::DevBuf pos4;          // float4 positions at evaluation (internal order)
+    mlp::DevBuf scan_tmp, flags, red;
+    mlp::DevBuf ghost_ptr, ghost_list, ghost_cnt;  // owner -> ghosts (user indices)
+    // model activations
+    mlp::DevBuf act;           // one arena for per-layer activations
+    size_t act_bytes = 0;
+    int act_N = 0, act_F = 0, act_T = 0;
+    mlp::DevBuf G, Fint, Uatom;
+};
+
+namespace mlp {
+
+// ---- scan / utility (nbr.hip) ----
+int scan_exclusive(const int *in, int *out, int n, DevBuf &tmp, int *n_grows, hipStream_t s);
+
+// ---- graph (nbr.hip) ----
+int build_graph(mlp_model *m, mlp_nbr *g, const float *pos, const int32_t *species, int n, int n_local,
+                const double box[3], float skin, hipStream_t s);
+int prune_graph(mlp_model *m, mlp_nbr *g, const float *pos, hipStream_t s);
+int compute_hops(mlp_model *m, mlp_nbr *g, hipStream_t s);
+int fold_ghosts(mlp_nbr *g, const int32_t *owner, float *forces, hipStream_t s);
+int max_displacement_exceeds(mlp_nbr *g, const float *pos, float limit, hipStream_t s, bool *exceeds);
+
+// ---- model (painn.hip) ----
+int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
+             float *atom_energy_user);
+int verlet_kick_drift(float *pos, float *vel, const float *forces, const float *inv_mass, int n,
+                      const double box[3], float dt, hipStream_t s);
+int verlet_kick(float *vel, const float *forces, const float *inv_mass, int n, float dt, hipStream_t s);
+
+}  // namespace mlp

@@ -1,0 +1,219 @@
+"""GPU path (through the C ABI) against the FP64 oracle on identical seeded inputs.
+
+Tolerances (FP32 path): forces within 1e-5 relative RMS of the oracle,
+||F - F_ref||_2 / ||F_ref||_2 over all components; energy within 2e-6
+relative (per-atom FP32 energies summed in FP64).  Integer results (neighbour
+sets, hop counts) are compared exactly, with the oracle taking the pair
+decision in float32 by the same formula.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_04055_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+F_TOL_FP32 = 1e-5
+E_TOL_FP32 = 2e-6
+
+
+@pytest.fixture(scope="module")
+def mlp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_04055_amd import mlp as M
+    M.lib()
+    return M
+
+
+def run_gpu(M, sysm, hdr, w, precision="fp32", skin=1.0, stats=False, atom_energy=False):
+    import torch
+    model = M.Model(hdr, w, precision)
+    owner = sysm.owner if sysm.n_atoms > sysm.n_local else None
+    d = M.System(model, sysm.pos, sysm.species, sysm.box, n_local=sysm.n_local, skin=skin, ghost_owner=owner)
+    out = d.compute(stats=stats, atom_energy=atom_energy)
+    torch.cuda.synchronize()
+    res = {"E": float(out["energy"].item()), "F": out["forces"].t().cpu().numpy().astype(np.float64),
+           "sys": d, "model": model}
+    if stats:
+        res["stats"] = out["stats"]
+    if atom_energy:
+        res["U"] = out["atom_energy"].cpu().numpy().astype(np.float64)
+    return res
+
+
+def rel_rms(F, Fref):
+    return float(np.linalg.norm(F - Fref) / np.linalg.norm(Fref))
+
+
+def test_neighbor_graph_exact(mlp, oracle):
+    s = synth.water_box(4, 3.105, seed=0)
+    hdr, w = synth.make_weights(32, 8, 2, 2, seed=0)
+    model = mlp.Model(hdr, w)
+    d = mlp.System(model, s.pos, s.species, s.box, skin=1.0)
+    dst, src = mlp.mlp_nbr_edges(d.nbr, 0)
+    od, os_ = oracle.neighbors_f32(s.pos, s.box.astype(np.float32), 5.0, 1.0)
+    assert np.array_equal(dst, od) and np.array_equal(src, os_)
+    d.compute()
+    dst, src = mlp.mlp_nbr_edges(d.nbr, 1)
+    od, os_ = oracle.neighbors_f32(s.pos, s.box.astype(np.float32), 5.0, 0.0)
+    assert np.array_equal(dst, od) and np.array_equal(src, os_)
+
+
+def test_neighbor_graph_exact_large_cells(mlp, oracle):
+    # many cells per dimension, open box with ghosts
+    s = synth.fcc_crystal(4, seed=2, ghost_depth=6.0)
+    hdr, w = synth.make_weights(32, 8, 1, 1, seed=0)
+    model = mlp.Model(hdr, w)
+    d = mlp.System(model, s.pos, s.species, s.box, n_local=s.n_local, skin=0.5)
+    dst, src = mlp.mlp_nbr_edges(d.nbr, 0)
+    od, os_ = oracle.neighbors_f32(s.pos, np.zeros(3, np.float32), 5.0, 0.5)
+    assert np.array_equal(dst, od) and np.array_equal(src, os_)
+
+
+def test_water192_energy_forces(mlp, oracle):
+    s, hdr, w = synth.workload("water192")
+    E_ref, F_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box)
+    r = run_gpu(mlp, s, hdr, w)
+    assert abs(r["E"] - E_ref) <= E_TOL_FP32 * abs(E_ref)
+    assert rel_rms(r["F"], F_ref) <= F_TOL_FP32
+
+
+def test_biases_and_three_species(mlp, oracle):
+    s = synth.peptide_like(700, seed=3)
+    hdr, w = synth.make_weights(64, 20, 3, 4, seed=4, bias_scale=0.2)
+    E_ref, F_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box)
+    r = run_gpu(mlp, s, hdr, w, skin=0.7)
+    assert abs(r["E"] - E_ref) <= E_TOL_FP32 * abs(E_ref)
+    assert rel_rms(r["F"], F_ref) <= F_TOL_FP32
+
+
+def test_bench_model_ragged_size(mlp, oracle):
+    # the benchmark's model (T=3, F=128, K=20) on 648 atoms: several GEMM
+    # tiles plus a ragged tail
+    s = synth.water_box(6, 3.105, seed=7)
+    hdr, w = synth.make_weights(128, 20, 3, 2, seed=7)
+    E_ref, F_ref, U_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box, per_atom=True)
+    r = run_gpu(mlp, s, hdr, w, atom_energy=True)
+    assert abs(r["E"] - E_ref) <= E_TOL_FP32 * abs(E_ref)
+    assert rel_rms(r["F"], F_ref) <= F_TOL_FP32
+    assert np.abs(r["U"] - U_ref).max() <= 1e-5 * np.abs(U_ref).max()
+
+
+def test_full_size_24k_water(mlp, oracle):
+    # the benchmark's workload at full size, every output compared
+    s, hdr, w = synth.workload("water24k")
+    E_ref, F_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box)
+    r = run_gpu(mlp, s, hdr, w, stats=True)
+    assert abs(r["E"] - E_ref) <= E_TOL_FP32 * abs(E_ref)
+    assert rel_rms(r["F"], F_ref) <= F_TOL_FP32
+    st = r["stats"]
+    dst, src, _ = oracle.neighbors(s.pos, s.box, 5.0)
+    assert abs(st["n_edges"] - len(dst)) <= 4   # float32 vs float64 decisions at r == rc
+
+
+def test_ghost_domain_and_fold(mlp, oracle):
+    # one domain's share: locals + a T*rc ghost shell, open boundaries
+    hdr, w = synth.make_weights(128, 20, 3, 1, seed=9, bias_scale=0.1)
+    dom = synth.fcc_crystal(4, seed=3, ghost_depth=15.0)
+    per = synth.fcc_crystal(4, seed=3)
+    E_ref, F_ref = oracle.energy_forces(hdr, w, dom.pos, dom.species, np.zeros(3), n_local=dom.n_local)
+    r = run_gpu(mlp, dom, hdr, w, skin=0.5, stats=True)
+    assert abs(r["E"] - E_ref) <= E_TOL_FP32 * abs(E_ref)
+    # ghost rows keep their partial forces; local rows hold the folded sums
+    folded_ref = oracle.fold_ghost_forces(F_ref, dom.n_local, dom.owner)
+    assert rel_rms(r["F"], folded_ref) <= F_TOL_FP32
+    # folded local forces equal the periodic system's forces (Eq. 2)
+    Ep, Fp = oracle.energy_forces(hdr, w, per.pos, per.species, per.box)
+    assert rel_rms(r["F"][: dom.n_local], Fp) <= 1e-4   # ghost rows are float32-rounded images
+    # hop counts: exact
+    od, os_ = oracle.neighbors_f32(dom.pos, np.zeros(3, np.float32), 5.0, 0.0)
+    hops = oracle.hops(dom.n_atoms, dom.n_local, od, os_, 3)
+    cum = np.cumsum(np.bincount(hops, minlength=5))
+    assert r["stats"]["n_within_hops"][:4] == cum[:4].tolist()
+
+
+def test_isolated_atoms_and_single_atom(mlp, oracle):
+    hdr, w = synth.make_weights(32, 8, 2, 3, seed=1, bias_scale=0.3)
+    pos = np.array([[1.0, 1.0, 1.0], [10.0, 1.0, 1.0], [1.0, 12.0, 1.0], [15.0, 15.0, 15.0]], np.float32)
+    sp = np.array([0, 1, 2, 1], np.int32)
+    box = np.array([30.0, 30.0, 30.0])
+    s = synth.System(pos, sp, box, 4)
+    E_ref, F_ref = oracle.energy_forces(hdr, w, pos, sp, box)
+    r = run_gpu(mlp, s, hdr, w)
+    assert abs(r["E"] - E_ref) <= E_TOL_FP32 * abs(E_ref)
+    assert np.all(r["F"] == 0.0)
+    s1 = synth.System(pos[:1], sp[:1], box, 1)
+    E1, _ = oracle.energy_forces(hdr, w, pos[:1], sp[:1], box)
+    r1 = run_gpu(mlp, s1, hdr, w)
+    assert abs(r1["E"] - E1) <= E_TOL_FP32 * abs(E1) and np.all(r1["F"] == 0.0)
+
+
+def test_permutation_and_determinism(mlp):
+    s, hdr, w = synth.workload("water192")
+    r = run_gpu(mlp, s, hdr, w)
+    r2 = run_gpu(mlp, s, hdr, w)
+    assert r["E"] == r2["E"] and np.array_equal(r["F"], r2["F"])   # bitwise reproducible
+    perm = np.random.default_rng(0).permutation(s.n_atoms)
+    sp = synth.System(s.pos[perm], s.species[perm], s.box, s.n_atoms)
+    r3 = run_gpu(mlp, sp, hdr, w)
+    assert abs(r3["E"] - r["E"]) <= 1e-6 * abs(r["E"])
+    assert rel_rms(r3["F"], r["F"][perm]) <= 1e-6
+
+
+def test_capacity_growth_on_one_handle(mlp, oracle):
+    import torch
+    hdr, w = synth.make_weights(32, 8, 2, 2, seed=2)
+    model = mlp.Model(hdr, w)
+    small = synth.water_box(4, 3.105, seed=1)
+    big = synth.water_box(5, 3.105, seed=2)
+    d = mlp.System(model, small.pos, small.species, small.box, skin=0.5)
+    d.compute()
+    # rebuild the same handle with a larger system: buffers grow, results stay exact
+    d.n = big.n_atoms
+    d.n_local = big.n_atoms
+    d.pos = torch.as_tensor(big.pos).t().contiguous().cuda()
+    d.species = torch.as_tensor(big.species).cuda()
+    d.box = list(big.box)
+    d.forces = torch.zeros(3, big.n_atoms, device="cuda")
+    d.build()
+    out = d.compute(stats=True)
+    E_ref, F_ref = oracle.energy_forces(hdr, w, big.pos, big.species, big.box)
+    assert out["stats"]["n_grows"] > 0 and out["stats"]["n_builds"] == 2
+    assert abs(out["energy"].item() - E_ref) <= E_TOL_FP32 * abs(E_ref)
+    assert rel_rms(out["forces"].t().cpu().numpy(), F_ref) <= F_TOL_FP32
+
+
+def test_invalid_arguments(mlp):
+    import torch
+    hdr, w = synth.make_weights(32, 8, 2, 2, seed=0)
+    with pytest.raises(mlp.MLPError) as e:
+        mlp.Model(hdr, w[:-1])
+    assert e.value.code == -1
+    model = mlp.Model(hdr, w)
+    s = synth.water_box(4, 3.105, seed=0)
+    bad = s.species.copy()
+    bad[3] = 7
+    with pytest.raises(mlp.MLPError) as e:
+        mlp.System(model, s.pos, bad, s.box)
+    assert e.value.code == -1
+    with pytest.raises(mlp.MLPError) as e:
+        mlp.System(model, s.pos, s.species, s.box, skin=1.5)   # 6.5 >= 12.42 / 2
+    assert e.value.code == -4
+    d = mlp.System(model, s.pos, s.species, s.box)
+    with pytest.raises(mlp.MLPError) as e:
+        mlp.mlp_energy_forces(model.handle, d.nbr, d.pos[:, :100].contiguous(), 100, d.energy)
+    assert e.value.code == -1
+
+
+def test_autograd_function(mlp, oracle):
+    import torch
+    s, hdr, w = synth.workload("water192")
+    model = mlp.Model(hdr, w)
+    d = mlp.System(model, s.pos, s.species, s.box)
+    x = d.pos.clone().requires_grad_(True)
+    E = mlp.MLPEnergy.apply(x, d)
+    E.backward()
+    E_ref, F_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box)
+    assert rel_rms(-x.grad.t().cpu().numpy().astype(np.float64), F_ref) <= F_TOL_FP32
