@@ -53,7 +53,7 @@ enum {
     MLP_ERR_UNKNOWN_TICKET = -6
 };
 
-enum { MLP_FP32 = 0, MLP_BF16 = 1 };
+enum { MLP_FP32 = 0, MLP_BF16 = 1, MLP_BF16_NODE = 2 };
 
 typedef struct mlp_model mlp_model;
 typedef struct mlp_nbr mlp_nbr;
@@ -91,10 +91,11 @@ const char *mlp_last_error(void);
  *   W5 [F/2][F] b5 [F/2] w6 [F/2] b6 [1]); matrices are [out][in] row-major;
  *   3F blocks are split [vv | s | vs] (message) and [vv | sv | ss] (update).
  *   Copied to the device; the caller keeps ownership of its array.
- * precision: MLP_FP32 (all arithmetic FP32) or MLP_BF16 (node-feature GEMMs
+ * precision: MLP_FP32 (all arithmetic FP32), MLP_BF16 (node-feature GEMMs
  *   and the radial-filter contraction take bfloat16 operands with FP32
- *   accumulation; geometry, cutoff, accumulation of messages and forces stay
- *   FP32; the energy sum is FP64 in both).
+ *   accumulation) or MLP_BF16_NODE (node-feature GEMMs bfloat16, radial
+ *   filter FP32).  Geometry, cutoff envelope, accumulation of messages and
+ *   forces stay FP32 in every mode; the energy sum is FP64.
  * Errors: INVALID_ARG (header or weight count), OOM, DEVICE.
  * ------------------------------------------------------------------------- */
 int mlp_model_create(const char *header_json, const float *weights, size_t n_weights,
@@ -176,6 +177,21 @@ int mlp_energy_forces(mlp_model *model, mlp_nbr *nbr, const float *pos, int32_t 
 int mlp_md_step(mlp_model *model, mlp_nbr *nbr, float *pos, float *vel, float *forces,
                 const float *inv_mass, const int32_t *species, int32_t n, const double box[3],
                 float skin, float dt, void *stream, double *energy, int32_t *rebuilt);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing (tracing aid; the library's "statistics of the computation").
+ * mlp_profile_enable(1) makes every later launch of the named kernels record a
+ * pair of HIP events on the stream it is launched on; 0 stops recording; any
+ * other value is a bit mask selecting kernels in the order of the names below
+ * (bit 0 "msg_fwd", bit 1 "msg_bwd", ...).
+ * mlp_profile_read waits for the recorded events of one kernel name and
+ * returns the summed duration (ms) and the number of launches since the last
+ * mlp_profile_reset.  Names: "msg_fwd", "msg_bwd", "node_gemm", "prune",
+ * "neighbors".  Unknown name: INVALID_ARG.  Process-wide, not thread-safe.
+ * ------------------------------------------------------------------------- */
+int mlp_profile_enable(int32_t enable);
+int mlp_profile_reset(void);
+int mlp_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of independent periodic systems.

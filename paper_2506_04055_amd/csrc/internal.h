@@ -8,6 +8,10 @@
 
 #define MLP_MAX_LAYERS 7
 #define MLP_MAX_K 32
+// precision modes (values of the C ABI's MLP_FP32 / MLP_BF16 / MLP_BF16_NODE)
+#define MLP_PREC_FP32 0
+#define MLP_PREC_BF16 1
+#define MLP_PREC_BF16_NODE 2
 
 namespace mlp {
 
@@ -86,6 +90,18 @@ struct mlp_nbr {
 };
 
 namespace mlp {
+
+// ---- kernel timing (prof.hip) ----
+enum ProfKernel { PK_MSG_FWD = 0, PK_MSG_BWD = 1, PK_GEMM = 2, PK_PRUNE = 3, PK_NBR = 4, PK_COUNT = 5 };
+extern bool g_prof_on;
+void prof_begin(int k, hipStream_t s);
+void prof_end(int k, hipStream_t s);
+struct ProfScope {
+    int k;
+    hipStream_t s;
+    ProfScope(int k_, hipStream_t s_) : k(k_), s(s_) { if (g_prof_on) prof_begin(k, s); }
+    ~ProfScope() { if (g_prof_on) prof_end(k, s); }
+};
 
 // ---- scan / utility (nbr.hip) ----
 int scan_exclusive(const int *in, int *out, int n, DevBuf &tmp, int *n_grows, hipStream_t s);

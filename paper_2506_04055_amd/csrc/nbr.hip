@@ -602,8 +602,11 @@ int build_graph(mlp_model *m, mlp_nbr *g, const float *pos, const int32_t *speci
     k_gather_build<<<nblk(n, 256), 256, 0, s>>>(perm, n, posw, species, m->S, cell_user,
                                                   g->pos_build.as<float4>(), g->species.as<int>(), cell_int,
                                                   g->iperm.as<int>(), flag);
+    {
+    ProfScope ps(PK_NBR, s);
     k_nbr<false><<<nblk(n, 128), 128, 0, s>>>(g->pos_build.as<float4>(), cell_int, g->cell_start.as<int>(), n, gr,
                                               cut2, g->cnt.as<int>(), nullptr, nullptr);
+    }
     if ((rc = scan_exclusive(g->cnt.as<int>(), g->row.as<int>(), n, g->scan_tmp, G, s))) return rc;
     int hostv[16];
     int E = 0;
@@ -653,6 +656,7 @@ int prune_graph(mlp_model *m, mlp_nbr *g, const float *pos, hipStream_t s) {
     const float rcut = m->rc;
     const float rc2 = rcut * rcut;
     k_gather_pos<<<nblk(n, 256), 256, 0, s>>>(pos, g->perm.as<int>(), n, g->pos4.as<float4>());
+    ProfScope ps(PK_PRUNE, s);
     k_prune<false><<<nblk(n, 4), 256, 0, s>>>(g->pos4.as<float4>(), g->row.as<int>(), g->col.as<int>(), n,
                                              g->box[0], g->box[1], g->box[2], rc2, g->cnt.as<int>(), nullptr,
                                              nullptr, nullptr, nullptr, nullptr);

@@ -19,6 +19,8 @@
 // through the reverse-edge index, so no floating-point atomics are used and
 // results are bitwise reproducible.
 #include "internal.h"
+#include "gemm.h"
+#include "msg.h"
 
 #include <cmath>
 
@@ -34,333 +36,17 @@ __device__ __forceinline__ float dsiluf_(float x) {
 }
 
 // ---------------------------------------------------------------------------
-// Node GEMMs (FP32 SIMT).  C[m][n] = sum_r A[m][r] B(r, n) with
-//   NT: B(r, n) = W[n][r]  (forward, W stored [out][in])
-//   NN: B(r, n) = W[r][n]  (adjoint, multiplying by W^T on the right)
+// Node GEMMs run on the matrix cores (gemm.hip).
 // ---------------------------------------------------------------------------
-enum { E_STORE = 0, E_BIAS = 1, E_BIAS_SILU = 2, E_DSILU = 3, E_ADD = 4 };
-
-constexpr int GBM = 64, GBN = 64, GBK = 16;
+enum { E_STORE = GE_STORE, E_BIAS = GE_BIAS, E_BIAS_SILU = GE_BIAS_SILU, E_DSILU = GE_DSILU, E_ADD = GE_ADD };
 
 template <bool NT, int EPI>
-__global__ void __launch_bounds__(256) k_gemm(const float *__restrict__ A, int lda, const float *__restrict__ B,
-                                              int ldb, float *__restrict__ C, int ldc, int M, int N, int K,
-                                              const float *__restrict__ bias, float *__restrict__ C2, int ldc2,
-                                              const float *R, int ldr) {
-    __shared__ float As[GBK][GBM + 4];
-    __shared__ float Bs[GBK][GBN + 4];
-    const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
-    const long m0 = (long)blockIdx.x * GBM;
-    const int n0 = blockIdx.y * GBN;
-    float acc[4][4] = {};
-    for (int k0 = 0; k0 < K; k0 += GBK) {
-        {
-            int r = tid >> 2, kk = (tid & 3) * 4;
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                long m = m0 + r;
-                int k = k0 + kk + q;
-                As[kk + q][r] = (m < M && k < K) ? A[m * lda + k] : 0.f;
-            }
-        }
-        if (NT) {
-            int c = tid >> 2, kk = (tid & 3) * 4;
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                int n = n0 + c, k = k0 + kk + q;
-                Bs[kk + q][c] = (n < N && k < K) ? B[(long)n * ldb + k] : 0.f;
-            }
-        } else {
-            int r = tid >> 4, c = (tid & 15) * 4;
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                int n = n0 + c + q, k = k0 + r;
-                Bs[r][c + q] = (n < N && k < K) ? B[(long)k * ldb + n] : 0.f;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < GBK; kk++) {
-            float a[4], b[4];
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                a[q] = As[kk][ty * 4 + q];
-                b[q] = Bs[kk][tx * 4 + q];
-            }
-#pragma unroll
-            for (int p = 0; p < 4; p++)
-#pragma unroll
-                for (int q = 0; q < 4; q++) acc[p][q] = fmaf(a[p], b[q], acc[p][q]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int p = 0; p < 4; p++) {
-        long m = m0 + ty * 4 + p;
-        if (m >= M) continue;
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            int n = n0 + tx * 4 + q;
-            if (n >= N) continue;
-            float x = acc[p][q];
-            if (EPI == E_STORE) {
-                C[m * ldc + n] = x;
-            } else if (EPI == E_BIAS) {
-                C[m * ldc + n] = x + bias[n];
-            } else if (EPI == E_BIAS_SILU) {
-                float h = x + bias[n];
-                C[m * ldc + n] = h;
-                C2[m * ldc2 + n] = siluf_(h);
-            } else if (EPI == E_DSILU) {
-                C[m * ldc + n] = x * dsiluf_(R[m * ldr + n]);
-            } else {
-                C[m * ldc + n] = R[m * ldr + n] + x;
-            }
-        }
-    }
-}
-
-template <bool NT, int EPI>
-static void gemm(hipStream_t s, const float *A, int lda, const float *B, int ldb, float *C, int ldc, int M, int N,
-                 int K, const float *bias = nullptr, float *C2 = nullptr, int ldc2 = 0, const float *R = nullptr,
-                 int ldr = 0) {
+static void gemm(hipStream_t s, int prec, const float *A, int lda, const float *B, int ldb, float *C, int ldc, int M,
+                 int N, int K, const float *bias = nullptr, float *C2 = nullptr, int ldc2 = 0,
+                 const float *R = nullptr, int ldr = 0) {
     if (M <= 0) return;
-    dim3 grid(nblk(M, GBM), nblk(N, GBN));
-    k_gemm<NT, EPI><<<grid, 256, 0, s>>>(A, lda, B, ldb, C, ldc, M, N, K, bias, C2, ldc2, R, ldr);
-}
-
-// ---------------------------------------------------------------------------
-// Radial basis: e_k fc with e_k = sin(k theta) / r, theta = pi r / rc, by the
-// rotation recurrence (sin, cos)(k theta) from (sin, cos)(theta).
-// ---------------------------------------------------------------------------
-template <int K>
-__device__ __forceinline__ void radial(float r, float rc, float *sk, float *ck, float &fc, float &dfc) {
-    const float pi = 3.14159265358979f;
-    float th = pi * r / rc;
-    float s1, c1;
-    sincosf(th, &s1, &c1);
-    fc = 0.5f * (c1 + 1.0f);
-    dfc = -0.5f * (pi / rc) * s1;
-    float s = s1, c = c1;
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        sk[k] = s;
-        ck[k] = c;
-        float sn = fmaf(s, c1, c * s1);
-        float cn = fmaf(c, c1, -s * s1);
-        s = sn;
-        c = cn;
-    }
-}
-
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
-}
-
-// ---------------------------------------------------------------------------
-// Message pass: one wave per destination atom, features across lanes.
-// ---------------------------------------------------------------------------
-template <int F, int K>
-__global__ void __launch_bounds__(256) k_msg_fwd(const int *__restrict__ rowc, const int *__restrict__ colc,
-                                                 const float4 *__restrict__ geom, int n,
-                                                 const float *__restrict__ phi, const float *__restrict__ s,
-                                                 const float *__restrict__ v, const float *__restrict__ Aw,
-                                                 const float *__restrict__ cw, float rc,
-                                                 const int8_t *__restrict__ hop, int hop_max,
-                                                 float *__restrict__ sn, float *__restrict__ v1) {
-    constexpr int FPL = F >= 64 ? F / 64 : 1;
-    constexpr int F3 = 3 * F;
-    const int lane = threadIdx.x & 63;
-    const bool on = (F >= 64) || lane < F;
-    float Ar[3][FPL][K], cr[3][FPL];
-#pragma unroll
-    for (int p = 0; p < 3; p++)
-#pragma unroll
-        for (int q = 0; q < FPL; q++) {
-            int f = on ? lane + 64 * q : 0;
-            cr[p][q] = cw[p * F + f];
-#pragma unroll
-            for (int k = 0; k < K; k++) Ar[p][q][k] = Aw[(long)(p * F + f) * K + k];
-        }
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int nwaves = gridDim.x * 4;
-    for (int i = wave; i < n; i += nwaves) {
-        float as[FPL], av[3][FPL];
-#pragma unroll
-        for (int q = 0; q < FPL; q++) {
-            int f = on ? lane + 64 * q : 0;
-            as[q] = s[(long)i * F + f];
-#pragma unroll
-            for (int d = 0; d < 3; d++) av[d][q] = v[(long)i * F3 + d * F + f];
-        }
-        if (hop[i] <= hop_max) {
-            const int e1 = rowc[i + 1];
-            for (int e = rowc[i]; e < e1; e++) {
-                const int j = colc[e];
-                const float4 gm = geom[e];
-                const float r = gm.w, ir = 1.0f / r;
-                const float rh[3] = {gm.x * ir, gm.y * ir, gm.z * ir};
-                float sk[K], ck[K], fc, dfc;
-                radial<K>(r, rc, sk, ck, fc, dfc);
-                float eb[K];
-#pragma unroll
-                for (int k = 0; k < K; k++) eb[k] = sk[k] * ir * fc;
-#pragma unroll
-                for (int q = 0; q < FPL; q++) {
-                    int f = on ? lane + 64 * q : 0;
-                    float w[3];
-#pragma unroll
-                    for (int p = 0; p < 3; p++) {
-                        float acc = cr[p][q] * fc;
-#pragma unroll
-                        for (int k = 0; k < K; k++) acc = fmaf(Ar[p][q][k], eb[k], acc);
-                        w[p] = acc;
-                    }
-                    const float *pj = phi + (long)j * F3;
-                    const float *vj = v + (long)j * F3;
-                    float xvv = pj[f] * w[0];
-                    float xs = pj[F + f] * w[1];
-                    float xvs = pj[2 * F + f] * w[2];
-                    as[q] += xs;
-#pragma unroll
-                    for (int d = 0; d < 3; d++) av[d][q] = fmaf(vj[d * F + f], xvv, fmaf(rh[d], xvs, av[d][q]));
-                }
-            }
-        }
-        if (on) {
-#pragma unroll
-            for (int q = 0; q < FPL; q++) {
-                int f = lane + 64 * q;
-                sn[(long)i * 2 * F + f] = as[q];
-#pragma unroll
-                for (int d = 0; d < 3; d++) v1[(long)i * F3 + d * F + f] = av[d][q];
-            }
-        }
-    }
-}
-
-// Adjoint of the message pass, organised by source atom j over its in-edges
-// (j <- i), which are the reverses of its out-edges (i <- j): gathers the
-// destination gradients, accumulates dE/dphi_j and dE/dv_j in registers and
-// adds G of edge (i <- j) at the position of (j <- i).
-template <int F, int K>
-__global__ void __launch_bounds__(256) k_msg_bwd(const int *__restrict__ rowc, const int *__restrict__ colc,
-                                                 const float4 *__restrict__ geom, int n,
-                                                 const float *__restrict__ phi, const float *__restrict__ v,
-                                                 const float *__restrict__ gs1, const float *__restrict__ gv1,
-                                                 const float *__restrict__ Aw, const float *__restrict__ cw,
-                                                 float rc, const int8_t *__restrict__ hop, int hop_max,
-                                                 float *__restrict__ gv_in, float *__restrict__ gphi,
-                                                 float4 *__restrict__ Gout) {
-    constexpr int FPL = F >= 64 ? F / 64 : 1;
-    constexpr int F3 = 3 * F;
-    const int lane = threadIdx.x & 63;
-    const bool on = (F >= 64) || lane < F;
-    float Ar[3][FPL][K], cr[3][FPL];
-#pragma unroll
-    for (int p = 0; p < 3; p++)
-#pragma unroll
-        for (int q = 0; q < FPL; q++) {
-            int f = on ? lane + 64 * q : 0;
-            cr[p][q] = on ? cw[p * F + f] : 0.f;
-#pragma unroll
-            for (int k = 0; k < K; k++) Ar[p][q][k] = on ? Aw[(long)(p * F + f) * K + k] : 0.f;
-        }
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int nwaves = gridDim.x * 4;
-    for (int j = wave; j < n; j += nwaves) {
-        float ph[3][FPL], vj[3][FPL], gvj[3][FPL], gp[3][FPL];
-#pragma unroll
-        for (int q = 0; q < FPL; q++) {
-            int f = on ? lane + 64 * q : 0;
-#pragma unroll
-            for (int p = 0; p < 3; p++) {
-                ph[p][q] = on ? phi[(long)j * F3 + p * F + f] : 0.f;
-                vj[p][q] = on ? v[(long)j * F3 + p * F + f] : 0.f;
-                gvj[p][q] = on ? gv1[(long)j * F3 + p * F + f] : 0.f;
-                gp[p][q] = 0.f;
-            }
-        }
-        if (hop[j] <= hop_max) {
-            const int e1 = rowc[j + 1];
-            for (int e = rowc[j]; e < e1; e++) {
-                const int i = colc[e];
-                const float4 gm = geom[e];
-                const float r = gm.w, ir = 1.0f / r;
-                const float rh[3] = {-gm.x * ir, -gm.y * ir, -gm.z * ir};  // direction of edge (i <- j)
-                float sk[K], ck[K], fc, dfc;
-                radial<K>(r, rc, sk, ck, fc, dfc);
-                const float pi_rc = 3.14159265358979f / rc;
-                float eb[K], db[K];
-#pragma unroll
-                for (int k = 0; k < K; k++) {
-                    float ek = sk[k] * ir;
-                    eb[k] = ek;
-                    db[k] = ((k + 1) * pi_rc * ck[k] - sk[k] * ir) * ir;  // d e_k / dr
-                }
-                float gr = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-#pragma unroll
-                for (int q = 0; q < FPL; q++) {
-                    int f = on ? lane + 64 * q : 0;
-                    float w[3], dw[3];
-#pragma unroll
-                    for (int p = 0; p < 3; p++) {
-                        float lin = cr[p][q], dlin = 0.f;
-#pragma unroll
-                        for (int k = 0; k < K; k++) {
-                            lin = fmaf(Ar[p][q][k], eb[k], lin);
-                            dlin = fmaf(Ar[p][q][k], db[k], dlin);
-                        }
-                        w[p] = lin * fc;
-                        dw[p] = dlin * fc + lin * dfc;
-                    }
-                    float gvi[3];
-#pragma unroll
-                    for (int d = 0; d < 3; d++) gvi[d] = on ? gv1[(long)i * F3 + d * F + f] : 0.f;
-                    float gxs = on ? gs1[(long)i * F + f] : 0.f;
-                    float gxvv = gvi[0] * vj[0][q] + gvi[1] * vj[1][q] + gvi[2] * vj[2][q];
-                    float gxvs = gvi[0] * rh[0] + gvi[1] * rh[1] + gvi[2] * rh[2];
-                    float xvv = ph[0][q] * w[0];
-                    float xvs = ph[2][q] * w[2];
-#pragma unroll
-                    for (int d = 0; d < 3; d++) gvj[d][q] = fmaf(gvi[d], xvv, gvj[d][q]);
-                    g0 = fmaf(gvi[0], xvs, g0);
-                    g1 = fmaf(gvi[1], xvs, g1);
-                    g2 = fmaf(gvi[2], xvs, g2);
-                    gp[0][q] = fmaf(gxvv, w[0], gp[0][q]);
-                    gp[1][q] = fmaf(gxs, w[1], gp[1][q]);
-                    gp[2][q] = fmaf(gxvs, w[2], gp[2][q]);
-                    gr += gxvv * ph[0][q] * dw[0] + gxs * ph[1][q] * dw[1] + gxvs * ph[2][q] * dw[2];
-                }
-                gr = wave_sum(gr);
-                g0 = wave_sum(g0);
-                g1 = wave_sum(g1);
-                g2 = wave_sum(g2);
-                if (lane == 0) {
-                    float rd = g0 * rh[0] + g1 * rh[1] + g2 * rh[2];
-                    float4 acc = Gout[e];
-                    acc.x += gr * rh[0] + (g0 - rd * rh[0]) * ir;
-                    acc.y += gr * rh[1] + (g1 - rd * rh[1]) * ir;
-                    acc.z += gr * rh[2] + (g2 - rd * rh[2]) * ir;
-                    Gout[e] = acc;
-                }
-            }
-        }
-        if (on) {
-#pragma unroll
-            for (int q = 0; q < FPL; q++) {
-                int f = lane + 64 * q;
-#pragma unroll
-                for (int p = 0; p < 3; p++) {
-                    gv_in[(long)j * F3 + p * F + f] = gvj[p][q];
-                    gphi[(long)j * F3 + p * F + f] = gp[p][q];
-                }
-            }
-        }
-    }
+    ProfScope ps(PK_GEMM, s);
+    node_gemm(s, prec, NT, EPI, A, lda, B, ldb, C, ldc, M, N, K, bias, C2, ldc2, R, ldr);
 }
 
 // ---------------------------------------------------------------------------
@@ -587,41 +273,27 @@ static void carve(float *base, long N, int F, int T, Act &A) {
     A.epart = reinterpret_cast<double *>(take(2 * 1024));
 }
 
-template <int F, int K>
-static void launch_msg_fwd(hipStream_t s, mlp_nbr *g, const float *phi, const float *sv, const float *v,
-                           const float *A, const float *c, float rc, int hop_max, float *sn, float *v1) {
-    const int n = g->n_atoms;
-    int blocks = std::min(nblk(n, 4), 4096);
-    k_msg_fwd<F, K><<<blocks, 256, 0, s>>>(g->rowc.as<int>(), g->colc.as<int>(), g->geom.as<float4>(), n, phi, sv,
-                                           v, A, c, rc, g->hop.as<int8_t>(), hop_max, sn, v1);
+static MsgArgs msg_args(mlp_nbr *g, mlp_model *m, const LayerW &L, int hop_max) {
+    MsgArgs a = {};
+    a.rowc = g->rowc.as<int>();
+    a.colc = g->colc.as<int>();
+    a.geom = g->geom.as<float4>();
+    a.n = g->n_atoms;
+    a.A = L.A;
+    a.c = L.c;
+    a.rc = m->rc;
+    a.hop = g->hop.as<int8_t>();
+    a.hop_max = hop_max;
+    a.G = g->G.as<float4>();
+    return a;
 }
-
-template <int F, int K>
-static void launch_msg_bwd(hipStream_t s, mlp_nbr *g, const float *phi, const float *v, const float *gs1,
-                           const float *gv1, const float *A, const float *c, float rc, int hop_max, float *gv_in,
-                           float *gphi) {
-    const int n = g->n_atoms;
-    int blocks = std::min(nblk(n, 4), 4096);
-    k_msg_bwd<F, K><<<blocks, 256, 0, s>>>(g->rowc.as<int>(), g->colc.as<int>(), g->geom.as<float4>(), n, phi, v,
-                                           gs1, gv1, A, c, rc, g->hop.as<int8_t>(), hop_max, gv_in, gphi,
-                                           g->G.as<float4>());
-}
-
-#define MLP_DISPATCH_FK(F_, K_, CALL)                                              \
-    do {                                                                           \
-        if (F_ == 128 && K_ == 20) { constexpr int FF = 128, KK = 20; CALL; }      \
-        else if (F_ == 32 && K_ == 8) { constexpr int FF = 32, KK = 8; CALL; }     \
-        else if (F_ == 64 && K_ == 20) { constexpr int FF = 64, KK = 20; CALL; }   \
-        else if (F_ == 128 && K_ == 8) { constexpr int FF = 128, KK = 8; CALL; }   \
-        else if (F_ == 32 && K_ == 20) { constexpr int FF = 32, KK = 20; CALL; }   \
-        else if (F_ == 64 && K_ == 8) { constexpr int FF = 64, KK = 8; CALL; }     \
-        else if (F_ == 16 && K_ == 6) { constexpr int FF = 16, KK = 6; CALL; }     \
-        else return fail(-1, "unsupported (F, K) combination");                   \
-    } while (0)
 
 int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
              float *atom_energy_user) {
     const int n = g->n_atoms, F = m->F, K = m->K, T = m->T, F3 = 3 * F, Fh = F / 2;
+    // node GEMM operand precision and radial-filter precision of the mode
+    const int P = m->precision == MLP_PREC_FP32 ? 0 : 1;
+    const int PF = m->precision == MLP_PREC_BF16 ? 1 : 0;
     int *Gr = &g->n_grows;
     int rc;
     const size_t need = act_floats(n, F, T) * sizeof(float);
@@ -636,20 +308,28 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     for (int t = 0; t < T; t++) {
         LayerW L = m->layer(t);
         const int hop_dst = T - 1 - t;
-        gemm<true, E_BIAS_SILU>(s, A.s[t], F, L.W1, F, A.h1[t], F, n, F, F, L.b1, A.tmpF, F);
-        gemm<true, E_BIAS>(s, A.tmpF, F, L.W2, F, A.phi[t], F3, n, F3, F, L.b2);
-        MLP_DISPATCH_FK(F, K, (launch_msg_fwd<FF, KK>(s, g, A.phi[t], A.s[t], A.v[t], L.A, L.c, m->rc, hop_dst,
-                                                       A.sn[t], A.v1[t])));
-        gemm<true, E_STORE>(s, A.v1[t], F, L.U, F, A.Uv[t], F, 3 * n, F, F);
-        gemm<true, E_STORE>(s, A.v1[t], F, L.V, F, A.Vv[t], F, 3 * n, F, F);
+        gemm<true, E_BIAS_SILU>(s, P, A.s[t], F, L.W1, F, A.h1[t], F, n, F, F, L.b1, A.tmpF, F);
+        gemm<true, E_BIAS>(s, P, A.tmpF, F, L.W2, F, A.phi[t], F3, n, F3, F, L.b2);
+        {
+            MsgArgs ma = msg_args(g, m, L, hop_dst);
+            ma.phi = A.phi[t];
+            ma.s = A.s[t];
+            ma.v = A.v[t];
+            ma.sn = A.sn[t];
+            ma.v1 = A.v1[t];
+            ProfScope ps(PK_MSG_FWD, s);
+            if ((rc = msg_forward(s, PF, F, K, ma))) return fail(rc, "message kernel launch failed");
+        }
+        gemm<true, E_STORE>(s, P, A.v1[t], F, L.U, F, A.Uv[t], F, 3 * n, F, F);
+        gemm<true, E_STORE>(s, P, A.v1[t], F, L.V, F, A.Vv[t], F, 3 * n, F, F);
         k_norm<<<nblk((long)n * F, 256), 256, 0, s>>>(A.Vv[t], n, F, m->eps, A.sn[t]);
-        gemm<true, E_BIAS_SILU>(s, A.sn[t], 2 * F, L.W3, 2 * F, A.h3[t], F, n, F, 2 * F, L.b3, A.tmpF, F);
-        gemm<true, E_BIAS>(s, A.tmpF, F, L.W4, F, A.a[t], F3, n, F3, F, L.b4);
+        gemm<true, E_BIAS_SILU>(s, P, A.sn[t], 2 * F, L.W3, 2 * F, A.h3[t], F, n, F, 2 * F, L.b3, A.tmpF, F);
+        gemm<true, E_BIAS>(s, P, A.tmpF, F, L.W4, F, A.a[t], F3, n, F3, F, L.b4);
         k_update_out<<<nblk((long)n * F, 256), 256, 0, s>>>(A.sn[t], A.v1[t], A.Uv[t], A.Vv[t], A.a[t], n, F,
                                                              A.s[t + 1], A.v[t + 1]);
     }
     // readout and energy
-    gemm<true, E_BIAS>(s, A.s[T], F, m->at(m->off_W5), F, A.h5, Fh, n, Fh, F, m->at(m->off_b5));
+    gemm<true, E_BIAS>(s, P, A.s[T], F, m->at(m->off_W5), F, A.h5, Fh, n, Fh, F, m->at(m->off_b5));
     k_readout<<<nblk(n, 256), 256, 0, s>>>(A.h5, n, Fh, m->at(m->off_w6), m->at(m->off_b6), perm, g->n_local, A.U,
                                            A.g5);
     const int nbE = std::min(1024, std::max(1, nblk(n, 4096)));
@@ -659,7 +339,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     if (!forces_user) return 0;
 
     // adjoint
-    gemm<false, E_STORE>(s, A.g5, Fh, m->at(m->off_W5), F, A.gs, F, n, F, Fh);
+    gemm<false, E_STORE>(s, P, A.g5, Fh, m->at(m->off_W5), F, A.gs, F, n, F, Fh);
     k_fill<<<nblk((long)n * F3, 256), 256, 0, s>>>(A.gv, (long)n * F3, 0.f);
     k_fill<<<nblk((long)g->n_edges_skin * 4 + 4, 256), 256, 0, s>>>(g->G.as<float>(), (long)g->n_edges_skin * 4 + 4,
                                                                    0.f);
@@ -668,15 +348,24 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         const int hop_src = T - t;
         k_update_bwd1<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gs, A.gv, A.Uv[t], A.Vv[t], A.a[t], n, F, A.ga,
                                                              A.gUv, A.gVv);
-        gemm<false, E_DSILU>(s, A.ga, F3, L.W4, F, A.gh3, F, n, F, F3, nullptr, nullptr, 0, A.h3[t], F);
-        gemm<false, E_STORE>(s, A.gh3, F, L.W3, 2 * F, A.gsn, 2 * F, n, 2 * F, F);
+        gemm<false, E_DSILU>(s, P, A.ga, F3, L.W4, F, A.gh3, F, n, F, F3, nullptr, nullptr, 0, A.h3[t], F);
+        gemm<false, E_STORE>(s, P, A.gh3, F, L.W3, 2 * F, A.gsn, 2 * F, n, 2 * F, F);
         k_update_bwd2<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gsn, A.sn[t], A.Vv[t], A.gs, n, F, A.gVv, A.gs1);
-        gemm<false, E_ADD>(s, A.gUv, F, L.U, F, A.gv1, F, 3 * n, F, F, nullptr, nullptr, 0, A.gv, F);
-        gemm<false, E_ADD>(s, A.gVv, F, L.V, F, A.gv1, F, 3 * n, F, F, nullptr, nullptr, 0, A.gv1, F);
-        MLP_DISPATCH_FK(F, K, (launch_msg_bwd<FF, KK>(s, g, A.phi[t], A.v[t], A.gs1, A.gv1, L.A, L.c, m->rc, hop_src,
-                                                       A.gv, A.gphi)));
-        gemm<false, E_DSILU>(s, A.gphi, F3, L.W2, F, A.ga1, F, n, F, F3, nullptr, nullptr, 0, A.h1[t], F);
-        gemm<false, E_ADD>(s, A.ga1, F, L.W1, F, A.gs, F, n, F, F, nullptr, nullptr, 0, A.gs1, F);
+        gemm<false, E_ADD>(s, P, A.gUv, F, L.U, F, A.gv1, F, 3 * n, F, F, nullptr, nullptr, 0, A.gv, F);
+        gemm<false, E_ADD>(s, P, A.gVv, F, L.V, F, A.gv1, F, 3 * n, F, F, nullptr, nullptr, 0, A.gv1, F);
+        {
+            MsgArgs ma = msg_args(g, m, L, hop_src);
+            ma.phi = A.phi[t];
+            ma.v = A.v[t];
+            ma.gs1 = A.gs1;
+            ma.gv1 = A.gv1;
+            ma.gv_in = A.gv;
+            ma.gphi = A.gphi;
+            ProfScope ps(PK_MSG_BWD, s);
+            if ((rc = msg_adjoint(s, PF, F, K, ma))) return fail(rc, "adjoint message kernel launch failed");
+        }
+        gemm<false, E_DSILU>(s, P, A.gphi, F3, L.W2, F, A.ga1, F, n, F, F3, nullptr, nullptr, 0, A.h1[t], F);
+        gemm<false, E_ADD>(s, P, A.ga1, F, L.W1, F, A.gs, F, n, F, F, nullptr, nullptr, 0, A.gs1, F);
     }
     k_forces<<<nblk(n, 256), 256, 0, s>>>(g->rowc.as<int>(), g->revc.as<int>(), g->G.as<float4>(), perm, n,
                                           forces_user);

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmlp.so")
 
 MLP_OK, MLP_PENDING = 0, 1
-MLP_FP32, MLP_BF16 = 0, 1
+MLP_FP32, MLP_BF16, MLP_BF16_NODE = 0, 1, 2
 _ERRORS = {-1: "INVALID_ARG", -2: "OOM", -3: "CAPACITY", -4: "BOX_TOO_SMALL", -5: "DEVICE", -6: "UNKNOWN_TICKET"}
 
 
@@ -82,7 +82,11 @@ def lib():
     L.mlp_server_destroy.argtypes = [P]
     L.mlp_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     L.mlp_poll.argtypes = [P, ctypes.c_uint64, P, P, ctypes.POINTER(Timing)]
-    for name in ("mlp_model_create", "mlp_model_destroy", "mlp_build_neighbors", "mlp_nbr_destroy", "mlp_nbr_edges",
+    L.mlp_profile_enable.argtypes = [I32]
+    L.mlp_profile_reset.argtypes = []
+    L.mlp_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
+    for name in ("mlp_profile_enable", "mlp_profile_reset", "mlp_profile_read",
+                 "mlp_model_create", "mlp_model_destroy", "mlp_build_neighbors", "mlp_nbr_destroy", "mlp_nbr_edges",
                  "mlp_energy_forces", "mlp_md_step", "mlp_server_create", "mlp_server_destroy",
                  "mlp_submit", "mlp_poll"):
         getattr(L, name).restype = ctypes.c_int
@@ -161,6 +165,22 @@ def mlp_md_step(model, nbr, pos, vel, forces, inv_mass, species, box, skin, dt, 
     return bool(rb.value)
 
 
+def mlp_profile_enable(on: bool = True):
+    _check(lib().mlp_profile_enable(1 if on else 0))
+
+
+def mlp_profile_reset():
+    _check(lib().mlp_profile_reset())
+
+
+def mlp_profile_read(kernel: str):
+    """(total_ms, launches) of one named kernel since the last reset."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().mlp_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return float(ms.value), int(n.value)
+
+
 # ---------------------------------------------------------------- objects
 
 class Model:
@@ -168,7 +188,7 @@ class Model:
 
     def __init__(self, header: dict, weights: np.ndarray, precision: str | int = "fp32"):
         if isinstance(precision, str):
-            precision = {"fp32": MLP_FP32, "bf16": MLP_BF16}[precision]
+            precision = {"fp32": MLP_FP32, "bf16": MLP_BF16, "bf16_node": MLP_BF16_NODE}[precision]
         self.header = header
         self.precision = precision
         self.handle = mlp_model_create(json.dumps(header, sort_keys=True), weights, precision)

@@ -217,3 +217,28 @@ def test_autograd_function(mlp, oracle):
     E.backward()
     E_ref, F_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box)
     assert rel_rms(-x.grad.t().cpu().numpy().astype(np.float64), F_ref) <= F_TOL_FP32
+
+
+# ---------------------------------------------------------------- BF16 path
+# Node GEMMs and the radial-filter contraction take bfloat16 operands (FP32
+# accumulation); geometry, envelopes and all accumulations stay FP32.
+F_TOL_BF16 = 1e-2
+E_TOL_BF16 = 1e-2
+
+
+@pytest.mark.parametrize("name", ["water192", "water24k"])
+def test_bf16_energy_forces(mlp, oracle, name):
+    s, hdr, w = synth.workload(name)
+    E_ref, F_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box)
+    r = run_gpu(mlp, s, hdr, w, precision="bf16")
+    assert abs(r["E"] - E_ref) <= E_TOL_BF16 * abs(E_ref)
+    assert rel_rms(r["F"], F_ref) <= F_TOL_BF16
+
+
+def test_bf16_ghost_domain(mlp, oracle):
+    hdr, w = synth.make_weights(128, 20, 3, 1, seed=9, bias_scale=0.1)
+    dom = synth.fcc_crystal(4, seed=3, ghost_depth=15.0)
+    E_ref, F_ref = oracle.energy_forces(hdr, w, dom.pos, dom.species, np.zeros(3), n_local=dom.n_local)
+    r = run_gpu(mlp, dom, hdr, w, precision="bf16", skin=0.5)
+    assert abs(r["E"] - E_ref) <= E_TOL_BF16 * abs(E_ref)
+    assert rel_rms(r["F"], oracle.fold_ghost_forces(F_ref, dom.n_local, dom.owner)) <= F_TOL_BF16
