@@ -347,15 +347,4 @@ int mlp_nbr_edges(mlp_nbr *g, int32_t which, int32_t *dst, int32_t *src, int64_t
     return MLP_OK;
 }
 
-int mlp_server_create(mlp_model *, size_t, int32_t, mlp_server **) {
-    return fail(MLP_ERR_INVALID_ARG, "server not available in this build");
-}
-int mlp_server_destroy(mlp_server *) { return MLP_OK; }
-int mlp_submit(mlp_server *, const mlp_request *, uint64_t *) {
-    return fail(MLP_ERR_INVALID_ARG, "server not available in this build");
-}
-int mlp_poll(mlp_server *, uint64_t, double *, float *, mlp_timing *) {
-    return fail(MLP_ERR_UNKNOWN_TICKET, "server not available in this build");
-}
-
 }  // extern "C"

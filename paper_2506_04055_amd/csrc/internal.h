@@ -115,8 +115,10 @@ int fold_ghosts(mlp_nbr *g, const int32_t *owner, float *forces, hipStream_t s);
 int max_displacement_exceeds(mlp_nbr *g, const float *pos, float limit, hipStream_t s, bool *exceeds);
 
 // ---- model (painn.hip) ----
+// Energy of each of n_seg segments (seg_dev: device [n_seg + 1] internal row
+// offsets, or nullptr for one segment covering all rows), forces of all rows.
 int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
-             float *atom_energy_user);
+             float *atom_energy_user, int n_seg = 1, const int *seg_dev = nullptr);
 int verlet_kick_drift(float *pos, float *vel, const float *forces, const float *inv_mass, int n,
                       const double box[3], float dt, hipStream_t s);
 int verlet_kick(float *vel, const float *forces, const float *inv_mass, int n, float dt, hipStream_t s);

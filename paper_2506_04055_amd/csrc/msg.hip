@@ -89,6 +89,25 @@ __device__ __forceinline__ void basis_slots(float r, float rc, bool valid, int g
     }
 }
 
+// The B operand of one chunk as the MFMA consumes it: 8 packed bfloat16
+// values (bf16) or NS floats (f32).
+template <int P, int K>
+struct BOp {
+    float v[Basis<P, K>::NS];
+    __device__ __forceinline__ void set(const float *eb) {
+#pragma unroll
+        for (int q = 0; q < Basis<P, K>::NS; q++) v[q] = eb[q];
+    }
+};
+template <int K>
+struct BOp<1, K> {
+    v8bf v;
+    __device__ __forceinline__ void set(const float *eb) {
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[q] = (__bf16)eb[q];
+    }
+};
+
 // Stage A' = [c | A] (3F x (K+1)) into LDS in the layout the A operand reads.
 template <int P, int F, int K>
 struct WStage {
@@ -113,21 +132,18 @@ __device__ __forceinline__ void stage_weights(const float *__restrict__ A, const
 
 // w (4 features x this lane's edge) of 16-feature tile t from the basis operand.
 template <int P, int F, int K>
-__device__ __forceinline__ v4f filter_tile(const void *lds, int t, const float *eb, int lane) {
+__device__ __forceinline__ v4f filter_tile(const void *lds, int t, const BOp<P, K> &b, int lane) {
     using WS = WStage<P, F, K>;
     v4f acc = {0.f, 0.f, 0.f, 0.f};
     const int row = 16 * t + (lane & 15), g = lane >> 4;
-    if (P == 1) {
+    if constexpr (P == 1) {
         const v8bf a = *reinterpret_cast<const v8bf *>(reinterpret_cast<const __bf16 *>(lds) + row * WS::LD + 8 * g);
-        v8bf b;
-#pragma unroll
-        for (int q = 0; q < 8; q++) b[q] = (__bf16)eb[q];
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.v, acc, 0, 0, 0);
     } else {
         const float *w = reinterpret_cast<const float *>(lds) + row * WS::LD;
 #pragma unroll
         for (int s = 0; s < Basis<P, K>::NS; s++)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w[4 * s + g], eb[s], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w[4 * s + g], b.v[s], acc, 0, 0, 0);
     }
     return acc;
 }
@@ -178,7 +194,8 @@ __global__ void __launch_bounds__(256) k_msg_fwd_mfma(const int *__restrict__ ro
         const int deg = active ? e1 - e0 : 0;
         for (int cb = 0; cb < deg || cb == 0; cb += 16 * CMAX) {
             int jj[CMAX];
-            float rh[CMAX][3], eb[CMAX][SL];
+            float rh[CMAX][3];
+            BOp<P, K> eb[CMAX];
             const int nch = min(CMAX, (deg - cb + 15) / 16);
 #pragma unroll
             for (int c = 0; c < CMAX; c++) {
@@ -190,7 +207,9 @@ __global__ void __launch_bounds__(256) k_msg_fwd_mfma(const int *__restrict__ ro
                 rh[c][0] = gm.x * ir;
                 rh[c][1] = gm.y * ir;
                 rh[c][2] = gm.z * ir;
-                basis_slots<P, K, false>(gm.w, rc, valid, g, eb[c], nullptr);
+                float tmp[SL];
+                basis_slots<P, K, false>(gm.w, rc, valid, g, tmp, nullptr);
+                eb[c].set(tmp);
             }
 #pragma unroll 1
             for (int gi = 0; gi < NG; gi++) {
@@ -265,7 +284,8 @@ __global__ void __launch_bounds__(256) k_msg_bwd_mfma(const int *__restrict__ ro
         const int deg = active ? e1 - e0 : 0;
         for (int cb = 0; cb < deg || cb == 0; cb += 16 * CMAX) {
             int ii[CMAX];
-            float rh[CMAX][3], rr[CMAX], eb[CMAX][SL], db[CMAX][SL];
+            float rh[CMAX][3], rr[CMAX];
+            BOp<P, K> eb[CMAX], db[CMAX];
             float grh[CMAX][3], gr[CMAX];
             const int nch = min(CMAX, (deg - cb + 15) / 16);
 #pragma unroll
@@ -279,7 +299,10 @@ __global__ void __launch_bounds__(256) k_msg_bwd_mfma(const int *__restrict__ ro
                 rh[c][0] = -gm.x * ir;   // direction of the message edge (i <- j): x_j - x_i
                 rh[c][1] = -gm.y * ir;
                 rh[c][2] = -gm.z * ir;
-                basis_slots<P, K, true>(gm.w, rc, valid, g, eb[c], db[c]);
+                float te[SL], td[SL];
+                basis_slots<P, K, true>(gm.w, rc, valid, g, te, td);
+                eb[c].set(te);
+                db[c].set(td);
                 grh[c][0] = grh[c][1] = grh[c][2] = 0.f;
                 gr[c] = 0.f;
             }

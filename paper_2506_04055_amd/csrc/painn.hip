@@ -152,13 +152,19 @@ __global__ void k_readout(const float *__restrict__ h5, int n, int Fh, const flo
 
 constexpr int ERED = 256;
 
-__global__ void __launch_bounds__(ERED) k_energy_partial(const float *__restrict__ U, const int *__restrict__ perm,
-                                                         int n, int n_local, double *__restrict__ part) {
+// E_b = sum of U_i over the local atoms of segment b (internal rows
+// [seg[b], seg[b+1]), or [0, n) without segments), in FP64 with a fixed
+// order: one block per segment, strided partial sums, then a tree.  A
+// segment's energy is therefore the same whether it is evaluated alone or
+// packed into a batch.
+__global__ void __launch_bounds__(ERED) k_energy_seg(const float *__restrict__ U, const int *__restrict__ perm,
+                                                     const int *__restrict__ seg, int n, int n_local,
+                                                     double *__restrict__ E) {
     __shared__ double sh[ERED];
+    const int b = blockIdx.x;
+    const int a = seg ? seg[b] : 0, e = seg ? seg[b + 1] : n;
     double acc = 0.0;
-    const long per = ((long)n + gridDim.x - 1) / gridDim.x;
-    const long a = (long)blockIdx.x * per, b = min((long)n, a + per);
-    for (long i = a + threadIdx.x; i < b; i += ERED)
+    for (int i = a + threadIdx.x; i < e; i += ERED)
         if (perm[i] < n_local) acc += (double)U[i];
     sh[threadIdx.x] = acc;
     __syncthreads();
@@ -166,21 +172,7 @@ __global__ void __launch_bounds__(ERED) k_energy_partial(const float *__restrict
         if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
-}
-
-__global__ void __launch_bounds__(ERED) k_energy_final(const double *__restrict__ part, int nb,
-                                                       double *__restrict__ E) {
-    __shared__ double sh[ERED];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nb; i += ERED) acc += part[i];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = ERED / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *E = sh[0];
+    if (threadIdx.x == 0) E[b] = sh[0];
 }
 
 __global__ void k_fill(float *__restrict__ p, long n, float val) {
@@ -289,7 +281,7 @@ static MsgArgs msg_args(mlp_nbr *g, mlp_model *m, const LayerW &L, int hop_max) 
 }
 
 int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
-             float *atom_energy_user) {
+             float *atom_energy_user, int n_seg, const int *seg_dev) {
     const int n = g->n_atoms, F = m->F, K = m->K, T = m->T, F3 = 3 * F, Fh = F / 2;
     // node GEMM operand precision and radial-filter precision of the mode
     const int P = m->precision == MLP_PREC_FP32 ? 0 : 1;
@@ -332,9 +324,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     gemm<true, E_BIAS>(s, P, A.s[T], F, m->at(m->off_W5), F, A.h5, Fh, n, Fh, F, m->at(m->off_b5));
     k_readout<<<nblk(n, 256), 256, 0, s>>>(A.h5, n, Fh, m->at(m->off_w6), m->at(m->off_b6), perm, g->n_local, A.U,
                                            A.g5);
-    const int nbE = std::min(1024, std::max(1, nblk(n, 4096)));
-    k_energy_partial<<<nbE, ERED, 0, s>>>(A.U, perm, n, g->n_local, A.epart);
-    k_energy_final<<<1, ERED, 0, s>>>(A.epart, nbE, energy);
+    k_energy_seg<<<std::max(1, n_seg), ERED, 0, s>>>(A.U, perm, seg_dev, n, g->n_local, energy);
     if (atom_energy_user) k_scatter_energy<<<nblk(n, 256), 256, 0, s>>>(A.U, perm, n, atom_energy_user);
     if (!forces_user) return 0;
 

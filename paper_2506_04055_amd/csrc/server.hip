@@ -1,0 +1,423 @@
+// Continuous batching of independent periodic systems (mlp_server_*,
+// mlp_submit, mlp_poll).
+//
+// A scheduler thread owns two streams.  Requests are admitted in arrival
+// order while a slot is free and the admitted footprint stays within the HBM
+// budget; each admitted request is copied to the device, gets its cell-list
+// graph built and pruned on the prep stream, and waits as "ready".  Whenever
+// no launch wave is running, every ready request is packed into one ragged
+// batch (concatenated pruned CSR with atom and edge offsets, one energy
+// segment per system) and evaluated by a single pass of the kernels on the
+// compute stream, while the next arrivals are copied and built on the prep
+// stream.  Results are copied back into pinned memory; mlp_poll hands them
+// over.  The fixed-shape buffering of the paper (Results, "Runtime
+// optimizations and buffering") becomes grow-only device buffers here: the
+// batch arena and the slots only grow.
+#include "../../include/mlp.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+namespace mlp {
+
+using clk = std::chrono::steady_clock;
+
+struct Req {
+    uint64_t ticket = 0;
+    int n = 0;
+    double box[3] = {0, 0, 0};
+    float *h_pos = nullptr;      // pinned, SoA 3 x n
+    int *h_species = nullptr;    // pinned
+    float *h_forces = nullptr;   // pinned, SoA 3 x n
+    double energy = 0.0;
+    int state = 0;               // 0 queued, 1 admitted, 2 ready, 3 running, 4 done, < 0 error
+    int err = 0;
+    std::string errmsg;
+    int slot = -1;
+    int64_t n_edges = 0;
+    size_t bytes = 0;
+    clk::time_point t_submit, t_admit, t_done;
+    int batch_size = 0;
+};
+
+struct Slot {
+    mlp_nbr *nbr = nullptr;
+    DevBuf pos, species;
+    bool busy = false;
+};
+
+__global__ void k_pack_atoms(const int *__restrict__ rowc, const int *__restrict__ perm, const int *__restrict__ sp,
+                             int nb, int aoff, int eoff, int *__restrict__ browc, int *__restrict__ bperm,
+                             int *__restrict__ bsp, int8_t *__restrict__ bhop, int last) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > nb) return;
+    if (k == nb) {
+        if (last) browc[aoff + nb] = eoff + rowc[nb];
+        return;
+    }
+    browc[aoff + k] = eoff + rowc[k];
+    bperm[aoff + k] = aoff + perm[k];
+    bsp[aoff + k] = sp[k];
+    bhop[aoff + k] = 0;
+}
+
+__global__ void k_pack_edges(const int *__restrict__ colc, const int *__restrict__ revc,
+                             const float4 *__restrict__ geom, int eb, int aoff, int eoff, int *__restrict__ bcol,
+                             int *__restrict__ brev, float4 *__restrict__ bgeom) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= eb) return;
+    bcol[eoff + e] = aoff + colc[e];
+    brev[eoff + e] = eoff + revc[e];
+    bgeom[eoff + e] = geom[e];
+}
+
+// Device bytes of one system of n atoms: activations of every layer, the
+// adjoint's work arrays and graph buffers for up to 120 neighbours within
+// rc + skin per atom.
+static size_t footprint(const mlp_model *m, int n) {
+    const size_t F = m->F, T = m->T;
+    const size_t act = (23 * T + 4 + 27) * F * 4 + 64;
+    const size_t graph = 120 * 60 + 96;
+    return (size_t)n * (act + graph) + (1u << 20);
+}
+
+}  // namespace mlp
+
+using namespace mlp;
+
+struct mlp_server {
+    mlp_model *m = nullptr;
+    size_t budget = 0, reserved = 0;
+    int max_slots = 0;
+    int device = 0;
+    std::vector<Slot> slots;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    std::thread th;
+    std::deque<Req *> pending;
+    std::unordered_map<uint64_t, Req *> all;
+    std::vector<Req *> ready, running;
+    uint64_t next_ticket = 1;
+    hipStream_t s_prep = nullptr, s_comp = nullptr;
+    hipEvent_t ev_wave = nullptr;
+    bool wave_in_flight = false;
+    mlp_nbr batch;              // packed graph + activations of the running wave
+    DevBuf seg, energies, forces;
+    double *h_energies = nullptr;
+    int h_energies_cap = 0;
+    std::vector<int> h_seg;
+    float skin = 0.0f;
+};
+
+namespace {
+
+void fail_req(Req *r, int code, const char *msg) {
+    r->state = code < 0 ? code : -5;
+    r->err = r->state;
+    r->errmsg = msg ? msg : "";
+}
+
+// Copy, build and prune one admitted request on the prep stream.
+void prepare(mlp_server *S, Req *r) {
+    Slot &sl = S->slots[r->slot];
+    int *G = &sl.nbr->n_grows;
+    if (sl.pos.ensure(sizeof(float) * 3 * (size_t)r->n, 1.2, G) || sl.species.ensure(sizeof(int) * (size_t)r->n, 1.2, G)) {
+        fail_req(r, MLP_ERR_OOM, mlp_last_error());
+        return;
+    }
+    hipMemcpyAsync(sl.pos.p, r->h_pos, sizeof(float) * 3 * r->n, hipMemcpyHostToDevice, S->s_prep);
+    hipMemcpyAsync(sl.species.p, r->h_species, sizeof(int) * r->n, hipMemcpyHostToDevice, S->s_prep);
+    mlp_nbr *g = sl.nbr;
+    int rc = build_graph(S->m, g, sl.pos.as<float>(), sl.species.as<int>(), r->n, r->n, r->box, S->skin, S->s_prep);
+    if (!rc) rc = prune_graph(S->m, g, sl.pos.as<float>(), S->s_prep);
+    if (rc) {
+        fail_req(r, rc, mlp_last_error());
+        return;
+    }
+    int Ec = 0;
+    if (hipMemcpyAsync(&Ec, g->rowc.as<int>() + r->n, sizeof(int), hipMemcpyDeviceToHost, S->s_prep) != hipSuccess ||
+        hipStreamSynchronize(S->s_prep) != hipSuccess) {
+        fail_req(r, MLP_ERR_DEVICE, "prep stream failed");
+        return;
+    }
+    r->n_edges = Ec;
+    r->state = 2;
+}
+
+// Pack all ready requests and launch one evaluation on the compute stream.
+int launch_wave(mlp_server *S) {
+    std::vector<Req *> &W = S->running;
+    W = S->ready;
+    S->ready.clear();
+    const int B = (int)W.size();
+    int64_t Nt = 0, Et = 0;
+    for (Req *r : W) {
+        Nt += r->n;
+        Et += r->n_edges;
+    }
+    mlp_nbr &g = S->batch;
+    int *G = &g.n_grows;
+    int rc;
+    if ((rc = g.rowc.ensure(sizeof(int) * (Nt + 1), 1.25, G)) || (rc = g.perm.ensure(sizeof(int) * Nt, 1.25, G)) ||
+        (rc = g.species.ensure(sizeof(int) * Nt, 1.25, G)) || (rc = g.hop.ensure(Nt + 16, 1.25, G)) ||
+        (rc = g.colc.ensure(sizeof(int) * Et + 16, 1.25, G)) || (rc = g.revc.ensure(sizeof(int) * Et + 16, 1.25, G)) ||
+        (rc = g.geom.ensure(sizeof(float4) * Et + 16, 1.25, G)) ||
+        (rc = S->seg.ensure(sizeof(int) * (B + 1), 1.25, G)) ||
+        (rc = S->energies.ensure(sizeof(double) * B, 1.25, G)) ||
+        (rc = S->forces.ensure(sizeof(float) * 3 * Nt, 1.25, G)))
+        return rc;
+    if (S->h_energies_cap < B) {
+        if (S->h_energies) hipHostFree(S->h_energies);
+        S->h_energies_cap = std::max(B, 2 * S->h_energies_cap);
+        if (hipHostMalloc((void **)&S->h_energies, sizeof(double) * S->h_energies_cap, 0) != hipSuccess)
+            return fail(MLP_ERR_OOM, "pinned allocation failed");
+    }
+    S->h_seg.assign(B + 1, 0);
+    int64_t aoff = 0, eoff = 0;
+    for (int b = 0; b < B; b++) {
+        Req *r = W[b];
+        mlp_nbr *sg = S->slots[r->slot].nbr;
+        k_pack_atoms<<<(r->n + 256) / 256, 256, 0, S->s_comp>>>(sg->rowc.as<int>(), sg->perm.as<int>(),
+                                                                 sg->species.as<int>(), r->n, (int)aoff, (int)eoff,
+                                                                 g.rowc.as<int>(), g.perm.as<int>(),
+                                                                 g.species.as<int>(), g.hop.as<int8_t>(), b == B - 1);
+        if (r->n_edges > 0)
+            k_pack_edges<<<(int)((r->n_edges + 255) / 256), 256, 0, S->s_comp>>>(
+                sg->colc.as<int>(), sg->revc.as<int>(), sg->geom.as<float4>(), (int)r->n_edges, (int)aoff, (int)eoff,
+                g.colc.as<int>(), g.revc.as<int>(), g.geom.as<float4>());
+        S->h_seg[b] = (int)aoff;
+        aoff += r->n;
+        eoff += r->n_edges;
+        r->state = 3;
+        r->batch_size = B;
+    }
+    S->h_seg[B] = (int)aoff;
+    HIP_TRY(hipMemcpyAsync(S->seg.p, S->h_seg.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, S->s_comp));
+    g.n_atoms = (int)Nt;
+    g.n_local = (int)Nt;
+    g.n_edges_skin = Et;
+    g.n_builds = 1;
+    if ((rc = evaluate(S->m, &g, S->s_comp, S->energies.as<double>(), S->forces.as<float>(), nullptr, B,
+                       S->seg.as<int>())))
+        return rc;
+    HIP_TRY(hipMemcpyAsync(S->h_energies, S->energies.p, sizeof(double) * B, hipMemcpyDeviceToHost, S->s_comp));
+    for (int b = 0; b < B; b++) {
+        Req *r = W[b];
+        const float *F = S->forces.as<float>();
+        for (int d = 0; d < 3; d++)
+            HIP_TRY(hipMemcpyAsync(r->h_forces + (size_t)d * r->n, F + (size_t)d * Nt + S->h_seg[b],
+                                   sizeof(float) * r->n, hipMemcpyDeviceToHost, S->s_comp));
+    }
+    HIP_TRY(hipEventRecord(S->ev_wave, S->s_comp));
+    S->wave_in_flight = true;
+    return 0;
+}
+
+void finish_wave(mlp_server *S) {
+    const auto now = clk::now();
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (size_t b = 0; b < S->running.size(); b++) {
+        Req *r = S->running[b];
+        r->energy = S->h_energies[b];
+        r->t_done = now;
+        r->state = 4;
+        S->slots[r->slot].busy = false;
+        S->reserved -= r->bytes;
+        r->slot = -1;
+    }
+    S->running.clear();
+    S->wave_in_flight = false;
+    S->cv.notify_all();
+}
+
+void scheduler(mlp_server *S) {
+    hipSetDevice(S->device);
+    for (;;) {
+        std::vector<Req *> admitted;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (!S->wave_in_flight && S->pending.empty() && S->ready.empty())
+                S->cv.wait_for(lk, std::chrono::microseconds(200));
+            if (S->stop && S->pending.empty() && S->ready.empty() && !S->wave_in_flight) break;
+            // admission in arrival order: a free slot and room in the budget
+            while (!S->pending.empty()) {
+                Req *r = S->pending.front();
+                int free_slot = -1;
+                for (int k = 0; k < (int)S->slots.size(); k++)
+                    if (!S->slots[k].busy) {
+                        free_slot = k;
+                        break;
+                    }
+                if (free_slot < 0 || S->reserved + r->bytes > S->budget) break;
+                S->pending.pop_front();
+                S->slots[free_slot].busy = true;
+                S->reserved += r->bytes;
+                r->slot = free_slot;
+                r->state = 1;
+                r->t_admit = clk::now();
+                admitted.push_back(r);
+            }
+        }
+        for (Req *r : admitted) {
+            prepare(S, r);
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (r->state == 2) {
+                S->ready.push_back(r);
+            } else {
+                S->slots[r->slot].busy = false;
+                S->reserved -= r->bytes;
+                r->slot = -1;
+                r->t_done = clk::now();
+            }
+        }
+        if (S->wave_in_flight && hipEventQuery(S->ev_wave) == hipSuccess) finish_wave(S);
+        if (!S->wave_in_flight && !S->ready.empty()) {
+            int rc = launch_wave(S);
+            if (rc) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                for (Req *r : S->running) {
+                    fail_req(r, rc, mlp_last_error());
+                    S->slots[r->slot].busy = false;
+                    S->reserved -= r->bytes;
+                    r->slot = -1;
+                    r->t_done = clk::now();
+                }
+                S->running.clear();
+            }
+        }
+        if (S->wave_in_flight && admitted.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+void free_req(Req *r) {
+    if (r->h_pos) hipHostFree(r->h_pos);
+    if (r->h_species) hipHostFree(r->h_species);
+    if (r->h_forces) hipHostFree(r->h_forces);
+    delete r;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mlp_server_create(mlp_model *m, size_t hbm_budget_bytes, int32_t max_slots, mlp_server **out) {
+    if (!m || !out || max_slots < 1 || hbm_budget_bytes == 0) return fail(MLP_ERR_INVALID_ARG, "bad argument");
+    mlp_server *S = new mlp_server();
+    S->m = m;
+    S->budget = hbm_budget_bytes;
+    S->max_slots = max_slots;
+    S->skin = 0.0f;
+    hipGetDevice(&S->device);
+    S->slots.resize(max_slots);
+    for (auto &sl : S->slots) sl.nbr = new mlp_nbr();
+    if (hipStreamCreateWithFlags(&S->s_prep, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&S->s_comp, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&S->ev_wave, hipEventDisableTiming) != hipSuccess) {
+        delete S;
+        return fail(MLP_ERR_DEVICE, "stream creation failed");
+    }
+    S->th = std::thread(scheduler, S);
+    *out = S;
+    return MLP_OK;
+}
+
+int mlp_server_destroy(mlp_server *S) {
+    if (!S) return MLP_OK;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        for (Req *r : S->pending) {
+            fail_req(r, MLP_ERR_UNKNOWN_TICKET, "server destroyed");
+        }
+        S->pending.clear();
+    }
+    S->cv.notify_all();
+    if (S->th.joinable()) S->th.join();
+    hipStreamSynchronize(S->s_comp);
+    hipStreamSynchronize(S->s_prep);
+    for (auto &kv : S->all) free_req(kv.second);
+    for (auto &sl : S->slots) {
+        sl.pos.release();
+        sl.species.release();
+        mlp_nbr_destroy(sl.nbr);
+    }
+    DevBuf *bufs[] = {&S->batch.rowc, &S->batch.perm, &S->batch.species, &S->batch.hop, &S->batch.colc,
+                      &S->batch.revc, &S->batch.geom, &S->batch.act, &S->batch.G, &S->seg, &S->energies,
+                      &S->forces};
+    for (DevBuf *b : bufs) b->release();
+    if (S->h_energies) hipHostFree(S->h_energies);
+    hipEventDestroy(S->ev_wave);
+    hipStreamDestroy(S->s_prep);
+    hipStreamDestroy(S->s_comp);
+    delete S;
+    return MLP_OK;
+}
+
+int mlp_submit(mlp_server *S, const mlp_request *q, uint64_t *ticket) {
+    if (!S || !q || !ticket || !q->pos || !q->species || q->n_atoms <= 0)
+        return fail(MLP_ERR_INVALID_ARG, "bad request");
+    const size_t bytes = footprint(S->m, q->n_atoms);
+    if (bytes > S->budget) return fail(MLP_ERR_INVALID_ARG, "request exceeds the server's device-memory budget");
+    for (int d = 0; d < 3; d++)
+        if (!(q->box[d] > 0.0)) return fail(MLP_ERR_INVALID_ARG, "served systems must be periodic (box > 0)");
+    Req *r = new Req();
+    r->n = q->n_atoms;
+    std::memcpy(r->box, q->box, sizeof(r->box));
+    r->bytes = bytes;
+    if (hipHostMalloc((void **)&r->h_pos, sizeof(float) * 3 * r->n, 0) != hipSuccess ||
+        hipHostMalloc((void **)&r->h_species, sizeof(int) * r->n, 0) != hipSuccess ||
+        hipHostMalloc((void **)&r->h_forces, sizeof(float) * 3 * r->n, 0) != hipSuccess) {
+        free_req(r);
+        return fail(MLP_ERR_OOM, "pinned staging allocation failed");
+    }
+    std::memcpy(r->h_pos, q->pos, sizeof(float) * 3 * r->n);
+    std::memcpy(r->h_species, q->species, sizeof(int) * r->n);
+    r->t_submit = clk::now();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        r->ticket = S->next_ticket++;
+        S->pending.push_back(r);
+        S->all[r->ticket] = r;
+    }
+    S->cv.notify_all();
+    *ticket = r->ticket;
+    return MLP_OK;
+}
+
+int mlp_poll(mlp_server *S, uint64_t ticket, double *energy, float *forces, mlp_timing *timing) {
+    if (!S) return fail(MLP_ERR_INVALID_ARG, "null server");
+    Req *r = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->all.find(ticket);
+        if (it == S->all.end()) return fail(MLP_ERR_UNKNOWN_TICKET, "unknown or retired ticket");
+        r = it->second;
+        if (r->state >= 0 && r->state < 4) return MLP_PENDING;
+        S->all.erase(it);
+    }
+    int rc = MLP_OK;
+    if (r->state < 0) {
+        rc = fail(r->err, r->errmsg);
+    } else {
+        if (energy) *energy = r->energy;
+        if (forces) std::memcpy(forces, r->h_forces, sizeof(float) * 3 * r->n);
+        if (timing) {
+            timing->latency_us = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
+            timing->queue_us = std::chrono::duration<double, std::micro>(r->t_admit - r->t_submit).count();
+            timing->batch_size = r->batch_size;
+        }
+    }
+    free_req(r);
+    return rc;
+}
+
+}  // extern "C"

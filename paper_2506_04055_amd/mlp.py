@@ -262,3 +262,44 @@ class MLPEnergy(torch.autograd.Function):
     def backward(ctx, grad_e):
         (F,) = ctx.saved_tensors
         return (-grad_e.to(F.dtype) * F), None
+
+
+class Server:
+    """Continuous-batching request server (mlp_server_create / mlp_submit /
+    mlp_poll).  Requests are periodic systems given as host arrays."""
+
+    def __init__(self, model: Model, hbm_budget_bytes: int, max_slots: int = 64):
+        self.model = model
+        self.handle = ctypes.c_void_p()
+        _check(lib().mlp_server_create(model.handle, int(hbm_budget_bytes), int(max_slots),
+                                       ctypes.byref(self.handle)))
+
+    def submit(self, pos_aos, species, box) -> int:
+        pos = np.ascontiguousarray(np.asarray(pos_aos, np.float32).T)       # SoA (3, N)
+        sp = np.ascontiguousarray(species, np.int32)
+        req = Request(pos.ctypes.data_as(ctypes.c_void_p), sp.ctypes.data_as(ctypes.c_void_p), pos.shape[1],
+                      (ctypes.c_double * 3)(*[float(b) for b in box]))
+        t = ctypes.c_uint64(0)
+        _check(lib().mlp_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket: int, n_atoms: int):
+        """None while pending, else (energy, forces (N, 3) float32, timing dict)."""
+        e = ctypes.c_double(0.0)
+        F = np.empty((3, n_atoms), np.float32)
+        tm = Timing()
+        rc = lib().mlp_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(e),
+                            F.ctypes.data_as(ctypes.c_void_p), ctypes.byref(tm))
+        if rc == MLP_PENDING:
+            return None
+        _check(rc)
+        return float(e.value), F.T.copy(), {"latency_us": tm.latency_us, "queue_us": tm.queue_us,
+                                            "batch_size": tm.batch_size}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.mlp_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()

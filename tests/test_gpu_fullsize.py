@@ -1,0 +1,112 @@
+"""Full-size workloads on the GPU.
+
+* One GPU's share of a perturbed fcc crystal: 1,048,576 local atoms plus the
+  T*rc = 15 A ghost shell (1,462,103 rows).  The oracle cannot evaluate the
+  whole domain in test time, so outputs are sampled and each sample is
+  checked against the oracle on an exact sub-domain: U_i depends only on
+  atoms within T*rc of i, and the partial force on atom k of the domain's
+  local energy involves only local atoms within T*rc of k, whose environments
+  lie within 2*T*rc of k.  Properties that hold at any size are checked on
+  every row.
+* The 48,000-atom liquid-vapour slab, compared with the oracle on every row.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_04055_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mlp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_04055_amd import mlp as M
+    M.lib()
+    return M
+
+
+@pytest.fixture(scope="module")
+def fcc_domain():
+    return synth.fcc_crystal(64, seed=0, ghost_depth=15.0)
+
+
+def _gpu_domain(mlp, dom, hdr, w, precision, owner):
+    import gc
+    import torch
+    model = mlp.Model(hdr, w, precision)
+    d = mlp.System(model, dom.pos, dom.species, dom.box, n_local=dom.n_local, skin=0.5, ghost_owner=owner)
+    out = d.compute(atom_energy=True, stats=True)
+    torch.cuda.synchronize()
+    res = (float(out["energy"].item()), out["forces"].t().cpu().numpy().astype(np.float64),
+           out["atom_energy"].cpu().numpy().astype(np.float64), out["stats"])
+    del out, d, model          # release the ~75 GB activation arena before the next case
+    gc.collect()
+    torch.cuda.empty_cache()
+    return res
+
+
+@pytest.mark.parametrize("precision,ftol,etol", [("fp32", 5e-5, 2e-5), ("bf16", 3e-2, 3e-2)])
+def test_fcc_million_atom_domain_sampled(mlp, oracle, fcc_domain, precision, ftol, etol):
+    dom = fcc_domain
+    T = 3
+    hdr, w = synth.make_weights(128, 20, T, 1, seed=0)
+    E, F_raw, U, st = _gpu_domain(mlp, dom, hdr, w, precision, None)
+    assert st["n_atoms"] == dom.n_atoms and st["n_within_hops"][0] == dom.n_local
+    # the hop sets are nested and grow with t; atoms beyond T hops exist in a T*rc shell
+    hops = st["n_within_hops"][: T + 1]
+    assert all(a < b for a, b in zip(hops, hops[1:])) and hops[T] <= dom.n_atoms
+    assert abs(E - U[: dom.n_local].sum()) <= 1e-9 * np.abs(U[: dom.n_local]).sum()
+    p = dom.pos.astype(np.float64)
+    rng = np.random.default_rng(11)
+    f_rms = np.sqrt((F_raw[: dom.n_local] ** 2).sum(1).mean())
+    u_scale = np.abs(U[: dom.n_local]).mean()
+    # per-atom energies of sampled local atoms (one deep inside, others random)
+    samples = [dom.n_local // 2] + rng.choice(dom.n_local, 2, replace=False).tolist()
+    for i in samples:
+        near = np.nonzero(((p - p[i]) ** 2).sum(1) < (T * 5.0) ** 2)[0]
+        order = np.concatenate([[i], near[near != i]])
+        Eo, _, Uo = oracle.energy_forces(hdr, w, p[order], dom.species[order], np.zeros(3), n_local=1,
+                                         per_atom=True)
+        assert abs(U[i] - Eo) <= etol * u_scale
+    # partial forces of the local energy on sampled rows (a local and a ghost)
+    for k in [samples[1], dom.n_local + int(rng.integers(dom.n_atoms - dom.n_local))]:
+        d2 = ((p - p[k]) ** 2).sum(1)
+        env = np.nonzero(d2 < (2 * T * 5.0) ** 2)[0]
+        loc = env[(env < dom.n_local) & (d2[env] < (T * 5.0) ** 2)]
+        rest = np.setdiff1d(env, loc)
+        order = np.concatenate([loc, rest])
+        _, Fo = oracle.energy_forces(hdr, w, p[order], dom.species[order], np.zeros(3), n_local=len(loc))
+        kk = int(np.nonzero(order == k)[0][0])
+        assert np.linalg.norm(F_raw[k] - Fo[kk]) <= ftol * f_rms
+
+
+def test_fcc_million_atom_fold_properties(mlp, fcc_domain):
+    # folded forces of one domain's share of a periodic crystal sum to zero
+    # (translation invariance of the periodic energy), and the fold only
+    # changes local rows
+    dom = fcc_domain
+    hdr, w = synth.make_weights(128, 20, 3, 1, seed=0)
+    E1, F_raw, U, _ = _gpu_domain(mlp, dom, hdr, w, "fp32", None)
+    E2, F_fold, _, _ = _gpu_domain(mlp, dom, hdr, w, "fp32", dom.owner)
+    assert E1 == E2
+    assert np.array_equal(F_fold[dom.n_local:], F_raw[dom.n_local:])
+    net = F_fold[: dom.n_local].sum(0)
+    assert np.abs(net).max() <= 1e-4 * np.abs(F_fold[: dom.n_local]).sum(0).max()
+
+
+@pytest.mark.parametrize("precision,ftol", [("fp32", 1e-5), ("bf16", 1e-2)])
+def test_slab_full_size(mlp, oracle, precision, ftol):
+    s, hdr, w = synth.workload("slab48k")
+    import torch
+    E_ref, F_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box)
+    model = mlp.Model(hdr, w, precision)
+    d = mlp.System(model, s.pos, s.species, s.box, skin=1.0)
+    out = d.compute(stats=True)
+    torch.cuda.synchronize()
+    F = out["forces"].t().cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(F - F_ref) / np.linalg.norm(F_ref) <= ftol
+    # vacuum gap: the vapour molecules' neighbourhoods are sparse
+    assert out["stats"]["n_edges"] < 60 * s.n_atoms

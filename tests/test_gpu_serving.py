@@ -1,0 +1,119 @@
+"""Serving path (mlp_server_create / mlp_submit / mlp_poll) on the GPU.
+
+Requests are packed into ragged launch waves.  Each system's internal atom
+order, edge order and reduction order are the same alone and in a batch, so
+results in the mix must equal the single-system results exactly."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2506_04055_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mlp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_04055_amd import mlp as M
+    M.lib()
+    return M
+
+
+def wait_all(server, tickets, sizes, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t, n in zip(tickets, sizes):
+            if t in out:
+                continue
+            r = server.poll(t, n)
+            if r is not None:
+                out[t] = r
+        assert time.time() - t0 < timeout, "requests did not complete"
+        time.sleep(0.001)
+    return [out[t] for t in tickets]
+
+
+def single(mlp, model, s):
+    import torch
+    d = mlp.System(model, s.pos, s.species, s.box, skin=0.0)
+    out = d.compute()
+    torch.cuda.synchronize()
+    return float(out["energy"].item()), out["forces"].t().cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_alone_equals_in_the_mix(mlp, precision):
+    hdr, w = synth.make_weights(128, 20, 3, 4, seed=5)
+    model = mlp.Model(hdr, w, precision)
+    sizes = [500, 1300, 2900, 740, 2050, 811]
+    systems = [synth.peptide_like(n, seed=100 + k) for k, n in enumerate(sizes)]
+    server = mlp.Server(model, hbm_budget_bytes=8 << 30, max_slots=16)
+    tickets = [server.submit(s.pos, s.species, s.box) for s in systems]
+    res = wait_all(server, tickets, sizes)
+    batch_sizes = [r[2]["batch_size"] for r in res]
+    for s, (E, F, tm) in zip(systems, res):
+        E1, F1 = single(mlp, model, s)
+        assert E == E1
+        assert np.array_equal(F, F1)
+        assert tm["latency_us"] > 0 and tm["queue_us"] >= 0
+    assert max(batch_sizes) > 1          # at least one wave packed several systems
+    server.close()
+
+
+def test_served_result_matches_oracle(mlp, oracle):
+    hdr, w = synth.make_weights(64, 20, 3, 4, seed=6, bias_scale=0.1)
+    model = mlp.Model(hdr, w, "fp32")
+    s = synth.peptide_like(900, seed=7)
+    server = mlp.Server(model, hbm_budget_bytes=2 << 30, max_slots=4)
+    (E, F, tm), = wait_all(server, [server.submit(s.pos, s.species, s.box)], [s.n_atoms])
+    E_ref, F_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box)
+    assert abs(E - E_ref) <= 2e-6 * abs(E_ref)
+    assert np.linalg.norm(F - F_ref) / np.linalg.norm(F_ref) <= 1e-5
+    server.close()
+
+
+def test_admission_under_a_tight_budget(mlp):
+    # a budget that holds one request at a time: requests are admitted in
+    # arrival order as memory frees up, and all complete correctly
+    hdr, w = synth.make_weights(32, 8, 2, 4, seed=2)
+    model = mlp.Model(hdr, w, "fp32")
+    sizes = [600, 900, 700, 1000]
+    systems = [synth.peptide_like(n, seed=k) for k, n in enumerate(sizes)]
+    server = mlp.Server(model, hbm_budget_bytes=20 << 20, max_slots=8)   # one ~11-18 MB request at a time
+    tickets = [server.submit(s.pos, s.species, s.box) for s in systems]
+    res = wait_all(server, tickets, sizes)
+    assert all(r[2]["batch_size"] == 1 for r in res)
+    for s, (E, F, tm) in zip(systems, res):
+        E1, F1 = single(mlp, model, s)
+        assert E == E1 and np.array_equal(F, F1)
+    server.close()
+
+
+def test_serving_errors(mlp):
+    hdr, w = synth.make_weights(32, 8, 2, 4, seed=2)
+    model = mlp.Model(hdr, w, "fp32")
+    server = mlp.Server(model, hbm_budget_bytes=64 << 20, max_slots=2)
+    with pytest.raises(mlp.MLPError) as e:           # larger than the whole budget
+        big = synth.peptide_like(20000, seed=1)
+        server.submit(big.pos, big.species, big.box)
+    assert e.value.code == -1
+    tiny = synth.peptide_like(30, seed=1)            # box below 2 (rc + skin)
+    t = server.submit(tiny.pos, tiny.species, tiny.box)
+    t0 = time.time()
+    while True:
+        try:
+            r = server.poll(t, tiny.n_atoms)
+        except mlp.MLPError as err:
+            assert err.code == -4
+            break
+        assert r is None and time.time() - t0 < 30
+        time.sleep(0.001)
+    with pytest.raises(mlp.MLPError) as e:
+        server.poll(12345, 10)
+    assert e.value.code == -6
+    server.close()
