@@ -225,6 +225,8 @@ def main():
     ap.add_argument("--single", action="store_true", help="time the headline precision only")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--no-extra", action="store_true", help="skip the fcc-domain and slab timings")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 256 MiB device to device (calibrates the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -235,6 +237,12 @@ def main():
     import torch
     from paper_2506_04055_amd import mlp, synth
 
+    if args.copy_probe:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     head = run_md(mlp, synth, torch, args.precision, args.steps, args.warmup, profile=True)
     roof = roofline(head, args.precision, args.steps)
     hdr = head["hdr"]

@@ -53,7 +53,7 @@ enum {
     MLP_ERR_UNKNOWN_TICKET = -6
 };
 
-enum { MLP_FP32 = 0, MLP_BF16 = 1, MLP_BF16_NODE = 2 };
+enum { MLP_FP32 = 0, MLP_BF16 = 1, MLP_BF16_FAST = 2 };
 
 typedef struct mlp_model mlp_model;
 typedef struct mlp_nbr mlp_nbr;
@@ -91,11 +91,16 @@ const char *mlp_last_error(void);
  *   W5 [F/2][F] b5 [F/2] w6 [F/2] b6 [1]); matrices are [out][in] row-major;
  *   3F blocks are split [vv | s | vs] (message) and [vv | sv | ss] (update).
  *   Copied to the device; the caller keeps ownership of its array.
- * precision: MLP_FP32 (all arithmetic FP32), MLP_BF16 (node-feature GEMMs
- *   and the radial-filter contraction take bfloat16 operands with FP32
- *   accumulation) or MLP_BF16_NODE (node-feature GEMMs bfloat16, radial
- *   filter FP32).  Geometry, cutoff envelope, accumulation of messages and
- *   forces stay FP32 in every mode; the energy sum is FP64.
+ * precision: the operand form of the matrix-core contractions (node-feature
+ *   GEMMs and the radial filter):
+ *   MLP_FP32      FP32 operands (v_mfma_f32_16x16x4_f32);
+ *   MLP_BF16      split bfloat16 operands x = hi + lo, three products per
+ *                 tile on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16);
+ *   MLP_BF16_FAST plain bfloat16 operands (one product; bfloat16 rounding of
+ *                 activations and weights, ~3e-2 force error with random
+ *                 N(0, 1/fan_in) weights at F = 128, T = 3).
+ *   Accumulation is FP32 in every mode; geometry, cutoff envelope, message
+ *   and force accumulation stay FP32; the energy sum is FP64.
  * Errors: INVALID_ARG (header or weight count), OOM, DEVICE.
  * ------------------------------------------------------------------------- */
 int mlp_model_create(const char *header_json, const float *weights, size_t n_weights,

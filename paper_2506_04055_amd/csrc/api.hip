@@ -171,7 +171,7 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
         if (!found) return fail(MLP_ERR_INVALID_ARG, "(F, K) combination is not compiled in this build");
     }
     if (!(rc > 0.0) || !(eps > 0.0)) return fail(MLP_ERR_INVALID_ARG, "r_c and eps must be positive");
-    if (precision != MLP_FP32 && precision != MLP_BF16 && precision != MLP_BF16_NODE)
+    if (precision != MLP_FP32 && precision != MLP_BF16 && precision != MLP_BF16_FAST)
         return fail(MLP_ERR_INVALID_ARG, "unknown precision");
     mlp_model *m = new mlp_model();
     m->F = (int)F; m->K = (int)K; m->T = (int)T; m->S = (int)S;

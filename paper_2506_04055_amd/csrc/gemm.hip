@@ -13,6 +13,11 @@
 //   f32:  A[l%16][k0 + g],           B[k0 + g][l%16]
 //   bf16: A[l%16][8g .. 8g+7],       B[8g .. 8g+7][l%16]
 //   D:    rows 4g .. 4g+3, column l%16 (4 accumulator registers)
+// Split-bf16 mode (P = 2) stages each operand as x = hi + lo with
+// hi = bf16(x), lo = bf16(x - hi), and accumulates the three products
+// lo*hi + hi*lo + hi*hi on the bf16 matrix cores (the lo*lo term is below
+// FP32 rounding of the sum's leading part): ~16 significant bits per operand
+// at the bf16 instruction rate.
 #include "gemm.h"
 
 namespace mlp {
@@ -32,7 +37,8 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(const float *__restrict__ A, 
                                                    int M, int N, int K, const float *__restrict__ bias,
                                                    float *__restrict__ C2, int ldc2, const float *R, int ldr) {
     __shared__ __attribute__((aligned(16))) float smf[P == 0 ? 2 * TBM * LDF : 1];
-    __shared__ __attribute__((aligned(16))) __bf16 smh[P == 1 ? 2 * TBM * LDH : 1];
+    __shared__ __attribute__((aligned(16))) __bf16 smh[P >= 1 ? 2 * TBM * LDH : 1];
+    __shared__ __attribute__((aligned(16))) __bf16 sml[P == 2 ? 2 * TBM * LDH : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -61,7 +67,11 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(const float *__restrict__ A, 
                 for (int q = 0; q < 8; q++) smf[r * LDF + kq + q] = v[q];
             } else {
 #pragma unroll
-                for (int q = 0; q < 8; q++) smh[r * LDH + kq + q] = (__bf16)v[q];
+                for (int q = 0; q < 8; q++) {
+                    const __bf16 h = (__bf16)v[q];
+                    smh[r * LDH + kq + q] = h;
+                    if (P == 2) sml[r * LDH + kq + q] = (__bf16)(v[q] - (float)h);
+                }
             }
         }
         // stage B as [n][k]
@@ -90,7 +100,11 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(const float *__restrict__ A, 
                 for (int q = 0; q < 8; q++) smf[TBM * LDF + nn * LDF + kq + q] = v[q];
             } else {
 #pragma unroll
-                for (int q = 0; q < 8; q++) smh[TBM * LDH + nn * LDH + kq + q] = (__bf16)v[q];
+                for (int q = 0; q < 8; q++) {
+                    const __bf16 h = (__bf16)v[q];
+                    smh[TBM * LDH + nn * LDH + kq + q] = h;
+                    if (P == 2) sml[TBM * LDH + nn * LDH + kq + q] = (__bf16)(v[q] - (float)h);
+                }
             }
         }
         __syncthreads();
@@ -115,6 +129,21 @@ __global__ void __launch_bounds__(256) k_gemm_mfma(const float *__restrict__ A, 
             for (int t = 0; t < 2; t++) {
                 a[t] = *reinterpret_cast<const v8bf *>(&smh[(wm * 32 + t * 16 + c16) * LDH + 8 * g]);
                 b[t] = *reinterpret_cast<const v8bf *>(&smh[TBM * LDH + (wn * 32 + t * 16 + c16) * LDH + 8 * g]);
+            }
+            if (P == 2) {
+                v8bf al[2], bl[2];
+#pragma unroll
+                for (int t = 0; t < 2; t++) {
+                    al[t] = *reinterpret_cast<const v8bf *>(&sml[(wm * 32 + t * 16 + c16) * LDH + 8 * g]);
+                    bl[t] = *reinterpret_cast<const v8bf *>(&sml[TBM * LDH + (wn * 32 + t * 16 + c16) * LDH + 8 * g]);
+                }
+#pragma unroll
+                for (int ta = 0; ta < 2; ta++)
+#pragma unroll
+                    for (int tb = 0; tb < 2; tb++) {
+                        acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ta], b[tb], acc[ta][tb], 0, 0, 0);
+                        acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ta], bl[tb], acc[ta][tb], 0, 0, 0);
+                    }
             }
 #pragma unroll
             for (int ta = 0; ta < 2; ta++)
@@ -177,8 +206,10 @@ int node_gemm(hipStream_t s, int precision, bool nt, int epi, const float *A, in
     }
     if (precision == 0) {
         if (nt) { GE(0, true) } else { GE(0, false) }
-    } else {
+    } else if (precision == 1) {
         if (nt) { GE(1, true) } else { GE(1, false) }
+    } else {
+        if (nt) { GE(2, true) } else { GE(2, false) }
     }
 #undef GE
 #undef GL

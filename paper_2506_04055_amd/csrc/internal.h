@@ -8,10 +8,10 @@
 
 #define MLP_MAX_LAYERS 7
 #define MLP_MAX_K 32
-// precision modes (values of the C ABI's MLP_FP32 / MLP_BF16 / MLP_BF16_NODE)
+// precision modes (values of the C ABI's MLP_FP32 / MLP_BF16 / MLP_BF16_FAST)
 #define MLP_PREC_FP32 0
 #define MLP_PREC_BF16 1
-#define MLP_PREC_BF16_NODE 2
+#define MLP_PREC_BF16_FAST 2
 
 namespace mlp {
 

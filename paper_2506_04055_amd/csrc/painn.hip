@@ -283,9 +283,10 @@ static MsgArgs msg_args(mlp_nbr *g, mlp_model *m, const LayerW &L, int hop_max) 
 int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
              float *atom_energy_user, int n_seg, const int *seg_dev) {
     const int n = g->n_atoms, F = m->F, K = m->K, T = m->T, F3 = 3 * F, Fh = F / 2;
-    // node GEMM operand precision and radial-filter precision of the mode
-    const int P = m->precision == MLP_PREC_FP32 ? 0 : 1;
-    const int PF = m->precision == MLP_PREC_BF16 ? 1 : 0;
+    // MFMA operand form of the mode (node GEMMs and radial filter alike):
+    // 0 FP32, 1 plain bfloat16, 2 split bfloat16 (hi + lo)
+    const int P = m->precision == MLP_PREC_FP32 ? 0 : (m->precision == MLP_PREC_BF16 ? 2 : 1);
+    const int PF = P;
     int *Gr = &g->n_grows;
     int rc;
     const size_t need = act_floats(n, F, T) * sizeof(float);

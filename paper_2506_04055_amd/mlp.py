@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmlp.so")
 
 MLP_OK, MLP_PENDING = 0, 1
-MLP_FP32, MLP_BF16, MLP_BF16_NODE = 0, 1, 2
+MLP_FP32, MLP_BF16, MLP_BF16_FAST = 0, 1, 2
 _ERRORS = {-1: "INVALID_ARG", -2: "OOM", -3: "CAPACITY", -4: "BOX_TOO_SMALL", -5: "DEVICE", -6: "UNKNOWN_TICKET"}
 
 
@@ -188,7 +188,7 @@ class Model:
 
     def __init__(self, header: dict, weights: np.ndarray, precision: str | int = "fp32"):
         if isinstance(precision, str):
-            precision = {"fp32": MLP_FP32, "bf16": MLP_BF16, "bf16_node": MLP_BF16_NODE}[precision]
+            precision = {"fp32": MLP_FP32, "bf16": MLP_BF16, "bf16_fast": MLP_BF16_FAST}[precision]
         self.header = header
         self.precision = precision
         self.handle = mlp_model_create(json.dumps(header, sort_keys=True), weights, precision)
