@@ -242,7 +242,7 @@ static void release_all(mlp_nbr *g) {
     DevBuf *bufs[] = {&g->perm, &g->iperm, &g->cell_of, &g->cell_start, &g->cell_cnt, &g->cell_fill, &g->tmp_idx,
                       &g->pos_build, &g->species, &g->row, &g->col, &g->rev, &g->rowc, &g->colc, &g->revc,
                       &g->geom, &g->map, &g->oldidx, &g->cnt, &g->hop, &g->pos4, &g->scan_tmp, &g->flags,
-                      &g->red, &g->ghost_ptr, &g->ghost_list, &g->ghost_cnt, &g->act, &g->G, &g->Fint, &g->Uatom};
+                      &g->red, &g->ghost_ptr, &g->ghost_list, &g->ghost_cnt, &g->act, &g->G, &g->Gs, &g->Fint, &g->Uatom};
     for (DevBuf *b : bufs) b->release();
 }
 
@@ -250,7 +250,7 @@ static int64_t held_bytes(mlp_nbr *g) {
     DevBuf *bufs[] = {&g->perm, &g->iperm, &g->cell_of, &g->cell_start, &g->cell_cnt, &g->cell_fill, &g->tmp_idx,
                       &g->pos_build, &g->species, &g->row, &g->col, &g->rev, &g->rowc, &g->colc, &g->revc,
                       &g->geom, &g->map, &g->oldidx, &g->cnt, &g->hop, &g->pos4, &g->scan_tmp, &g->flags,
-                      &g->red, &g->ghost_ptr, &g->ghost_list, &g->ghost_cnt, &g->act, &g->G, &g->Fint, &g->Uatom};
+                      &g->red, &g->ghost_ptr, &g->ghost_list, &g->ghost_cnt, &g->act, &g->G, &g->Gs, &g->Fint, &g->Uatom};
     int64_t t = 0;
     for (DevBuf *b : bufs) t += (int64_t)b->bytes;
     return t;

@@ -86,7 +86,7 @@ struct mlp_nbr {
     mlp::DevBuf act;           // one arena for per-layer activations
     size_t act_bytes = 0;
     int act_N = 0, act_F = 0, act_T = 0;
-    mlp::DevBuf G, Fint, Uatom;
+    mlp::DevBuf G, Gs, Fint, Uatom;   // Gs: per-pass edge sums of the adjoint
 };
 
 namespace mlp {

@@ -17,11 +17,20 @@ struct MsgArgs {
     float *sn, *v1;           // forward outputs (s1 inside [s1 | n] rows of 2F)
     const float *gs1, *gv1;   // adjoint inputs
     float *gv_in, *gphi;      // adjoint outputs
-    float4 *G;                // per-edge geometric gradient accumulator
+    float4 *S;                // per-pass edge sums (dE/dr, dE/drhat), slot p at S + p * s_stride
+    long s_stride;
 };
 
 // Return 0, -1 (unsupported F, K) or -5 (launch error).
 int msg_forward(hipStream_t st, int precision, int F, int K, const MsgArgs &a);
 int msg_adjoint(hipStream_t st, int precision, int F, int K, const MsgArgs &a);
+
+// Feature passes of the message kernels (edge-sum slots the adjoint needs).
+int msg_passes(int F);
+// Over the pruned edges (count rowc[n], at most ne_max): G[e] assembled from
+// the npass slots of S (slot p at S + p * s_stride), and the slots zeroed.
+int msg_assemble_G(hipStream_t st, const int *rowc, int n, long ne_max, const float4 *geom, const float4 *S,
+                   long s_stride, int npass, float4 *G);
+int msg_clear_S(hipStream_t st, const int *rowc, int n, long ne_max, float4 *S, long s_stride, int npass);
 
 }  // namespace mlp

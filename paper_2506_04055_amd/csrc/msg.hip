@@ -2,28 +2,43 @@
 //
 // Per directed edge (i <- j) the filter is w = A' e~(r), a dense K+1 -> 3F
 // contraction with A' = [c | A] and e~ = [fc, e_1 fc, ..., e_K fc],
-// e_k = sin(k pi r / rc) / r.  A wave owns one atom; its edges are taken 16
-// at a time.  For each chunk the filter is computed as 16 x 16 MFMA tiles
-// (16 features x 16 edges):
+// e_k = sin(k pi r / rc) / r.  A wave owns one atom and takes its edges 16 at
+// a time.  The filter of a chunk is computed as 16 x 16 MFMA tiles (16
+// features x 16 edges):
 //   A operand = 16 rows of A' (staged in LDS once per workgroup),
 //   B operand = e~ of the 16 edges (each lane evaluates the basis slots it
-//               holds; padding slots of a short last chunk are zero, so they
-//               contribute nothing),
-// and written to a per-wave LDS buffer.  A vector phase then runs with lane =
-// (edge parity, feature): it gathers 128-byte segments of the neighbour rows,
-// forms the products and accumulates per feature in registers, so sums over
-// edges need no cross-lane traffic except one final pairing.  Precision P = 0:
-// FP32 operands (v_mfma_f32_16x16x4_f32); P = 1: bfloat16 operands
-// (v_mfma_f32_16x16x32_bf16); P = 2: split bfloat16 operands x = hi + lo
-// (hi = bf16(x), lo = bf16(x - hi)) with the three products lo*hi + hi*lo +
-// hi*hi; accumulation FP32 in all.  Every sum has a fixed order, so results
-// are bitwise reproducible.
+//               holds; the slots of padding edges are zero, so they
+//               contribute nothing).
+// The accumulator of a tile leaves lane l = 16 g + e holding features
+// 4g .. 4g+3 of the tile for edge e.  That is the layout the rest of the pass
+// works in: lane (e, g) gathers the matching 16-byte pieces of its edge's
+// neighbour rows, forms the products in registers, and
+//   * sums over the features of an edge stay inside the lane, plus one
+//     exchange across the four lane rows;
+//   * sums over the edges of the atom stay inside the lane over the chunks,
+//     plus one 16-lane DPP row reduction per atom.
+// No LDS round trip sits between the matrix cores and the vector ALUs.
+//
+// Features are processed in passes of W = min(F, 32): blockIdx.y is the pass.
+// Workgroups are dispatched in linear order, so the workgroups of pass p are
+// issued before those of pass p + 1 and the rows gathered at any time are
+// W-feature slices (6 W floats per neighbour), a working set the per-XCD L2
+// holds.  The basis is re-evaluated per pass.
+//
+// Precision P = 0: FP32 operands (v_mfma_f32_16x16x4_f32); P = 1: bfloat16
+// operands (v_mfma_f32_16x16x32_bf16); P = 2: split bfloat16 operands
+// x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) with the three products
+// lo*hi + hi*lo + hi*hi; accumulation FP32 in all.  Every sum has a fixed
+// order, so results are bitwise reproducible.
 //
 // The adjoint is organised by source atom j over its in-edges (j <- i), the
 // reverses of the edges (i <- j) that carried j's messages; it gathers the
-// destination gradients, accumulates dE/dphi_j and dE/dv_j, and for every
-// edge computes G = dE/d(x_j - x_i) = (dE/dr) rhat + (I - rhat rhat^T) gr / r
-// with dE/dr = sum_f dE/dw_f dw_f/dr, dw/dr = A' de~/dr (a second MFMA).
+// destination gradients and accumulates dE/dphi_j and dE/dv_j.  For every edge
+// it also forms S = (dE/dr, dE/drhat) summed over the pass's features (dE/dr
+// through dw/dr = A' de~/dr, a second MFMA), and adds it to the pass's own
+// slot of a per-edge accumulator, so no two passes write the same memory.  The
+// edge gradient G = dE/d(x_j - x_i) = (dE/dr) rhat + (I - rhat rhat^T) dE/drhat / r
+// is linear in S and is assembled once after the last layer.
 #include "internal.h"
 #include "msg.h"
 
@@ -53,7 +68,7 @@ __device__ __forceinline__ void basis_slots(float r, float rc, bool valid, int g
         }
         return;
     }
-    const float ir = 1.0f / r;
+    const float ir = __builtin_amdgcn_rcpf(r);
     const float th = pi * r / rc;
     float s1, c1;
     sincosf(th, &s1, &c1);
@@ -135,35 +150,50 @@ struct BOp<2, K> {
     }
 };
 
-// Stage A' = [c | A] (3F x (K+1)) into LDS in the layout the A operand reads.
+// Features per pass and the pass count.
+template <int F>
+struct Pass {
+    static constexpr int W = F < 32 ? F : 32;   // features per pass
+    static constexpr int N = F / W;             // passes
+    static constexpr int TU = W / 16;           // 16-feature tiles per part and pass
+};
+
+// LDS image of the pass's rows of A' = [c | A]: local row q W + f holds the
+// global row q F + p W + f (part q = 0, 1, 2), in the layout the A operand
+// reads (reduction index contiguous).
 template <int P, int F, int K>
 struct WStage {
     static constexpr int KP = Basis<P, K>::KP;
-    static constexpr int LD = P >= 1 ? KP + 8 : KP + 1;   // padded row stride (elements)
-    static constexpr int ELEMS = 3 * F * LD * (P == 2 ? 2 : 1);   // split mode: hi table, then lo table
+    static constexpr int ROWS = 3 * Pass<F>::W;
+    static constexpr int LD = P >= 1 ? KP + 8 : KP + 1;          // padded row stride (elements)
+    static constexpr int ELEMS = ROWS * LD * (P == 2 ? 2 : 1);   // split mode: hi table, then lo table
     static constexpr int BYTES = ELEMS * (P >= 1 ? 2 : 4);
 };
 
 template <int P, int F, int K>
-__device__ __forceinline__ void stage_weights(const float *__restrict__ A, const float *__restrict__ c, void *lds) {
+__device__ __forceinline__ void stage_pass(const float *__restrict__ A, const float *__restrict__ c, int p,
+                                           void *lds) {
     using WS = WStage<P, F, K>;
-    for (int idx = threadIdx.x; idx < 3 * F * WS::KP; idx += blockDim.x) {
-        const int f = idx / WS::KP, k = idx % WS::KP;
+    constexpr int W = Pass<F>::W;
+    for (int idx = threadIdx.x; idx < WS::ROWS * WS::KP; idx += blockDim.x) {
+        const int lr = idx / WS::KP, k = idx % WS::KP;
+        const int f = (lr / W) * F + p * W + lr % W;
         float v = 0.f;
         if (k == 0) v = c[f];
         else if (k <= K) v = A[(long)f * K + (k - 1)];
         if (P >= 1) {
             const __bf16 h = (__bf16)v;
-            reinterpret_cast<__bf16 *>(lds)[f * WS::LD + k] = h;
-            if (P == 2) reinterpret_cast<__bf16 *>(lds)[3 * F * WS::LD + f * WS::LD + k] = (__bf16)(v - (float)h);
+            reinterpret_cast<__bf16 *>(lds)[lr * WS::LD + k] = h;
+            if (P == 2) reinterpret_cast<__bf16 *>(lds)[WS::ROWS * WS::LD + lr * WS::LD + k] = (__bf16)(v - (float)h);
         } else {
-            reinterpret_cast<float *>(lds)[f * WS::LD + k] = v;
+            reinterpret_cast<float *>(lds)[lr * WS::LD + k] = v;
         }
     }
     __syncthreads();
 }
 
-// w (4 features x this lane's edge) of 16-feature tile t from the basis operand.
+// Filter values of local tile t (rows 16t .. 16t+15): lane (e, g) receives
+// features 4g .. 4g+3 of the tile for its edge e.
 template <int P, int F, int K>
 __device__ __forceinline__ v4f filter_tile(const void *lds, int t, const BOp<P, K> &b, int lane) {
     using WS = WStage<P, F, K>;
@@ -175,7 +205,7 @@ __device__ __forceinline__ v4f filter_tile(const void *lds, int t, const BOp<P, 
     } else if constexpr (P == 2) {
         const __bf16 *t0 = reinterpret_cast<const __bf16 *>(lds) + row * WS::LD + 8 * g;
         const v8bf a = *reinterpret_cast<const v8bf *>(t0);
-        const v8bf al = *reinterpret_cast<const v8bf *>(t0 + 3 * F * WS::LD);
+        const v8bf al = *reinterpret_cast<const v8bf *>(t0 + WS::ROWS * WS::LD);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b.v, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.lo, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.v, acc, 0, 0, 0);
@@ -188,48 +218,39 @@ __device__ __forceinline__ v4f filter_tile(const void *lds, int t, const BOp<P, 
     return acc;
 }
 
-// Sum over the L lanes of each aligned group of L lanes (L = 2 * M0), leaving
-// the lane at position p in its group with entries [p*Q/L, (p+1)*Q/L).
-// Fixed pairings, so the summation order never changes.
-template <int H>
-__device__ __forceinline__ void rs_stage(float *a, int lane, int m) {
-    // Both halves are exchanged and summed, then each lane keeps the half its
-    // position selects.  Selecting between two computed sums (not between two
-    // array slots) keeps every array index a compile-time constant.
-    const bool hi = (lane & m) != 0;
-#pragma unroll
-    for (int q = 0; q < H; q++) {
-        const float lo_sum = a[q] + __shfl_xor(a[q], m, 64);
-        const float hi_sum = a[q + H] + __shfl_xor(a[q + H], m, 64);
-        a[q] = hi ? hi_sum : lo_sum;
-    }
+// DPP move inside rows of 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
-template <int Q, int M0>
-__device__ __forceinline__ void reduce_scatter(float *a, int lane) {
-    if constexpr (M0 >= 1 && Q >= 2) {
-        rs_stage<Q / 2>(a, lane, M0);
-        reduce_scatter<Q / 2, M0 / 2>(a, lane);
-    }
+// Sum over the 16 lanes of each row (lanes 16g .. 16g+15), by rotations of the
+// row and quad permutations; every lane of the row receives the total.
+__device__ __forceinline__ float row_sum16(float x) {
+    x += dpp<0x128>(x);   // row_ror:8
+    x += dpp<0x124>(x);   // row_ror:4
+    x += dpp<0x4E>(x);    // quad_perm [2,3,0,1]
+    x += dpp<0xB1>(x);    // quad_perm [1,0,3,2]
+    return x;
 }
 
-// LDS written by some lanes of a wave and read by others: make the writes
-// visible within the wave (waves of a workgroup work on different atoms and
-// never wait for each other).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+__device__ __forceinline__ v4f ld4(const float *p) { return *reinterpret_cast<const v4f *>(p); }
+__device__ __forceinline__ void st4(float *p, v4f x) { *reinterpret_cast<v4f *>(p) = x; }
 
-constexpr int WAVES = 8;   // waves per workgroup
-constexpr int PW = 32;     // features per pass of the vector phase
+constexpr int MW = 4;   // waves per workgroup
+#ifndef FWD_WAVES
+#define FWD_WAVES 3
+#endif
+#ifndef BWD_WAVES
+#define BWD_WAVES 2
+#endif
 
 // Atoms handled by this wave.  Workgroups are dispatched round-robin over the
-// XCDs, each with its own L2; XCD x gets the contiguous slice
-// [x n / nx, (x+1) n / nx) of the cell-sorted atoms, and the waves of its
-// workgroups interleave over that slice, so neighbour rows gathered by one
-// XCD stay in its L2.  The slices partition [0, n) whatever the grid size.
+// XCDs, each with its own L2; with gridDim.x a multiple of 8, XCD x runs the
+// workgroups with blockIdx.x % 8 == x and gets the contiguous slice
+// [x n / 8, (x+1) n / 8) of the cell-sorted atoms; the waves of its workgroups
+// interleave over that slice, so neighbour rows gathered by one XCD stay in
+// its L2.  The slices partition [0, n) whatever the grid size.
 struct XcdRange {
     int first, end, stride;
     __device__ __forceinline__ explicit XcdRange(int n) {
@@ -244,313 +265,301 @@ struct XcdRange {
     }
 };
 
-// Per-wave LDS: filter values of one pass for the 16 edges of a chunk,
-// [edge][part][feature in pass], and the chunk's edge records (8 floats each).
-template <int P, int F, int K>
-struct MsgLds {
-    static constexpr int WBUF = 16 * 3 * PW;
-    static constexpr int PER_WAVE = WBUF + 16 * 8;
-    static constexpr int BYTES = WStage<P, F, K>::BYTES + WAVES * PER_WAVE * 4;
-};
-
-// Filter tiles of pass p (features [p*PW, p*PW + FP) of each part) for the
-// current chunk, written to the wave's LDS buffer as [edge][part][feature].
-template <int P, int F, int K>
-__device__ __forceinline__ void filter_pass_to_lds(const void *lds, const BOp<P, K> &b, int p, int lane,
-                                                   float *wbuf) {
-    constexpr int NG = F / 16, FP = F < PW ? F : PW;
-    const int g = lane >> 4, el = lane & 15;
-#pragma unroll
-    for (int q = 0; q < 3; q++)
-#pragma unroll
-        for (int u = 0; u < FP / 16; u++) {
-            const int t = q * NG + (p * PW) / 16 + u;
-            const v4f d = filter_tile<P, F, K>(lds, t, b, lane);
-            *reinterpret_cast<float4 *>(&wbuf[(el * 3 + q) * PW + 16 * u + 4 * g]) = make_float4(d[0], d[1], d[2], d[3]);
-        }
-}
-
 // ---------------------------------------------------------------------------
-// Forward message pass.  Per chunk of 16 edges: the filter tiles on MFMA, then
-// a vector phase with lane = (edge parity, feature) that gathers 128-byte row
-// segments of the source atoms and accumulates in registers.
+// Forward message pass, one feature pass (blockIdx.y) per workgroup.
 // ---------------------------------------------------------------------------
 template <int P, int F, int K>
-__global__ void __launch_bounds__(64 * WAVES) k_msg_fwd_mfma(const int *__restrict__ rowc,
-                                                            const int *__restrict__ colc,
-                                                            const float4 *__restrict__ geom, int n,
-                                                            const float *__restrict__ phi,
-                                                            const float *__restrict__ s,
-                                                            const float *__restrict__ v,
-                                                            const float *__restrict__ Aw,
-                                                            const float *__restrict__ cw, float rc,
-                                                            const int8_t *__restrict__ hop, int hop_max,
-                                                            float *__restrict__ sn, float *__restrict__ v1) {
-    using LS = MsgLds<P, F, K>;
-    constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS;
-    constexpr int FP = F < PW ? F : PW, NP = F / FP;
-    __shared__ __attribute__((aligned(16))) char lds[LS::BYTES];
-    stage_weights<P, F, K>(Aw, cw, lds);
-    const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15;
-    const int eh = lane >> 5, fi = lane & 31;
-    float *wbuf = reinterpret_cast<float *>(lds + WStage<P, F, K>::BYTES) + (threadIdx.x >> 6) * LS::PER_WAVE;
-    float *erec = wbuf + LS::WBUF;
+__global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FWD_WAVES))) k_msg_fwd(const int *__restrict__ rowc, const int *__restrict__ colc,
+                                                     const float4 *__restrict__ geom, int n,
+                                                     const float *__restrict__ phi, const float *__restrict__ s,
+                                                     const float *__restrict__ v, const float *__restrict__ Aw,
+                                                     const float *__restrict__ cw, float rc,
+                                                     const int8_t *__restrict__ hop, int hop_max,
+                                                     float *__restrict__ sn, float *__restrict__ v1) {
+    constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F>::W, TU = Pass<F>::TU;
+    __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K>::BYTES];
+    const int p = blockIdx.y;
+    stage_pass<P, F, K>(Aw, cw, p, lds);
+    const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
+    const int fo = p * W + 4 * g;   // first feature of this lane (tile u adds 16 u)
     const XcdRange xr(n);
     for (int i = xr.first; i < xr.end; i += xr.stride) {
         const int e0 = rowc[i], e1 = rowc[i + 1];
         const int deg = hop[i] <= hop_max ? e1 - e0 : 0;
-        float acc[NP][4];
+        v4f as[TU], av[3][TU];
 #pragma unroll
-        for (int p = 0; p < NP; p++) acc[p][0] = acc[p][1] = acc[p][2] = acc[p][3] = 0.f;
+        for (int u = 0; u < TU; u++) {
+            as[u] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int d = 0; d < 3; d++) av[d][u] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
         for (int cb = 0; cb < deg; cb += 16) {
-            const bool valid = cb + el < deg;
+            const bool valid = cb + e < deg;
             float4 gm = make_float4(0.f, 0.f, 0.f, rc);
-            int jj = i;
+            int j = i;
             if (valid) {
-                gm = geom[e0 + cb + el];
-                jj = colc[e0 + cb + el];
+                gm = geom[e0 + cb + e];
+                j = colc[e0 + cb + e];
             }
+            const float *pj = phi + (long)j * F3 + fo;
+            const float *vj = v + (long)j * F3 + fo;
+            v4f ph[3][TU], vv[3][TU];
+#pragma unroll
+            for (int q = 0; q < 3; q++)
+#pragma unroll
+                for (int u = 0; u < TU; u++) {
+                    ph[q][u] = ld4(pj + q * F + 16 * u);
+                    vv[q][u] = ld4(vj + q * F + 16 * u);
+                }
             float eb[SL];
             basis_slots<P, K, false>(gm.w, rc, valid, g, eb, nullptr);
             BOp<P, K> bop;
             bop.set(eb);
-            if (g == 0) {
-                const float ir = 1.0f / gm.w;
-                *reinterpret_cast<float4 *>(&erec[el * 8]) = make_float4(__int_as_float(jj), gm.x * ir, gm.y * ir, gm.z * ir);
-            }
+            const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
+            const float rx = gm.x * ir, ry = gm.y * ir, rz = gm.z * ir;
 #pragma unroll
-            for (int p = 0; p < NP; p++) {
-                filter_pass_to_lds<P, F, K>(lds, bop, p, lane, wbuf);
-                wave_lds_sync();
-                if (fi < FP) {
-                    const int f = p * PW + fi;
-#pragma unroll 4
-                    for (int st = 0; st < 8; st++) {
-                        const int ed = 2 * st + eh;
-                        const float4 rec = *reinterpret_cast<const float4 *>(&erec[ed * 8]);
-                        const int j = __float_as_int(rec.x);
-                        const float wvv = wbuf[(ed * 3 + 0) * PW + fi];
-                        const float ws = wbuf[(ed * 3 + 1) * PW + fi];
-                        const float wvs = wbuf[(ed * 3 + 2) * PW + fi];
-                        const float *pj = phi + (long)j * F3 + f;
-                        const float *vj = v + (long)j * F3 + f;
-                        const float xvv = pj[0] * wvv, xvs = pj[2 * F] * wvs;
-                        acc[p][0] = fmaf(pj[F], ws, acc[p][0]);
-                        acc[p][1] = fmaf(vj[0], xvv, fmaf(rec.y, xvs, acc[p][1]));
-                        acc[p][2] = fmaf(vj[F], xvv, fmaf(rec.z, xvs, acc[p][2]));
-                        acc[p][3] = fmaf(vj[2 * F], xvv, fmaf(rec.w, xvs, acc[p][3]));
-                    }
+            for (int u = 0; u < TU; u++) {
+                const v4f wvv = filter_tile<P, F, K>(lds, u, bop, lane);
+                const v4f ws = filter_tile<P, F, K>(lds, TU + u, bop, lane);
+                const v4f wvs = filter_tile<P, F, K>(lds, 2 * TU + u, bop, lane);
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const float xvv = ph[0][u][r] * wvv[r], xvs = ph[2][u][r] * wvs[r];
+                    as[u][r] = fmaf(ph[1][u][r], ws[r], as[u][r]);
+                    av[0][u][r] = fmaf(vv[0][u][r], xvv, fmaf(rx, xvs, av[0][u][r]));
+                    av[1][u][r] = fmaf(vv[1][u][r], xvv, fmaf(ry, xvs, av[1][u][r]));
+                    av[2][u][r] = fmaf(vv[2][u][r], xvv, fmaf(rz, xvs, av[2][u][r]));
                 }
-                wave_lds_sync();
             }
         }
-        // the two edge parities hold partial sums of the same feature
+        // sum over the 16 edge lanes of each row
 #pragma unroll
-        for (int p = 0; p < NP; p++)
+        for (int u = 0; u < TU; u++)
 #pragma unroll
-            for (int c = 0; c < 4; c++) acc[p][c] += __shfl_xor(acc[p][c], 32, 64);
-        if (eh == 0 && fi < FP) {
+            for (int r = 0; r < 4; r++) {
+                as[u][r] = row_sum16(as[u][r]);
 #pragma unroll
-            for (int p = 0; p < NP; p++) {
-                const int f = p * PW + fi;
-                sn[(long)i * 2 * F + f] = s[(long)i * F + f] + acc[p][0];
+                for (int d = 0; d < 3; d++) av[d][u][r] = row_sum16(av[d][u][r]);
+            }
+        if (e == 0) {
+#pragma unroll
+            for (int u = 0; u < TU; u++) {
+                const int f = fo + 16 * u;
+                st4(sn + (long)i * 2 * F + f, ld4(s + (long)i * F + f) + as[u]);
 #pragma unroll
                 for (int d = 0; d < 3; d++)
-                    v1[(long)i * F3 + d * F + f] = v[(long)i * F3 + d * F + f] + acc[p][1 + d];
+                    st4(v1 + (long)i * F3 + d * F + f, ld4(v + (long)i * F3 + d * F + f) + av[d][u]);
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint of the message pass.  Per chunk of 16 in-edges (j <- i) of the
-// source atom j: per pass, the filter tiles (then their radial derivatives)
-// on MFMA, and a vector phase over (edge parity, feature) lanes that gathers
-// the destinations' gradients.  dE/dphi_j and dE/dv_j accumulate in registers;
-// the per-edge sums over features (dE/dr and dE/drhat) are reduced across the
-// 32 feature lanes once per chunk and give G of edge (i <- j), added at the
-// position of (j <- i).
+// Adjoint of the message pass, one feature pass (blockIdx.y) per workgroup.
+// Per chunk of 16 in-edges (j <- i) of the source atom j: the filter tiles and
+// their radial derivatives on MFMA, the destinations' gradient pieces
+// gathered per lane, dE/dphi_j and dE/dv_j accumulated in registers, and the
+// edge sums S = (dE/dr, dE/drhat) of the pass added to the pass's slot.
 // ---------------------------------------------------------------------------
 template <int P, int F, int K>
-__global__ void __launch_bounds__(64 * WAVES) k_msg_bwd_mfma(const int *__restrict__ rowc,
-                                                            const int *__restrict__ colc,
-                                                            const float4 *__restrict__ geom, int n,
-                                                            const float *__restrict__ phi,
-                                                            const float *__restrict__ v,
-                                                            const float *__restrict__ gs1,
-                                                            const float *__restrict__ gv1,
-                                                            const float *__restrict__ Aw,
-                                                            const float *__restrict__ cw, float rc,
-                                                            const int8_t *__restrict__ hop, int hop_max,
-                                                            float *__restrict__ gv_in, float *__restrict__ gphi,
-                                                            float4 *__restrict__ Gout) {
-    using LS = MsgLds<P, F, K>;
-    constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS;
-    constexpr int FP = F < PW ? F : PW, NP = F / FP;
-    __shared__ __attribute__((aligned(16))) char lds[LS::BYTES];
-    stage_weights<P, F, K>(Aw, cw, lds);
-    const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15;
-    const int eh = lane >> 5, fi = lane & 31;
-    float *wbuf = reinterpret_cast<float *>(lds + WStage<P, F, K>::BYTES) + (threadIdx.x >> 6) * LS::PER_WAVE;
-    float *erec = wbuf + LS::WBUF;
+__global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BWD_WAVES))) k_msg_bwd(const int *__restrict__ rowc, const int *__restrict__ colc,
+                                                     const float4 *__restrict__ geom, int n,
+                                                     const float *__restrict__ phi, const float *__restrict__ v,
+                                                     const float *__restrict__ gs1, const float *__restrict__ gv1,
+                                                     const float *__restrict__ Aw, const float *__restrict__ cw,
+                                                     float rc, const int8_t *__restrict__ hop, int hop_max,
+                                                     float *__restrict__ gv_in, float *__restrict__ gphi,
+                                                     float4 *__restrict__ S, long s_stride) {
+    constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F>::W, TU = Pass<F>::TU;
+    __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K>::BYTES];
+    const int p = blockIdx.y;
+    stage_pass<P, F, K>(Aw, cw, p, lds);
+    float4 *Sp = S + (long)p * s_stride;
+    const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
+    const int fo = p * W + 4 * g;
     const XcdRange xr(n);
     for (int j = xr.first; j < xr.end; j += xr.stride) {
         const int e0 = rowc[j], e1 = rowc[j + 1];
         const int deg = hop[j] <= hop_max ? e1 - e0 : 0;
-        // One pass per block of FP features.  G is linear in (dE/dr, dE/drhat),
-        // so each pass adds the share of its features to G directly.
-#pragma unroll 1
-        for (int p = 0; p < NP; p++) {
-            const int f = p * PW + (fi < FP ? fi : 0);
-            float ph[3], vj[3];
+        v4f ph[3][TU], vj[3][TU], agp[3][TU], agv[3][TU];
 #pragma unroll
-            for (int q = 0; q < 3; q++) {
-                ph[q] = phi[(long)j * F3 + q * F + f];
-                vj[q] = v[(long)j * F3 + q * F + f];
+        for (int q = 0; q < 3; q++)
+#pragma unroll
+            for (int u = 0; u < TU; u++) {
+                ph[q][u] = ld4(phi + (long)j * F3 + q * F + fo + 16 * u);
+                vj[q][u] = ld4(v + (long)j * F3 + q * F + fo + 16 * u);
+                agp[q][u] = v4f{0.f, 0.f, 0.f, 0.f};
+                agv[q][u] = v4f{0.f, 0.f, 0.f, 0.f};
             }
-            float agp0 = 0.f, agp1 = 0.f, agp2 = 0.f, agv0 = 0.f, agv1 = 0.f, agv2 = 0.f;
-#pragma unroll 1
-            for (int cb = 0; cb < deg; cb += 16) {
-                const bool valid = cb + el < deg;
-                float4 gm = make_float4(0.f, 0.f, 0.f, rc);
-                int ii = j;
-                if (valid) {
-                    gm = geom[e0 + cb + el];
-                    ii = colc[e0 + cb + el];
-                }
-                float eb[SL], db[SL];
-                basis_slots<P, K, true>(gm.w, rc, valid, g, eb, db);
-                BOp<P, K> bop, dop;
-                bop.set(eb);
-                dop.set(db);
-                if (g == 0) {
-                    const float ir = 1.0f / gm.w;
-                    // direction of the message edge (i <- j) is x_j - x_i = -(x_i - x_j)
-                    *reinterpret_cast<float4 *>(&erec[el * 8]) =
-                        make_float4(__int_as_float(ii), -gm.x * ir, -gm.y * ir, -gm.z * ir);
-                    erec[el * 8 + 4] = gm.w;
-                }
-                float part[8][4];   // per step: dE/dr, dE/drhat (x, y, z) over this lane's features
-                float keep[8][4];   // gathered dE/ds1_i, dE/dv1_i reused by the derivative phase
-                filter_pass_to_lds<P, F, K>(lds, bop, p, lane, wbuf);
-                wave_lds_sync();
-#pragma unroll
-                for (int st = 0; st < 8; st++) {
-                    const int ed = 2 * st + eh;
-                    const float4 rec = *reinterpret_cast<const float4 *>(&erec[ed * 8]);
-                    const int i = __float_as_int(rec.x);
-                    const float w0 = wbuf[(ed * 3 + 0) * PW + fi];
-                    const float w1 = wbuf[(ed * 3 + 1) * PW + fi];
-                    const float w2 = wbuf[(ed * 3 + 2) * PW + fi];
-                    const float gs = gs1[(long)i * F + f];
-                    const float ga = gv1[(long)i * F3 + f];
-                    const float gb = gv1[(long)i * F3 + F + f];
-                    const float gc = gv1[(long)i * F3 + 2 * F + f];
-                    keep[st][0] = gs;
-                    keep[st][1] = ga;
-                    keep[st][2] = gb;
-                    keep[st][3] = gc;
-                    const float gxvv = fmaf(ga, vj[0], fmaf(gb, vj[1], gc * vj[2]));
-                    const float gxvs = fmaf(ga, rec.y, fmaf(gb, rec.z, gc * rec.w));
-                    const float xvv = ph[0] * w0, xvs = ph[2] * w2;
-                    agv0 = fmaf(ga, xvv, agv0);
-                    agv1 = fmaf(gb, xvv, agv1);
-                    agv2 = fmaf(gc, xvv, agv2);
-                    agp0 = fmaf(gxvv, w0, agp0);
-                    agp1 = fmaf(gs, w1, agp1);
-                    agp2 = fmaf(gxvs, w2, agp2);
-                    part[st][1] = ga * xvs;
-                    part[st][2] = gb * xvs;
-                    part[st][3] = gc * xvs;
-                }
-                wave_lds_sync();
-                filter_pass_to_lds<P, F, K>(lds, dop, p, lane, wbuf);
-                wave_lds_sync();
-#pragma unroll
-                for (int st = 0; st < 8; st++) {
-                    const int ed = 2 * st + eh;
-                    const float4 rec = *reinterpret_cast<const float4 *>(&erec[ed * 8]);
-                    const float d0 = wbuf[(ed * 3 + 0) * PW + fi];
-                    const float d1 = wbuf[(ed * 3 + 1) * PW + fi];
-                    const float d2 = wbuf[(ed * 3 + 2) * PW + fi];
-                    const float gxvv = fmaf(keep[st][1], vj[0], fmaf(keep[st][2], vj[1], keep[st][3] * vj[2]));
-                    const float gxvs = fmaf(keep[st][1], rec.y, fmaf(keep[st][2], rec.z, keep[st][3] * rec.w));
-                    part[st][0] = fmaf(gxvv * ph[0], d0, fmaf(keep[st][0] * ph[1], d1, gxvs * ph[2] * d2));
-                }
-                if (fi >= FP) {
-#pragma unroll
-                    for (int st = 0; st < 8; st++) part[st][0] = part[st][1] = part[st][2] = part[st][3] = 0.f;
-                }
-                // sum over the 32 feature lanes of each edge parity; lane fi
-                // then holds entry fi = 4 * step + component
-                float flat[32];
-#pragma unroll
-                for (int st = 0; st < 8; st++)
-#pragma unroll
-                    for (int c = 0; c < 4; c++) flat[4 * st + c] = part[st][c];
-                reduce_scatter<32, 16>(flat, lane);
-                const float c1 = __shfl_down(flat[0], 1, 64);
-                const float c2 = __shfl_down(flat[0], 2, 64);
-                const float c3 = __shfl_down(flat[0], 3, 64);
-                const int ed = 2 * (fi >> 2) + eh;
-                if ((fi & 3) == 0 && cb + ed < deg) {
-                    const float4 rec = *reinterpret_cast<const float4 *>(&erec[ed * 8]);
-                    const float ir = 1.0f / erec[ed * 8 + 4];
-                    const float gr = flat[0];
-                    const float rd = c1 * rec.y + c2 * rec.z + c3 * rec.w;
-                    float4 G = Gout[e0 + cb + ed];
-                    G.x += gr * rec.y + (c1 - rd * rec.y) * ir;
-                    G.y += gr * rec.z + (c2 - rd * rec.z) * ir;
-                    G.z += gr * rec.w + (c3 - rd * rec.w) * ir;
-                    Gout[e0 + cb + ed] = G;
-                }
-                wave_lds_sync();
+        for (int cb = 0; cb < deg; cb += 16) {
+            const bool valid = cb + e < deg;
+            float4 gm = make_float4(0.f, 0.f, 0.f, rc);
+            int i = j;
+            if (valid) {
+                gm = geom[e0 + cb + e];
+                i = colc[e0 + cb + e];
             }
-            // the two edge parities hold partial sums of the same feature
-            agp0 += __shfl_xor(agp0, 32, 64);
-            agp1 += __shfl_xor(agp1, 32, 64);
-            agp2 += __shfl_xor(agp2, 32, 64);
-            agv0 += __shfl_xor(agv0, 32, 64);
-            agv1 += __shfl_xor(agv1, 32, 64);
-            agv2 += __shfl_xor(agv2, 32, 64);
-            if (eh == 0 && fi < FP) {
-                const long b = (long)j * F3 + f;
-                gphi[b] = agp0;
-                gphi[b + F] = agp1;
-                gphi[b + 2 * F] = agp2;
-                gv_in[b] = gv1[b] + agv0;
-                gv_in[b + F] = gv1[b + F] + agv1;
-                gv_in[b + 2 * F] = gv1[b + 2 * F] + agv2;
+            v4f gs[TU], gv[3][TU];
+#pragma unroll
+            for (int u = 0; u < TU; u++) {
+                gs[u] = ld4(gs1 + (long)i * F + fo + 16 * u);
+#pragma unroll
+                for (int d = 0; d < 3; d++) gv[d][u] = ld4(gv1 + (long)i * F3 + d * F + fo + 16 * u);
             }
+            float eb[SL], db[SL];
+            basis_slots<P, K, true>(gm.w, rc, valid, g, eb, db);
+            BOp<P, K> bop, dop;
+            bop.set(eb);
+            dop.set(db);
+            // direction of the message edge (i <- j) is x_j - x_i = -(x_i - x_j)
+            const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
+            const float rx = -gm.x * ir, ry = -gm.y * ir, rz = -gm.z * ir;
+            float sr = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+            for (int u = 0; u < TU; u++) {
+                const v4f w0 = filter_tile<P, F, K>(lds, u, bop, lane);
+                const v4f w1 = filter_tile<P, F, K>(lds, TU + u, bop, lane);
+                const v4f w2 = filter_tile<P, F, K>(lds, 2 * TU + u, bop, lane);
+                const v4f d0 = filter_tile<P, F, K>(lds, u, dop, lane);
+                const v4f d1 = filter_tile<P, F, K>(lds, TU + u, dop, lane);
+                const v4f d2 = filter_tile<P, F, K>(lds, 2 * TU + u, dop, lane);
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const float ga = gv[0][u][r], gb = gv[1][u][r], gc = gv[2][u][r], gsr = gs[u][r];
+                    const float gxvv = fmaf(ga, vj[0][u][r], fmaf(gb, vj[1][u][r], gc * vj[2][u][r]));
+                    const float gxvs = fmaf(ga, rx, fmaf(gb, ry, gc * rz));
+                    const float xvv = ph[0][u][r] * w0[r], xvs = ph[2][u][r] * w2[r];
+                    agv[0][u][r] = fmaf(ga, xvv, agv[0][u][r]);
+                    agv[1][u][r] = fmaf(gb, xvv, agv[1][u][r]);
+                    agv[2][u][r] = fmaf(gc, xvv, agv[2][u][r]);
+                    agp[0][u][r] = fmaf(gxvv, w0[r], agp[0][u][r]);
+                    agp[1][u][r] = fmaf(gsr, w1[r], agp[1][u][r]);
+                    agp[2][u][r] = fmaf(gxvs, w2[r], agp[2][u][r]);
+                    sx = fmaf(ga, xvs, sx);
+                    sy = fmaf(gb, xvs, sy);
+                    sz = fmaf(gc, xvs, sz);
+                    sr = fmaf(gxvv * ph[0][u][r], d0[r],
+                              fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr)));
+                }
+            }
+            // sum over the four lane rows (all features of the pass)
+            sr += __shfl_xor(sr, 16, 64);
+            sx += __shfl_xor(sx, 16, 64);
+            sy += __shfl_xor(sy, 16, 64);
+            sz += __shfl_xor(sz, 16, 64);
+            sr += __shfl_xor(sr, 32, 64);
+            sx += __shfl_xor(sx, 32, 64);
+            sy += __shfl_xor(sy, 32, 64);
+            sz += __shfl_xor(sz, 32, 64);
+            if (g == 0 && valid) {
+                float4 a = Sp[e0 + cb + e];
+                a.x += sr;
+                a.y += sx;
+                a.z += sy;
+                a.w += sz;
+                Sp[e0 + cb + e] = a;
+            }
+        }
+        // sum over the 16 edge lanes of each row
+#pragma unroll
+        for (int q = 0; q < 3; q++)
+#pragma unroll
+            for (int u = 0; u < TU; u++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    agp[q][u][r] = row_sum16(agp[q][u][r]);
+                    agv[q][u][r] = row_sum16(agv[q][u][r]);
+                }
+        if (e == 0) {
+#pragma unroll
+            for (int q = 0; q < 3; q++)
+#pragma unroll
+                for (int u = 0; u < TU; u++) {
+                    const long b = (long)j * F3 + q * F + fo + 16 * u;
+                    st4(gphi + b, agp[q][u]);
+                    st4(gv_in + b, ld4(gv1 + b) + agv[q][u]);
+                }
         }
     }
 }
 
+// G of each pruned edge from the per-pass sums: G = dE/dr rhat + (g - (g . rhat) rhat) / r,
+// with rhat the direction of the message edge, the reverse of the stored one.
+// The pruned edge count is rowc[n], read on the device.
+__global__ void k_assemble_G(const int *__restrict__ rowc, int n, const float4 *__restrict__ geom,
+                             const float4 *__restrict__ S, long s_stride, int npass, float4 *__restrict__ G) {
+    const long ne = rowc[n];
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (long)gridDim.x * blockDim.x) {
+        float4 a = S[e];
+        for (int p = 1; p < npass; p++) {
+            const float4 b = S[(long)p * s_stride + e];
+            a.x += b.x;
+            a.y += b.y;
+            a.z += b.z;
+            a.w += b.w;
+        }
+        const float4 gm = geom[e];
+        const float ir = 1.0f / gm.w;
+        const float rx = -gm.x * ir, ry = -gm.y * ir, rz = -gm.z * ir;
+        const float rd = a.y * rx + a.z * ry + a.w * rz;
+        G[e] = make_float4(a.x * rx + (a.y - rd * rx) * ir, a.x * ry + (a.z - rd * ry) * ir,
+                           a.x * rz + (a.w - rd * rz) * ir, 0.f);
+    }
+}
+
+// Zero the npass slots over the pruned edges (count rowc[n], read on the device).
+__global__ void k_clear_S(const int *__restrict__ rowc, int n, float4 *__restrict__ S, long s_stride, int npass) {
+    const long ne = rowc[n];
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (long)gridDim.x * blockDim.x)
+        for (int p = 0; p < npass; p++) S[(long)p * s_stride + e] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+static int grid_x(int n) {
+    int b = std::min((n + MW - 1) / MW, 2048);
+    if (b >= 8) b -= b % 8;   // keeps blockIdx.x % 8 the XCD in every pass row
+    return std::max(1, b);
+}
+
 template <int P, int F, int K>
 static int launch_fwd(hipStream_t st, const MsgArgs &a) {
-    const int blocks = std::max(1, std::min((a.n + WAVES - 1) / WAVES, 2048));
-    k_msg_fwd_mfma<P, F, K><<<blocks, 64 * WAVES, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.s, a.v, a.A, a.c,
-                                                          a.rc, a.hop, a.hop_max, a.sn, a.v1);
+    dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F>::N);
+    k_msg_fwd<P, F, K><<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.s, a.v, a.A, a.c, a.rc,
+                                                 a.hop, a.hop_max, a.sn, a.v1);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
 template <int P, int F, int K>
 static int launch_bwd(hipStream_t st, const MsgArgs &a) {
-    const int blocks = std::max(1, std::min((a.n + WAVES - 1) / WAVES, 2048));
-    k_msg_bwd_mfma<P, F, K><<<blocks, 64 * WAVES, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.v, a.gs1, a.gv1,
-                                                          a.A, a.c, a.rc, a.hop, a.hop_max, a.gv_in, a.gphi, a.G);
+    dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F>::N);
+    k_msg_bwd<P, F, K><<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.v, a.gs1, a.gv1, a.A, a.c,
+                                                 a.rc, a.hop, a.hop_max, a.gv_in, a.gphi, a.S, a.s_stride);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
-#define MSG_DISPATCH(FN, P_)                                                     \
-    do {                                                                         \
-        if (F == 128 && K == 20) return FN<P_, 128, 20>(st, a);                   \
-        if (F == 128 && K == 8) return FN<P_, 128, 8>(st, a);                     \
-        if (F == 64 && K == 20) return FN<P_, 64, 20>(st, a);                     \
-        if (F == 64 && K == 8) return FN<P_, 64, 8>(st, a);                       \
-        if (F == 32 && K == 20) return FN<P_, 32, 20>(st, a);                     \
-        if (F == 32 && K == 8) return FN<P_, 32, 8>(st, a);                       \
-        if (F == 16 && K == 6) return FN<P_, 16, 6>(st, a);                       \
+int msg_passes(int F) { return F < 32 ? 1 : F / 32; }
+
+static unsigned edge_blocks(long ne_max) { return (unsigned)std::max(1L, std::min((ne_max + 255) / 256, 8192L)); }
+
+int msg_assemble_G(hipStream_t st, const int *rowc, int n, long ne_max, const float4 *geom, const float4 *S,
+                   long s_stride, int npass, float4 *G) {
+    k_assemble_G<<<edge_blocks(ne_max), 256, 0, st>>>(rowc, n, geom, S, s_stride, npass, G);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int msg_clear_S(hipStream_t st, const int *rowc, int n, long ne_max, float4 *S, long s_stride, int npass) {
+    k_clear_S<<<edge_blocks(ne_max), 256, 0, st>>>(rowc, n, S, s_stride, npass);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+#define MSG_DISPATCH(FN, P_)                                     \
+    do {                                                         \
+        if (F == 128 && K == 20) return FN<P_, 128, 20>(st, a);  \
+        if (F == 128 && K == 8) return FN<P_, 128, 8>(st, a);    \
+        if (F == 64 && K == 20) return FN<P_, 64, 20>(st, a);    \
+        if (F == 64 && K == 8) return FN<P_, 64, 8>(st, a);      \
+        if (F == 32 && K == 20) return FN<P_, 32, 20>(st, a);    \
+        if (F == 32 && K == 8) return FN<P_, 32, 8>(st, a);      \
+        if (F == 16 && K == 6) return FN<P_, 16, 6>(st, a);      \
     } while (0)
 
 int msg_forward(hipStream_t st, int precision, int F, int K, const MsgArgs &a) {

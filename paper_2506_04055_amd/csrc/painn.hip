@@ -276,7 +276,8 @@ static MsgArgs msg_args(mlp_nbr *g, mlp_model *m, const LayerW &L, int hop_max) 
     a.rc = m->rc;
     a.hop = g->hop.as<int8_t>();
     a.hop_max = hop_max;
-    a.G = g->G.as<float4>();
+    a.S = g->Gs.as<float4>();
+    a.s_stride = g->n_edges_skin;
     return a;
 }
 
@@ -291,7 +292,10 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     int rc;
     const size_t need = act_floats(n, F, T) * sizeof(float);
     if ((rc = g->act.ensure(need, 1.2, Gr))) return rc;
-    if ((rc = g->G.ensure(sizeof(float4) * (size_t)g->n_edges_skin + 64, 1.2, Gr))) return rc;
+    const int npass = msg_passes(F);
+    const long ne = g->n_edges_skin;
+    if ((rc = g->G.ensure(sizeof(float4) * (size_t)ne + 64, 1.2, Gr))) return rc;
+    if ((rc = g->Gs.ensure(sizeof(float4) * (size_t)ne * npass + 64, 1.2, Gr))) return rc;
     Act A;
     carve(g->act.as<float>(), n, F, T, A);
     const int *perm = g->perm.as<int>();
@@ -332,8 +336,8 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     // adjoint
     gemm<false, E_STORE>(s, P, A.g5, Fh, m->at(m->off_W5), F, A.gs, F, n, F, Fh);
     k_fill<<<nblk((long)n * F3, 256), 256, 0, s>>>(A.gv, (long)n * F3, 0.f);
-    k_fill<<<nblk((long)g->n_edges_skin * 4 + 4, 256), 256, 0, s>>>(g->G.as<float>(), (long)g->n_edges_skin * 4 + 4,
-                                                                   0.f);
+    if ((rc = msg_clear_S(s, g->rowc.as<int>(), n, ne, g->Gs.as<float4>(), ne, npass)))
+        return fail(rc, "edge-sum clear kernel launch failed");
     for (int t = T - 1; t >= 0; t--) {
         LayerW L = m->layer(t);
         const int hop_src = T - t;
@@ -358,6 +362,9 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         gemm<false, E_DSILU>(s, P, A.gphi, F3, L.W2, F, A.ga1, F, n, F, F3, nullptr, nullptr, 0, A.h1[t], F);
         gemm<false, E_ADD>(s, P, A.ga1, F, L.W1, F, A.gs, F, n, F, F, nullptr, nullptr, 0, A.gs1, F);
     }
+    if ((rc = msg_assemble_G(s, g->rowc.as<int>(), n, ne, g->geom.as<float4>(), g->Gs.as<float4>(), ne, npass,
+                             g->G.as<float4>())))
+        return fail(rc, "edge-gradient kernel launch failed");
     k_forces<<<nblk(n, 256), 256, 0, s>>>(g->rowc.as<int>(), g->revc.as<int>(), g->G.as<float4>(), perm, n,
                                           forces_user);
     HIP_TRY(hipGetLastError());

@@ -85,7 +85,8 @@ __global__ void k_pack_edges(const int *__restrict__ colc, const int *__restrict
 static size_t footprint(const mlp_model *m, int n) {
     const size_t F = m->F, T = m->T;
     const size_t act = (23 * T + 4 + 27) * F * 4 + 64;
-    const size_t graph = 120 * 60 + 96;
+    const size_t npass = F < 32 ? 1 : F / 32;
+    const size_t graph = 120 * (60 + 16 * npass) + 96;   // per-pass edge sums of the adjoint included
     return (size_t)n * (act + graph) + (1u << 20);
 }
 
@@ -351,7 +352,7 @@ int mlp_server_destroy(mlp_server *S) {
         mlp_nbr_destroy(sl.nbr);
     }
     DevBuf *bufs[] = {&S->batch.rowc, &S->batch.perm, &S->batch.species, &S->batch.hop, &S->batch.colc,
-                      &S->batch.revc, &S->batch.geom, &S->batch.act, &S->batch.G, &S->seg, &S->energies,
+                      &S->batch.revc, &S->batch.geom, &S->batch.act, &S->batch.G, &S->batch.Gs, &S->seg, &S->energies,
                       &S->forces};
     for (DevBuf *b : bufs) b->release();
     if (S->h_energies) hipHostFree(S->h_energies);
