@@ -2,6 +2,8 @@
 #include "../../include/mlp.h"
 #include "internal.h"
 
+#include <vector>
+
 #include <cctype>
 #include <cmath>
 #include <cstdlib>
@@ -206,6 +208,42 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
         delete m;
         return fail(MLP_ERR_DEVICE, "weight copy failed");
     }
+    // the weight matrices of the node GEMMs, packed once as B operands
+    struct Item {
+        const float *W;
+        int R, C;
+        bool tr;
+        mlp::PackedW *dst;
+    };
+    std::vector<Item> items;
+    const int Fi = (int)F;
+    for (int t = 0; t < (int)T; t++) {
+        const mlp::LayerW L = m->layer(t);
+        const float *Wm[6] = {L.W1, L.W2, L.U, L.V, L.W3, L.W4};
+        const int R[6] = {Fi, 3 * Fi, Fi, Fi, Fi, 3 * Fi}, C[6] = {Fi, Fi, Fi, Fi, 2 * Fi, Fi};
+        for (int q = 0; q < 6; q++) {
+            items.push_back({Wm[q], R[q], C[q], false, &m->pk[t][q]});
+            items.push_back({Wm[q], R[q], C[q], true, &m->pk[t][6 + q]});
+        }
+    }
+    items.push_back({m->at(m->off_W5), Fi / 2, Fi, false, &m->pk_W5});
+    items.push_back({m->at(m->off_W5), Fi / 2, Fi, true, &m->pk_W5t});
+    size_t pk_bytes = 0;
+    for (const Item &it : items) pk_bytes += mlp::packed_bytes(it.R, it.C, it.tr);
+    int prc = hipMalloc(&m->pk_dev, pk_bytes) == hipSuccess ? 0 : MLP_ERR_OOM;
+    for (size_t q = 0, o = 0; prc == 0 && q < items.size(); q++) {
+        const Item &it = items[q];
+        if (mlp::pack_weight(nullptr, it.W, it.R, it.C, it.tr, (char *)m->pk_dev + o, it.dst)) prc = MLP_ERR_DEVICE;
+        o += mlp::packed_bytes(it.R, it.C, it.tr);
+    }
+    if (prc == 0 && hipDeviceSynchronize() != hipSuccess) prc = MLP_ERR_DEVICE;
+    if (prc) {
+        (void)hipGetLastError();
+        if (m->pk_dev) hipFree(m->pk_dev);
+        hipFree(m->w_dev);
+        delete m;
+        return fail(prc, "weight packing failed");
+    }
     *out = m;
     return MLP_OK;
 }
@@ -214,6 +252,7 @@ int mlp_model_destroy(mlp_model *m) {
     if (!m) return MLP_OK;
     if (m->w_dev) hipFree(m->w_dev);
     if (m->wb_dev) hipFree(m->wb_dev);
+    if (m->pk_dev) hipFree(m->pk_dev);
     delete m;
     return MLP_OK;
 }

@@ -6,11 +6,30 @@ namespace mlp {
 
 enum { GE_STORE = 0, GE_BIAS = 1, GE_BIAS_SILU = 2, GE_DSILU = 3, GE_ADD = 4 };
 
+// One weight matrix packed as the B operand of C = A B: element (k, n) of B
+// at [n][k] (reduction index contiguous), zero-padded to Np x Kp
+// (Np a multiple of 128, Kp a multiple of 32).  f32 holds it in FP32, hi the
+// bfloat16 rounding and lo the bfloat16 rounding of the remainder.
+struct PackedW {
+    const float *f32 = nullptr;
+    const __bf16 *hi = nullptr, *lo = nullptr;
+    int N = 0, K = 0, Np = 0, Kp = 0;
+};
+
+// Bytes of device memory (a multiple of 256) that pack_weight needs for an
+// R x C matrix in the given orientation (all three forms).
+size_t packed_bytes(int R, int C, bool transpose);
+// Pack W (row-major R x C, FP32, device) into `arena` (device, 256-byte
+// aligned, packed_bytes long): transpose = false gives B = W^T (forward, W
+// stored [out][in]), transpose = true gives B = W (adjoint).  Returns 0 or -5.
+int pack_weight(hipStream_t s, const float *W, int R, int C, bool transpose, void *arena, PackedW *out);
+
+// C = epilogue(A B) for A (M x K, row stride lda, FP32).
 // precision: 0 = FP32 operands, 1 = bfloat16 operands, 2 = split bfloat16
 // operands (hi + lo, three products); FP32 accumulation in all.
 // Returns 0 or -5 (launch error).
-int node_gemm(hipStream_t s, int precision, bool nt, int epi, const float *A, int lda, const float *B, int ldb,
-              float *C, int ldc, int M, int N, int K, const float *bias = nullptr, float *C2 = nullptr,
-              int ldc2 = 0, const float *R = nullptr, int ldr = 0);
+int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, const PackedW &B, float *C, int ldc,
+              int M, const float *bias = nullptr, float *C2 = nullptr, int ldc2 = 0, const float *R = nullptr,
+              int ldr = 0);
 
 }  // namespace mlp

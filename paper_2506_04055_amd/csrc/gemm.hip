@@ -1,215 +1,256 @@
 // Node-feature GEMMs on the matrix cores (MFMA), with fused epilogues.
 //
-//   C[m][n] = sum_r A[m][r] B(r, n)
-//   NT: B(r, n) = W[n][r]   (forward: W stored [out][in])
-//   NN: B(r, n) = W[r][n]   (adjoint: multiply by W^T on the right)
+//   C[m][n] = epilogue( sum_k A[m][k] B(k, n) )
 //
-// 64 x 64 output tile per 256-thread workgroup; the four waves own 32 x 32
-// quadrants (2 x 2 MFMA tiles of 16 x 16).  A and B tiles are staged in LDS
-// with the reduction index contiguous.  FP32 mode uses
-// v_mfma_f32_16x16x4_f32; BF16 mode rounds both operands to bfloat16 when
-// staging and uses v_mfma_f32_16x16x32_bf16; accumulation is FP32 in both.
-// Operand lane layout (16 x 16 output tile, lane l, g = l / 16):
-//   f32:  A[l%16][k0 + g],           B[k0 + g][l%16]
-//   bf16: A[l%16][8g .. 8g+7],       B[8g .. 8g+7][l%16]
-//   D:    rows 4g .. 4g+3, column l%16 (4 accumulator registers)
-// Split-bf16 mode (P = 2) stages each operand as x = hi + lo with
-// hi = bf16(x), lo = bf16(x - hi), and accumulates the three products
-// lo*hi + hi*lo + hi*hi on the bf16 matrix cores (the lo*lo term is below
-// FP32 rounding of the sum's leading part): ~16 significant bits per operand
-// at the bf16 instruction rate.
+// A is an FP32 activation matrix (rows = atoms, or atoms x 3 for vector
+// features); B is a weight matrix packed once per model (pack_weight) as
+// [n][k] with the reduction index contiguous, in FP32 and as bfloat16 hi / lo
+// parts, zero-padded so that no load of B needs a bound check.
+//
+// Each wave owns 16 rows of C and sweeps the columns in chunks of 128 (eight
+// 16 x 16 MFMA tiles).  A workgroup of four waves (64 rows) stages each
+// (128-column x 128-k) chunk of B in LDS once and every wave reads its B
+// fragments from there; A is loaded from global memory straight into the
+// MFMA operand layout:
+//   bf16 (v_mfma_f32_16x16x32_bf16): lane l = 16 g + c holds
+//        A[row c][k0 + 8g .. k0 + 8g + 7] and B[k0 + 8g .. +7][col c];
+//   f32  (v_mfma_f32_16x16x4_f32): lane l holds A[row c][k0 + 4g + j] and
+//        B[k0 + 4g + j][col c] in MFMA step j = 0..3 (one 16-byte load each;
+//        the k order inside a 16-block is permuted alike on both sides, which
+//        the sum does not see);
+//   D:   lane l holds rows 4g .. 4g+3 of column c.
+// Split-bf16 mode (P = 2) rounds A on the fly to x = hi + lo with
+// hi = bf16(x), lo = bf16(x - hi), and accumulates lo*hi + hi*lo + hi*hi
+// (the lo*lo term is below FP32 rounding of the leading part): ~16
+// significant bits per operand at the bf16 instruction rate.  A is read once
+// per 128-column chunk, so a GEMM with N <= 128 streams A and C through HBM
+// once; B moves from L2 once per 64 rows.
 #include "gemm.h"
+
+#include <algorithm>
 
 namespace mlp {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
+constexpr int GW = 4;          // waves per workgroup
+constexpr int NCH = 128;       // output columns per chunk
+constexpr int CT = NCH / 16;   // MFMA tiles per chunk
+
+static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
 __device__ __forceinline__ float g_sigmoid(float x) { return 1.0f / (1.0f + __expf(-x)); }
+__device__ __forceinline__ v4f gld4(const float *p) { return *reinterpret_cast<const v4f *>(p); }
 
-constexpr int TBM = 64, TBN = 64, TBK = 32;
-constexpr int LDF = TBK + 4;   // f32 LDS row stride (floats)
-constexpr int LDH = TBK + 8;   // bf16 LDS row stride (elements)
-
-template <int P, bool NT, int EPI>
-__global__ void __launch_bounds__(256) k_gemm_mfma(const float *__restrict__ A, int lda,
-                                                   const float *__restrict__ B, int ldb, float *C, int ldc,
-                                                   int M, int N, int K, const float *__restrict__ bias,
-                                                   float *__restrict__ C2, int ldc2, const float *R, int ldr) {
-    __shared__ __attribute__((aligned(16))) float smf[P == 0 ? 2 * TBM * LDF : 1];
-    __shared__ __attribute__((aligned(16))) __bf16 smh[P >= 1 ? 2 * TBM * LDH : 1];
-    __shared__ __attribute__((aligned(16))) __bf16 sml[P == 2 ? 2 * TBM * LDH : 1];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int g = lane >> 4, c16 = lane & 15;
-    const long m0 = (long)blockIdx.x * TBM;
-    const int n0 = blockIdx.y * TBN;
-    v4f acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; a++)
-#pragma unroll
-        for (int b = 0; b < 2; b++) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-
-    for (int k0 = 0; k0 < K; k0 += TBK) {
-        // stage A: 64 rows x 32 k, 8 consecutive k per thread
-        {
-            const int r = tid >> 2, kq = (tid & 3) * 8;
-            const long m = m0 + r;
-            float v[8];
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-                int k = k0 + kq + q;
-                v[q] = (m < M && k < K) ? A[m * lda + k] : 0.f;
-            }
-            if (P == 0) {
-#pragma unroll
-                for (int q = 0; q < 8; q++) smf[r * LDF + kq + q] = v[q];
-            } else {
-#pragma unroll
-                for (int q = 0; q < 8; q++) {
-                    const __bf16 h = (__bf16)v[q];
-                    smh[r * LDH + kq + q] = h;
-                    if (P == 2) sml[r * LDH + kq + q] = (__bf16)(v[q] - (float)h);
-                }
-            }
-        }
-        // stage B as [n][k]
-        {
-            float v[8];
-            int nn, kq;
-            if (NT) {
-                nn = tid >> 2;
-                kq = (tid & 3) * 8;
-#pragma unroll
-                for (int q = 0; q < 8; q++) {
-                    int n = n0 + nn, k = k0 + kq + q;
-                    v[q] = (n < N && k < K) ? B[(long)n * ldb + k] : 0.f;
-                }
-            } else {
-                nn = tid & 63;
-                kq = (tid >> 6) * 8;
-#pragma unroll
-                for (int q = 0; q < 8; q++) {
-                    int n = n0 + nn, k = k0 + kq + q;
-                    v[q] = (n < N && k < K) ? B[(long)k * ldb + n] : 0.f;
-                }
-            }
-            if (P == 0) {
-#pragma unroll
-                for (int q = 0; q < 8; q++) smf[TBM * LDF + nn * LDF + kq + q] = v[q];
-            } else {
-#pragma unroll
-                for (int q = 0; q < 8; q++) {
-                    const __bf16 h = (__bf16)v[q];
-                    smh[TBM * LDH + nn * LDH + kq + q] = h;
-                    if (P == 2) sml[TBM * LDH + nn * LDH + kq + q] = (__bf16)(v[q] - (float)h);
-                }
-            }
-        }
-        __syncthreads();
-        if (P == 0) {
-#pragma unroll
-            for (int kk = 0; kk < TBK; kk += 4) {
-                float a[2], b[2];
-#pragma unroll
-                for (int t = 0; t < 2; t++) {
-                    a[t] = smf[(wm * 32 + t * 16 + c16) * LDF + kk + g];
-                    b[t] = smf[TBM * LDF + (wn * 32 + t * 16 + c16) * LDF + kk + g];
-                }
-#pragma unroll
-                for (int ta = 0; ta < 2; ta++)
-#pragma unroll
-                    for (int tb = 0; tb < 2; tb++)
-                        acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
-            }
-        } else {
-            v8bf a[2], b[2];
-#pragma unroll
-            for (int t = 0; t < 2; t++) {
-                a[t] = *reinterpret_cast<const v8bf *>(&smh[(wm * 32 + t * 16 + c16) * LDH + 8 * g]);
-                b[t] = *reinterpret_cast<const v8bf *>(&smh[TBM * LDH + (wn * 32 + t * 16 + c16) * LDH + 8 * g]);
-            }
-            if (P == 2) {
-                v8bf al[2], bl[2];
-#pragma unroll
-                for (int t = 0; t < 2; t++) {
-                    al[t] = *reinterpret_cast<const v8bf *>(&sml[(wm * 32 + t * 16 + c16) * LDH + 8 * g]);
-                    bl[t] = *reinterpret_cast<const v8bf *>(&sml[TBM * LDH + (wn * 32 + t * 16 + c16) * LDH + 8 * g]);
-                }
-#pragma unroll
-                for (int ta = 0; ta < 2; ta++)
-#pragma unroll
-                    for (int tb = 0; tb < 2; tb++) {
-                        acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ta], b[tb], acc[ta][tb], 0, 0, 0);
-                        acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ta], bl[tb], acc[ta][tb], 0, 0, 0);
-                    }
-            }
-#pragma unroll
-            for (int ta = 0; ta < 2; ta++)
-#pragma unroll
-                for (int tb = 0; tb < 2; tb++)
-                    acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
-        }
-        __syncthreads();
+// Layout of one packed matrix in its arena: f32 [Np][Kp], then hi, then lo.
+struct PackLayout {
+    int N, K, Np, Kp;
+    size_t cnt, off_hi, off_lo, bytes;
+    PackLayout(int R, int C, bool tr) {
+        N = tr ? C : R;
+        K = tr ? R : C;
+        Np = round_up(N, NCH);
+        Kp = round_up(K, 32);
+        cnt = (size_t)Np * Kp;
+        off_hi = (cnt * sizeof(float) + 255) & ~size_t(255);
+        off_lo = off_hi + ((cnt * sizeof(__bf16) + 255) & ~size_t(255));
+        bytes = off_lo + ((cnt * sizeof(__bf16) + 255) & ~size_t(255));
     }
-    // epilogue
+};
+
+size_t packed_bytes(int R, int C, bool transpose) { return PackLayout(R, C, transpose).bytes; }
+
+__global__ void k_pack(const float *__restrict__ W, int C, bool tr, int N, int K, int Np, int Kp,
+                       float *__restrict__ f, __bf16 *__restrict__ hi, __bf16 *__restrict__ lo) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)Np * Kp) return;
+    const int n = (int)(idx / Kp), k = (int)(idx % Kp);
+    float v = 0.f;
+    if (n < N && k < K) v = tr ? W[(long)k * C + n] : W[(long)n * C + k];
+    f[idx] = v;
+    const __bf16 h = (__bf16)v;
+    hi[idx] = h;
+    lo[idx] = (__bf16)(v - (float)h);
+}
+
+int pack_weight(hipStream_t s, const float *W, int R, int C, bool transpose, void *arena, PackedW *out) {
+    const PackLayout L(R, C, transpose);
+    char *b = reinterpret_cast<char *>(arena);
+    float *f = reinterpret_cast<float *>(b);
+    __bf16 *hi = reinterpret_cast<__bf16 *>(b + L.off_hi);
+    __bf16 *lo = reinterpret_cast<__bf16 *>(b + L.off_lo);
+    k_pack<<<(unsigned)((L.cnt + 255) / 256), 256, 0, s>>>(W, C, transpose, L.N, L.K, L.Np, L.Kp, f, hi, lo);
+    if (hipGetLastError() != hipSuccess) return -5;
+    PackedW p;
+    p.N = L.N;
+    p.K = L.K;
+    p.Np = L.Np;
+    p.Kp = L.Kp;
+    p.f32 = f;
+    p.hi = hi;
+    p.lo = lo;
+    *out = p;
+    return 0;
+}
+
+// LDS image of one (128-column x KC) chunk of B: bf16 hi rows then lo rows
+// (P >= 1), or FP32 rows (P = 0); rows padded to spread the banks.
+constexpr int KC = 128;
+constexpr int LDH = KC + 8;   // bf16 elements per LDS row
+constexpr int LDF = KC + 4;   // floats per LDS row
+template <int P>
+struct GemmLds {
+    static constexpr int BYTES = P == 0 ? NCH * LDF * 4 : NCH * LDH * 2 * (P == 2 ? 2 : 1);
+};
+
+template <int P, int EPI>
+__global__ void __launch_bounds__(64 * GW) k_gemm(const float *__restrict__ A, int lda, PackedW B, float *C, int ldc,
+                                                  int M, const float *__restrict__ bias, float *__restrict__ C2,
+                                                  int ldc2, const float *R, int ldr) {
+    __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
+    const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+    const long m0 = ((long)blockIdx.x * GW + (threadIdx.x >> 6)) * 16;
+    const long arow = m0 + c16;
+    const bool rowok = arow < M;
+    const float *Ar = A + (rowok ? arow : 0) * (long)lda;
+    const int K = B.K;
+    for (int n0 = 0; n0 < B.N; n0 += NCH) {
+        v4f acc[CT];
 #pragma unroll
-    for (int ta = 0; ta < 2; ta++)
+        for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int kc = 0; kc < K; kc += KC) {
+            // stage B[n0 .. n0+127][kc .. kc+kcl) (all waves; rows beyond M still take part)
+            const int kcl = min(KC, B.Kp - kc);
+            __syncthreads();
+            if constexpr (P >= 1) {
+                const int vr = kcl / 8;   // 16-byte vectors per row
+                for (int idx = threadIdx.x; idx < NCH * vr; idx += blockDim.x) {
+                    const int n = idx / vr, q = idx % vr;
+                    const long go = (long)(n0 + n) * B.Kp + kc + 8 * q;
+                    __bf16 *h = reinterpret_cast<__bf16 *>(lds) + n * LDH + 8 * q;
+                    *reinterpret_cast<v8bf *>(h) = *reinterpret_cast<const v8bf *>(B.hi + go);
+                    if (P == 2) *reinterpret_cast<v8bf *>(h + NCH * LDH) = *reinterpret_cast<const v8bf *>(B.lo + go);
+                }
+            } else {
+                const int vr = kcl / 4;
+                for (int idx = threadIdx.x; idx < NCH * vr; idx += blockDim.x) {
+                    const int n = idx / vr, q = idx % vr;
+                    *reinterpret_cast<v4f *>(reinterpret_cast<float *>(lds) + n * LDF + 4 * q) =
+                        gld4(B.f32 + (long)(n0 + n) * B.Kp + kc + 4 * q);
+                }
+            }
+            __syncthreads();
+            const int kend = min(K, kc + KC);
+            if constexpr (P >= 1) {
+                for (int k0 = kc; k0 < kend; k0 += 32) {
+                    const int ka = k0 + 8 * g;
+                    float a[8];
+                    if (rowok && ka + 8 <= K) {
+                        const v4f x = gld4(Ar + ka), y = gld4(Ar + ka + 4);
 #pragma unroll
-        for (int tb = 0; tb < 2; tb++) {
-            const int n = n0 + wn * 32 + tb * 16 + c16;
-            if (n >= N) continue;
+                        for (int q = 0; q < 4; q++) {
+                            a[q] = x[q];
+                            a[4 + q] = y[q];
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 8; q++) a[q] = (rowok && ka + q < K) ? Ar[ka + q] : 0.f;
+                    }
+                    v8bf ah, al;
+#pragma unroll
+                    for (int q = 0; q < 8; q++) {
+                        ah[q] = (__bf16)a[q];
+                        if (P == 2) al[q] = (__bf16)(a[q] - (float)ah[q]);
+                    }
+                    const __bf16 *bb = reinterpret_cast<const __bf16 *>(lds) + c16 * LDH + (k0 - kc) + 8 * g;
+#pragma unroll
+                    for (int t = 0; t < CT; t++) {
+                        const v8bf bh = *reinterpret_cast<const v8bf *>(bb + 16 * t * LDH);
+                        if constexpr (P == 2) {
+                            const v8bf bl = *reinterpret_cast<const v8bf *>(bb + 16 * t * LDH + NCH * LDH);
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[t], 0, 0, 0);
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[t], 0, 0, 0);
+                        }
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[t], 0, 0, 0);
+                    }
+                }
+            } else {
+                for (int k0 = kc; k0 < kend; k0 += 16) {
+                    const int ka = k0 + 4 * g;
+                    v4f a;
+                    if (rowok && ka + 4 <= K) {
+                        a = gld4(Ar + ka);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; q++) a[q] = (rowok && ka + q < K) ? Ar[ka + q] : 0.f;
+                    }
+                    const float *bb = reinterpret_cast<const float *>(lds) + c16 * LDF + (k0 - kc) + 4 * g;
+#pragma unroll
+                    for (int t = 0; t < CT; t++) {
+                        const v4f b = *reinterpret_cast<const v4f *>(bb + 16 * t * LDF);
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], acc[t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // epilogue: lane holds rows m0 + 4g + r of column n0 + 16t + c16
+#pragma unroll
+        for (int t = 0; t < CT; t++) {
+            const int n = n0 + 16 * t + c16;
+            if (n >= B.N) continue;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const long m = m0 + wm * 32 + ta * 16 + 4 * g + r;
+                const long m = m0 + 4 * g + r;
                 if (m >= M) continue;
-                float x = acc[ta][tb][r];
+                const float x = acc[t][r];
                 if (EPI == GE_STORE) {
                     C[m * ldc + n] = x;
                 } else if (EPI == GE_BIAS) {
                     C[m * ldc + n] = x + bias[n];
                 } else if (EPI == GE_BIAS_SILU) {
-                    float h = x + bias[n];
+                    const float h = x + bias[n];
                     C[m * ldc + n] = h;
                     C2[m * ldc2 + n] = h * g_sigmoid(h);
                 } else if (EPI == GE_DSILU) {
-                    float h = R[m * ldr + n];
-                    float sg = g_sigmoid(h);
+                    const float h = R[m * ldr + n];
+                    const float sg = g_sigmoid(h);
                     C[m * ldc + n] = x * (sg * (1.0f + h * (1.0f - sg)));
                 } else {
                     C[m * ldc + n] = R[m * ldr + n] + x;
                 }
             }
         }
+    }
 }
 
-template <int P, bool NT, int EPI>
-static void launch(hipStream_t s, const float *A, int lda, const float *B, int ldb, float *C, int ldc, int M, int N,
-                   int K, const float *bias, float *C2, int ldc2, const float *R, int ldr) {
-    dim3 grid((unsigned)((M + TBM - 1) / TBM), (unsigned)((N + TBN - 1) / TBN));
-    k_gemm_mfma<P, NT, EPI><<<grid, 256, 0, s>>>(A, lda, B, ldb, C, ldc, M, N, K, bias, C2, ldc2, R, ldr);
+template <int P, int EPI>
+static void launch(hipStream_t s, const float *A, int lda, const PackedW &B, float *C, int ldc, int M,
+                   const float *bias, float *C2, int ldc2, const float *R, int ldr) {
+    const unsigned blocks = (unsigned)((M + 16 * GW - 1) / (16 * GW));
+    k_gemm<P, EPI><<<blocks, 64 * GW, 0, s>>>(A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr);
 }
 
-int node_gemm(hipStream_t s, int precision, bool nt, int epi, const float *A, int lda, const float *B, int ldb,
-              float *C, int ldc, int M, int N, int K, const float *bias, float *C2, int ldc2, const float *R,
-              int ldr) {
-    if (M <= 0 || N <= 0 || K <= 0) return 0;
-#define GL(P_, NT_, E_) launch<P_, NT_, E_>(s, A, lda, B, ldb, C, ldc, M, N, K, bias, C2, ldc2, R, ldr)
-#define GE(P_, NT_)                                 \
-    switch (epi) {                                  \
-        case GE_STORE: GL(P_, NT_, GE_STORE); break; \
-        case GE_BIAS: GL(P_, NT_, GE_BIAS); break;   \
-        case GE_BIAS_SILU: GL(P_, NT_, GE_BIAS_SILU); break; \
-        case GE_DSILU: GL(P_, NT_, GE_DSILU); break; \
-        default: GL(P_, NT_, GE_ADD); break;         \
+int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, const PackedW &B, float *C, int ldc,
+              int M, const float *bias, float *C2, int ldc2, const float *R, int ldr) {
+    if (M <= 0 || B.N <= 0 || B.K <= 0) return 0;
+#define GL(P_, E_) launch<P_, E_>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr)
+#define GE(P_)                                   \
+    switch (epi) {                               \
+        case GE_STORE: GL(P_, GE_STORE); break;   \
+        case GE_BIAS: GL(P_, GE_BIAS); break;     \
+        case GE_BIAS_SILU: GL(P_, GE_BIAS_SILU); break; \
+        case GE_DSILU: GL(P_, GE_DSILU); break;   \
+        default: GL(P_, GE_ADD); break;           \
     }
     if (precision == 0) {
-        if (nt) { GE(0, true) } else { GE(0, false) }
+        GE(0)
     } else if (precision == 1) {
-        if (nt) { GE(1, true) } else { GE(1, false) }
+        GE(1)
     } else {
-        if (nt) { GE(2, true) } else { GE(2, false) }
+        GE(2)
     }
 #undef GE
 #undef GL

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <string>
 
+#include "gemm.h"
+
 #define MLP_MAX_LAYERS 7
 #define MLP_MAX_K 32
 // precision modes (values of the C ABI's MLP_FP32 / MLP_BF16 / MLP_BF16_FAST)
@@ -46,6 +48,9 @@ struct LayerW {
     const float *W1, *b1, *W2, *b2, *A, *c, *U, *V, *W3, *b3, *W4, *b4;
 };
 
+// Indices into mlp_model::pk[t]: forward (B = W^T) then adjoint (B = W).
+enum { WP_W1 = 0, WP_W2, WP_U, WP_V, WP_W3, WP_W4, WP_W1T, WP_W2T, WP_UT, WP_VT, WP_W3T, WP_W4T };
+
 }  // namespace mlp
 
 struct mlp_model {
@@ -57,6 +62,11 @@ struct mlp_model {
     size_t off_emb;
     size_t off_layer[MLP_MAX_LAYERS][12];
     size_t off_W5, off_b5, off_w6, off_b6;
+    // weight matrices packed as GEMM B operands (gemm.h): per layer
+    // W1 W2 U V W3 W4 for the forward, then the same six for the adjoint
+    mlp::PackedW pk[MLP_MAX_LAYERS][12];
+    mlp::PackedW pk_W5, pk_W5t;
+    void *pk_dev = nullptr;
     mlp::LayerW layer(int t) const;
     const float *at(size_t off) const { return w_dev + off; }
     const __hip_bfloat16 *atb(size_t off) const { return wb_dev + off; }

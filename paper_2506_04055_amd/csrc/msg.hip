@@ -54,69 +54,90 @@ struct Basis {
     static constexpr int SLOTS = P >= 1 ? 8 : NS;                     // basis values held per lane
 };
 
-// Basis values (and optionally their r-derivatives) for the slots a lane holds.
-// bf16: slots k = 8g + q (q = 0..7); f32: slots k = g + 4s (s = 0..NS-1).
+// sin and cos of th in [0, pi] without range reduction: with x = th - pi/2 in
+// [-pi/2, pi/2], sin th = cos x and cos th = -sin x, both from their Taylor
+// series (through x^13 and x^14; truncation below 1e-9 on this interval).
+__device__ __forceinline__ void sincos_0pi(float th, float &s, float &c) {
+    const float x = th - 1.57079632679489662f, x2 = x * x;
+    float p = 1.0f / 6227020800.0f;
+    p = fmaf(p, x2, -1.0f / 39916800.0f);
+    p = fmaf(p, x2, 1.0f / 362880.0f);
+    p = fmaf(p, x2, -1.0f / 5040.0f);
+    p = fmaf(p, x2, 1.0f / 120.0f);
+    p = fmaf(p, x2, -1.0f / 6.0f);
+    p = fmaf(p, x2, 1.0f);
+    float q = -1.0f / 87178291200.0f;
+    q = fmaf(q, x2, 1.0f / 479001600.0f);
+    q = fmaf(q, x2, -1.0f / 3628800.0f);
+    q = fmaf(q, x2, 1.0f / 40320.0f);
+    q = fmaf(q, x2, -1.0f / 720.0f);
+    q = fmaf(q, x2, 1.0f / 24.0f);
+    q = fmaf(q, x2, -0.5f);
+    q = fmaf(q, x2, 1.0f);
+    s = q;
+    c = -x * p;
+}
+
+// Basis values (and optionally their r-derivatives) for the slots a lane
+// holds: bf16 slots k = 8g + q (q = 0..7), f32 slots k = g + 4q (q = 0..NS-1).
+// r < rc for every valid edge, so th = pi r / rc lies in [0, pi).  The lane's
+// first angle k0 th comes from angle doubling, the rest from the Chebyshev
+// recurrences sin((k+d) th) = 2 cos(d th) sin(k th) - sin((k-d) th) (and the
+// same for cos).  Slots k > K meet zero weight columns, so their values do not
+// matter as long as they are finite.  Padding edges (valid = false, ir = 0)
+// get exact zeros.
 template <int P, int K, bool DERIV>
-__device__ __forceinline__ void basis_slots(float r, float rc, bool valid, int g, float *eb, float *db) {
+__device__ __forceinline__ void basis_slots(float r, float ir, float pirc, bool valid, int g, float *eb, float *db) {
     constexpr int SL = Basis<P, K>::SLOTS;
-    const float pi = 3.14159265358979f;
-    if (!valid) {
-#pragma unroll
-        for (int q = 0; q < SL; q++) {
-            eb[q] = 0.f;
-            if (DERIV) db[q] = 0.f;
-        }
-        return;
-    }
-    const float ir = __builtin_amdgcn_rcpf(r);
-    const float th = pi * r / rc;
     float s1, c1;
-    sincosf(th, &s1, &c1);
-    const float fc = 0.5f * (c1 + 1.0f);
-    const float dfc = -0.5f * (pi / rc) * s1;
-    const int k0 = P >= 1 ? 8 * g : g;
-    const int kstep = P >= 1 ? 1 : 4;
-    // (sin, cos) of 2, 4, 8, 16 and 24 theta by angle doubling and addition
-    // from the one small-argument sincos, so no large-argument reduction runs
+    sincos_0pi(r * pirc, s1, c1);
+    const float fc = valid ? 0.5f * (c1 + 1.0f) : 0.f;
+    const float dfc = valid ? -0.5f * pirc * s1 : 0.f;
+    const float es = ir * fc;                    // e_k = sin(k th) es
+    const float da = pirc * es, dbb = ir * (dfc - es);   // de_k = cos(k th) k da + sin(k th) dbb
     const float s2 = 2.0f * s1 * c1, c2 = fmaf(-2.0f * s1, s1, 1.0f);
     const float s4 = 2.0f * s2 * c2, c4 = fmaf(-2.0f * s2, s2, 1.0f);
-    float sk, ck, ss, cs;
-    if (kstep == 1) {
+    float sk, ck, sm, cm, tc;
+    int k0, step;
+    if constexpr (P >= 1) {
         const float s8 = 2.0f * s4 * c4, c8 = fmaf(-2.0f * s4, s4, 1.0f);
         const float s16 = 2.0f * s8 * c8, c16 = fmaf(-2.0f * s8, s8, 1.0f);
         const float s24 = fmaf(s16, c8, c16 * s8), c24 = fmaf(c16, c8, -s16 * s8);
         sk = g == 0 ? 0.f : (g == 1 ? s8 : (g == 2 ? s16 : s24));
         ck = g == 0 ? 1.f : (g == 1 ? c8 : (g == 2 ? c16 : c24));
-        ss = s1;
-        cs = c1;
+        sm = fmaf(sk, c1, -ck * s1);   // sin((k0 - 1) th)
+        cm = fmaf(ck, c1, sk * s1);
+        tc = 2.0f * c1;
+        k0 = 8 * g;
+        step = 1;
     } else {
         const float s3 = fmaf(s2, c1, c2 * s1), c3 = fmaf(c2, c1, -s2 * s1);
         sk = g == 0 ? 0.f : (g == 1 ? s1 : (g == 2 ? s2 : s3));
         ck = g == 0 ? 1.f : (g == 1 ? c1 : (g == 2 ? c2 : c3));
-        ss = s4;
-        cs = c4;
+        sm = fmaf(sk, c4, -ck * s4);   // sin((k0 - 4) th)
+        cm = fmaf(ck, c4, sk * s4);
+        tc = 2.0f * c4;
+        k0 = g;
+        step = 4;
     }
 #pragma unroll
     for (int q = 0; q < SL; q++) {
-        const int k = k0 + kstep * q;
-        float e, de;
-        if (k == 0) {
+        float e = sk * es, de = 0.f;
+        if (DERIV) de = fmaf(ck, (float)(k0 + step * q) * da, sk * dbb);
+        if (q == 0 && g == 0) {   // k = 0: the envelope itself
             e = fc;
             de = dfc;
-        } else if (k <= K) {
-            const float ek = sk * ir;
-            e = ek * fc;
-            de = ((float)k * (pi / rc) * ck * ir - ek * ir) * fc + ek * dfc;
-        } else {
-            e = 0.f;
-            de = 0.f;
         }
         eb[q] = e;
         if (DERIV) db[q] = de;
-        const float sn = fmaf(sk, cs, ck * ss);
-        const float cn = fmaf(ck, cs, -sk * ss);
+        const float sn = fmaf(tc, sk, -sm);
+        sm = sk;
         sk = sn;
-        ck = cn;
+        if (DERIV) {
+            const float cn = fmaf(tc, ck, -cm);
+            cm = ck;
+            ck = cn;
+        }
     }
 }
 
@@ -234,10 +255,22 @@ __device__ __forceinline__ float row_sum16(float x) {
     return x;
 }
 
+// The weight image, at an offset the compiler cannot see through, so the A
+// operands are re-read from LDS in every chunk instead of being held in 48
+// registers across the chunk loop (which would cost occupancy).
+__device__ __forceinline__ const char *lds_chunk(const char *lds) {
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return lds + z;
+}
+
 __device__ __forceinline__ v4f ld4(const float *p) { return *reinterpret_cast<const v4f *>(p); }
 __device__ __forceinline__ void st4(float *p, v4f x) { *reinterpret_cast<v4f *>(p) = x; }
 
-constexpr int MW = 4;   // waves per workgroup
+#ifndef MSG_MW
+#define MSG_MW 4
+#endif
+constexpr int MW = MSG_MW;   // waves per workgroup
 #ifndef FWD_WAVES
 #define FWD_WAVES 3
 #endif
@@ -283,6 +316,7 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
     const int fo = p * W + 4 * g;   // first feature of this lane (tile u adds 16 u)
     const XcdRange xr(n);
+    const float pirc = 3.14159265358979f / rc;
     for (int i = xr.first; i < xr.end; i += xr.stride) {
         const int e0 = rowc[i], e1 = rowc[i + 1];
         const int deg = hop[i] <= hop_max ? e1 - e0 : 0;
@@ -294,6 +328,7 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
             for (int d = 0; d < 3; d++) av[d][u] = v4f{0.f, 0.f, 0.f, 0.f};
         }
         for (int cb = 0; cb < deg; cb += 16) {
+            const char *wl = lds_chunk(lds);
             const bool valid = cb + e < deg;
             float4 gm = make_float4(0.f, 0.f, 0.f, rc);
             int j = i;
@@ -311,17 +346,17 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
                     ph[q][u] = ld4(pj + q * F + 16 * u);
                     vv[q][u] = ld4(vj + q * F + 16 * u);
                 }
+            const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
             float eb[SL];
-            basis_slots<P, K, false>(gm.w, rc, valid, g, eb, nullptr);
+            basis_slots<P, K, false>(gm.w, ir, pirc, valid, g, eb, nullptr);
             BOp<P, K> bop;
             bop.set(eb);
-            const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
             const float rx = gm.x * ir, ry = gm.y * ir, rz = gm.z * ir;
 #pragma unroll
             for (int u = 0; u < TU; u++) {
-                const v4f wvv = filter_tile<P, F, K>(lds, u, bop, lane);
-                const v4f ws = filter_tile<P, F, K>(lds, TU + u, bop, lane);
-                const v4f wvs = filter_tile<P, F, K>(lds, 2 * TU + u, bop, lane);
+                const v4f wvv = filter_tile<P, F, K>(wl, u, bop, lane);
+                const v4f ws = filter_tile<P, F, K>(wl, TU + u, bop, lane);
+                const v4f wvs = filter_tile<P, F, K>(wl, 2 * TU + u, bop, lane);
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     const float xvv = ph[0][u][r] * wvv[r], xvs = ph[2][u][r] * wvs[r];
@@ -378,6 +413,7 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BW
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
     const int fo = p * W + 4 * g;
     const XcdRange xr(n);
+    const float pirc = 3.14159265358979f / rc;
     for (int j = xr.first; j < xr.end; j += xr.stride) {
         const int e0 = rowc[j], e1 = rowc[j + 1];
         const int deg = hop[j] <= hop_max ? e1 - e0 : 0;
@@ -392,6 +428,7 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BW
                 agv[q][u] = v4f{0.f, 0.f, 0.f, 0.f};
             }
         for (int cb = 0; cb < deg; cb += 16) {
+            const char *wl = lds_chunk(lds);
             const bool valid = cb + e < deg;
             float4 gm = make_float4(0.f, 0.f, 0.f, rc);
             int i = j;
@@ -406,23 +443,23 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BW
 #pragma unroll
                 for (int d = 0; d < 3; d++) gv[d][u] = ld4(gv1 + (long)i * F3 + d * F + fo + 16 * u);
             }
+            const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
             float eb[SL], db[SL];
-            basis_slots<P, K, true>(gm.w, rc, valid, g, eb, db);
+            basis_slots<P, K, true>(gm.w, ir, pirc, valid, g, eb, db);
             BOp<P, K> bop, dop;
             bop.set(eb);
             dop.set(db);
             // direction of the message edge (i <- j) is x_j - x_i = -(x_i - x_j)
-            const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
             const float rx = -gm.x * ir, ry = -gm.y * ir, rz = -gm.z * ir;
             float sr = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
 #pragma unroll
             for (int u = 0; u < TU; u++) {
-                const v4f w0 = filter_tile<P, F, K>(lds, u, bop, lane);
-                const v4f w1 = filter_tile<P, F, K>(lds, TU + u, bop, lane);
-                const v4f w2 = filter_tile<P, F, K>(lds, 2 * TU + u, bop, lane);
-                const v4f d0 = filter_tile<P, F, K>(lds, u, dop, lane);
-                const v4f d1 = filter_tile<P, F, K>(lds, TU + u, dop, lane);
-                const v4f d2 = filter_tile<P, F, K>(lds, 2 * TU + u, dop, lane);
+                const v4f w0 = filter_tile<P, F, K>(wl, u, bop, lane);
+                const v4f w1 = filter_tile<P, F, K>(wl, TU + u, bop, lane);
+                const v4f w2 = filter_tile<P, F, K>(wl, 2 * TU + u, bop, lane);
+                const v4f d0 = filter_tile<P, F, K>(wl, u, dop, lane);
+                const v4f d1 = filter_tile<P, F, K>(wl, TU + u, dop, lane);
+                const v4f d2 = filter_tile<P, F, K>(wl, 2 * TU + u, dop, lane);
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     const float ga = gv[0][u][r], gb = gv[1][u][r], gc = gv[2][u][r], gsr = gs[u][r];

@@ -40,13 +40,13 @@ __device__ __forceinline__ float dsiluf_(float x) {
 // ---------------------------------------------------------------------------
 enum { E_STORE = GE_STORE, E_BIAS = GE_BIAS, E_BIAS_SILU = GE_BIAS_SILU, E_DSILU = GE_DSILU, E_ADD = GE_ADD };
 
-template <bool NT, int EPI>
-static void gemm(hipStream_t s, int prec, const float *A, int lda, const float *B, int ldb, float *C, int ldc, int M,
-                 int N, int K, const float *bias = nullptr, float *C2 = nullptr, int ldc2 = 0,
-                 const float *R = nullptr, int ldr = 0) {
+template <int EPI>
+static void gemm(hipStream_t s, int prec, const float *A, int lda, const PackedW &B, float *C, int ldc, int M,
+                 const float *bias = nullptr, float *C2 = nullptr, int ldc2 = 0, const float *R = nullptr,
+                 int ldr = 0) {
     if (M <= 0) return;
     ProfScope ps(PK_GEMM, s);
-    node_gemm(s, prec, NT, EPI, A, lda, B, ldb, C, ldc, M, N, K, bias, C2, ldc2, R, ldr);
+    node_gemm(s, prec, EPI, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,8 +305,8 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     for (int t = 0; t < T; t++) {
         LayerW L = m->layer(t);
         const int hop_dst = T - 1 - t;
-        gemm<true, E_BIAS_SILU>(s, P, A.s[t], F, L.W1, F, A.h1[t], F, n, F, F, L.b1, A.tmpF, F);
-        gemm<true, E_BIAS>(s, P, A.tmpF, F, L.W2, F, A.phi[t], F3, n, F3, F, L.b2);
+        gemm<E_BIAS_SILU>(s, P, A.s[t], F, m->pk[t][WP_W1], A.h1[t], F, n, L.b1, A.tmpF, F);
+        gemm<E_BIAS>(s, P, A.tmpF, F, m->pk[t][WP_W2], A.phi[t], F3, n, L.b2);
         {
             MsgArgs ma = msg_args(g, m, L, hop_dst);
             ma.phi = A.phi[t];
@@ -317,16 +317,16 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             ProfScope ps(PK_MSG_FWD, s);
             if ((rc = msg_forward(s, PF, F, K, ma))) return fail(rc, "message kernel launch failed");
         }
-        gemm<true, E_STORE>(s, P, A.v1[t], F, L.U, F, A.Uv[t], F, 3 * n, F, F);
-        gemm<true, E_STORE>(s, P, A.v1[t], F, L.V, F, A.Vv[t], F, 3 * n, F, F);
+        gemm<E_STORE>(s, P, A.v1[t], F, m->pk[t][WP_U], A.Uv[t], F, 3 * n);
+        gemm<E_STORE>(s, P, A.v1[t], F, m->pk[t][WP_V], A.Vv[t], F, 3 * n);
         k_norm<<<nblk((long)n * F, 256), 256, 0, s>>>(A.Vv[t], n, F, m->eps, A.sn[t]);
-        gemm<true, E_BIAS_SILU>(s, P, A.sn[t], 2 * F, L.W3, 2 * F, A.h3[t], F, n, F, 2 * F, L.b3, A.tmpF, F);
-        gemm<true, E_BIAS>(s, P, A.tmpF, F, L.W4, F, A.a[t], F3, n, F3, F, L.b4);
+        gemm<E_BIAS_SILU>(s, P, A.sn[t], 2 * F, m->pk[t][WP_W3], A.h3[t], F, n, L.b3, A.tmpF, F);
+        gemm<E_BIAS>(s, P, A.tmpF, F, m->pk[t][WP_W4], A.a[t], F3, n, L.b4);
         k_update_out<<<nblk((long)n * F, 256), 256, 0, s>>>(A.sn[t], A.v1[t], A.Uv[t], A.Vv[t], A.a[t], n, F,
                                                              A.s[t + 1], A.v[t + 1]);
     }
     // readout and energy
-    gemm<true, E_BIAS>(s, P, A.s[T], F, m->at(m->off_W5), F, A.h5, Fh, n, Fh, F, m->at(m->off_b5));
+    gemm<E_BIAS>(s, P, A.s[T], F, m->pk_W5, A.h5, Fh, n, m->at(m->off_b5));
     k_readout<<<nblk(n, 256), 256, 0, s>>>(A.h5, n, Fh, m->at(m->off_w6), m->at(m->off_b6), perm, g->n_local, A.U,
                                            A.g5);
     k_energy_seg<<<std::max(1, n_seg), ERED, 0, s>>>(A.U, perm, seg_dev, n, g->n_local, energy);
@@ -334,7 +334,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     if (!forces_user) return 0;
 
     // adjoint
-    gemm<false, E_STORE>(s, P, A.g5, Fh, m->at(m->off_W5), F, A.gs, F, n, F, Fh);
+    gemm<E_STORE>(s, P, A.g5, Fh, m->pk_W5t, A.gs, F, n);
     k_fill<<<nblk((long)n * F3, 256), 256, 0, s>>>(A.gv, (long)n * F3, 0.f);
     if ((rc = msg_clear_S(s, g->rowc.as<int>(), n, ne, g->Gs.as<float4>(), ne, npass)))
         return fail(rc, "edge-sum clear kernel launch failed");
@@ -343,11 +343,11 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         const int hop_src = T - t;
         k_update_bwd1<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gs, A.gv, A.Uv[t], A.Vv[t], A.a[t], n, F, A.ga,
                                                              A.gUv, A.gVv);
-        gemm<false, E_DSILU>(s, P, A.ga, F3, L.W4, F, A.gh3, F, n, F, F3, nullptr, nullptr, 0, A.h3[t], F);
-        gemm<false, E_STORE>(s, P, A.gh3, F, L.W3, 2 * F, A.gsn, 2 * F, n, 2 * F, F);
+        gemm<E_DSILU>(s, P, A.ga, F3, m->pk[t][WP_W4T], A.gh3, F, n, nullptr, nullptr, 0, A.h3[t], F);
+        gemm<E_STORE>(s, P, A.gh3, F, m->pk[t][WP_W3T], A.gsn, 2 * F, n);
         k_update_bwd2<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gsn, A.sn[t], A.Vv[t], A.gs, n, F, A.gVv, A.gs1);
-        gemm<false, E_ADD>(s, P, A.gUv, F, L.U, F, A.gv1, F, 3 * n, F, F, nullptr, nullptr, 0, A.gv, F);
-        gemm<false, E_ADD>(s, P, A.gVv, F, L.V, F, A.gv1, F, 3 * n, F, F, nullptr, nullptr, 0, A.gv1, F);
+        gemm<E_ADD>(s, P, A.gUv, F, m->pk[t][WP_UT], A.gv1, F, 3 * n, nullptr, nullptr, 0, A.gv, F);
+        gemm<E_ADD>(s, P, A.gVv, F, m->pk[t][WP_VT], A.gv1, F, 3 * n, nullptr, nullptr, 0, A.gv1, F);
         {
             MsgArgs ma = msg_args(g, m, L, hop_src);
             ma.phi = A.phi[t];
@@ -359,8 +359,8 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             ProfScope ps(PK_MSG_BWD, s);
             if ((rc = msg_adjoint(s, PF, F, K, ma))) return fail(rc, "adjoint message kernel launch failed");
         }
-        gemm<false, E_DSILU>(s, P, A.gphi, F3, L.W2, F, A.ga1, F, n, F, F3, nullptr, nullptr, 0, A.h1[t], F);
-        gemm<false, E_ADD>(s, P, A.ga1, F, L.W1, F, A.gs, F, n, F, F, nullptr, nullptr, 0, A.gs1, F);
+        gemm<E_DSILU>(s, P, A.gphi, F3, m->pk[t][WP_W2T], A.ga1, F, n, nullptr, nullptr, 0, A.h1[t], F);
+        gemm<E_ADD>(s, P, A.ga1, F, m->pk[t][WP_W1T], A.gs, F, n, nullptr, nullptr, 0, A.gs1, F);
     }
     if ((rc = msg_assemble_G(s, g->rowc.as<int>(), n, ne, g->geom.as<float4>(), g->Gs.as<float4>(), ne, npass,
                              g->G.as<float4>())))
