@@ -10,6 +10,7 @@ struct MsgArgs {
     const float4 *geom;       // (dx, dy, dz, r) of each pruned edge, d = x_src - x_dst
     int n;
     const float *phi, *s, *v; // layer inputs (phi of the message MLP)
+    const float *u;           // v * phi_vv, rows [x | y | z] of 3F (forward gathers)
     const float *A, *c;       // filter weights [3F][K], [3F]
     float rc;
     const int8_t *hop;
@@ -17,7 +18,7 @@ struct MsgArgs {
     float *sn, *v1;           // forward outputs (s1 inside [s1 | n] rows of 2F)
     const float *gs1, *gv1;   // adjoint inputs
     float *gv_in, *gphi;      // adjoint outputs
-    float4 *S;                // per-pass edge sums (dE/dr, dE/drhat), slot p at S + p * s_stride
+    float4 *S;                // this layer's edge sums (dE/dr, dE/drhat), pass p at S + p * s_stride
     long s_stride;
 };
 
@@ -25,12 +26,11 @@ struct MsgArgs {
 int msg_forward(hipStream_t st, int precision, int F, int K, const MsgArgs &a);
 int msg_adjoint(hipStream_t st, int precision, int F, int K, const MsgArgs &a);
 
-// Feature passes of the message kernels (edge-sum slots the adjoint needs).
+// Feature passes of the adjoint (edge-sum slots per layer).
 int msg_passes(int F);
-// Over the pruned edges (count rowc[n], at most ne_max): G[e] assembled from
-// the npass slots of S (slot p at S + p * s_stride), and the slots zeroed.
+// G[e] over the pruned edges (count rowc[n], at most ne_max), assembled from
+// the nslot slots of S (slot q at S + q * s_stride; one per layer and pass).
 int msg_assemble_G(hipStream_t st, const int *rowc, int n, long ne_max, const float4 *geom, const float4 *S,
-                   long s_stride, int npass, float4 *G);
-int msg_clear_S(hipStream_t st, const int *rowc, int n, long ne_max, float4 *S, long s_stride, int npass);
+                   long s_stride, int nslot, float4 *G);
 
 }  // namespace mlp

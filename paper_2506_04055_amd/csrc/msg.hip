@@ -35,10 +35,11 @@
 // reverses of the edges (i <- j) that carried j's messages; it gathers the
 // destination gradients and accumulates dE/dphi_j and dE/dv_j.  For every edge
 // it also forms S = (dE/dr, dE/drhat) summed over the pass's features (dE/dr
-// through dw/dr = A' de~/dr, a second MFMA), and adds it to the pass's own
-// slot of a per-edge accumulator, so no two passes write the same memory.  The
-// edge gradient G = dE/d(x_j - x_i) = (dE/dr) rhat + (I - rhat rhat^T) dE/drhat / r
-// is linear in S and is assembled once after the last layer.
+// through dw/dr = A' de~/dr, a second MFMA) and stores it in the slot of its
+// (layer, pass): every slot is written exactly once, so no two launches or
+// passes touch the same memory and nothing is read back.  The edge gradient
+// G = dE/d(x_j - x_i) = (dE/dr) rhat + (I - rhat rhat^T) dE/drhat / r is linear
+// in S and is assembled once after the last layer.
 #include "internal.h"
 #include "msg.h"
 
@@ -171,10 +172,10 @@ struct BOp<2, K> {
     }
 };
 
-// Features per pass and the pass count.
-template <int F>
+// Features per pass (at most WM) and the pass count.
+template <int F, int WM>
 struct Pass {
-    static constexpr int W = F < 32 ? F : 32;   // features per pass
+    static constexpr int W = F < WM ? F : WM;   // features per pass
     static constexpr int N = F / W;             // passes
     static constexpr int TU = W / 16;           // 16-feature tiles per part and pass
 };
@@ -182,20 +183,20 @@ struct Pass {
 // LDS image of the pass's rows of A' = [c | A]: local row q W + f holds the
 // global row q F + p W + f (part q = 0, 1, 2), in the layout the A operand
 // reads (reduction index contiguous).
-template <int P, int F, int K>
+template <int P, int F, int K, int WM>
 struct WStage {
     static constexpr int KP = Basis<P, K>::KP;
-    static constexpr int ROWS = 3 * Pass<F>::W;
+    static constexpr int ROWS = 3 * Pass<F, WM>::W;
     static constexpr int LD = P >= 1 ? KP + 8 : KP + 1;          // padded row stride (elements)
     static constexpr int ELEMS = ROWS * LD * (P == 2 ? 2 : 1);   // split mode: hi table, then lo table
     static constexpr int BYTES = ELEMS * (P >= 1 ? 2 : 4);
 };
 
-template <int P, int F, int K>
+template <int P, int F, int K, int WM>
 __device__ __forceinline__ void stage_pass(const float *__restrict__ A, const float *__restrict__ c, int p,
                                            void *lds) {
-    using WS = WStage<P, F, K>;
-    constexpr int W = Pass<F>::W;
+    using WS = WStage<P, F, K, WM>;
+    constexpr int W = Pass<F, WM>::W;
     for (int idx = threadIdx.x; idx < WS::ROWS * WS::KP; idx += blockDim.x) {
         const int lr = idx / WS::KP, k = idx % WS::KP;
         const int f = (lr / W) * F + p * W + lr % W;
@@ -215,9 +216,9 @@ __device__ __forceinline__ void stage_pass(const float *__restrict__ A, const fl
 
 // Filter values of local tile t (rows 16t .. 16t+15): lane (e, g) receives
 // features 4g .. 4g+3 of the tile for its edge e.
-template <int P, int F, int K>
+template <int P, int F, int K, int WM>
 __device__ __forceinline__ v4f filter_tile(const void *lds, int t, const BOp<P, K> &b, int lane) {
-    using WS = WStage<P, F, K>;
+    using WS = WStage<P, F, K, WM>;
     v4f acc = {0.f, 0.f, 0.f, 0.f};
     const int row = 16 * t + (lane & 15), g = lane >> 4;
     if constexpr (P == 1) {
@@ -271,6 +272,13 @@ __device__ __forceinline__ void st4(float *p, v4f x) { *reinterpret_cast<v4f *>(
 #define MSG_MW 4
 #endif
 constexpr int MW = MSG_MW;   // waves per workgroup
+// features per pass of the forward and the adjoint (16 or 32)
+#ifndef FWD_W
+#define FWD_W 32
+#endif
+#ifndef BWD_W
+#define BWD_W 32
+#endif
 #ifndef FWD_WAVES
 #define FWD_WAVES 3
 #endif
@@ -304,15 +312,17 @@ struct XcdRange {
 template <int P, int F, int K>
 __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FWD_WAVES))) k_msg_fwd(const int *__restrict__ rowc, const int *__restrict__ colc,
                                                      const float4 *__restrict__ geom, int n,
-                                                     const float *__restrict__ phi, const float *__restrict__ s,
-                                                     const float *__restrict__ v, const float *__restrict__ Aw,
+                                                     const float *__restrict__ phi, const float *__restrict__ uvp,
+                                                     const float *__restrict__ s, const float *__restrict__ v,
+                                                     const float *__restrict__ Aw,
                                                      const float *__restrict__ cw, float rc,
                                                      const int8_t *__restrict__ hop, int hop_max,
                                                      float *__restrict__ sn, float *__restrict__ v1) {
-    constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F>::W, TU = Pass<F>::TU;
-    __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K>::BYTES];
+    constexpr int WM = FWD_W;
+    constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F, WM>::W, TU = Pass<F, WM>::TU;
+    __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K, WM>::BYTES];
     const int p = blockIdx.y;
-    stage_pass<P, F, K>(Aw, cw, p, lds);
+    stage_pass<P, F, K, WM>(Aw, cw, p, lds);
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
     const int fo = p * W + 4 * g;   // first feature of this lane (tile u adds 16 u)
     const XcdRange xr(n);
@@ -327,25 +337,35 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
 #pragma unroll
             for (int d = 0; d < 3; d++) av[d][u] = v4f{0.f, 0.f, 0.f, 0.f};
         }
+        // edge records of the next chunk are loaded one chunk ahead
+        float4 gm_n = make_float4(0.f, 0.f, 0.f, rc);
+        int j_n = i;
+        if (e < deg) {
+            gm_n = geom[e0 + e];
+            j_n = colc[e0 + e];
+        }
         for (int cb = 0; cb < deg; cb += 16) {
             const char *wl = lds_chunk(lds);
             const bool valid = cb + e < deg;
-            float4 gm = make_float4(0.f, 0.f, 0.f, rc);
-            int j = i;
-            if (valid) {
-                gm = geom[e0 + cb + e];
-                j = colc[e0 + cb + e];
+            const float4 gm = gm_n;
+            const int j = j_n;
+            gm_n = make_float4(0.f, 0.f, 0.f, rc);
+            j_n = i;
+            if (cb + 16 + e < deg) {
+                gm_n = geom[e0 + cb + 16 + e];
+                j_n = colc[e0 + cb + 16 + e];
             }
+            // gathered: phi_s, phi_vs and u = v * phi_vv of the source (5 row slices)
             const float *pj = phi + (long)j * F3 + fo;
-            const float *vj = v + (long)j * F3 + fo;
-            v4f ph[3][TU], vv[3][TU];
+            const float *uj = uvp + (long)j * F3 + fo;
+            v4f ph[2][TU], uu[3][TU];
 #pragma unroll
-            for (int q = 0; q < 3; q++)
+            for (int u = 0; u < TU; u++) {
+                ph[0][u] = ld4(pj + F + 16 * u);
+                ph[1][u] = ld4(pj + 2 * F + 16 * u);
 #pragma unroll
-                for (int u = 0; u < TU; u++) {
-                    ph[q][u] = ld4(pj + q * F + 16 * u);
-                    vv[q][u] = ld4(vj + q * F + 16 * u);
-                }
+                for (int d = 0; d < 3; d++) uu[d][u] = ld4(uj + d * F + 16 * u);
+            }
             const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
             float eb[SL];
             basis_slots<P, K, false>(gm.w, ir, pirc, valid, g, eb, nullptr);
@@ -354,16 +374,16 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
             const float rx = gm.x * ir, ry = gm.y * ir, rz = gm.z * ir;
 #pragma unroll
             for (int u = 0; u < TU; u++) {
-                const v4f wvv = filter_tile<P, F, K>(wl, u, bop, lane);
-                const v4f ws = filter_tile<P, F, K>(wl, TU + u, bop, lane);
-                const v4f wvs = filter_tile<P, F, K>(wl, 2 * TU + u, bop, lane);
+                const v4f wvv = filter_tile<P, F, K, WM>(wl, u, bop, lane);
+                const v4f ws = filter_tile<P, F, K, WM>(wl, TU + u, bop, lane);
+                const v4f wvs = filter_tile<P, F, K, WM>(wl, 2 * TU + u, bop, lane);
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const float xvv = ph[0][u][r] * wvv[r], xvs = ph[2][u][r] * wvs[r];
-                    as[u][r] = fmaf(ph[1][u][r], ws[r], as[u][r]);
-                    av[0][u][r] = fmaf(vv[0][u][r], xvv, fmaf(rx, xvs, av[0][u][r]));
-                    av[1][u][r] = fmaf(vv[1][u][r], xvv, fmaf(ry, xvs, av[1][u][r]));
-                    av[2][u][r] = fmaf(vv[2][u][r], xvv, fmaf(rz, xvs, av[2][u][r]));
+                    const float xvs = ph[1][u][r] * wvs[r];
+                    as[u][r] = fmaf(ph[0][u][r], ws[r], as[u][r]);
+                    av[0][u][r] = fmaf(uu[0][u][r], wvv[r], fmaf(rx, xvs, av[0][u][r]));
+                    av[1][u][r] = fmaf(uu[1][u][r], wvv[r], fmaf(ry, xvs, av[1][u][r]));
+                    av[2][u][r] = fmaf(uu[2][u][r], wvv[r], fmaf(rz, xvs, av[2][u][r]));
                 }
             }
         }
@@ -394,7 +414,7 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
 // Per chunk of 16 in-edges (j <- i) of the source atom j: the filter tiles and
 // their radial derivatives on MFMA, the destinations' gradient pieces
 // gathered per lane, dE/dphi_j and dE/dv_j accumulated in registers, and the
-// edge sums S = (dE/dr, dE/drhat) of the pass added to the pass's slot.
+// edge sums S = (dE/dr, dE/drhat) of the pass stored in the pass's slot.
 // ---------------------------------------------------------------------------
 template <int P, int F, int K>
 __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BWD_WAVES))) k_msg_bwd(const int *__restrict__ rowc, const int *__restrict__ colc,
@@ -405,10 +425,11 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BW
                                                      float rc, const int8_t *__restrict__ hop, int hop_max,
                                                      float *__restrict__ gv_in, float *__restrict__ gphi,
                                                      float4 *__restrict__ S, long s_stride) {
-    constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F>::W, TU = Pass<F>::TU;
-    __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K>::BYTES];
+    constexpr int WM = BWD_W;
+    constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F, WM>::W, TU = Pass<F, WM>::TU;
+    __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K, WM>::BYTES];
     const int p = blockIdx.y;
-    stage_pass<P, F, K>(Aw, cw, p, lds);
+    stage_pass<P, F, K, WM>(Aw, cw, p, lds);
     float4 *Sp = S + (long)p * s_stride;
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
     const int fo = p * W + 4 * g;
@@ -427,14 +448,25 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BW
                 agp[q][u] = v4f{0.f, 0.f, 0.f, 0.f};
                 agv[q][u] = v4f{0.f, 0.f, 0.f, 0.f};
             }
+        // edges of an atom beyond the hop range carry no gradient in this layer
+        if (hop[j] > hop_max)
+            for (int q = e0 + lane; q < e1; q += 64) Sp[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 gm_n = make_float4(0.f, 0.f, 0.f, rc);
+        int i_n = j;
+        if (e < deg) {
+            gm_n = geom[e0 + e];
+            i_n = colc[e0 + e];
+        }
         for (int cb = 0; cb < deg; cb += 16) {
             const char *wl = lds_chunk(lds);
             const bool valid = cb + e < deg;
-            float4 gm = make_float4(0.f, 0.f, 0.f, rc);
-            int i = j;
-            if (valid) {
-                gm = geom[e0 + cb + e];
-                i = colc[e0 + cb + e];
+            const float4 gm = gm_n;
+            const int i = i_n;
+            gm_n = make_float4(0.f, 0.f, 0.f, rc);
+            i_n = j;
+            if (cb + 16 + e < deg) {
+                gm_n = geom[e0 + cb + 16 + e];
+                i_n = colc[e0 + cb + 16 + e];
             }
             v4f gs[TU], gv[3][TU];
 #pragma unroll
@@ -454,12 +486,12 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BW
             float sr = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
 #pragma unroll
             for (int u = 0; u < TU; u++) {
-                const v4f w0 = filter_tile<P, F, K>(wl, u, bop, lane);
-                const v4f w1 = filter_tile<P, F, K>(wl, TU + u, bop, lane);
-                const v4f w2 = filter_tile<P, F, K>(wl, 2 * TU + u, bop, lane);
-                const v4f d0 = filter_tile<P, F, K>(wl, u, dop, lane);
-                const v4f d1 = filter_tile<P, F, K>(wl, TU + u, dop, lane);
-                const v4f d2 = filter_tile<P, F, K>(wl, 2 * TU + u, dop, lane);
+                const v4f w0 = filter_tile<P, F, K, WM>(wl, u, bop, lane);
+                const v4f w1 = filter_tile<P, F, K, WM>(wl, TU + u, bop, lane);
+                const v4f w2 = filter_tile<P, F, K, WM>(wl, 2 * TU + u, bop, lane);
+                const v4f d0 = filter_tile<P, F, K, WM>(wl, u, dop, lane);
+                const v4f d1 = filter_tile<P, F, K, WM>(wl, TU + u, dop, lane);
+                const v4f d2 = filter_tile<P, F, K, WM>(wl, 2 * TU + u, dop, lane);
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     const float ga = gv[0][u][r], gb = gv[1][u][r], gc = gv[2][u][r], gsr = gs[u][r];
@@ -488,14 +520,7 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BW
             sx += __shfl_xor(sx, 32, 64);
             sy += __shfl_xor(sy, 32, 64);
             sz += __shfl_xor(sz, 32, 64);
-            if (g == 0 && valid) {
-                float4 a = Sp[e0 + cb + e];
-                a.x += sr;
-                a.y += sx;
-                a.z += sy;
-                a.w += sz;
-                Sp[e0 + cb + e] = a;
-            }
+            if (g == 0 && valid) Sp[e0 + cb + e] = make_float4(sr, sx, sy, sz);
         }
         // sum over the 16 edge lanes of each row
 #pragma unroll
@@ -544,13 +569,6 @@ __global__ void k_assemble_G(const int *__restrict__ rowc, int n, const float4 *
     }
 }
 
-// Zero the npass slots over the pruned edges (count rowc[n], read on the device).
-__global__ void k_clear_S(const int *__restrict__ rowc, int n, float4 *__restrict__ S, long s_stride, int npass) {
-    const long ne = rowc[n];
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (long)gridDim.x * blockDim.x)
-        for (int p = 0; p < npass; p++) S[(long)p * s_stride + e] = make_float4(0.f, 0.f, 0.f, 0.f);
-}
-
 static int grid_x(int n) {
     int b = std::min((n + MW - 1) / MW, 2048);
     if (b >= 8) b -= b % 8;   // keeps blockIdx.x % 8 the XCD in every pass row
@@ -559,32 +577,27 @@ static int grid_x(int n) {
 
 template <int P, int F, int K>
 static int launch_fwd(hipStream_t st, const MsgArgs &a) {
-    dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F>::N);
-    k_msg_fwd<P, F, K><<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.s, a.v, a.A, a.c, a.rc,
+    dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F, FWD_W>::N);
+    k_msg_fwd<P, F, K><<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.u, a.s, a.v, a.A, a.c, a.rc,
                                                  a.hop, a.hop_max, a.sn, a.v1);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
 template <int P, int F, int K>
 static int launch_bwd(hipStream_t st, const MsgArgs &a) {
-    dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F>::N);
+    dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F, BWD_W>::N);
     k_msg_bwd<P, F, K><<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.v, a.gs1, a.gv1, a.A, a.c,
                                                  a.rc, a.hop, a.hop_max, a.gv_in, a.gphi, a.S, a.s_stride);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
-int msg_passes(int F) { return F < 32 ? 1 : F / 32; }
+int msg_passes(int F) { return F < BWD_W ? 1 : F / BWD_W; }
 
 static unsigned edge_blocks(long ne_max) { return (unsigned)std::max(1L, std::min((ne_max + 255) / 256, 8192L)); }
 
 int msg_assemble_G(hipStream_t st, const int *rowc, int n, long ne_max, const float4 *geom, const float4 *S,
                    long s_stride, int npass, float4 *G) {
     k_assemble_G<<<edge_blocks(ne_max), 256, 0, st>>>(rowc, n, geom, S, s_stride, npass, G);
-    return hipGetLastError() == hipSuccess ? 0 : -5;
-}
-
-int msg_clear_S(hipStream_t st, const int *rowc, int n, long ne_max, float4 *S, long s_stride, int npass) {
-    k_clear_S<<<edge_blocks(ne_max), 256, 0, st>>>(rowc, n, S, s_stride, npass);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 

@@ -415,11 +415,12 @@ __global__ void __launch_bounds__(256) k_prune(const float4 *__restrict__ p4, co
     if (!FILL && lane == 0) cnt[i] = c;
 }
 
+// One thread per pruned edge (count rowc[n], read on the device).
 __global__ void k_prune_rev(const int *__restrict__ rowc, int n, const int *__restrict__ oldidx,
                             const int *__restrict__ rev, const int *__restrict__ map, int *__restrict__ revc) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int e = rowc[i]; e < rowc[i + 1]; e++) revc[e] = map[rev[oldidx[e]]];
+    const long ne = rowc[n];
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (long)gridDim.x * blockDim.x)
+        revc[e] = map[rev[oldidx[e]]];
 }
 
 // ---------------------------------------------------------------------------
@@ -444,8 +445,13 @@ __global__ void k_hop_round(const int *__restrict__ rowc, const int *__restrict_
 }
 
 __global__ void k_hop_hist(const int8_t *__restrict__ hop, int n, int *__restrict__ hist) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicAdd(&hist[hop[i]], 1);
+    // per-workgroup counts in LDS, then one global add per bin and workgroup
+    __shared__ int h[MLP_MAX_LAYERS + 2];
+    if (threadIdx.x < MLP_MAX_LAYERS + 2) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) atomicAdd(&h[hop[i]], 1);
+    __syncthreads();
+    if (threadIdx.x < MLP_MAX_LAYERS + 2 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -665,8 +671,8 @@ int prune_graph(mlp_model *m, mlp_nbr *g, const float *pos, hipStream_t s) {
                                             g->box[0], g->box[1], g->box[2], rc2, nullptr, g->rowc.as<int>(),
                                             g->colc.as<int>(), g->geom.as<float4>(), g->map.as<int>(),
                                             g->oldidx.as<int>());
-    k_prune_rev<<<nblk(n, 128), 128, 0, s>>>(g->rowc.as<int>(), n, g->oldidx.as<int>(), g->rev.as<int>(),
-                                             g->map.as<int>(), g->revc.as<int>());
+    k_prune_rev<<<(int)std::max<int64_t>(1, std::min<int64_t>((g->n_edges_skin + 255) / 256, 8192)), 256, 0, s>>>(
+        g->rowc.as<int>(), n, g->oldidx.as<int>(), g->rev.as<int>(), g->map.as<int>(), g->revc.as<int>());
     HIP_TRY(hipGetLastError());
     return 0;
 }
@@ -685,7 +691,8 @@ int compute_hops(mlp_model *m, mlp_nbr *g, hipStream_t s) {
 int hop_histogram(mlp_model *m, mlp_nbr *g, hipStream_t s, int *hist_host /* T+2 */) {
     int *flag = g->flags.as<int>();
     HIP_TRY(hipMemsetAsync(flag + 16, 0, sizeof(int) * 16, s));
-    k_hop_hist<<<nblk(g->n_atoms, 256), 256, 0, s>>>(g->hop.as<int8_t>(), g->n_atoms, flag + 16);
+    k_hop_hist<<<std::max(1, std::min(nblk(g->n_atoms, 256), 1024)), 256, 0, s>>>(g->hop.as<int8_t>(), g->n_atoms,
+                                                                                  flag + 16);
     HIP_TRY(hipMemcpyAsync(hist_host, flag + 16, sizeof(int) * (m->T + 2), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return 0;

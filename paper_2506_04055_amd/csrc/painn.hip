@@ -64,6 +64,20 @@ __global__ void k_embed(const int *__restrict__ species, const float *__restrict
     v[i * 3 * F + 2 * F + f] = 0.f;
 }
 
+// u[i][d][f] = v[i][d][f] phi[i][f] (phi_vv), four features per thread.
+__global__ void k_vprod(const float *__restrict__ v, const float *__restrict__ phi, int n, int F,
+                        float *__restrict__ u) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * F / 4) return;
+    const long i = idx / (F / 4);
+    const int f = 4 * (int)(idx % (F / 4));
+    const float4 p = *reinterpret_cast<const float4 *>(phi + i * 3 * F + f);
+    for (int d = 0; d < 3; d++) {
+        const float4 x = *reinterpret_cast<const float4 *>(v + i * 3 * F + d * F + f);
+        *reinterpret_cast<float4 *>(u + i * 3 * F + d * F + f) = make_float4(x.x * p.x, x.y * p.y, x.z * p.z, x.w * p.w);
+    }
+}
+
 __global__ void k_norm(const float *__restrict__ Vv, int n, int F, float eps, float *__restrict__ sn) {
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n * F) return;
@@ -150,7 +164,7 @@ __global__ void k_readout(const float *__restrict__ h5, int n, int Fh, const flo
     U[i] = u;
 }
 
-constexpr int ERED = 256;
+constexpr int ERED = 1024;
 
 // E_b = sum of U_i over the local atoms of segment b (internal rows
 // [seg[b], seg[b+1]), or [0, n) without segments), in FP64 with a fixed
@@ -163,10 +177,16 @@ __global__ void __launch_bounds__(ERED) k_energy_seg(const float *__restrict__ U
     __shared__ double sh[ERED];
     const int b = blockIdx.x;
     const int a = seg ? seg[b] : 0, e = seg ? seg[b + 1] : n;
-    double acc = 0.0;
-    for (int i = a + threadIdx.x; i < e; i += ERED)
-        if (perm[i] < n_local) acc += (double)U[i];
-    sh[threadIdx.x] = acc;
+    // four interleaved partial sums per thread keep four loads in flight
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i0 = a + threadIdx.x; i0 < e; i0 += 4 * ERED) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int i = i0 + q * ERED;
+            if (i < e && perm[i] < n_local) acc[q] += (double)U[i];
+        }
+    }
+    sh[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     __syncthreads();
     for (int off = ERED / 2; off > 0; off >>= 1) {
         if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
@@ -182,24 +202,42 @@ __global__ void k_fill(float *__restrict__ p, long n, float val) {
 
 // F_k = sum over in-edges e of (G at rev(e)) - (G at e), scattered to the
 // caller's atom order (SoA).
+// Sixteen lanes per atom (one DPP row): lane q takes the atom's edges
+// q, q + 16, ..., and the row sum gives the force.
+__device__ __forceinline__ float row16_sum(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));   // row_ror:8
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xF, 0xF, false));   // row_ror:4
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));    // quad [2,3,0,1]
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));    // quad [1,0,3,2]
+    return x;
+}
+
 __global__ void k_forces(const int *__restrict__ rowc, const int *__restrict__ revc,
                          const float4 *__restrict__ Gout, const int *__restrict__ perm, int n,
                          float *__restrict__ F) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = (int)(t >> 4), q = (int)(t & 15);
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    for (int e = rowc[k]; e < rowc[k + 1]; e++) {
-        const int re = revc[e];
-        if (re < 0) continue;  // cannot happen for a symmetric graph; never index with it
-        float4 a = Gout[re], b = Gout[e];
-        fx += a.x - b.x;
-        fy += a.y - b.y;
-        fz += a.z - b.z;
+    if (k < n) {
+        for (int e = rowc[k] + q; e < rowc[k + 1]; e += 16) {
+            const int re = revc[e];
+            if (re < 0) continue;  // cannot happen for a symmetric graph; never index with it
+            const float4 a = Gout[re], b = Gout[e];
+            fx += a.x - b.x;
+            fy += a.y - b.y;
+            fz += a.z - b.z;
+        }
     }
-    int u = perm[k];
-    F[u] = fx;
-    F[(long)n + u] = fy;
-    F[2 * (long)n + u] = fz;
+    // every lane of the wave takes part in the row sums (n need not fill the grid)
+    fx = row16_sum(fx);
+    fy = row16_sum(fy);
+    fz = row16_sum(fz);
+    if (k < n && q == 0) {
+        const int u = perm[k];
+        F[u] = fx;
+        F[(long)n + u] = fy;
+        F[2 * (long)n + u] = fz;
+    }
 }
 
 __global__ void k_scatter_energy(const float *__restrict__ U, const int *__restrict__ perm, int n,
@@ -216,6 +254,7 @@ struct Act {
     float *h1[MLP_MAX_LAYERS], *phi[MLP_MAX_LAYERS], *sn[MLP_MAX_LAYERS], *v1[MLP_MAX_LAYERS],
         *Uv[MLP_MAX_LAYERS], *Vv[MLP_MAX_LAYERS], *h3[MLP_MAX_LAYERS], *a[MLP_MAX_LAYERS];
     float *gs, *gv, *gs1, *gv1, *gphi, *ga, *gh3, *gsn, *gUv, *gVv, *ga1, *tmpF, *h5, *g5, *U;
+    float *u;   // v * phi_vv of the current forward layer (shares gUv: the adjoint starts after the forward)
     double *epart;
 };
 
@@ -257,6 +296,7 @@ static void carve(float *base, long N, int F, int T, Act &A) {
     A.gsn = take(2 * NF);
     A.gUv = take(3 * NF);
     A.gVv = take(3 * NF);
+    A.u = A.gUv;
     A.ga1 = take(NF);
     A.tmpF = take(NF);
     A.h5 = take(NF / 2 + 64);
@@ -295,7 +335,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     const int npass = msg_passes(F);
     const long ne = g->n_edges_skin;
     if ((rc = g->G.ensure(sizeof(float4) * (size_t)ne + 64, 1.2, Gr))) return rc;
-    if ((rc = g->Gs.ensure(sizeof(float4) * (size_t)ne * npass + 64, 1.2, Gr))) return rc;
+    if ((rc = g->Gs.ensure(sizeof(float4) * (size_t)ne * npass * T + 64, 1.2, Gr))) return rc;
     Act A;
     carve(g->act.as<float>(), n, F, T, A);
     const int *perm = g->perm.as<int>();
@@ -307,9 +347,12 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         const int hop_dst = T - 1 - t;
         gemm<E_BIAS_SILU>(s, P, A.s[t], F, m->pk[t][WP_W1], A.h1[t], F, n, L.b1, A.tmpF, F);
         gemm<E_BIAS>(s, P, A.tmpF, F, m->pk[t][WP_W2], A.phi[t], F3, n, L.b2);
+        // u = v * phi_vv: the rows the message pass gathers together with phi_s and phi_vs
+        k_vprod<<<nblk((long)n * F / 4, 256), 256, 0, s>>>(A.v[t], A.phi[t], n, F, A.u);
         {
             MsgArgs ma = msg_args(g, m, L, hop_dst);
             ma.phi = A.phi[t];
+            ma.u = A.u;
             ma.s = A.s[t];
             ma.v = A.v[t];
             ma.sn = A.sn[t];
@@ -336,8 +379,6 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     // adjoint
     gemm<E_STORE>(s, P, A.g5, Fh, m->pk_W5t, A.gs, F, n);
     k_fill<<<nblk((long)n * F3, 256), 256, 0, s>>>(A.gv, (long)n * F3, 0.f);
-    if ((rc = msg_clear_S(s, g->rowc.as<int>(), n, ne, g->Gs.as<float4>(), ne, npass)))
-        return fail(rc, "edge-sum clear kernel launch failed");
     for (int t = T - 1; t >= 0; t--) {
         LayerW L = m->layer(t);
         const int hop_src = T - t;
@@ -356,17 +397,18 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             ma.gv1 = A.gv1;
             ma.gv_in = A.gv;
             ma.gphi = A.gphi;
+            ma.S = g->Gs.as<float4>() + (size_t)t * npass * ne;
             ProfScope ps(PK_MSG_BWD, s);
             if ((rc = msg_adjoint(s, PF, F, K, ma))) return fail(rc, "adjoint message kernel launch failed");
         }
         gemm<E_DSILU>(s, P, A.gphi, F3, m->pk[t][WP_W2T], A.ga1, F, n, nullptr, nullptr, 0, A.h1[t], F);
         gemm<E_ADD>(s, P, A.ga1, F, m->pk[t][WP_W1T], A.gs, F, n, nullptr, nullptr, 0, A.gs1, F);
     }
-    if ((rc = msg_assemble_G(s, g->rowc.as<int>(), n, ne, g->geom.as<float4>(), g->Gs.as<float4>(), ne, npass,
+    if ((rc = msg_assemble_G(s, g->rowc.as<int>(), n, ne, g->geom.as<float4>(), g->Gs.as<float4>(), ne, npass * T,
                              g->G.as<float4>())))
         return fail(rc, "edge-gradient kernel launch failed");
-    k_forces<<<nblk(n, 256), 256, 0, s>>>(g->rowc.as<int>(), g->revc.as<int>(), g->G.as<float4>(), perm, n,
-                                          forces_user);
+    k_forces<<<nblk(16L * n, 256), 256, 0, s>>>(g->rowc.as<int>(), g->revc.as<int>(), g->G.as<float4>(), perm, n,
+                                                forces_user);
     HIP_TRY(hipGetLastError());
     return 0;
 }
