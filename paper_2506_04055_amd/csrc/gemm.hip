@@ -99,9 +99,12 @@ int pack_weight(hipStream_t s, const float *W, int R, int C, bool transpose, voi
 constexpr int KC = 128;
 constexpr int LDH = KC + 8;   // bf16 elements per LDS row
 constexpr int LDF = KC + 4;   // floats per LDS row
+constexpr int LDC = NCH + 4;  // floats per row of the output tile parked in LDS
 template <int P>
 struct GemmLds {
-    static constexpr int BYTES = P == 0 ? NCH * LDF * 4 : NCH * LDH * 2 * (P == 2 ? 2 : 1);
+    static constexpr int B_BYTES = P == 0 ? NCH * LDF * 4 : NCH * LDH * 2 * (P == 2 ? 2 : 1);
+    static constexpr int C_BYTES = GW * 16 * LDC * 4;
+    static constexpr int BYTES = B_BYTES > C_BYTES ? B_BYTES : C_BYTES;
 };
 
 template <int P, int EPI>
@@ -196,32 +199,47 @@ __global__ void __launch_bounds__(64 * GW) k_gemm(const float *__restrict__ A, i
                 }
             }
         }
-        // epilogue: lane holds rows m0 + 4g + r of column n0 + 16t + c16
+        // Epilogue through LDS: each wave parks its 16 x 128 tile in LDS in the
+        // accumulator layout and reads it back by rows, so C (and R, C2) move
+        // as whole rows in 16-byte vectors (two 512-byte rows per instruction).
+        __syncthreads();   // every wave is done with the B chunk in LDS
+        float *ct = reinterpret_cast<float *>(lds) + (threadIdx.x >> 6) * 16 * LDC;
 #pragma unroll
-        for (int t = 0; t < CT; t++) {
-            const int n = n0 + 16 * t + c16;
-            if (n >= B.N) continue;
+        for (int t = 0; t < CT; t++)
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const long m = m0 + 4 * g + r;
-                if (m >= M) continue;
-                const float x = acc[t][r];
-                if (EPI == GE_STORE) {
-                    C[m * ldc + n] = x;
-                } else if (EPI == GE_BIAS) {
-                    C[m * ldc + n] = x + bias[n];
-                } else if (EPI == GE_BIAS_SILU) {
-                    const float h = x + bias[n];
-                    C[m * ldc + n] = h;
-                    C2[m * ldc2 + n] = h * g_sigmoid(h);
-                } else if (EPI == GE_DSILU) {
-                    const float h = R[m * ldr + n];
-                    const float sg = g_sigmoid(h);
-                    C[m * ldc + n] = x * (sg * (1.0f + h * (1.0f - sg)));
-                } else {
-                    C[m * ldc + n] = R[m * ldr + n] + x;
+            for (int r = 0; r < 4; r++) ct[(4 * g + r) * LDC + 16 * t + c16] = acc[t][r];
+        __syncthreads();
+        const int ncols = min(NCH, B.N - n0);   // a multiple of 4
+#pragma unroll
+        for (int it = 0; it < 16 * NCH / 4 / 64; it++) {
+            const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
+            const long m = m0 + row;
+            if (m >= M || c4 >= ncols) continue;
+            const int n = n0 + c4;
+            const v4f x = *reinterpret_cast<const v4f *>(ct + row * LDC + c4);
+            v4f o;
+            if (EPI == GE_STORE) {
+                o = x;
+            } else if (EPI == GE_BIAS || EPI == GE_BIAS_SILU) {
+#pragma unroll
+                for (int q = 0; q < 4; q++) o[q] = x[q] + bias[n + q];
+                if (EPI == GE_BIAS_SILU) {
+                    v4f sl;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) sl[q] = o[q] * g_sigmoid(o[q]);
+                    *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = sl;
                 }
+            } else if (EPI == GE_DSILU) {
+                const v4f h = gld4(R + m * ldr + n);
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const float sg = g_sigmoid(h[q]);
+                    o[q] = x[q] * (sg * (1.0f + h[q] * (1.0f - sg)));
+                }
+            } else {
+                o = gld4(R + m * ldr + n) + x;
             }
+            *reinterpret_cast<v4f *>(C + m * ldc + n) = o;
         }
     }
 }
