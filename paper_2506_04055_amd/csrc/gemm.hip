@@ -96,7 +96,10 @@ int pack_weight(hipStream_t s, const float *W, int R, int C, bool transpose, voi
 
 // LDS image of one (128-column x KC) chunk of B: bf16 hi rows then lo rows
 // (P >= 1), or FP32 rows (P = 0); rows padded to spread the banks.
-constexpr int KC = 128;
+#ifndef GEMM_KC
+#define GEMM_KC 64
+#endif
+constexpr int KC = GEMM_KC;
 constexpr int LDH = KC + 8;   // bf16 elements per LDS row
 constexpr int LDF = KC + 4;   // floats per LDS row
 constexpr int LDC = NCH + 4;  // floats per row of the output tile parked in LDS
