@@ -58,6 +58,7 @@ enum { MLP_FP32 = 0, MLP_BF16 = 1, MLP_BF16_FAST = 2 };
 typedef struct mlp_model mlp_model;
 typedef struct mlp_nbr mlp_nbr;
 typedef struct mlp_server mlp_server;
+typedef struct mlp_nvt mlp_nvt;
 
 /* Statistics of one evaluation (the library "returns statistics of the
  * computation", Results, "Runtime optimizations and buffering"). */
@@ -182,6 +183,40 @@ int mlp_energy_forces(mlp_model *model, mlp_nbr *nbr, const float *pos, int32_t 
 int mlp_md_step(mlp_model *model, mlp_nbr *nbr, float *pos, float *vel, float *forces,
                 const float *inv_mass, const int32_t *species, int32_t n, const double box[3],
                 float skin, float dt, void *stream, double *energy, int32_t *rebuilt);
+
+/* ---------------------------------------------------------------------------
+ * NVT thermostat (Methods, "Molecular Dynamics Simulations": the production
+ * and timing runs are NVT with a Nose-Hoover thermostat of a given damping
+ * time).  A chain of `chain` Nose-Hoover thermostats with masses
+ * Q_1 = n_dof kB T tau^2 and Q_k = kB T tau^2 (k > 1), positions and
+ * velocities starting at zero, state kept in FP64 on the device.
+ * mlp_nvt_create: n_dof >= 1 (3N - 3 when the centre-of-mass momentum is
+ *   removed), temperature in K (> 0), tau in fs (> 0), 1 <= chain <= 8.
+ *   Allocates device memory; synchronous.  Errors: INVALID_ARG, OOM, DEVICE.
+ * mlp_nvt_destroy: frees the handle (NULL is accepted).
+ * mlp_nvt_read: host copies of the chain positions xi[chain] and velocities
+ *   vxi[chain] (1/fs) (each may be NULL), the thermostat energy
+ *   sum_k Q_k vxi_k^2 / 2 + n_dof kB T xi_1 + kB T sum_{k>1} xi_k (eV) and
+ *   the kinetic energy (eV) after the last step.  The extended energy
+ *   kinetic + potential + thermostat energy is the step's conserved quantity.
+ *   Synchronises the stream.  Errors: INVALID_ARG, DEVICE.
+ * ------------------------------------------------------------------------- */
+int mlp_nvt_create(int32_t n_dof, double temperature, double tau_fs, int32_t chain, mlp_nvt **out);
+int mlp_nvt_destroy(mlp_nvt *nvt);
+int mlp_nvt_read(mlp_nvt *nvt, double *xi, double *vxi, double *thermostat_energy, double *kinetic,
+                 void *stream);
+
+/* ---------------------------------------------------------------------------
+ * mlp_md_step_nvt — one NVT step: the thermostat chain propagated over dt/2
+ * (velocities scaled on the device), the mlp_md_step velocity-Verlet step
+ * (same arguments, same rebuild rule, same single synchronisation), and the
+ * chain propagated over dt/2 again.  inv_mass must be the same array the
+ * kinetic energy is meant for (m = 1 / inv_mass, amu).
+ * Errors: those of mlp_md_step, and INVALID_ARG for a NULL thermostat.
+ * ------------------------------------------------------------------------- */
+int mlp_md_step_nvt(mlp_model *model, mlp_nbr *nbr, mlp_nvt *nvt, float *pos, float *vel, float *forces,
+                    const float *inv_mass, const int32_t *species, int32_t n, const double box[3], float skin,
+                    float dt, void *stream, double *energy, int32_t *rebuilt);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing (tracing aid; the library's "statistics of the computation").

@@ -154,3 +154,97 @@ def velocity_verlet(header, weights, pos, vel, species, masses, box, dt: float, 
         v += 0.5 * dt * F * inv_m
         Es.append(E)
     return x, v, np.array(Es)
+
+
+KB_EV = 8.617333262e-5     # Boltzmann constant, eV / K
+MVV2E = 1.0 / ACC_UNIT     # amu Angstrom^2 / fs^2 -> eV
+
+
+def nhc_half_step(state: dict, ke: float, h: float) -> tuple[float, float]:
+    """Propagate a Nose-Hoover chain over a time h (the thermostat part of the
+    NVT splitting; the paper's runs are NVT with a Nose-Hoover thermostat,
+    Methods, "Molecular Dynamics Simulations").  The chain equations are
+        d xi_k / dt = v_k,
+        d v_1 / dt = (2 KE - N_f kT) / Q_1 - v_1 v_2,
+        d v_k / dt = (Q_{k-1} v_{k-1}^2 - kT) / Q_k - v_k v_{k+1},  (last: no v_{k+1} term)
+    and the particle velocities are scaled by exp(-int v_1 dt).  The update is
+    the symmetric Trotter splitting of these flows: chain kicks from the last
+    thermostat to the first, each damped by its successor over half the kick
+    interval on both sides; one scaling of the particles and one drift of
+    every xi over h; the same kicks from the first thermostat to the last.
+    state: {"Q": array, "v": array, "xi": array, "nf": float, "kT": float};
+    updated in place.  Returns (velocity scale factor, kinetic energy after
+    scaling)."""
+    Q, v, xi, nf, kT = state["Q"], state["v"], state["xi"], state["nf"], state["kT"]
+    M = len(Q)
+
+    def g(k, ke_now):
+        if k == 0:
+            return (2.0 * ke_now - nf * kT) / Q[0]
+        return (Q[k - 1] * v[k - 1] ** 2 - kT) / Q[k]
+
+    quarter = h / 4.0
+    v[M - 1] += (h / 2.0) * g(M - 1, ke)
+    for k in range(M - 2, -1, -1):
+        damp = np.exp(-quarter * v[k + 1])
+        v[k] *= damp
+        v[k] += (h / 2.0) * g(k, ke)
+        v[k] *= damp
+    scale = np.exp(-h * v[0])
+    ke = ke * scale * scale
+    xi += h * v
+    for k in range(M - 1):
+        damp = np.exp(-quarter * v[k + 1])
+        v[k] *= damp
+        v[k] += (h / 2.0) * g(k, ke)
+        v[k] *= damp
+    v[M - 1] += (h / 2.0) * g(M - 1, ke)
+    return float(scale), float(ke)
+
+
+def nhc_state(n_dof: int, temperature: float, tau_fs: float, chain: int) -> dict:
+    """Chain of `chain` thermostats at rest, Q_1 = N_f kT tau^2, Q_k = kT tau^2."""
+    kT = KB_EV * temperature
+    Q = np.array([(n_dof if k == 0 else 1.0) * kT * tau_fs ** 2 for k in range(chain)], np.float64)
+    return {"Q": Q, "v": np.zeros(chain), "xi": np.zeros(chain), "nf": float(n_dof), "kT": kT}
+
+
+def thermostat_energy(state: dict) -> float:
+    """sum_k Q_k v_k^2 / 2 + N_f kT xi_1 + kT sum_{k>1} xi_k."""
+    Q, v, xi = state["Q"], state["v"], state["xi"]
+    return float(0.5 * np.sum(Q * v * v) + state["nf"] * state["kT"] * xi[0] + state["kT"] * np.sum(xi[1:]))
+
+
+def kinetic_energy(vel, species, masses) -> float:
+    m = np.asarray(masses, np.float64)[np.asarray(species)]
+    return float(0.5 * MVV2E * np.sum(m[:, None] * np.asarray(vel, np.float64) ** 2))
+
+
+def nhc_velocity_verlet(header, weights, pos, vel, species, masses, box, dt: float, n_steps: int, state: dict,
+                        force_fn=None):
+    """NVT steps in FP64: chain over dt/2, velocity Verlet, chain over dt/2.
+    force_fn(x) -> (E, F) replaces the PaiNN oracle when given.  Returns
+    (pos, vel, potential energies, kinetic energies, thermostat energies)."""
+    x = np.array(pos, np.float64)
+    v = np.array(vel, np.float64)
+    m = np.asarray(masses, np.float64)[np.asarray(species)]
+    inv_m = (ACC_UNIT / m)[:, None]
+    ef = force_fn or (lambda y: energy_forces(header, weights, y, species, box))
+    E, F = ef(x)
+    Es, Ks, Hs = [], [], []
+    for _ in range(n_steps):
+        s, _ = nhc_half_step(state, kinetic_energy(v, species, masses), 0.5 * dt)
+        v *= s
+        v += 0.5 * dt * F * inv_m
+        x += dt * v
+        for d in range(3):
+            if box[d] > 0:
+                x[:, d] = np.mod(x[:, d], box[d])
+        E, F = ef(x)
+        v += 0.5 * dt * F * inv_m
+        s, ke = nhc_half_step(state, kinetic_energy(v, species, masses), 0.5 * dt)
+        v *= s
+        Es.append(E)
+        Ks.append(ke)
+        Hs.append(thermostat_energy(state))
+    return x, v, np.array(Es), np.array(Ks), np.array(Hs)

@@ -78,6 +78,11 @@ def lib():
     L.mlp_energy_forces.argtypes = [P, P, P, I32, I32, P, P, P, P, P, ctypes.POINTER(Stats)]
     L.mlp_md_step.argtypes = [P, P, P, P, P, P, P, I32, P, ctypes.c_float, ctypes.c_float, P, P,
                               ctypes.POINTER(I32)]
+    L.mlp_nvt_create.argtypes = [I32, ctypes.c_double, ctypes.c_double, I32, ctypes.POINTER(P)]
+    L.mlp_nvt_destroy.argtypes = [P]
+    L.mlp_nvt_read.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), P]
+    L.mlp_md_step_nvt.argtypes = [P, P, P, P, P, P, P, P, I32, P, ctypes.c_float, ctypes.c_float, P, P,
+                                  ctypes.POINTER(I32)]
     L.mlp_server_create.argtypes = [P, ctypes.c_size_t, I32, ctypes.POINTER(P)]
     L.mlp_server_destroy.argtypes = [P]
     L.mlp_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
@@ -88,7 +93,7 @@ def lib():
     for name in ("mlp_profile_enable", "mlp_profile_reset", "mlp_profile_read",
                  "mlp_model_create", "mlp_model_destroy", "mlp_build_neighbors", "mlp_nbr_destroy", "mlp_nbr_edges",
                  "mlp_energy_forces", "mlp_md_step", "mlp_server_create", "mlp_server_destroy",
-                 "mlp_submit", "mlp_poll"):
+                 "mlp_submit", "mlp_poll", "mlp_nvt_create", "mlp_nvt_destroy", "mlp_nvt_read", "mlp_md_step_nvt"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -163,6 +168,43 @@ def mlp_md_step(model, nbr, pos, vel, forces, inv_mass, species, box, skin, dt, 
                              int(pos.shape[1]), _box_arr(box), float(skin), float(dt), _stream(stream),
                              _ptr(energy), ctypes.byref(rb)))
     return bool(rb.value)
+
+
+def mlp_md_step_nvt(model, nbr, nvt, pos, vel, forces, inv_mass, species, box, skin, dt, energy, stream=None):
+    rb = ctypes.c_int32(0)
+    _check(lib().mlp_md_step_nvt(model, nbr, nvt, _ptr(pos), _ptr(vel), _ptr(forces), _ptr(inv_mass),
+                                 _ptr(species), int(pos.shape[1]), _box_arr(box), float(skin), float(dt),
+                                 _stream(stream), _ptr(energy), ctypes.byref(rb)))
+    return bool(rb.value)
+
+
+class Thermostat:
+    """Nose-Hoover chain state on the device (mlp_nvt_*)."""
+
+    def __init__(self, n_dof: int, temperature: float, tau_fs: float, chain: int = 3):
+        h = ctypes.c_void_p()
+        _check(lib().mlp_nvt_create(int(n_dof), float(temperature), float(tau_fs), int(chain), ctypes.byref(h)))
+        self.handle, self.chain = h, int(chain)
+
+    def read(self, stream=None):
+        """(xi, vxi, thermostat energy (eV), kinetic energy (eV)) after the last step."""
+        xi = np.zeros(self.chain)
+        vxi = np.zeros(self.chain)
+        eth, ke = ctypes.c_double(), ctypes.c_double()
+        _check(lib().mlp_nvt_read(self.handle, xi.ctypes.data, vxi.ctypes.data, ctypes.byref(eth), ctypes.byref(ke),
+                                  _stream(stream)))
+        return xi, vxi, eth.value, ke.value
+
+    def close(self):
+        if self.handle:
+            lib().mlp_nvt_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mlp_profile_enable(on: bool = True):

@@ -336,3 +336,85 @@ def test_collinear_chain_reduces_to_scalar_model(oracle):
         xp[i] += h; xm[i] -= h
         assert abs(-(energy(xp) - energy(xm)) / (2 * h) - Fo[i, 0]) <= 1e-6 * np.abs(Fo).max()
     assert np.abs(Fo[:, 1:]).max() <= 1e-12 * np.abs(Fo).max()
+
+
+# --------------------------------------------------------------------------
+# Nose-Hoover chain (NVT) oracle.
+# --------------------------------------------------------------------------
+def _md_water192():
+    s, hdr, w = synth.workload("water192")
+    V = synth.weight_views(hdr, w)
+    for t in range(hdr["T"]):
+        V[f"l{t}.A"][...] *= np.float32(synth.MD_FILTER_SCALE)
+        V[f"l{t}.c"][...] *= np.float32(synth.MD_FILTER_SCALE)
+    V["w6"][...] *= np.float32(synth.MD_READOUT_SCALE)
+    return s, hdr, w
+
+
+def test_nhc_with_infinite_damping_is_velocity_verlet(oracle):
+    # Q -> infinity: the chain never moves, the scale factor is exactly 1 and
+    # the NVT step is the plain velocity-Verlet step
+    s, hdr, w = _md_water192()
+    v0 = synth.maxwell_velocities(s, 300.0, seed=1)
+    st = oracle.nhc_state(3 * s.n_atoms - 3, 300.0, 1e30, 3)
+    x1, v1, E1, _, _ = oracle.nhc_velocity_verlet(hdr, w, s.pos, v0, s.species, s.masses, s.box, 0.5, 4, st)
+    x2, v2, E2 = oracle.velocity_verlet(hdr, w, s.pos, v0, s.species, s.masses, s.box, 0.5, 4)
+    assert np.array_equal(x1, x2) and np.array_equal(v1, v2) and np.array_equal(E1, E2)
+
+
+def _chain_ode(t, y, nf, kT, Q):
+    # y = [ln KE, xi_1..xi_M, v_1..v_M]; free particles (F = 0): the chain
+    # equations of motion with p_xi = Q v
+    M = len(Q)
+    ke = np.exp(y[0])
+    v = y[1 + M:]
+    dv = np.empty(M)
+    for k in range(M):
+        base = (2.0 * ke - nf * kT) / Q[0] if k == 0 else (Q[k - 1] * v[k - 1] ** 2 - kT) / Q[k]
+        dv[k] = base - (v[k] * v[k + 1] if k + 1 < M else 0.0)
+    return np.concatenate([[-2.0 * v[0]], v, dv])
+
+
+@pytest.mark.parametrize("chain", [1, 3])
+def test_nhc_free_particles_follow_the_chain_equations(oracle, chain):
+    # With zero forces the NVT flow reduces to a closed ODE for (KE, xi, v);
+    # a tight general-purpose solve of that ODE pins the splitting, and the
+    # error shrinks as dt^2 (second-order integrator)
+    from scipy.integrate import solve_ivp
+    n, T0, T_target, tau, t_end = 64, 600.0, 300.0, 40.0, 200.0
+    species = np.zeros(n, np.int32)
+    masses = np.array([12.0])
+    rng = np.random.default_rng(3)
+    vel = rng.standard_normal((n, 3)) * np.sqrt(oracle.KB_EV * T0 / 12.0 * oracle.ACC_UNIT)
+    pos = rng.uniform(0, 50, (n, 3))
+    zero = lambda x: (0.0, np.zeros_like(x))
+    nf = 3 * n
+    errs = []
+    for dt in (2.0, 1.0):
+        st = oracle.nhc_state(nf, T_target, tau, chain)
+        ke0 = oracle.kinetic_energy(vel, species, masses)
+        _, v, _, K, H = oracle.nhc_velocity_verlet(None, None, pos, vel, species, masses, np.zeros(3), dt,
+                                                   int(round(t_end / dt)), st, force_fn=zero)
+        y0 = np.concatenate([[np.log(ke0)], np.zeros(chain), np.zeros(chain)])
+        sol = solve_ivp(_chain_ode, (0.0, t_end), y0, args=(float(nf), st["kT"], st["Q"]), rtol=1e-12,
+                        atol=1e-14, method="DOP853")
+        y = sol.y[:, -1]
+        errs.append(max(abs(K[-1] - np.exp(y[0])) / np.exp(y[0]),
+                        np.abs(st["v"] - y[1 + chain:]).max() / np.abs(y[1 + chain:]).max()))
+        # the thermostat has moved the kinetic energy substantially
+        assert abs(K[-1] - ke0) > 0.1 * ke0
+    assert errs[1] < 2e-3
+    assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+def test_nhc_extended_energy_is_conserved(oracle):
+    # H = KE + E_pot + thermostat energy is the conserved quantity of the NVT
+    # flow; with a strongly coupled thermostat the kinetic energy moves a lot
+    # while H stays put to the integrator's O(dt^2)
+    s, hdr, w = _md_water192()
+    v0 = synth.maxwell_velocities(s, 600.0, seed=2)
+    st = oracle.nhc_state(3 * s.n_atoms - 3, 300.0, 25.0, 3)
+    _, _, E, K, H = oracle.nhc_velocity_verlet(hdr, w, s.pos, v0, s.species, s.masses, s.box, 0.25, 160, st)
+    ext = E + K + H
+    assert np.ptp(K) > 0.3 * K[0]
+    assert np.ptp(ext) < 2e-3 * np.ptp(K)
