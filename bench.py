@@ -228,6 +228,79 @@ def measure_eval(mlp, synth, torch, name: str, precision: str, reps: int = 5, sk
     return res
 
 
+def measure_al_nvt(mlp, synth, torch, precision: str, n_cells: int = 35, equil: int = 100, prod: int = 250):
+    """The paper's aluminium MD protocol (Methods, "Molecular Dynamics
+    Simulations"): fcc a = 4.065 A replicated n_cells^3 (4 n_cells^3 atoms;
+    35 gives 171,500, the most the paper's framework ran for PaiNN on one
+    80 GB A100, Table 2), NVT with a Nose-Hoover chain (damping 1.1 ps) at
+    1000 K, dt = 3 fs, skin 2.0 A, 100 equilibration then 250 timed
+    production steps."""
+    import gc
+    s, hdr, w = synth.al_nvt_workload(n_cells)
+    n = s.n_atoms
+    model = mlp.Model(hdr, w, precision)
+    d = mlp.System(model, s.pos, s.species, s.box, skin=2.0)
+    vel = torch.as_tensor(synth.maxwell_velocities(s, 1000.0, seed=0)).t().contiguous().cuda()
+    inv_m = torch.as_tensor((1.0 / s.masses[s.species]).astype(np.float32)).cuda()
+    th = mlp.Thermostat(3 * n - 3, 1000.0, 1100.0, 3)
+    d.compute()
+
+    def step():
+        return mlp.mlp_md_step_nvt(model.handle, d.nbr, th.handle, d.pos, vel, d.forces, inv_m, d.species, d.box,
+                                   2.0, 3.0, d.energy)
+
+    for _ in range(equil):
+        step()
+    torch.cuda.synchronize()
+    _, _, eth0, ke0 = th.read()
+    e0 = d.energy.item()
+    rebuilds, temps = 0, []
+    t0 = time.perf_counter()
+    for k in range(prod):
+        rebuilds += step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    _, _, eth1, ke1 = th.read()
+    e1 = d.energy.item()
+    kb = 8.617333262e-5
+    res = {"atoms": n, "precision": precision, "steps_equil": equil, "steps_prod": prod,
+           "atom_steps_per_s": round(n * prod / el, 1), "ms_per_step": round(1e3 * el / prod, 3),
+           "T_end_K": round(2 * ke1 / ((3 * n - 3) * kb), 1), "rebuilds_prod": rebuilds,
+           "extended_energy_change_per_atom_eV": (e1 + ke1 + eth1 - e0 - ke0 - eth0) / n,
+           "finite": bool(np.isfinite(e1) and np.isfinite(ke1))}
+    th.close()
+    del d, model
+    gc.collect()
+    torch.cuda.empty_cache()
+    return res
+
+
+def measure_capacity(mlp, synth, torch, n_cells: int = 110):
+    """One energy + force evaluation of the largest fcc-Al PaiNN system
+    (F = 64, T = 4, skin 2.0 A) that fits one MI355X: the analogue of the
+    paper's "maximum atoms on one GPU" (Table 2)."""
+    import gc
+    s, hdr, w = synth.al_nvt_workload(n_cells)
+    try:
+        model = mlp.Model(hdr, w, "bf16")
+        d = mlp.System(model, s.pos, s.species, s.box, skin=2.0)
+        st = d.compute(stats=True)["stats"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d.compute()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res = {"atoms": s.n_atoms, "device_GB": round(st["device_bytes"] / 2**30, 2),
+               "ms_per_eval": round(1e3 * el, 1), "n_edges_rc": int(st["n_edges"]),
+               "finite": bool(np.isfinite(d.energy.item()))}
+        del d, model
+    except mlp.MLPError as e:
+        res = {"atoms": s.n_atoms, "error": str(e)[:300]}
+    gc.collect()
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +366,8 @@ def main():
                                                   for p in ("fp32", "bf16")},
             "water_slab_48k": {p: measure_eval(mlp, synth, torch, "slab48k", p, reps=5, skin=1.0)
                                for p in ("fp32", "bf16")},
+            "al_fcc_nvt_171500": measure_al_nvt(mlp, synth, torch, args.precision),
+            "max_atoms_one_gpu_al_fcc_painn_T4_F64": measure_capacity(mlp, synth, torch),
         }
 
     if not args.no_cpu_baseline:
