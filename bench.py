@@ -46,17 +46,26 @@ PEAKS = {  # published MI355X figures
 
 
 def per_edge_flops(F: int, K: int):
-    """Algorithmic flops per directed edge within rc per layer.
-    Forward message: the K+1 -> 3F filter (6(K+1)F) plus products and
-    accumulation (12F).  Adjoint: the filter and its radial derivative
-    (12(K+1)F) plus the per-edge gradient terms (28F)."""
-    return {"msg_fwd": 6 * (K + 1) * F + 12 * F, "msg_bwd": 12 * (K + 1) * F + 28 * F}
+    """Algorithmic flops per directed edge within rc, for the first layer
+    (v = 0 and no gradient into the embedding) and for every later layer
+    (fma = 2 flops, one filter output = K + 1 multiply-adds).
+    Forward, later layers: filter w (3F outputs) 6(K+1)F; per feature
+    x = phi o w (3), s += x_s (1), v += v_j x_vv + rhat x_vs (12): 16F.
+    First layer: w_s, w_vs 4(K+1)F; x_s, x_vs (2), s (1), rhat x_vs (6): 9F.
+    Adjoint, later layers: w and dw/dr 12(K+1)F; per feature dE/dx_vv and
+    dE/dx_vs (10), dE/dphi_j (6), dE/dv_j (7), dE/dr (9), dE/drhat (7): 39F.
+    First layer: w_vs, dw_s/dr, dw_vs/dr 6(K+1)F; dE/dx_vs (5), dE/dr (6),
+    dE/drhat (7): 18F."""
+    return {"msg_fwd": (4 * (K + 1) * F + 9 * F, 6 * (K + 1) * F + 16 * F),
+            "msg_bwd": (6 * (K + 1) * F + 18 * F, 12 * (K + 1) * F + 39 * F)}
 
 
 def node_flops_per_step(n_atoms: int, F: int, T: int):
-    """Node GEMM flops per step: forward 30 F^2 per atom per layer
-    (message MLP 8 F^2, update 22 F^2), adjoint twice that, readout 2 x F^2."""
-    return n_atoms * (T * 90 * F * F + 2 * F * F)
+    """Node GEMM flops per step: forward per atom and layer message MLP 8 F^2
+    (W1, W2) and update 22 F^2 (U, V on three rows, W3, W4); the adjoint
+    the same with transposed weights; the first layer's message MLP depends
+    on the species only (no per-atom GEMM either way); readout 2 x F^2."""
+    return n_atoms * ((60 * T - 16) * F * F + 2 * F * F)
 
 
 def source_hash(kernel_file: str) -> str:
@@ -143,8 +152,12 @@ def roofline(md, precision: str, steps: int):
     avg_s = tot_ms / max(launches, 1) / 1e3
     pe = per_edge_flops(F, K)
     if dom in pe:
-        flops_launch = pe[dom] * md["n_edges_mean"]
-        note = f"{pe[dom]} flop/edge x {md['n_edges_mean']:.0f} edges within rc"
+        # one launch per layer: the first layer's work plus T - 1 later ones
+        first, later = pe[dom]
+        per_step = (first + (T - 1) * later) * md["n_edges_mean"]
+        flops_launch = per_step * steps / max(launches, 1)
+        note = (f"({first} + {T - 1} x {later}) / {T} flop/edge (first layer, later layers) "
+                f"x {md['n_edges_mean']:.0f} edges within rc")
     else:
         per_step = node_flops_per_step(n, F, T)
         flops_launch = per_step * steps / max(launches, 1)

@@ -236,9 +236,17 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
         if (mlp::pack_weight(nullptr, it.W, it.R, it.C, it.tr, (char *)m->pk_dev + o, it.dst)) prc = MLP_ERR_DEVICE;
         o += mlp::packed_bytes(it.R, it.C, it.tr);
     }
+    // first-layer phi per species, followed by the scratch of its two GEMMs
+    float *tab = nullptr;
+    if (prc == 0 && hipMalloc(&tab, sizeof(float) * 5 * (size_t)S * F) != hipSuccess) prc = MLP_ERR_OOM;
+    if (prc == 0) {
+        m->phi0_dev = tab;
+        prc = mlp::first_layer_table(m, nullptr, tab + 3 * (size_t)S * F);
+    }
     if (prc == 0 && hipDeviceSynchronize() != hipSuccess) prc = MLP_ERR_DEVICE;
     if (prc) {
         (void)hipGetLastError();
+        if (tab) hipFree(tab);
         if (m->pk_dev) hipFree(m->pk_dev);
         hipFree(m->w_dev);
         delete m;
@@ -253,6 +261,7 @@ int mlp_model_destroy(mlp_model *m) {
     if (m->w_dev) hipFree(m->w_dev);
     if (m->wb_dev) hipFree(m->wb_dev);
     if (m->pk_dev) hipFree(m->pk_dev);
+    if (m->phi0_dev) hipFree(m->phi0_dev);
     delete m;
     return MLP_OK;
 }

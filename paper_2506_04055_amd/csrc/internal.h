@@ -67,6 +67,9 @@ struct mlp_model {
     mlp::PackedW pk[MLP_MAX_LAYERS][12];
     mlp::PackedW pk_W5, pk_W5t;
     void *pk_dev = nullptr;
+    // phi of the first layer per species ([S][3F]): s = emb[species] there, so
+    // the first message MLP depends on the species alone
+    float *phi0_dev = nullptr;
     mlp::LayerW layer(int t) const;
     const float *at(size_t off) const { return w_dev + off; }
     const __hip_bfloat16 *atb(size_t off) const { return wb_dev + off; }
@@ -129,6 +132,9 @@ int max_displacement_exceeds(mlp_nbr *g, const float *pos, float limit, hipStrea
 // offsets, or nullptr for one segment covering all rows), forces of all rows.
 int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
              float *atom_energy_user, int n_seg = 1, const int *seg_dev = nullptr);
+// Fill m->phi0_dev (device, S x 3F) from the embedding and the first layer's
+// message MLP, in the model's precision; tmp: device scratch of 2 S F floats.
+int first_layer_table(mlp_model *m, hipStream_t s, float *tmp);
 int verlet_kick_drift(float *pos, float *vel, const float *forces, const float *inv_mass, int n,
                       const double box[3], float dt, hipStream_t s);
 int verlet_kick(float *vel, const float *forces, const float *inv_mass, int n, float dt, hipStream_t s);

@@ -20,6 +20,9 @@ struct MsgArgs {
     float *gv_in, *gphi;      // adjoint outputs
     float4 *S;                // this layer's edge sums (dE/dr, dE/drhat), pass p at S + p * s_stride
     long s_stride;
+    // First layer: v = 0 on input (the forward neither reads v nor u) and the
+    // inputs s, v need no gradient (the adjoint writes S only, not gphi or gv_in).
+    bool layer0;
 };
 
 // Return 0, -1 (unsupported F, K) or -5 (launch error).

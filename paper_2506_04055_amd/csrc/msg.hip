@@ -309,7 +309,7 @@ struct XcdRange {
 // ---------------------------------------------------------------------------
 // Forward message pass, one feature pass (blockIdx.y) per workgroup.
 // ---------------------------------------------------------------------------
-template <int P, int F, int K>
+template <int P, int F, int K, bool V0>
 __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FWD_WAVES))) k_msg_fwd(const int *__restrict__ rowc, const int *__restrict__ colc,
                                                      const float4 *__restrict__ geom, int n,
                                                      const float *__restrict__ phi, const float *__restrict__ uvp,
@@ -355,7 +355,8 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
                 gm_n = geom[e0 + cb + 16 + e];
                 j_n = colc[e0 + cb + 16 + e];
             }
-            // gathered: phi_s, phi_vs and u = v * phi_vv of the source (5 row slices)
+            // gathered: phi_s, phi_vs and (after the first layer) u = v * phi_vv
+            // of the source (2 or 5 row slices)
             const float *pj = phi + (long)j * F3 + fo;
             const float *uj = uvp + (long)j * F3 + fo;
             v4f ph[2][TU], uu[3][TU];
@@ -363,8 +364,9 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
             for (int u = 0; u < TU; u++) {
                 ph[0][u] = ld4(pj + F + 16 * u);
                 ph[1][u] = ld4(pj + 2 * F + 16 * u);
+                if constexpr (!V0)
 #pragma unroll
-                for (int d = 0; d < 3; d++) uu[d][u] = ld4(uj + d * F + 16 * u);
+                    for (int d = 0; d < 3; d++) uu[d][u] = ld4(uj + d * F + 16 * u);
             }
             const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
             float eb[SL];
@@ -374,16 +376,23 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
             const float rx = gm.x * ir, ry = gm.y * ir, rz = gm.z * ir;
 #pragma unroll
             for (int u = 0; u < TU; u++) {
-                const v4f wvv = filter_tile<P, F, K, WM>(wl, u, bop, lane);
+                v4f wvv;
+                if constexpr (!V0) wvv = filter_tile<P, F, K, WM>(wl, u, bop, lane);
                 const v4f ws = filter_tile<P, F, K, WM>(wl, TU + u, bop, lane);
                 const v4f wvs = filter_tile<P, F, K, WM>(wl, 2 * TU + u, bop, lane);
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     const float xvs = ph[1][u][r] * wvs[r];
                     as[u][r] = fmaf(ph[0][u][r], ws[r], as[u][r]);
-                    av[0][u][r] = fmaf(uu[0][u][r], wvv[r], fmaf(rx, xvs, av[0][u][r]));
-                    av[1][u][r] = fmaf(uu[1][u][r], wvv[r], fmaf(ry, xvs, av[1][u][r]));
-                    av[2][u][r] = fmaf(uu[2][u][r], wvv[r], fmaf(rz, xvs, av[2][u][r]));
+                    if constexpr (V0) {
+                        av[0][u][r] = fmaf(rx, xvs, av[0][u][r]);
+                        av[1][u][r] = fmaf(ry, xvs, av[1][u][r]);
+                        av[2][u][r] = fmaf(rz, xvs, av[2][u][r]);
+                    } else {
+                        av[0][u][r] = fmaf(uu[0][u][r], wvv[r], fmaf(rx, xvs, av[0][u][r]));
+                        av[1][u][r] = fmaf(uu[1][u][r], wvv[r], fmaf(ry, xvs, av[1][u][r]));
+                        av[2][u][r] = fmaf(uu[2][u][r], wvv[r], fmaf(rz, xvs, av[2][u][r]));
+                    }
                 }
             }
         }
@@ -402,8 +411,10 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
                 const int f = fo + 16 * u;
                 st4(sn + (long)i * 2 * F + f, ld4(s + (long)i * F + f) + as[u]);
 #pragma unroll
-                for (int d = 0; d < 3; d++)
-                    st4(v1 + (long)i * F3 + d * F + f, ld4(v + (long)i * F3 + d * F + f) + av[d][u]);
+                for (int d = 0; d < 3; d++) {
+                    if constexpr (V0) st4(v1 + (long)i * F3 + d * F + f, av[d][u]);
+                    else st4(v1 + (long)i * F3 + d * F + f, ld4(v + (long)i * F3 + d * F + f) + av[d][u]);
+                }
             }
         }
     }
@@ -416,7 +427,7 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
 // gathered per lane, dE/dphi_j and dE/dv_j accumulated in registers, and the
 // edge sums S = (dE/dr, dE/drhat) of the pass stored in the pass's slot.
 // ---------------------------------------------------------------------------
-template <int P, int F, int K>
+template <int P, int F, int K, bool V0>
 __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BWD_WAVES))) k_msg_bwd(const int *__restrict__ rowc, const int *__restrict__ colc,
                                                      const float4 *__restrict__ geom, int n,
                                                      const float *__restrict__ phi, const float *__restrict__ v,
@@ -438,15 +449,19 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BW
     for (int j = xr.first; j < xr.end; j += xr.stride) {
         const int e0 = rowc[j], e1 = rowc[j + 1];
         const int deg = hop[j] <= hop_max ? e1 - e0 : 0;
+        // first layer: v_j = 0 and no node gradient, so phi_vv, v_j, dE/dphi_j
+        // and dE/dv_j drop out and only the edge sums remain
         v4f ph[3][TU], vj[3][TU], agp[3][TU], agv[3][TU];
 #pragma unroll
         for (int q = 0; q < 3; q++)
 #pragma unroll
             for (int u = 0; u < TU; u++) {
-                ph[q][u] = ld4(phi + (long)j * F3 + q * F + fo + 16 * u);
-                vj[q][u] = ld4(v + (long)j * F3 + q * F + fo + 16 * u);
-                agp[q][u] = v4f{0.f, 0.f, 0.f, 0.f};
-                agv[q][u] = v4f{0.f, 0.f, 0.f, 0.f};
+                if (!V0 || q > 0) ph[q][u] = ld4(phi + (long)j * F3 + q * F + fo + 16 * u);
+                if constexpr (!V0) {
+                    vj[q][u] = ld4(v + (long)j * F3 + q * F + fo + 16 * u);
+                    agp[q][u] = v4f{0.f, 0.f, 0.f, 0.f};
+                    agv[q][u] = v4f{0.f, 0.f, 0.f, 0.f};
+                }
             }
         // edges of an atom beyond the hop range carry no gradient in this layer
         if (hop[j] > hop_max)
@@ -486,27 +501,35 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BW
             float sr = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
 #pragma unroll
             for (int u = 0; u < TU; u++) {
-                const v4f w0 = filter_tile<P, F, K, WM>(wl, u, bop, lane);
-                const v4f w1 = filter_tile<P, F, K, WM>(wl, TU + u, bop, lane);
+                v4f w0, w1, d0;
+                if constexpr (!V0) {
+                    w0 = filter_tile<P, F, K, WM>(wl, u, bop, lane);
+                    w1 = filter_tile<P, F, K, WM>(wl, TU + u, bop, lane);
+                }
                 const v4f w2 = filter_tile<P, F, K, WM>(wl, 2 * TU + u, bop, lane);
-                const v4f d0 = filter_tile<P, F, K, WM>(wl, u, dop, lane);
+                if constexpr (!V0) d0 = filter_tile<P, F, K, WM>(wl, u, dop, lane);
                 const v4f d1 = filter_tile<P, F, K, WM>(wl, TU + u, dop, lane);
                 const v4f d2 = filter_tile<P, F, K, WM>(wl, 2 * TU + u, dop, lane);
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     const float ga = gv[0][u][r], gb = gv[1][u][r], gc = gv[2][u][r], gsr = gs[u][r];
-                    const float gxvv = fmaf(ga, vj[0][u][r], fmaf(gb, vj[1][u][r], gc * vj[2][u][r]));
                     const float gxvs = fmaf(ga, rx, fmaf(gb, ry, gc * rz));
-                    const float xvv = ph[0][u][r] * w0[r], xvs = ph[2][u][r] * w2[r];
+                    const float xvs = ph[2][u][r] * w2[r];
+                    sx = fmaf(ga, xvs, sx);
+                    sy = fmaf(gb, xvs, sy);
+                    sz = fmaf(gc, xvs, sz);
+                    if constexpr (V0) {
+                        sr = fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr));
+                        continue;
+                    }
+                    const float gxvv = fmaf(ga, vj[0][u][r], fmaf(gb, vj[1][u][r], gc * vj[2][u][r]));
+                    const float xvv = ph[0][u][r] * w0[r];
                     agv[0][u][r] = fmaf(ga, xvv, agv[0][u][r]);
                     agv[1][u][r] = fmaf(gb, xvv, agv[1][u][r]);
                     agv[2][u][r] = fmaf(gc, xvv, agv[2][u][r]);
                     agp[0][u][r] = fmaf(gxvv, w0[r], agp[0][u][r]);
                     agp[1][u][r] = fmaf(gsr, w1[r], agp[1][u][r]);
                     agp[2][u][r] = fmaf(gxvs, w2[r], agp[2][u][r]);
-                    sx = fmaf(ga, xvs, sx);
-                    sy = fmaf(gb, xvs, sy);
-                    sz = fmaf(gc, xvs, sz);
                     sr = fmaf(gxvv * ph[0][u][r], d0[r],
                               fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr)));
                 }
@@ -522,6 +545,7 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BW
             sz += __shfl_xor(sz, 32, 64);
             if (g == 0 && valid) Sp[e0 + cb + e] = make_float4(sr, sx, sy, sz);
         }
+        if constexpr (V0) continue;
         // sum over the 16 edge lanes of each row
 #pragma unroll
         for (int q = 0; q < 3; q++)
@@ -578,16 +602,18 @@ static int grid_x(int n) {
 template <int P, int F, int K>
 static int launch_fwd(hipStream_t st, const MsgArgs &a) {
     dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F, FWD_W>::N);
-    k_msg_fwd<P, F, K><<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.u, a.s, a.v, a.A, a.c, a.rc,
-                                                 a.hop, a.hop_max, a.sn, a.v1);
+    auto kern = a.layer0 ? k_msg_fwd<P, F, K, true> : k_msg_fwd<P, F, K, false>;
+    kern<<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.u, a.s, a.v, a.A, a.c, a.rc, a.hop,
+                                   a.hop_max, a.sn, a.v1);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
 template <int P, int F, int K>
 static int launch_bwd(hipStream_t st, const MsgArgs &a) {
     dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F, BWD_W>::N);
-    k_msg_bwd<P, F, K><<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.v, a.gs1, a.gv1, a.A, a.c,
-                                                 a.rc, a.hop, a.hop_max, a.gv_in, a.gphi, a.S, a.s_stride);
+    auto kern = a.layer0 ? k_msg_bwd<P, F, K, true> : k_msg_bwd<P, F, K, false>;
+    kern<<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.v, a.gs1, a.gv1, a.A, a.c, a.rc, a.hop,
+                                   a.hop_max, a.gv_in, a.gphi, a.S, a.s_stride);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 

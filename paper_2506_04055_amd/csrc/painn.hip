@@ -52,16 +52,18 @@ static void gemm(hipStream_t s, int prec, const float *A, int lda, const PackedW
 // ---------------------------------------------------------------------------
 // Elementwise node kernels
 // ---------------------------------------------------------------------------
-__global__ void k_embed(const int *__restrict__ species, const float *__restrict__ emb, int n, int F,
-                        float *__restrict__ s, float *__restrict__ v) {
+// First-layer inputs by species: s = emb[species] and phi = phi0[species]
+// (v = 0 there, which the first layer's kernels take as given).
+__global__ void k_embed(const int *__restrict__ species, const float *__restrict__ emb,
+                        const float *__restrict__ phi0, int n, int F, float *__restrict__ s,
+                        float *__restrict__ phi) {
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n * F) return;
     long i = idx / F;
     int f = idx % F;
-    s[idx] = emb[(long)species[i] * F + f];
-    v[i * 3 * F + f] = 0.f;
-    v[i * 3 * F + F + f] = 0.f;
-    v[i * 3 * F + 2 * F + f] = 0.f;
+    const long z = species[i];
+    s[idx] = emb[z * F + f];
+    for (int q = 0; q < 3; q++) phi[i * 3 * F + q * F + f] = phi0[z * 3 * F + q * F + f];
 }
 
 // u[i][d][f] = v[i][d][f] phi[i][f] (phi_vv), four features per thread.
@@ -321,6 +323,16 @@ static MsgArgs msg_args(mlp_nbr *g, mlp_model *m, const LayerW &L, int hop_max) 
     return a;
 }
 
+int first_layer_table(mlp_model *m, hipStream_t s, float *tmp) {
+    const int F = m->F, S = m->S;
+    const int P = m->precision == MLP_PREC_FP32 ? 0 : (m->precision == MLP_PREC_BF16 ? 2 : 1);
+    const LayerW L = m->layer(0);
+    // the same GEMMs as the later layers' node MLPs, on the S embedding rows
+    node_gemm(s, P, GE_BIAS_SILU, m->at(m->off_emb), F, m->pk[0][WP_W1], tmp, F, S, L.b1, tmp + (long)S * F, F);
+    node_gemm(s, P, GE_BIAS, tmp + (long)S * F, F, m->pk[0][WP_W2], m->phi0_dev, 3 * F, S, L.b2);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
 int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
              float *atom_energy_user, int n_seg, const int *seg_dev) {
     const int n = g->n_atoms, F = m->F, K = m->K, T = m->T, F3 = 3 * F, Fh = F / 2;
@@ -341,16 +353,20 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     const int *perm = g->perm.as<int>();
 
     // forward
-    k_embed<<<nblk((long)n * F, 256), 256, 0, s>>>(g->species.as<int>(), m->at(m->off_emb), n, F, A.s[0], A.v[0]);
+    k_embed<<<nblk((long)n * F, 256), 256, 0, s>>>(g->species.as<int>(), m->at(m->off_emb), m->phi0_dev, n, F,
+                                                   A.s[0], A.phi[0]);
     for (int t = 0; t < T; t++) {
         LayerW L = m->layer(t);
         const int hop_dst = T - 1 - t;
-        gemm<E_BIAS_SILU>(s, P, A.s[t], F, m->pk[t][WP_W1], A.h1[t], F, n, L.b1, A.tmpF, F);
-        gemm<E_BIAS>(s, P, A.tmpF, F, m->pk[t][WP_W2], A.phi[t], F3, n, L.b2);
-        // u = v * phi_vv: the rows the message pass gathers together with phi_s and phi_vs
-        k_vprod<<<nblk((long)n * F / 4, 256), 256, 0, s>>>(A.v[t], A.phi[t], n, F, A.u);
+        if (t > 0) {
+            gemm<E_BIAS_SILU>(s, P, A.s[t], F, m->pk[t][WP_W1], A.h1[t], F, n, L.b1, A.tmpF, F);
+            gemm<E_BIAS>(s, P, A.tmpF, F, m->pk[t][WP_W2], A.phi[t], F3, n, L.b2);
+            // u = v * phi_vv: the rows the message pass gathers together with phi_s and phi_vs
+            k_vprod<<<nblk((long)n * F / 4, 256), 256, 0, s>>>(A.v[t], A.phi[t], n, F, A.u);
+        }
         {
             MsgArgs ma = msg_args(g, m, L, hop_dst);
+            ma.layer0 = t == 0;
             ma.phi = A.phi[t];
             ma.u = A.u;
             ma.s = A.s[t];
@@ -398,9 +414,11 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             ma.gv_in = A.gv;
             ma.gphi = A.gphi;
             ma.S = g->Gs.as<float4>() + (size_t)t * npass * ne;
+            ma.layer0 = t == 0;
             ProfScope ps(PK_MSG_BWD, s);
             if ((rc = msg_adjoint(s, PF, F, K, ma))) return fail(rc, "adjoint message kernel launch failed");
         }
+        if (t == 0) break;   // the embedding carries no gradient
         gemm<E_DSILU>(s, P, A.gphi, F3, m->pk[t][WP_W2T], A.ga1, F, n, nullptr, nullptr, 0, A.h1[t], F);
         gemm<E_ADD>(s, P, A.ga1, F, m->pk[t][WP_W1T], A.gs, F, n, nullptr, nullptr, 0, A.gs1, F);
     }
