@@ -7,11 +7,14 @@
 // [n][k] with the reduction index contiguous, in FP32 and as bfloat16 hi / lo
 // parts, zero-padded so that no load of B needs a bound check.
 //
-// Each wave owns 16 rows of C and sweeps the columns in chunks of 128 (eight
-// 16 x 16 MFMA tiles).  A workgroup of four waves (64 rows) stages each
-// (128-column x 128-k) chunk of B in LDS once and every wave reads its B
-// fragments from there; A is loaded from global memory straight into the
-// MFMA operand layout:
+// Each wave owns 16 rows of C and one chunk of 128 columns (eight 16 x 16
+// MFMA tiles; the chunk is blockIdx.y, and grid.x is padded to a multiple of
+// 8 so the chunks of a row block share one XCD's L2).  The wave first loads
+// its whole 16 x K slice of A (K <= 384) into registers, already in MFMA
+// operand form, so all of its HBM reads are in flight at once and A is never
+// read twice by one wave.  A workgroup of four waves (64 rows) stages B in
+// LDS in chunks of KC k-columns, each thread loading a fixed share of the next
+// chunk into registers while the current one is multiplied:
 //   bf16 (v_mfma_f32_16x16x32_bf16): lane l = 16 g + c holds
 //        A[row c][k0 + 8g .. k0 + 8g + 7] and B[k0 + 8g .. +7][col c];
 //   f32  (v_mfma_f32_16x16x4_f32): lane l holds A[row c][k0 + 4g + j] and
@@ -22,9 +25,8 @@
 // Split-bf16 mode (P = 2) rounds A on the fly to x = hi + lo with
 // hi = bf16(x), lo = bf16(x - hi), and accumulates lo*hi + hi*lo + hi*hi
 // (the lo*lo term is below FP32 rounding of the leading part): ~16
-// significant bits per operand at the bf16 instruction rate.  A is read once
-// per 128-column chunk, so a GEMM with N <= 128 streams A and C through HBM
-// once; B moves from L2 once per 64 rows.
+// significant bits per operand at the bf16 instruction rate.  The epilogue's
+// second operand (residual or pre-activation) is fetched at the start too.
 #include "gemm.h"
 
 #include <algorithm>
@@ -99,6 +101,9 @@ int pack_weight(hipStream_t s, const float *W, int R, int C, bool transpose, voi
 #ifndef GEMM_KC
 #define GEMM_KC 64
 #endif
+#ifndef GEMM_RPRE
+#define GEMM_RPRE 1
+#endif
 constexpr int KC = GEMM_KC;
 constexpr int LDH = KC + 8;   // bf16 elements per LDS row
 constexpr int LDF = KC + 4;   // floats per LDS row
@@ -110,98 +115,166 @@ struct GemmLds {
     static constexpr int BYTES = B_BYTES > C_BYTES ? B_BYTES : C_BYTES;
 };
 
-template <int P, int EPI>
-__global__ void __launch_bounds__(64 * GW) k_gemm(const float *__restrict__ A, int lda, PackedW B, float *C, int ldc,
+#ifndef GEMM_WAVES4
+#define GEMM_WAVES4 3
+#endif
+// waves per SIMD the register budget is sized for (the A slice grows with K;
+// FP32 operands take twice the registers of bfloat16 hi + lo)
+template <int P, int KS>
+struct GemmWaves {
+    static constexpr int N = KS <= 4 ? GEMM_WAVES4 : (P == 0 ? 1 : 2);
+};
+template <int P, int EPI, int KS>
+__global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(GemmWaves<P, KS>::N))) k_gemm(const float *__restrict__ A, int lda, PackedW B, float *C, int ldc,
                                                   int M, const float *__restrict__ bias, float *__restrict__ C2,
                                                   int ldc2, const float *R, int ldr) {
     __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
+    // grid.x is padded to a multiple of 8 (the column chunks of one row block
+    // then run on one XCD and share its L2): padding workgroups leave at once
+    if ((long)blockIdx.x * GW * 16 >= M) return;
     const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
     const long m0 = ((long)blockIdx.x * GW + (threadIdx.x >> 6)) * 16;
+    const int n0 = blockIdx.y * NCH;
     const long arow = m0 + c16;
     const bool rowok = arow < M;
     const float *Ar = A + (rowok ? arow : 0) * (long)lda;
     const int K = B.K;
-    for (int n0 = 0; n0 < B.N; n0 += NCH) {
-        v4f acc[CT];
+    // The wave's 16 x K slice of A, loaded at once (all loads in flight
+    // together) and kept in MFMA operand form: block s covers k = 32 s .. 32 s + 31.
+    v8bf ah[KS], al[KS];
+    v4f af[KS][2];
 #pragma unroll
-        for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-        for (int kc = 0; kc < K; kc += KC) {
-            // stage B[n0 .. n0+127][kc .. kc+kcl) (all waves; rows beyond M still take part)
-            const int kcl = min(KC, B.Kp - kc);
-            __syncthreads();
-            if constexpr (P >= 1) {
-                const int vr = kcl / 8;   // 16-byte vectors per row
-                for (int idx = threadIdx.x; idx < NCH * vr; idx += blockDim.x) {
-                    const int n = idx / vr, q = idx % vr;
-                    const long go = (long)(n0 + n) * B.Kp + kc + 8 * q;
-                    __bf16 *h = reinterpret_cast<__bf16 *>(lds) + n * LDH + 8 * q;
-                    *reinterpret_cast<v8bf *>(h) = *reinterpret_cast<const v8bf *>(B.hi + go);
-                    if (P == 2) *reinterpret_cast<v8bf *>(h + NCH * LDH) = *reinterpret_cast<const v8bf *>(B.lo + go);
+    for (int s = 0; s < KS; s++) {
+        if constexpr (P >= 1) {
+            const int ka = 32 * s + 8 * g;
+            float a[8];
+            if (rowok && ka + 8 <= K) {
+                const v4f x = gld4(Ar + ka), y = gld4(Ar + ka + 4);
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    a[q] = x[q];
+                    a[4 + q] = y[q];
                 }
             } else {
-                const int vr = kcl / 4;
-                for (int idx = threadIdx.x; idx < NCH * vr; idx += blockDim.x) {
-                    const int n = idx / vr, q = idx % vr;
-                    *reinterpret_cast<v4f *>(reinterpret_cast<float *>(lds) + n * LDF + 4 * q) =
-                        gld4(B.f32 + (long)(n0 + n) * B.Kp + kc + 4 * q);
+#pragma unroll
+                for (int q = 0; q < 8; q++) a[q] = (rowok && ka + q < K) ? Ar[ka + q] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                ah[s][q] = (__bf16)a[q];
+                if (P == 2) al[s][q] = (__bf16)(a[q] - (float)ah[s][q]);
+            }
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int ka = 32 * s + 16 * h + 4 * g;
+                if (rowok && ka + 4 <= K) {
+                    af[s][h] = gld4(Ar + ka);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) af[s][h][q] = (rowok && ka + q < K) ? Ar[ka + q] : 0.f;
                 }
             }
-            __syncthreads();
-            const int kend = min(K, kc + KC);
+        }
+    }
+    // the epilogue's second operand (R) is fetched now, in the epilogue's
+    // row layout, so its latency overlaps the products
+    constexpr int EIT = 16 * NCH / 4 / 64;
+    const int ncols = min(NCH, B.N - n0);   // a multiple of 4
+    v4f rr[EIT];
+    if constexpr (GEMM_RPRE && (EPI == GE_DSILU || EPI == GE_ADD)) {
+#pragma unroll
+        for (int it = 0; it < EIT; it++) {
+            const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
+            const long m = m0 + row;
+            if (m < M && c4 < ncols) rr[it] = gld4(R + m * ldr + n0 + c4);
+        }
+    }
+    v4f acc[CT];
+#pragma unroll
+    for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    // B moves in stages of KC k-columns: the registers of the next stage are
+    // loaded from L2 while the current stage is multiplied out of LDS.  Each
+    // thread takes a fixed, unrolled share, so all loads of a stage are in
+    // flight together.
+    constexpr int VR = P >= 1 ? KC / 8 : KC / 4;   // 16-byte vectors per row of a stage
+    constexpr int IT = NCH * VR / (64 * GW);
+    static_assert(IT * 64 * GW == NCH * VR, "stage split");
+    constexpr int EV = P >= 1 ? 8 : 4;             // k-elements per vector
+    v8bf sh[IT], sl[IT];
+    v4f sf[IT];
+    auto fetch = [&](int kc) {
+        const int kcl = min(KC, B.Kp - kc);
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int idx = threadIdx.x + 64 * GW * it, n = idx / VR, q = idx % VR;
+            if (EV * q < kcl) {
+                const long go = (long)(n0 + n) * B.Kp + kc + EV * q;
+                if constexpr (P >= 1) {
+                    sh[it] = *reinterpret_cast<const v8bf *>(B.hi + go);
+                    if (P == 2) sl[it] = *reinterpret_cast<const v8bf *>(B.lo + go);
+                } else {
+                    sf[it] = gld4(B.f32 + go);
+                }
+            }
+        }
+    };
+    auto park = [&](int kc) {
+        const int kcl = min(KC, B.Kp - kc);
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int idx = threadIdx.x + 64 * GW * it, n = idx / VR, q = idx % VR;
+            if (EV * q < kcl) {
+                if constexpr (P >= 1) {
+                    __bf16 *h = reinterpret_cast<__bf16 *>(lds) + n * LDH + 8 * q;
+                    *reinterpret_cast<v8bf *>(h) = sh[it];
+                    if (P == 2) *reinterpret_cast<v8bf *>(h + NCH * LDH) = sl[it];
+                } else {
+                    *reinterpret_cast<v4f *>(reinterpret_cast<float *>(lds) + n * LDF + 4 * q) = sf[it];
+                }
+            }
+        }
+    };
+    fetch(0);
+#pragma unroll
+    for (int kc = 0; kc < KS * 32; kc += KC) {
+        if (kc >= K) break;
+        __syncthreads();   // every wave is done with the previous stage
+        park(kc);
+        __syncthreads();
+        if (kc + KC < K) fetch(kc + KC);
+#pragma unroll
+        for (int j = 0; j < KC / 32; j++) {
+            const int s = kc / 32 + j;
+            if (s >= KS || 32 * s >= K) break;
             if constexpr (P >= 1) {
-                for (int k0 = kc; k0 < kend; k0 += 32) {
-                    const int ka = k0 + 8 * g;
-                    float a[8];
-                    if (rowok && ka + 8 <= K) {
-                        const v4f x = gld4(Ar + ka), y = gld4(Ar + ka + 4);
+                const __bf16 *bb = reinterpret_cast<const __bf16 *>(lds) + c16 * LDH + 32 * j + 8 * g;
 #pragma unroll
-                        for (int q = 0; q < 4; q++) {
-                            a[q] = x[q];
-                            a[4 + q] = y[q];
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 8; q++) a[q] = (rowok && ka + q < K) ? Ar[ka + q] : 0.f;
+                for (int t = 0; t < CT; t++) {
+                    const v8bf bh = *reinterpret_cast<const v8bf *>(bb + 16 * t * LDH);
+                    if constexpr (P == 2) {
+                        const v8bf bl = *reinterpret_cast<const v8bf *>(bb + 16 * t * LDH + NCH * LDH);
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], bh, acc[t], 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], bl, acc[t], 0, 0, 0);
                     }
-                    v8bf ah, al;
-#pragma unroll
-                    for (int q = 0; q < 8; q++) {
-                        ah[q] = (__bf16)a[q];
-                        if (P == 2) al[q] = (__bf16)(a[q] - (float)ah[q]);
-                    }
-                    const __bf16 *bb = reinterpret_cast<const __bf16 *>(lds) + c16 * LDH + (k0 - kc) + 8 * g;
-#pragma unroll
-                    for (int t = 0; t < CT; t++) {
-                        const v8bf bh = *reinterpret_cast<const v8bf *>(bb + 16 * t * LDH);
-                        if constexpr (P == 2) {
-                            const v8bf bl = *reinterpret_cast<const v8bf *>(bb + 16 * t * LDH + NCH * LDH);
-                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[t], 0, 0, 0);
-                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[t], 0, 0, 0);
-                        }
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[t], 0, 0, 0);
-                    }
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], bh, acc[t], 0, 0, 0);
                 }
             } else {
-                for (int k0 = kc; k0 < kend; k0 += 16) {
-                    const int ka = k0 + 4 * g;
-                    v4f a;
-                    if (rowok && ka + 4 <= K) {
-                        a = gld4(Ar + ka);
-                    } else {
 #pragma unroll
-                        for (int q = 0; q < 4; q++) a[q] = (rowok && ka + q < K) ? Ar[ka + q] : 0.f;
-                    }
-                    const float *bb = reinterpret_cast<const float *>(lds) + c16 * LDF + (k0 - kc) + 4 * g;
+                for (int h = 0; h < 2; h++) {
+                    const float *bb = reinterpret_cast<const float *>(lds) + c16 * LDF + 32 * j + 16 * h + 4 * g;
 #pragma unroll
                     for (int t = 0; t < CT; t++) {
                         const v4f b = *reinterpret_cast<const v4f *>(bb + 16 * t * LDF);
 #pragma unroll
-                        for (int j = 0; j < 4; j++)
-                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], acc[t], 0, 0, 0);
+                        for (int q = 0; q < 4; q++)
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s][h][q], b[q], acc[t], 0, 0, 0);
                     }
                 }
             }
         }
+    }
+    {
         // Epilogue through LDS: each wave parks its 16 x 128 tile in LDS in the
         // accumulator layout and reads it back by rows, so C (and R, C2) move
         // as whole rows in 16-byte vectors (two 512-byte rows per instruction).
@@ -212,9 +285,8 @@ __global__ void __launch_bounds__(64 * GW) k_gemm(const float *__restrict__ A, i
 #pragma unroll
             for (int r = 0; r < 4; r++) ct[(4 * g + r) * LDC + 16 * t + c16] = acc[t][r];
         __syncthreads();
-        const int ncols = min(NCH, B.N - n0);   // a multiple of 4
 #pragma unroll
-        for (int it = 0; it < 16 * NCH / 4 / 64; it++) {
+        for (int it = 0; it < EIT; it++) {
             const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
             const long m = m0 + row;
             if (m >= M || c4 >= ncols) continue;
@@ -233,31 +305,44 @@ __global__ void __launch_bounds__(64 * GW) k_gemm(const float *__restrict__ A, i
                     *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = sl;
                 }
             } else if (EPI == GE_DSILU) {
-                const v4f h = gld4(R + m * ldr + n);
+                const v4f h = GEMM_RPRE ? rr[it] : gld4(R + m * ldr + n);
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     const float sg = g_sigmoid(h[q]);
                     o[q] = x[q] * (sg * (1.0f + h[q] * (1.0f - sg)));
                 }
             } else {
-                o = gld4(R + m * ldr + n) + x;
+                o = (GEMM_RPRE ? rr[it] : gld4(R + m * ldr + n)) + x;
             }
             *reinterpret_cast<v4f *>(C + m * ldc + n) = o;
         }
     }
 }
 
-template <int P, int EPI>
+template <int P, int EPI, int KS>
 static void launch(hipStream_t s, const float *A, int lda, const PackedW &B, float *C, int ldc, int M,
                    const float *bias, float *C2, int ldc2, const float *R, int ldr) {
-    const unsigned blocks = (unsigned)((M + 16 * GW - 1) / (16 * GW));
-    k_gemm<P, EPI><<<blocks, 64 * GW, 0, s>>>(A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr);
+    unsigned bx = (unsigned)((M + 16 * GW - 1) / (16 * GW));
+    const unsigned by = (unsigned)(B.Np / NCH);
+    if (by > 1) bx = (bx + 7) / 8 * 8;
+    k_gemm<P, EPI, KS><<<dim3(bx, by), 64 * GW, 0, s>>>(A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr);
+}
+
+template <int P, int EPI>
+static int launch_k(hipStream_t s, const float *A, int lda, const PackedW &B, float *C, int ldc, int M,
+                    const float *bias, float *C2, int ldc2, const float *R, int ldr) {
+    if (B.K <= 128) launch<P, EPI, 4>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr);
+    else if (B.K <= 256) launch<P, EPI, 8>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr);
+    else if (B.K <= 384) launch<P, EPI, 12>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr);
+    else return -1;
+    return 0;
 }
 
 int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, const PackedW &B, float *C, int ldc,
               int M, const float *bias, float *C2, int ldc2, const float *R, int ldr) {
     if (M <= 0 || B.N <= 0 || B.K <= 0) return 0;
-#define GL(P_, E_) launch<P_, E_>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr)
+    int rc = 0;
+#define GL(P_, E_) rc = launch_k<P_, E_>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr)
 #define GE(P_)                                   \
     switch (epi) {                               \
         case GE_STORE: GL(P_, GE_STORE); break;   \
@@ -275,6 +360,7 @@ int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, co
     }
 #undef GE
 #undef GL
+    if (rc) return rc;
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
