@@ -219,11 +219,12 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
     const int Fi = (int)F;
     for (int t = 0; t < (int)T; t++) {
         const mlp::LayerW L = m->layer(t);
-        const float *Wm[6] = {L.W1, L.W2, L.U, L.V, L.W3, L.W4};
-        const int R[6] = {Fi, 3 * Fi, Fi, Fi, Fi, 3 * Fi}, C[6] = {Fi, Fi, Fi, Fi, 2 * Fi, Fi};
-        for (int q = 0; q < 6; q++) {
+        // U and V are adjacent ([U; V] is one 2F x F row-major matrix)
+        const float *Wm[5] = {L.W1, L.W2, L.U, L.W3, L.W4};
+        const int R[5] = {Fi, 3 * Fi, 2 * Fi, Fi, 3 * Fi}, C[5] = {Fi, Fi, Fi, 2 * Fi, Fi};
+        for (int q = 0; q < 5; q++) {
             items.push_back({Wm[q], R[q], C[q], false, &m->pk[t][q]});
-            items.push_back({Wm[q], R[q], C[q], true, &m->pk[t][6 + q]});
+            items.push_back({Wm[q], R[q], C[q], true, &m->pk[t][5 + q]});
         }
     }
     items.push_back({m->at(m->off_W5), Fi / 2, Fi, false, &m->pk_W5});

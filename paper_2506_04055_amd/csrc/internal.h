@@ -48,8 +48,9 @@ struct LayerW {
     const float *W1, *b1, *W2, *b2, *A, *c, *U, *V, *W3, *b3, *W4, *b4;
 };
 
-// Indices into mlp_model::pk[t]: forward (B = W^T) then adjoint (B = W).
-enum { WP_W1 = 0, WP_W2, WP_U, WP_V, WP_W3, WP_W4, WP_W1T, WP_W2T, WP_UT, WP_VT, WP_W3T, WP_W4T };
+// Indices into mlp_model::pk[t]: forward (B = W^T) then adjoint (B = W);
+// UV is the stacked [U; V] (2F x F, adjacent in the weight layout).
+enum { WP_W1 = 0, WP_W2, WP_UV, WP_W3, WP_W4, WP_W1T, WP_W2T, WP_UVT, WP_W3T, WP_W4T, WP_COUNT };
 
 }  // namespace mlp
 
@@ -63,8 +64,8 @@ struct mlp_model {
     size_t off_layer[MLP_MAX_LAYERS][12];
     size_t off_W5, off_b5, off_w6, off_b6;
     // weight matrices packed as GEMM B operands (gemm.h): per layer
-    // W1 W2 U V W3 W4 for the forward, then the same six for the adjoint
-    mlp::PackedW pk[MLP_MAX_LAYERS][12];
+    // W1 W2 [U; V] W3 W4 for the forward, then the same five for the adjoint
+    mlp::PackedW pk[MLP_MAX_LAYERS][mlp::WP_COUNT];
     mlp::PackedW pk_W5, pk_W5t;
     void *pk_dev = nullptr;
     // phi of the first layer per species ([S][3F]): s = emb[species] there, so

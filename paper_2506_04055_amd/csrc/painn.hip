@@ -80,31 +80,32 @@ __global__ void k_vprod(const float *__restrict__ v, const float *__restrict__ p
     }
 }
 
-__global__ void k_norm(const float *__restrict__ Vv, int n, int F, float eps, float *__restrict__ sn) {
+// UV holds rows [Uv | Vv] of 2F for each (atom, direction): Uv(i, d, f) at
+// UV[(3 i + d) 2F + f], Vv(i, d, f) at UV[(3 i + d) 2F + F + f]; gUV likewise.
+__global__ void k_norm(const float *__restrict__ UV, int n, int F, float eps, float *__restrict__ sn) {
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n * F) return;
     long i = idx / F;
     int f = idx % F;
-    const float *q = Vv + i * 3 * F;
+    const float *q = UV + i * 6 * F + F;
     float x = eps;
-    for (int d = 0; d < 3; d++) x = fmaf(q[d * F + f], q[d * F + f], x);
+    for (int d = 0; d < 3; d++) x = fmaf(q[d * 2 * F + f], q[d * 2 * F + f], x);
     sn[i * 2 * F + F + f] = sqrtf(x);
 }
 
 __global__ void k_update_out(const float *__restrict__ sn, const float *__restrict__ v1,
-                             const float *__restrict__ Uv, const float *__restrict__ Vv,
-                             const float *__restrict__ a, int n, int F, float *__restrict__ s2,
-                             float *__restrict__ v2) {
+                             const float *__restrict__ UV, const float *__restrict__ a, int n, int F,
+                             float *__restrict__ s2, float *__restrict__ v2) {
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n * F) return;
     long i = idx / F;
     int f = idx % F;
-    const long b3 = i * 3 * F;
+    const long b3 = i * 3 * F, u6 = i * 6 * F;
     float sp = 0.f;
     float avv = a[b3 + f], asv = a[b3 + F + f], ass = a[b3 + 2 * F + f];
     for (int d = 0; d < 3; d++) {
-        float u = Uv[b3 + d * F + f];
-        sp = fmaf(u, Vv[b3 + d * F + f], sp);
+        float u = UV[u6 + d * 2 * F + f];
+        sp = fmaf(u, UV[u6 + d * 2 * F + F + f], sp);
         v2[b3 + d * F + f] = fmaf(avv, u, v1[b3 + d * F + f]);
     }
     s2[idx] = fmaf(asv, sp, sn[i * 2 * F + f] + ass);
@@ -112,23 +113,22 @@ __global__ void k_update_out(const float *__restrict__ sn, const float *__restri
 
 // Adjoint of the gated update (first part): da, dUv and the direct part of dVv.
 __global__ void k_update_bwd1(const float *__restrict__ gs2, const float *__restrict__ gv2,
-                              const float *__restrict__ Uv, const float *__restrict__ Vv,
-                              const float *__restrict__ a, int n, int F, float *__restrict__ ga,
-                              float *__restrict__ gUv, float *__restrict__ gVv) {
+                              const float *__restrict__ UV, const float *__restrict__ a, int n, int F,
+                              float *__restrict__ ga, float *__restrict__ gUV) {
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n * F) return;
     long i = idx / F;
     int f = idx % F;
-    const long b3 = i * 3 * F;
+    const long b3 = i * 3 * F, u6 = i * 6 * F;
     float g = gs2[idx];
     float avv = a[b3 + f], asv = a[b3 + F + f];
     float sp = 0.f, gavv = 0.f;
     for (int d = 0; d < 3; d++) {
-        float u = Uv[b3 + d * F + f], w = Vv[b3 + d * F + f], gv = gv2[b3 + d * F + f];
+        float u = UV[u6 + d * 2 * F + f], w = UV[u6 + d * 2 * F + F + f], gv = gv2[b3 + d * F + f];
         sp = fmaf(u, w, sp);
         gavv = fmaf(gv, u, gavv);
-        gUv[b3 + d * F + f] = gv * avv + g * asv * w;
-        gVv[b3 + d * F + f] = g * asv * u;
+        gUV[u6 + d * 2 * F + f] = gv * avv + g * asv * w;
+        gUV[u6 + d * 2 * F + F + f] = g * asv * u;
     }
     ga[b3 + f] = gavv;
     ga[b3 + F + f] = g * sp;
@@ -138,32 +138,51 @@ __global__ void k_update_bwd1(const float *__restrict__ gs2, const float *__rest
 // Adjoint of the gated update (second part): the norm's share of dVv and the
 // residual into ds1.
 __global__ void k_update_bwd2(const float *__restrict__ gsn, const float *__restrict__ sn,
-                              const float *__restrict__ Vv, const float *__restrict__ gs2, int n, int F,
-                              float *__restrict__ gVv, float *__restrict__ gs1) {
+                              const float *__restrict__ UV, const float *__restrict__ gs2, int n, int F,
+                              float *__restrict__ gUV, float *__restrict__ gs1) {
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n * F) return;
     long i = idx / F;
     int f = idx % F;
-    const long b3 = i * 3 * F;
+    const long u6 = i * 6 * F + F;
     float gn = gsn[i * 2 * F + F + f] / sn[i * 2 * F + F + f];
-    for (int d = 0; d < 3; d++) gVv[b3 + d * F + f] = fmaf(gn, Vv[b3 + d * F + f], gVv[b3 + d * F + f]);
+    for (int d = 0; d < 3; d++)
+        gUV[u6 + d * 2 * F + f] = fmaf(gn, UV[u6 + d * 2 * F + f], gUV[u6 + d * 2 * F + f]);
     gs1[idx] = gs2[idx] + gsn[i * 2 * F + f];
 }
 
 // Readout: U_i, and the gradient seed dE/dh5 = w6 o silu'(h5) on local atoms.
+// Sum over the 16 lanes of a DPP row.
+__device__ __forceinline__ float row16_sum(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));   // row_ror:8
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xF, 0xF, false));   // row_ror:4
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));    // quad [2,3,0,1]
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));    // quad [1,0,3,2]
+    return x;
+}
+
+// Readout U_i = b6 + sum_h w6[h] silu(h5[i][h]) and its gradient
+// g5 = w6 * silu'(h5) (zero for ghost rows), sixteen lanes per atom: lane q
+// takes features 4q .. 4q+3 (+ 64 per round) and the row sum gives U_i.
 __global__ void k_readout(const float *__restrict__ h5, int n, int Fh, const float *__restrict__ w6,
                           const float *__restrict__ b6, const int *__restrict__ perm, int n_local,
                           float *__restrict__ U, float *__restrict__ g5) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const bool local = perm[i] < n_local;
-    float u = b6[0];
-    for (int h = 0; h < Fh; h++) {
-        float x = h5[(long)i * Fh + h];
-        u = fmaf(w6[h], siluf_(x), u);
-        g5[(long)i * Fh + h] = local ? w6[h] * dsiluf_(x) : 0.f;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t >> 4), q = (int)(t & 15);
+    float u = 0.f;
+    if (i < n) {
+        const bool local = perm[i] < n_local;
+        for (int h = 4 * q; h < Fh; h += 64) {
+            const float4 x = *reinterpret_cast<const float4 *>(h5 + (long)i * Fh + h);
+            const float4 w = *reinterpret_cast<const float4 *>(w6 + h);
+            u = fmaf(w.x, siluf_(x.x), fmaf(w.y, siluf_(x.y), fmaf(w.z, siluf_(x.z), fmaf(w.w, siluf_(x.w), u))));
+            float4 gg = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (local) gg = make_float4(w.x * dsiluf_(x.x), w.y * dsiluf_(x.y), w.z * dsiluf_(x.z), w.w * dsiluf_(x.w));
+            *reinterpret_cast<float4 *>(g5 + (long)i * Fh + h) = gg;
+        }
     }
-    U[i] = u;
+    u = row16_sum(u);
+    if (q == 0 && i < n) U[i] = u + b6[0];
 }
 
 constexpr int ERED = 1024;
@@ -179,16 +198,23 @@ __global__ void __launch_bounds__(ERED) k_energy_seg(const float *__restrict__ U
     __shared__ double sh[ERED];
     const int b = blockIdx.x;
     const int a = seg ? seg[b] : 0, e = seg ? seg[b + 1] : n;
-    // four interleaved partial sums per thread keep four loads in flight
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i0 = a + threadIdx.x; i0 < e; i0 += 4 * ERED) {
+    // eight interleaved partial sums per thread; the row's energy and its
+    // local flag are loaded together, so eight pairs of loads are in flight
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i0 = a + threadIdx.x; i0 < e; i0 += 8 * ERED) {
+        float u[8];
+        int pm[8];
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
+        for (int q = 0; q < 8; q++) {
             const int i = i0 + q * ERED;
-            if (i < e && perm[i] < n_local) acc[q] += (double)U[i];
+            u[q] = i < e ? U[i] : 0.f;
+            pm[q] = i < e ? perm[i] : n_local;
         }
+#pragma unroll
+        for (int q = 0; q < 8; q++)
+            if (pm[q] < n_local) acc[q] += (double)u[q];
     }
-    sh[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    sh[threadIdx.x] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     __syncthreads();
     for (int off = ERED / 2; off > 0; off >>= 1) {
         if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
@@ -206,14 +232,6 @@ __global__ void k_fill(float *__restrict__ p, long n, float val) {
 // caller's atom order (SoA).
 // Sixteen lanes per atom (one DPP row): lane q takes the atom's edges
 // q, q + 16, ..., and the row sum gives the force.
-__device__ __forceinline__ float row16_sum(float x) {
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));   // row_ror:8
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xF, 0xF, false));   // row_ror:4
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));    // quad [2,3,0,1]
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));    // quad [1,0,3,2]
-    return x;
-}
-
 __global__ void k_forces(const int *__restrict__ rowc, const int *__restrict__ revc,
                          const float4 *__restrict__ Gout, const int *__restrict__ perm, int n,
                          float *__restrict__ F) {
@@ -254,9 +272,9 @@ __global__ void k_scatter_energy(const float *__restrict__ U, const int *__restr
 struct Act {
     float *s[MLP_MAX_LAYERS + 1], *v[MLP_MAX_LAYERS + 1];
     float *h1[MLP_MAX_LAYERS], *phi[MLP_MAX_LAYERS], *sn[MLP_MAX_LAYERS], *v1[MLP_MAX_LAYERS],
-        *Uv[MLP_MAX_LAYERS], *Vv[MLP_MAX_LAYERS], *h3[MLP_MAX_LAYERS], *a[MLP_MAX_LAYERS];
-    float *gs, *gv, *gs1, *gv1, *gphi, *ga, *gh3, *gsn, *gUv, *gVv, *ga1, *tmpF, *h5, *g5, *U;
-    float *u;   // v * phi_vv of the current forward layer (shares gUv: the adjoint starts after the forward)
+        *UV[MLP_MAX_LAYERS], *h3[MLP_MAX_LAYERS], *a[MLP_MAX_LAYERS];
+    float *gs, *gv, *gs1, *gv1, *gphi, *ga, *gh3, *gsn, *gUV, *ga1, *tmpF, *h5, *g5, *U;
+    float *u;   // v * phi_vv of the current forward layer (shares gUV: the adjoint starts after the forward)
     double *epart;
 };
 
@@ -283,8 +301,7 @@ static void carve(float *base, long N, int F, int T, Act &A) {
         A.phi[t] = take(3 * NF);
         A.sn[t] = take(2 * NF);
         A.v1[t] = take(3 * NF);
-        A.Uv[t] = take(3 * NF);
-        A.Vv[t] = take(3 * NF);
+        A.UV[t] = take(6 * NF);
         A.h3[t] = take(NF);
         A.a[t] = take(3 * NF);
     }
@@ -296,9 +313,8 @@ static void carve(float *base, long N, int F, int T, Act &A) {
     A.ga = take(3 * NF);
     A.gh3 = take(NF);
     A.gsn = take(2 * NF);
-    A.gUv = take(3 * NF);
-    A.gVv = take(3 * NF);
-    A.u = A.gUv;
+    A.gUV = take(6 * NF);
+    A.u = A.gUV;
     A.ga1 = take(NF);
     A.tmpF = take(NF);
     A.h5 = take(NF / 2 + 64);
@@ -376,18 +392,17 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             ProfScope ps(PK_MSG_FWD, s);
             if ((rc = msg_forward(s, PF, F, K, ma))) return fail(rc, "message kernel launch failed");
         }
-        gemm<E_STORE>(s, P, A.v1[t], F, m->pk[t][WP_U], A.Uv[t], F, 3 * n);
-        gemm<E_STORE>(s, P, A.v1[t], F, m->pk[t][WP_V], A.Vv[t], F, 3 * n);
-        k_norm<<<nblk((long)n * F, 256), 256, 0, s>>>(A.Vv[t], n, F, m->eps, A.sn[t]);
+        gemm<E_STORE>(s, P, A.v1[t], F, m->pk[t][WP_UV], A.UV[t], 2 * F, 3 * n);
+        k_norm<<<nblk((long)n * F, 256), 256, 0, s>>>(A.UV[t], n, F, m->eps, A.sn[t]);
         gemm<E_BIAS_SILU>(s, P, A.sn[t], 2 * F, m->pk[t][WP_W3], A.h3[t], F, n, L.b3, A.tmpF, F);
         gemm<E_BIAS>(s, P, A.tmpF, F, m->pk[t][WP_W4], A.a[t], F3, n, L.b4);
-        k_update_out<<<nblk((long)n * F, 256), 256, 0, s>>>(A.sn[t], A.v1[t], A.Uv[t], A.Vv[t], A.a[t], n, F,
-                                                             A.s[t + 1], A.v[t + 1]);
+        k_update_out<<<nblk((long)n * F, 256), 256, 0, s>>>(A.sn[t], A.v1[t], A.UV[t], A.a[t], n, F, A.s[t + 1],
+                                                             A.v[t + 1]);
     }
     // readout and energy
     gemm<E_BIAS>(s, P, A.s[T], F, m->pk_W5, A.h5, Fh, n, m->at(m->off_b5));
-    k_readout<<<nblk(n, 256), 256, 0, s>>>(A.h5, n, Fh, m->at(m->off_w6), m->at(m->off_b6), perm, g->n_local, A.U,
-                                           A.g5);
+    k_readout<<<nblk(16L * n, 256), 256, 0, s>>>(A.h5, n, Fh, m->at(m->off_w6), m->at(m->off_b6), perm,
+                                                 g->n_local, A.U, A.g5);
     k_energy_seg<<<std::max(1, n_seg), ERED, 0, s>>>(A.U, perm, seg_dev, n, g->n_local, energy);
     if (atom_energy_user) k_scatter_energy<<<nblk(n, 256), 256, 0, s>>>(A.U, perm, n, atom_energy_user);
     if (!forces_user) return 0;
@@ -398,13 +413,12 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     for (int t = T - 1; t >= 0; t--) {
         LayerW L = m->layer(t);
         const int hop_src = T - t;
-        k_update_bwd1<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gs, A.gv, A.Uv[t], A.Vv[t], A.a[t], n, F, A.ga,
-                                                             A.gUv, A.gVv);
+        k_update_bwd1<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gs, A.gv, A.UV[t], A.a[t], n, F, A.ga, A.gUV);
         gemm<E_DSILU>(s, P, A.ga, F3, m->pk[t][WP_W4T], A.gh3, F, n, nullptr, nullptr, 0, A.h3[t], F);
         gemm<E_STORE>(s, P, A.gh3, F, m->pk[t][WP_W3T], A.gsn, 2 * F, n);
-        k_update_bwd2<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gsn, A.sn[t], A.Vv[t], A.gs, n, F, A.gVv, A.gs1);
-        gemm<E_ADD>(s, P, A.gUv, F, m->pk[t][WP_UT], A.gv1, F, 3 * n, nullptr, nullptr, 0, A.gv, F);
-        gemm<E_ADD>(s, P, A.gVv, F, m->pk[t][WP_VT], A.gv1, F, 3 * n, nullptr, nullptr, 0, A.gv1, F);
+        k_update_bwd2<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gsn, A.sn[t], A.UV[t], A.gs, n, F, A.gUV, A.gs1);
+        // dv1 = [dUv | dVv] [U; V] + dv2 (the residual)
+        gemm<E_ADD>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * n, nullptr, nullptr, 0, A.gv, F);
         {
             MsgArgs ma = msg_args(g, m, L, hop_src);
             ma.phi = A.phi[t];
