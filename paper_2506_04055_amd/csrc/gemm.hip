@@ -96,33 +96,31 @@ int pack_weight(hipStream_t s, const float *W, int R, int C, bool transpose, voi
     return 0;
 }
 
-// LDS image of one (128-column x KC) chunk of B: bf16 hi rows then lo rows
+// LDS image of one (128-column x KC) stage of B: bf16 hi rows then lo rows
 // (P >= 1), or FP32 rows (P = 0); rows padded to spread the banks.
-#ifndef GEMM_KC
-#define GEMM_KC 64
-#endif
-#ifndef GEMM_RPRE
-#define GEMM_RPRE 1
-#endif
-constexpr int KC = GEMM_KC;
-constexpr int LDH = KC + 8;   // bf16 elements per LDS row
-constexpr int LDF = KC + 4;   // floats per LDS row
+template <int P>
+struct Stage {
+    static constexpr int KC = 64;                   // k-columns per stage
+    static constexpr int LDH = KC + 8;              // bf16 elements per LDS row
+    static constexpr int LDF = KC + 4;              // floats per LDS row
+};
 constexpr int LDC = NCH + 4;  // floats per row of the output tile parked in LDS
 template <int P>
 struct GemmLds {
-    static constexpr int B_BYTES = P == 0 ? NCH * LDF * 4 : NCH * LDH * 2 * (P == 2 ? 2 : 1);
+    static constexpr int B_BYTES =
+        P == 0 ? NCH * Stage<P>::LDF * 4 : NCH * Stage<P>::LDH * 2 * (P == 2 ? 2 : 1);
     static constexpr int C_BYTES = GW * 16 * LDC * 4;
     static constexpr int BYTES = B_BYTES > C_BYTES ? B_BYTES : C_BYTES;
 };
 
-#ifndef GEMM_WAVES4
-#define GEMM_WAVES4 3
-#endif
-// waves per SIMD the register budget is sized for (the A slice grows with K;
-// FP32 operands take twice the registers of bfloat16 hi + lo)
+// Waves per SIMD the register budget is sized for: the A slice held in
+// registers grows with K.  FP32 slices take twice the registers of bf16
+// hi + lo, so FP32 GEMMs with K > 128 leave the epilogue operand to the
+// epilogue instead of prefetching it.
 template <int P, int KS>
 struct GemmWaves {
-    static constexpr int N = KS <= 4 ? GEMM_WAVES4 : (P == 0 ? 1 : 2);
+    static constexpr int N = KS <= 4 ? 3 : 2;
+    static constexpr bool RPRE = !(P == 0 && KS > 4);
 };
 template <int P, int EPI, int KS>
 __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(GemmWaves<P, KS>::N))) k_gemm(const float *__restrict__ A, int lda, PackedW B, float *C, int ldc,
@@ -132,6 +130,7 @@ __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(Ge
     // grid.x is padded to a multiple of 8 (the column chunks of one row block
     // then run on one XCD and share its L2): padding workgroups leave at once
     if ((long)blockIdx.x * GW * 16 >= M) return;
+    constexpr int KC = Stage<P>::KC, LDH = Stage<P>::LDH, LDF = Stage<P>::LDF;
     const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
     const long m0 = ((long)blockIdx.x * GW + (threadIdx.x >> 6)) * 16;
     const int n0 = blockIdx.y * NCH;
@@ -182,7 +181,7 @@ __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(Ge
     constexpr int EIT = 16 * NCH / 4 / 64;
     const int ncols = min(NCH, B.N - n0);   // a multiple of 4
     v4f rr[EIT];
-    if constexpr (GEMM_RPRE && (EPI == GE_DSILU || EPI == GE_ADD)) {
+    if constexpr (GemmWaves<P, KS>::RPRE && (EPI == GE_DSILU || EPI == GE_ADD)) {
 #pragma unroll
         for (int it = 0; it < EIT; it++) {
             const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
@@ -305,14 +304,14 @@ __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(Ge
                     *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = sl;
                 }
             } else if (EPI == GE_DSILU) {
-                const v4f h = GEMM_RPRE ? rr[it] : gld4(R + m * ldr + n);
+                const v4f h = GemmWaves<P, KS>::RPRE ? rr[it] : gld4(R + m * ldr + n);
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     const float sg = g_sigmoid(h[q]);
                     o[q] = x[q] * (sg * (1.0f + h[q] * (1.0f - sg)));
                 }
             } else {
-                o = (GEMM_RPRE ? rr[it] : gld4(R + m * ldr + n)) + x;
+                o = (GemmWaves<P, KS>::RPRE ? rr[it] : gld4(R + m * ldr + n)) + x;
             }
             *reinterpret_cast<v4f *>(C + m * ldc + n) = o;
         }
