@@ -268,6 +268,37 @@ __device__ __forceinline__ const char *lds_chunk(const char *lds) {
 __device__ __forceinline__ v4f ld4(const float *p) { return *reinterpret_cast<const v4f *>(p); }
 __device__ __forceinline__ void st4(float *p, v4f x) { *reinterpret_cast<v4f *>(p) = x; }
 
+// Neighbour rows are gathered quarter-contiguously and then moved to the
+// accumulator layout through LDS.  In the accumulator layout lane (g, e) =
+// 16 g + e needs features 4g .. 4g+3 (of a 16-feature tile) of edge e, so
+// the 16 lanes of a quarter-wave would touch 16 different rows, 16 bytes
+// each: the L1 then serves one 16-byte piece per access.  Instead lane
+// (g, e) loads features 4(e % 4) .. +3 of the row of edge 4g + e/4 (each
+// quarter reads four whole 64-byte pieces) and stores them in LDS at the
+// slot of the lane that needs them, 16(e % 4) + 4g + e/4, from where every
+// lane reads its own slot.  Slot D sits at index swz(D): its bits 2-3 are
+// XOR-ed with its quarter, which keeps the writes and the reads of a
+// quarter-wave on 16 distinct 16-byte bank groups.
+struct Xch {
+    int src;   // lane holding the edge whose row this lane gathers
+    int fo;    // feature offset of the gathered piece inside a 16-feature tile
+    int wr;    // LDS slot this lane writes
+    int rd;    // LDS slot this lane reads
+    __device__ static int swz(int d) { return (d & 0x33) | ((((d >> 2) & 3) ^ (d >> 4)) << 2); }
+    __device__ Xch(int g, int e) {
+        src = 4 * g + (e >> 2);
+        fo = 4 * (e & 3);
+        wr = swz(16 * (e & 3) + 4 * g + (e >> 2));
+        rd = swz(16 * g + e);
+    }
+    // one 64-lane, 16-byte-per-lane exchange through the wave's buffer slot
+    __device__ v4f move(v4f *buf, v4f x) const {
+        buf[wr] = x;
+        __builtin_amdgcn_wave_barrier();   // the read sees the whole wave's writes
+        return buf[rd];
+    }
+};
+
 #ifndef MSG_MW
 #define MSG_MW 4
 #endif
@@ -280,7 +311,13 @@ constexpr int MW = MSG_MW;   // waves per workgroup
 #define BWD_W 32
 #endif
 #ifndef FWD_WAVES
-#define FWD_WAVES 3
+#define FWD_WAVES 4
+#endif
+#ifndef FWD_WAVES0
+#define FWD_WAVES0 4
+#endif
+#ifndef BWD_WAVES0
+#define BWD_WAVES0 4
 #endif
 #ifndef BWD_WAVES
 #define BWD_WAVES 2
@@ -310,7 +347,7 @@ struct XcdRange {
 // Forward message pass, one feature pass (blockIdx.y) per workgroup.
 // ---------------------------------------------------------------------------
 template <int P, int F, int K, bool V0>
-__global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FWD_WAVES))) k_msg_fwd(const int *__restrict__ rowc, const int *__restrict__ colc,
+__global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0 ? FWD_WAVES0 : FWD_WAVES))) k_msg_fwd(const int *__restrict__ rowc, const int *__restrict__ colc,
                                                      const float4 *__restrict__ geom, int n,
                                                      const float *__restrict__ phi, const float *__restrict__ uvp,
                                                      const float *__restrict__ s, const float *__restrict__ v,
@@ -321,10 +358,14 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
     constexpr int WM = FWD_W;
     constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F, WM>::W, TU = Pass<F, WM>::TU;
     __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K, WM>::BYTES];
+    constexpr int NX = V0 ? 2 : 5;   // row slices gathered per tile
+    __shared__ v4f xch[MW][NX][64];
     const int p = blockIdx.y;
     stage_pass<P, F, K, WM>(Aw, cw, p, lds);
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
     const int fo = p * W + 4 * g;   // first feature of this lane (tile u adds 16 u)
+    const Xch xc(g, e);
+    v4f(*xw)[64] = xch[threadIdx.x >> 6];
     const XcdRange xr(n);
     const float pirc = 3.14159265358979f / rc;
     for (int i = xr.first; i < xr.end; i += xr.stride) {
@@ -356,9 +397,10 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
                 j_n = colc[e0 + cb + 16 + e];
             }
             // gathered: phi_s, phi_vs and (after the first layer) u = v * phi_vv
-            // of the source (2 or 5 row slices)
-            const float *pj = phi + (long)j * F3 + fo;
-            const float *uj = uvp + (long)j * F3 + fo;
+            // of the source (2 or 5 row slices), quarter-contiguously
+            const int jq = __shfl(j, xc.src, 64);
+            const float *pj = phi + (long)jq * F3 + p * W + xc.fo;
+            const float *uj = uvp + (long)jq * F3 + p * W + xc.fo;
             v4f ph[2][TU], uu[3][TU];
 #pragma unroll
             for (int u = 0; u < TU; u++) {
@@ -367,6 +409,15 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
                 if constexpr (!V0)
 #pragma unroll
                     for (int d = 0; d < 3; d++) uu[d][u] = ld4(uj + d * F + 16 * u);
+            }
+            // ... and moved to the accumulator layout
+#pragma unroll
+            for (int u = 0; u < TU; u++) {
+                ph[0][u] = xc.move(xw[0], ph[0][u]);
+                ph[1][u] = xc.move(xw[1], ph[1][u]);
+                if constexpr (!V0)
+#pragma unroll
+                    for (int d = 0; d < 3; d++) uu[d][u] = xc.move(xw[2 + d], uu[d][u]);
             }
             const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
             float eb[SL];
@@ -428,7 +479,7 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(FW
 // edge sums S = (dE/dr, dE/drhat) of the pass stored in the pass's slot.
 // ---------------------------------------------------------------------------
 template <int P, int F, int K, bool V0>
-__global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BWD_WAVES))) k_msg_bwd(const int *__restrict__ rowc, const int *__restrict__ colc,
+__global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0 ? BWD_WAVES0 : BWD_WAVES))) k_msg_bwd(const int *__restrict__ rowc, const int *__restrict__ colc,
                                                      const float4 *__restrict__ geom, int n,
                                                      const float *__restrict__ phi, const float *__restrict__ v,
                                                      const float *__restrict__ gs1, const float *__restrict__ gv1,
@@ -439,11 +490,14 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BW
     constexpr int WM = BWD_W;
     constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F, WM>::W, TU = Pass<F, WM>::TU;
     __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K, WM>::BYTES];
+    __shared__ v4f xch[MW][4][64];
     const int p = blockIdx.y;
     stage_pass<P, F, K, WM>(Aw, cw, p, lds);
     float4 *Sp = S + (long)p * s_stride;
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
     const int fo = p * W + 4 * g;
+    const Xch xc(g, e);
+    v4f(*xw)[64] = xch[threadIdx.x >> 6];
     const XcdRange xr(n);
     const float pirc = 3.14159265358979f / rc;
     for (int j = xr.first; j < xr.end; j += xr.stride) {
@@ -483,12 +537,21 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(BW
                 gm_n = geom[e0 + cb + 16 + e];
                 i_n = colc[e0 + cb + 16 + e];
             }
+            // the destinations' gradient rows, gathered quarter-contiguously and
+            // moved to the accumulator layout
+            const int iq = __shfl(i, xc.src, 64);
             v4f gs[TU], gv[3][TU];
 #pragma unroll
             for (int u = 0; u < TU; u++) {
-                gs[u] = ld4(gs1 + (long)i * F + fo + 16 * u);
+                gs[u] = ld4(gs1 + (long)iq * F + p * W + xc.fo + 16 * u);
 #pragma unroll
-                for (int d = 0; d < 3; d++) gv[d][u] = ld4(gv1 + (long)i * F3 + d * F + fo + 16 * u);
+                for (int d = 0; d < 3; d++) gv[d][u] = ld4(gv1 + (long)iq * F3 + d * F + p * W + xc.fo + 16 * u);
+            }
+#pragma unroll
+            for (int u = 0; u < TU; u++) {
+                gs[u] = xc.move(xw[0], gs[u]);
+#pragma unroll
+                for (int d = 0; d < 3; d++) gv[d][u] = xc.move(xw[1 + d], gv[d][u]);
             }
             const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
             float eb[SL], db[SL];
