@@ -504,19 +504,26 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
         const int e0 = rowc[j], e1 = rowc[j + 1];
         const int deg = hop[j] <= hop_max ? e1 - e0 : 0;
         // first layer: v_j = 0 and no node gradient, so phi_vv, v_j, dE/dphi_j
-        // and dE/dv_j drop out and only the edge sums remain
-        v4f ph[3][TU], vj[3][TU], agp[3][TU], agv[3][TU];
+        // and dE/dv_j drop out and only the edge sums remain.
+        // Later layers accumulate Y_d = sum_e dE/dv1_d(i) w_vv (from which both
+        // dE/dv_j = phi_vv Y_d and dE/dphi_vv = sum_d v_jd Y_d follow once per
+        // atom), dE/dphi_s and dE/dphi_vs; the v_j term of dE/dr enters through
+        // c_d = v_jd phi_vv.
+        v4f ph[3][TU], cv[3][TU], Y[3][TU], ap[2][TU];
 #pragma unroll
-        for (int q = 0; q < 3; q++)
+        for (int u = 0; u < TU; u++) {
 #pragma unroll
-            for (int u = 0; u < TU; u++) {
-                if (!V0 || q > 0) ph[q][u] = ld4(phi + (long)j * F3 + q * F + fo + 16 * u);
-                if constexpr (!V0) {
-                    vj[q][u] = ld4(v + (long)j * F3 + q * F + fo + 16 * u);
-                    agp[q][u] = v4f{0.f, 0.f, 0.f, 0.f};
-                    agv[q][u] = v4f{0.f, 0.f, 0.f, 0.f};
+            for (int q = V0 ? 1 : 0; q < 3; q++) ph[q][u] = ld4(phi + (long)j * F3 + q * F + fo + 16 * u);
+            if constexpr (!V0) {
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    cv[d][u] = ld4(v + (long)j * F3 + d * F + fo + 16 * u) * ph[0][u];
+                    Y[d][u] = v4f{0.f, 0.f, 0.f, 0.f};
                 }
+                ap[0][u] = v4f{0.f, 0.f, 0.f, 0.f};
+                ap[1][u] = v4f{0.f, 0.f, 0.f, 0.f};
             }
+        }
         // edges of an atom beyond the hop range carry no gradient in this layer
         if (hop[j] > hop_max)
             for (int q = e0 + lane; q < e1; q += 64) Sp[q] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -585,16 +592,13 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
                         sr = fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr));
                         continue;
                     }
-                    const float gxvv = fmaf(ga, vj[0][u][r], fmaf(gb, vj[1][u][r], gc * vj[2][u][r]));
-                    const float xvv = ph[0][u][r] * w0[r];
-                    agv[0][u][r] = fmaf(ga, xvv, agv[0][u][r]);
-                    agv[1][u][r] = fmaf(gb, xvv, agv[1][u][r]);
-                    agv[2][u][r] = fmaf(gc, xvv, agv[2][u][r]);
-                    agp[0][u][r] = fmaf(gxvv, w0[r], agp[0][u][r]);
-                    agp[1][u][r] = fmaf(gsr, w1[r], agp[1][u][r]);
-                    agp[2][u][r] = fmaf(gxvs, w2[r], agp[2][u][r]);
-                    sr = fmaf(gxvv * ph[0][u][r], d0[r],
-                              fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr)));
+                    const float gc0 = fmaf(ga, cv[0][u][r], fmaf(gb, cv[1][u][r], gc * cv[2][u][r]));
+                    Y[0][u][r] = fmaf(ga, w0[r], Y[0][u][r]);
+                    Y[1][u][r] = fmaf(gb, w0[r], Y[1][u][r]);
+                    Y[2][u][r] = fmaf(gc, w0[r], Y[2][u][r]);
+                    ap[0][u][r] = fmaf(gsr, w1[r], ap[0][u][r]);
+                    ap[1][u][r] = fmaf(gxvs, w2[r], ap[1][u][r]);
+                    sr = fmaf(gc0, d0[r], fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr)));
                 }
             }
             // sum over the four lane rows (all features of the pass)
@@ -611,23 +615,29 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
         if constexpr (V0) continue;
         // sum over the 16 edge lanes of each row
 #pragma unroll
-        for (int q = 0; q < 3; q++)
+        for (int u = 0; u < TU; u++)
 #pragma unroll
-            for (int u = 0; u < TU; u++)
+            for (int r = 0; r < 4; r++) {
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    agp[q][u][r] = row_sum16(agp[q][u][r]);
-                    agv[q][u][r] = row_sum16(agv[q][u][r]);
-                }
+                for (int d = 0; d < 3; d++) Y[d][u][r] = row_sum16(Y[d][u][r]);
+                ap[0][u][r] = row_sum16(ap[0][u][r]);
+                ap[1][u][r] = row_sum16(ap[1][u][r]);
+            }
         if (e == 0) {
 #pragma unroll
-            for (int q = 0; q < 3; q++)
+            for (int u = 0; u < TU; u++) {
+                const long b = (long)j * F3 + fo + 16 * u;
+                const v4f pvv = ld4(phi + b);
+                v4f gvv = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int u = 0; u < TU; u++) {
-                    const long b = (long)j * F3 + q * F + fo + 16 * u;
-                    st4(gphi + b, agp[q][u]);
-                    st4(gv_in + b, ld4(gv1 + b) + agv[q][u]);
+                for (int d = 0; d < 3; d++) {
+                    gvv += ld4(v + b + d * F) * Y[d][u];
+                    st4(gv_in + b + d * F, ld4(gv1 + b + d * F) + pvv * Y[d][u]);
                 }
+                st4(gphi + b, gvv);
+                st4(gphi + b + F, ap[0][u]);
+                st4(gphi + b + 2 * F, ap[1][u]);
+            }
         }
     }
 }
