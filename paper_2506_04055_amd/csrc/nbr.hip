@@ -286,42 +286,57 @@ __device__ __forceinline__ float fold_once(float d, float L) {
     return d;
 }
 
+// Neighbours within rc + skin of row i, one wave per row.  The stencil cells
+// are visited in ascending order, runs of consecutive cells (z-neighbours
+// without a wrap) form one contiguous range of the cell-sorted rows, and each
+// range is tested 64 candidates at a time; a ballot and a prefix popcount
+// place the hits, so the columns of a row come out ascending, as from a
+// sequential scan.
 template <bool FILL>
-__global__ void k_nbr(const float4 *__restrict__ pb, const int *__restrict__ cell_int,
-                      const int *__restrict__ cell_start, int n, Grid g, float cut2,
-                      int *__restrict__ cnt, const int *__restrict__ row, int *__restrict__ col) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_nbr(const float4 *__restrict__ pb, const int *__restrict__ cell_int,
+                                             const int *__restrict__ cell_start, int n, Grid g, float cut2,
+                                             int *__restrict__ cnt, const int *__restrict__ row,
+                                             int *__restrict__ col) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
-    float4 pi = pb[i];
-    int cell = cell_int[i];
-    int cz = cell % g.nc[2];
-    int cy = (cell / g.nc[2]) % g.nc[1];
-    int cx = cell / (g.nc[2] * g.nc[1]);
+    const float4 pi = pb[i];
+    const int cell = cell_int[i];
+    const int cz = cell % g.nc[2];
+    const int cy = (cell / g.nc[2]) % g.nc[1];
+    const int cx = cell / (g.nc[2] * g.nc[1]);
     int lx[3], ly[3], lz[3];
-    int nx = stencil_list(cx, g.nc[0], g.L[0] > 0.f, lx);
-    int ny = stencil_list(cy, g.nc[1], g.L[1] > 0.f, ly);
-    int nz = stencil_list(cz, g.nc[2], g.L[2] > 0.f, lz);
+    const int nx = stencil_list(cx, g.nc[0], g.L[0] > 0.f, lx);
+    const int ny = stencil_list(cy, g.nc[1], g.L[1] > 0.f, ly);
+    const int nz = stencil_list(cz, g.nc[2], g.L[2] > 0.f, lz);
     int c = 0;
-    int o = FILL ? row[i] : 0;
+    const int o = FILL ? row[i] : 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
     for (int a = 0; a < nx; a++)
-        for (int b = 0; b < ny; b++)
-            for (int q = 0; q < nz; q++) {
-                int cc = (lx[a] * g.nc[1] + ly[b]) * g.nc[2] + lz[q];
-                int j0 = cell_start[cc], j1 = cell_start[cc + 1];
-                for (int j = j0; j < j1; j++) {
-                    if (j == i) continue;
-                    float4 pj = pb[j];
-                    float dx = fold_once(pj.x - pi.x, g.L[0]);
-                    float dy = fold_once(pj.y - pi.y, g.L[1]);
-                    float dz = fold_once(pj.z - pi.z, g.L[2]);
-                    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    if (r2 < cut2) {
-                        if (FILL) col[o + c] = j;
-                        c++;
+        for (int b = 0; b < ny; b++) {
+            const int base = (lx[a] * g.nc[1] + ly[b]) * g.nc[2];
+            for (int q = 0; q < nz;) {
+                int q1 = q;
+                while (q1 + 1 < nz && lz[q1 + 1] == lz[q1] + 1) q1++;
+                const int j0 = cell_start[base + lz[q]], j1 = cell_start[base + lz[q1] + 1];
+                q = q1 + 1;
+                for (int jb = j0; jb < j1; jb += 64) {
+                    const int j = jb + lane;
+                    bool hit = false;
+                    if (j < j1 && j != i) {
+                        const float4 pj = pb[j];
+                        const float dx = fold_once(pj.x - pi.x, g.L[0]);
+                        const float dy = fold_once(pj.y - pi.y, g.L[1]);
+                        const float dz = fold_once(pj.z - pi.z, g.L[2]);
+                        hit = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < cut2;
                     }
+                    const unsigned long long m = __ballot(hit);
+                    if (FILL && hit) col[o + c + __popcll(m & below)] = j;
+                    c += __popcll(m);
                 }
             }
-    if (!FILL) cnt[i] = c;
+        }
+    if (!FILL && lane == 0) cnt[i] = c;
 }
 
 __device__ __forceinline__ int find_sorted(const int *__restrict__ a, int lo, int hi, int key) {
@@ -333,13 +348,17 @@ __device__ __forceinline__ int find_sorted(const int *__restrict__ a, int lo, in
     return lo;
 }
 
-__global__ void k_rev(const int *__restrict__ row, const int *__restrict__ col, int n, int *__restrict__ rev,
-                      int *__restrict__ flag) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Reverse-edge index, one wave per row (lanes take the row's edges): the
+// position of i in the (ascending) row of j.
+__global__ void __launch_bounds__(256) k_rev(const int *__restrict__ row, const int *__restrict__ col, int n,
+                                             int *__restrict__ rev, int *__restrict__ flag) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
-    for (int e = row[i]; e < row[i + 1]; e++) {
-        int j = col[e];
-        int a = row[j], b = row[j + 1];
+    const int e1 = row[i + 1];
+    for (int e = row[i] + lane; e < e1; e += 64) {
+        const int j = col[e];
+        const int a = row[j], b = row[j + 1];
         int p = find_sorted(col, a, b, i);
         if (p >= b || col[p] != i) {
             atomicOr(flag, 4);
@@ -610,7 +629,7 @@ int build_graph(mlp_model *m, mlp_nbr *g, const float *pos, const int32_t *speci
                                                   g->iperm.as<int>(), flag);
     {
     ProfScope ps(PK_NBR, s);
-    k_nbr<false><<<nblk(n, 128), 128, 0, s>>>(g->pos_build.as<float4>(), cell_int, g->cell_start.as<int>(), n, gr,
+    k_nbr<false><<<nblk(n, 4), 256, 0, s>>>(g->pos_build.as<float4>(), cell_int, g->cell_start.as<int>(), n, gr,
                                               cut2, g->cnt.as<int>(), nullptr, nullptr);
     }
     if ((rc = scan_exclusive(g->cnt.as<int>(), g->row.as<int>(), n, g->scan_tmp, G, s))) return rc;
@@ -625,9 +644,9 @@ int build_graph(mlp_model *m, mlp_nbr *g, const float *pos, const int32_t *speci
     if ((rc = g->col.ensure(sizeof(int) * (size_t)E + 4, 1.2, G)) ||
         (rc = g->rev.ensure(sizeof(int) * (size_t)E + 4, 1.2, G)))
         return rc;
-    k_nbr<true><<<nblk(n, 128), 128, 0, s>>>(g->pos_build.as<float4>(), cell_int, g->cell_start.as<int>(), n, gr,
+    k_nbr<true><<<nblk(n, 4), 256, 0, s>>>(g->pos_build.as<float4>(), cell_int, g->cell_start.as<int>(), n, gr,
                                              cut2, nullptr, g->row.as<int>(), g->col.as<int>());
-    k_rev<<<nblk(n, 128), 128, 0, s>>>(g->row.as<int>(), g->col.as<int>(), n, g->rev.as<int>(), flag);
+    k_rev<<<nblk(n, 4), 256, 0, s>>>(g->row.as<int>(), g->col.as<int>(), n, g->rev.as<int>(), flag);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(hostv, flag, sizeof(int) * 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
