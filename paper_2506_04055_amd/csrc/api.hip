@@ -288,6 +288,10 @@ int mlp_build_neighbors(mlp_model *m, const float *pos, const int32_t *species, 
 }
 
 static void release_all(mlp_nbr *g) {
+    if (g->h_flag) {
+        hipHostFree(g->h_flag);
+        g->h_flag = nullptr;
+    }
     DevBuf *bufs[] = {&g->perm, &g->iperm, &g->cell_of, &g->cell_start, &g->cell_cnt, &g->cell_fill, &g->tmp_idx,
                       &g->pos_build, &g->species, &g->row, &g->col, &g->rev, &g->rowc, &g->colc, &g->revc,
                       &g->geom, &g->map, &g->oldidx, &g->cnt, &g->hop, &g->pos4, &g->scan_tmp, &g->flags,

@@ -101,6 +101,8 @@ struct mlp_nbr {
     size_t act_bytes = 0;
     int act_N = 0, act_F = 0, act_T = 0;
     mlp::DevBuf G, Gs, Fint, Uatom;   // Gs: per-pass edge sums of the adjoint
+    int *h_flag = nullptr;     // pinned host word for the per-step displacement check
+    int disp_epoch = 0;        // tag of the last displacement check
 };
 
 namespace mlp {

@@ -523,14 +523,15 @@ __global__ void k_fold(const int *__restrict__ ptr, int *__restrict__ list, int 
 // ---------------------------------------------------------------------------
 __global__ void k_maxdisp(const float *__restrict__ pos, const int *__restrict__ iperm,
                           const float4 *__restrict__ pb, int n, float L0, float L1, float L2, float lim2,
-                          int *__restrict__ flag) {
+                          int epoch, int *__restrict__ flag) {
     int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
     float4 q = pb[iperm[u]];
     float dx = min_image(pos[u] - q.x, L0);
     float dy = min_image(pos[(long)n + u] - q.y, L1);
     float dz = min_image(pos[2 * (long)n + u] - q.z, L2);
-    if (!(dx * dx + dy * dy + dz * dz <= lim2)) atomicOr(flag, 1);
+    // every atom that moved too far writes this check's tag (no reset needed)
+    if (!(dx * dx + dy * dy + dz * dz <= lim2)) *flag = epoch;
 }
 
 // ---------------------------------------------------------------------------
@@ -758,13 +759,22 @@ int export_edges(mlp_nbr *g, const int *row, const int *col, int32_t *dst, int32
 int max_displacement_exceeds(mlp_nbr *g, const float *pos, float limit, hipStream_t s, bool *exceeds) {
     const int n = g->n_atoms;
     int *flag = g->flags.as<int>();
-    HIP_TRY(hipMemsetAsync(flag + 2, 0, sizeof(int), s));
+    if (!g->h_flag) {
+        if (hipHostMalloc((void **)&g->h_flag, sizeof(int)) != hipSuccess) {
+            (void)hipGetLastError();
+            g->h_flag = nullptr;
+            return fail(-2, "pinned host allocation failed");
+        }
+    }
+    // tags 1, 2, ...: the word holds the tag of the last check that fired
+    // (the build clears it), so it never needs a reset on the stream
+    g->disp_epoch = g->disp_epoch == 0x7fffffff ? 1 : g->disp_epoch + 1;
+    const int epoch = g->disp_epoch;
     k_maxdisp<<<nblk(n, 256), 256, 0, s>>>(pos, g->iperm.as<int>(), g->pos_build.as<float4>(), n, g->box[0],
-                                           g->box[1], g->box[2], limit * limit, flag + 2);
-    int h = 0;
-    HIP_TRY(hipMemcpyAsync(&h, flag + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+                                           g->box[1], g->box[2], limit * limit, epoch, flag + 2);
+    HIP_TRY(hipMemcpyAsync(g->h_flag, flag + 2, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    *exceeds = h != 0;
+    *exceeds = *g->h_flag == epoch;
     return 0;
 }
 

@@ -112,6 +112,7 @@ __global__ void k_update_out(const float *__restrict__ sn, const float *__restri
 }
 
 // Adjoint of the gated update (first part): da, dUv and the direct part of dVv.
+// gv2 == nullptr stands for dE/dv2 = 0 (the last layer: the readout sees s only).
 __global__ void k_update_bwd1(const float *__restrict__ gs2, const float *__restrict__ gv2,
                               const float *__restrict__ UV, const float *__restrict__ a, int n, int F,
                               float *__restrict__ ga, float *__restrict__ gUV) {
@@ -124,7 +125,7 @@ __global__ void k_update_bwd1(const float *__restrict__ gs2, const float *__rest
     float avv = a[b3 + f], asv = a[b3 + F + f];
     float sp = 0.f, gavv = 0.f;
     for (int d = 0; d < 3; d++) {
-        float u = UV[u6 + d * 2 * F + f], w = UV[u6 + d * 2 * F + F + f], gv = gv2[b3 + d * F + f];
+        float u = UV[u6 + d * 2 * F + f], w = UV[u6 + d * 2 * F + F + f], gv = gv2 ? gv2[b3 + d * F + f] : 0.f;
         sp = fmaf(u, w, sp);
         gavv = fmaf(gv, u, gavv);
         gUV[u6 + d * 2 * F + f] = gv * avv + g * asv * w;
@@ -221,11 +222,6 @@ __global__ void __launch_bounds__(ERED) k_energy_seg(const float *__restrict__ U
         __syncthreads();
     }
     if (threadIdx.x == 0) E[b] = sh[0];
-}
-
-__global__ void k_fill(float *__restrict__ p, long n, float val) {
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = val;
 }
 
 // F_k = sum over in-edges e of (G at rev(e)) - (G at e), scattered to the
@@ -409,16 +405,18 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
 
     // adjoint
     gemm<E_STORE>(s, P, A.g5, Fh, m->pk_W5t, A.gs, F, n);
-    k_fill<<<nblk((long)n * F3, 256), 256, 0, s>>>(A.gv, (long)n * F3, 0.f);
     for (int t = T - 1; t >= 0; t--) {
         LayerW L = m->layer(t);
         const int hop_src = T - t;
-        k_update_bwd1<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gs, A.gv, A.UV[t], A.a[t], n, F, A.ga, A.gUV);
+        const bool last = t == T - 1;   // dE/dv of the last layer's output is zero
+        k_update_bwd1<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gs, last ? nullptr : A.gv, A.UV[t], A.a[t], n, F,
+                                                             A.ga, A.gUV);
         gemm<E_DSILU>(s, P, A.ga, F3, m->pk[t][WP_W4T], A.gh3, F, n, nullptr, nullptr, 0, A.h3[t], F);
         gemm<E_STORE>(s, P, A.gh3, F, m->pk[t][WP_W3T], A.gsn, 2 * F, n);
         k_update_bwd2<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gsn, A.sn[t], A.UV[t], A.gs, n, F, A.gUV, A.gs1);
         // dv1 = [dUv | dVv] [U; V] + dv2 (the residual)
-        gemm<E_ADD>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * n, nullptr, nullptr, 0, A.gv, F);
+        if (last) gemm<E_STORE>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * n);
+        else gemm<E_ADD>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * n, nullptr, nullptr, 0, A.gv, F);
         {
             MsgArgs ma = msg_args(g, m, L, hop_src);
             ma.phi = A.phi[t];
