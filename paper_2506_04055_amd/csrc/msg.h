@@ -22,7 +22,10 @@ struct MsgArgs {
     long s_stride;
     // First layer: v = 0 on input (the forward neither reads v nor u) and the
     // inputs s, v need no gradient (the adjoint writes S only, not gphi or gv_in).
+    // There phi and s point to per-species tables ([S][3F], [S][F]) whose rows
+    // are picked by species (device int32 per atom).
     bool layer0;
+    const int *species;
 };
 
 // Return 0, -1 (unsupported F, K) or -5 (launch error).

@@ -314,7 +314,7 @@ constexpr int MW = MSG_MW;   // waves per workgroup
 #define FWD_WAVES 4
 #endif
 #ifndef FWD_WAVES0
-#define FWD_WAVES0 4
+#define FWD_WAVES0 5
 #endif
 #ifndef BWD_WAVES0
 #define BWD_WAVES0 4
@@ -354,12 +354,14 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
                                                      const float *__restrict__ Aw,
                                                      const float *__restrict__ cw, float rc,
                                                      const int8_t *__restrict__ hop, int hop_max,
+                                                     const int *__restrict__ zsp,
                                                      float *__restrict__ sn, float *__restrict__ v1) {
     constexpr int WM = FWD_W;
     constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F, WM>::W, TU = Pass<F, WM>::TU;
     __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K, WM>::BYTES];
-    constexpr int NX = V0 ? 2 : 5;   // row slices gathered per tile
-    __shared__ v4f xch[MW][NX][64];
+    // first layer: phi and s are per-species tables (rows by zsp), a few rows
+    // that every gather hits in L1, read directly in the accumulator layout
+    __shared__ v4f xch[MW][V0 ? 1 : 5][64];
     const int p = blockIdx.y;
     stage_pass<P, F, K, WM>(Aw, cw, p, lds);
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
@@ -397,27 +399,34 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
                 j_n = colc[e0 + cb + 16 + e];
             }
             // gathered: phi_s, phi_vs and (after the first layer) u = v * phi_vv
-            // of the source (2 or 5 row slices), quarter-contiguously
-            const int jq = __shfl(j, xc.src, 64);
-            const float *pj = phi + (long)jq * F3 + p * W + xc.fo;
-            const float *uj = uvp + (long)jq * F3 + p * W + xc.fo;
+            // of the source (5 row slices, quarter-contiguously, then moved to
+            // the accumulator layout; the first layer's 2 from the table)
             v4f ph[2][TU], uu[3][TU];
+            if constexpr (V0) {
+                const float *pj = phi + (long)zsp[j] * F3 + fo;
 #pragma unroll
-            for (int u = 0; u < TU; u++) {
-                ph[0][u] = ld4(pj + F + 16 * u);
-                ph[1][u] = ld4(pj + 2 * F + 16 * u);
-                if constexpr (!V0)
+                for (int u = 0; u < TU; u++) {
+                    ph[0][u] = ld4(pj + F + 16 * u);
+                    ph[1][u] = ld4(pj + 2 * F + 16 * u);
+                }
+            } else {
+                const int jq = __shfl(j, xc.src, 64);
+                const float *pj = phi + (long)jq * F3 + p * W + xc.fo;
+                const float *uj = uvp + (long)jq * F3 + p * W + xc.fo;
+#pragma unroll
+                for (int u = 0; u < TU; u++) {
+                    ph[0][u] = ld4(pj + F + 16 * u);
+                    ph[1][u] = ld4(pj + 2 * F + 16 * u);
 #pragma unroll
                     for (int d = 0; d < 3; d++) uu[d][u] = ld4(uj + d * F + 16 * u);
-            }
-            // ... and moved to the accumulator layout
+                }
 #pragma unroll
-            for (int u = 0; u < TU; u++) {
-                ph[0][u] = xc.move(xw[0], ph[0][u]);
-                ph[1][u] = xc.move(xw[1], ph[1][u]);
-                if constexpr (!V0)
+                for (int u = 0; u < TU; u++) {
+                    ph[0][u] = xc.move(xw[0], ph[0][u]);
+                    ph[1][u] = xc.move(xw[1], ph[1][u]);
 #pragma unroll
                     for (int d = 0; d < 3; d++) uu[d][u] = xc.move(xw[2 + d], uu[d][u]);
+                }
             }
             const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
             float eb[SL];
@@ -460,7 +469,8 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
 #pragma unroll
             for (int u = 0; u < TU; u++) {
                 const int f = fo + 16 * u;
-                st4(sn + (long)i * 2 * F + f, ld4(s + (long)i * F + f) + as[u]);
+                const long si = V0 ? (long)zsp[i] : (long)i;
+                st4(sn + (long)i * 2 * F + f, ld4(s + si * F + f) + as[u]);
 #pragma unroll
                 for (int d = 0; d < 3; d++) {
                     if constexpr (V0) st4(v1 + (long)i * F3 + d * F + f, av[d][u]);
@@ -485,6 +495,7 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
                                                      const float *__restrict__ gs1, const float *__restrict__ gv1,
                                                      const float *__restrict__ Aw, const float *__restrict__ cw,
                                                      float rc, const int8_t *__restrict__ hop, int hop_max,
+                                                     const int *__restrict__ zsp,
                                                      float *__restrict__ gv_in, float *__restrict__ gphi,
                                                      float4 *__restrict__ S, long s_stride) {
     constexpr int WM = BWD_W;
@@ -513,7 +524,7 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
 #pragma unroll
         for (int u = 0; u < TU; u++) {
 #pragma unroll
-            for (int q = V0 ? 1 : 0; q < 3; q++) ph[q][u] = ld4(phi + (long)j * F3 + q * F + fo + 16 * u);
+            for (int q = V0 ? 1 : 0; q < 3; q++) ph[q][u] = ld4(phi + (V0 ? (long)zsp[j] : (long)j) * F3 + q * F + fo + 16 * u);
             if constexpr (!V0) {
 #pragma unroll
                 for (int d = 0; d < 3; d++) {
@@ -677,7 +688,7 @@ static int launch_fwd(hipStream_t st, const MsgArgs &a) {
     dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F, FWD_W>::N);
     auto kern = a.layer0 ? k_msg_fwd<P, F, K, true> : k_msg_fwd<P, F, K, false>;
     kern<<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.u, a.s, a.v, a.A, a.c, a.rc, a.hop,
-                                   a.hop_max, a.sn, a.v1);
+                                   a.hop_max, a.species, a.sn, a.v1);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
@@ -686,7 +697,7 @@ static int launch_bwd(hipStream_t st, const MsgArgs &a) {
     dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F, BWD_W>::N);
     auto kern = a.layer0 ? k_msg_bwd<P, F, K, true> : k_msg_bwd<P, F, K, false>;
     kern<<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.v, a.gs1, a.gv1, a.A, a.c, a.rc, a.hop,
-                                   a.hop_max, a.gv_in, a.gphi, a.S, a.s_stride);
+                                   a.hop_max, a.species, a.gv_in, a.gphi, a.S, a.s_stride);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 

@@ -52,19 +52,6 @@ static void gemm(hipStream_t s, int prec, const float *A, int lda, const PackedW
 // ---------------------------------------------------------------------------
 // Elementwise node kernels
 // ---------------------------------------------------------------------------
-// First-layer inputs by species: s = emb[species] and phi = phi0[species]
-// (v = 0 there, which the first layer's kernels take as given).
-__global__ void k_embed(const int *__restrict__ species, const float *__restrict__ emb,
-                        const float *__restrict__ phi0, int n, int F, float *__restrict__ s,
-                        float *__restrict__ phi) {
-    long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long)n * F) return;
-    long i = idx / F;
-    int f = idx % F;
-    const long z = species[i];
-    s[idx] = emb[z * F + f];
-    for (int q = 0; q < 3; q++) phi[i * 3 * F + q * F + f] = phi0[z * 3 * F + q * F + f];
-}
 
 // u[i][d][f] = v[i][d][f] phi[i][f] (phi_vv), four features per thread.
 __global__ void k_vprod(const float *__restrict__ v, const float *__restrict__ phi, int n, int F,
@@ -332,6 +319,7 @@ static MsgArgs msg_args(mlp_nbr *g, mlp_model *m, const LayerW &L, int hop_max) 
     a.hop_max = hop_max;
     a.S = g->Gs.as<float4>();
     a.s_stride = g->n_edges_skin;
+    a.species = g->species.as<int>();
     return a;
 }
 
@@ -365,8 +353,6 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     const int *perm = g->perm.as<int>();
 
     // forward
-    k_embed<<<nblk((long)n * F, 256), 256, 0, s>>>(g->species.as<int>(), m->at(m->off_emb), m->phi0_dev, n, F,
-                                                   A.s[0], A.phi[0]);
     for (int t = 0; t < T; t++) {
         LayerW L = m->layer(t);
         const int hop_dst = T - 1 - t;
@@ -379,9 +365,10 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         {
             MsgArgs ma = msg_args(g, m, L, hop_dst);
             ma.layer0 = t == 0;
-            ma.phi = A.phi[t];
+            // the first layer reads phi and s from the per-species tables
+            ma.phi = t == 0 ? m->phi0_dev : A.phi[t];
             ma.u = A.u;
-            ma.s = A.s[t];
+            ma.s = t == 0 ? m->at(m->off_emb) : A.s[t];
             ma.v = A.v[t];
             ma.sn = A.sn[t];
             ma.v1 = A.v1[t];
@@ -419,7 +406,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         else gemm<E_ADD>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * n, nullptr, nullptr, 0, A.gv, F);
         {
             MsgArgs ma = msg_args(g, m, L, hop_src);
-            ma.phi = A.phi[t];
+            ma.phi = t == 0 ? m->phi0_dev : A.phi[t];
             ma.v = A.v[t];
             ma.gs1 = A.gs1;
             ma.gv1 = A.gv1;
