@@ -32,4 +32,25 @@ int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, co
               int M, const float *bias = nullptr, float *C2 = nullptr, int ldc2 = 0, const float *R = nullptr,
               int ldr = 0);
 
+// Two chained products C2 = e2(act(A B1) B2) in one kernel, the intermediate
+// kept on chip.  e1 = GE_BIAS_SILU: act = SiLU(x + bias1), the pre-activation
+// x + bias1 also stored to C1; e1 = GE_DSILU: act = x * SiLU'(R1).  e2 =
+// GE_BIAS (+ bias2), GE_STORE or GE_ADD (+ R2).  B1 has at most 128 columns and
+// B2 as many rows.  Returns 0, -1 (unsupported shape or combination) or -5.
+struct GemmChain {
+    int e1 = GE_BIAS_SILU, e2 = GE_BIAS;
+    const float *A = nullptr;
+    int lda = 0, M = 0;
+    const PackedW *B1 = nullptr, *B2 = nullptr;
+    float *C1 = nullptr;
+    int ldc1 = 0;
+    const float *bias1 = nullptr, *R1 = nullptr;
+    int ldr1 = 0;
+    float *C2 = nullptr;
+    int ldc2 = 0;
+    const float *bias2 = nullptr, *R2 = nullptr;
+    int ldr2 = 0;
+};
+int node_gemm_chain(hipStream_t s, int precision, const GemmChain &c);
+
 }  // namespace mlp

@@ -122,84 +122,52 @@ struct GemmWaves {
     static constexpr int N = KS <= 4 ? 3 : 2;
     static constexpr bool RPRE = !(P == 0 && KS > 4);
 };
-template <int P, int EPI, int KS>
-__global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(GemmWaves<P, KS>::N))) k_gemm(const float *__restrict__ A, int lda, PackedW B, float *C, int ldc,
-                                                  int M, const float *__restrict__ bias, float *__restrict__ C2,
-                                                  int ldc2, const float *R, int ldr) {
-    __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
-    // grid.x is padded to a multiple of 8 (the column chunks of one row block
-    // then run on one XCD and share its L2): padding workgroups leave at once
-    if ((long)blockIdx.x * GW * 16 >= M) return;
-    constexpr int KC = Stage<P>::KC, LDH = Stage<P>::LDH, LDF = Stage<P>::LDF;
-    const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
-    const long m0 = ((long)blockIdx.x * GW + (threadIdx.x >> 6)) * 16;
-    const int n0 = blockIdx.y * NCH;
-    const long arow = m0 + c16;
-    const bool rowok = arow < M;
-    const float *Ar = A + (rowok ? arow : 0) * (long)lda;
-    const int K = B.K;
-    // The wave's 16 x K slice of A, loaded at once (all loads in flight
-    // together) and kept in MFMA operand form: block s covers k = 32 s .. 32 s + 31.
-    v8bf ah[KS], al[KS];
-    v4f af[KS][2];
+// ---------------------------------------------------------------------------
+// Building blocks shared by the single GEMM and the two-GEMM chain.
+// ---------------------------------------------------------------------------
+
+// The wave's 16 x (32 KS) slice of an A operand in MFMA operand form: block s
+// covers k = 32 s .. 32 s + 31 (bf16 forms: lane (c, g) holds k = 32 s + 8 g
+// .. +7 as hi and lo; FP32: k = 32 s + 16 h + 4 g .. +3 for h = 0, 1).
+template <int P, int KS>
+struct AOp {
+    v8bf hi[KS], lo[KS];
+    v4f f[KS][2];
+    // get4(k): the four values of this lane's row at k .. k+3 (zeros past K)
+    template <class Get4>
+    __device__ __forceinline__ void load(int g, Get4 get4) {
 #pragma unroll
-    for (int s = 0; s < KS; s++) {
-        if constexpr (P >= 1) {
-            const int ka = 32 * s + 8 * g;
-            float a[8];
-            if (rowok && ka + 8 <= K) {
-                const v4f x = gld4(Ar + ka), y = gld4(Ar + ka + 4);
+        for (int s = 0; s < KS; s++) {
+            if constexpr (P >= 1) {
+                const v4f x = get4(32 * s + 8 * g), y = get4(32 * s + 8 * g + 4);
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    a[q] = x[q];
-                    a[4 + q] = y[q];
+                for (int q = 0; q < 8; q++) {
+                    const float a = q < 4 ? x[q] : y[q - 4];
+                    hi[s][q] = (__bf16)a;
+                    if (P == 2) lo[s][q] = (__bf16)(a - (float)hi[s][q]);
                 }
             } else {
 #pragma unroll
-                for (int q = 0; q < 8; q++) a[q] = (rowok && ka + q < K) ? Ar[ka + q] : 0.f;
-            }
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-                ah[s][q] = (__bf16)a[q];
-                if (P == 2) al[s][q] = (__bf16)(a[q] - (float)ah[s][q]);
-            }
-        } else {
-#pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const int ka = 32 * s + 16 * h + 4 * g;
-                if (rowok && ka + 4 <= K) {
-                    af[s][h] = gld4(Ar + ka);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 4; q++) af[s][h][q] = (rowok && ka + q < K) ? Ar[ka + q] : 0.f;
-                }
+                for (int h = 0; h < 2; h++) f[s][h] = get4(32 * s + 16 * h + 4 * g);
             }
         }
     }
-    // the epilogue's second operand (R) is fetched now, in the epilogue's
-    // row layout, so its latency overlaps the products
-    constexpr int EIT = 16 * NCH / 4 / 64;
-    const int ncols = min(NCH, B.N - n0);   // a multiple of 4
-    v4f rr[EIT];
-    if constexpr (GemmWaves<P, KS>::RPRE && (EPI == GE_DSILU || EPI == GE_ADD)) {
-#pragma unroll
-        for (int it = 0; it < EIT; it++) {
-            const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
-            const long m = m0 + row;
-            if (m < M && c4 < ncols) rr[it] = gld4(R + m * ldr + n0 + c4);
-        }
-    }
-    v4f acc[CT];
-#pragma unroll
-    for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-    // B moves in stages of KC k-columns: the registers of the next stage are
-    // loaded from L2 while the current stage is multiplied out of LDS.  Each
-    // thread takes a fixed, unrolled share, so all loads of a stage are in
-    // flight together.
+};
+
+// acc[t] (columns n0 + 16 t .. n0 + 16 t + 15) += A[16 rows][0 .. K) B[0 .. K)[n0 .. n0 + 127].
+// B moves through LDS in stages of KC k-columns: the registers of the next
+// stage are loaded from L2 while the current stage is multiplied.  Each
+// thread takes a fixed, unrolled share, so all loads of a stage are in
+// flight together.  Starts with a workgroup barrier (LDS may still be read).
+template <int P, int KS>
+__device__ __forceinline__ void mma_pass(char *lds, const PackedW &B, int n0, int K, const AOp<P, KS> &a,
+                                         v4f *acc) {
+    constexpr int KC = Stage<P>::KC, LDH = Stage<P>::LDH, LDF = Stage<P>::LDF;
     constexpr int VR = P >= 1 ? KC / 8 : KC / 4;   // 16-byte vectors per row of a stage
     constexpr int IT = NCH * VR / (64 * GW);
     static_assert(IT * 64 * GW == NCH * VR, "stage split");
     constexpr int EV = P >= 1 ? 8 : 4;             // k-elements per vector
+    const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
     v8bf sh[IT], sl[IT];
     v4f sf[IT];
     auto fetch = [&](int kc) {
@@ -238,7 +206,7 @@ __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(Ge
 #pragma unroll
     for (int kc = 0; kc < KS * 32; kc += KC) {
         if (kc >= K) break;
-        __syncthreads();   // every wave is done with the previous stage
+        __syncthreads();   // every wave is done with the previous use of LDS
         park(kc);
         __syncthreads();
         if (kc + KC < K) fetch(kc + KC);
@@ -253,10 +221,10 @@ __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(Ge
                     const v8bf bh = *reinterpret_cast<const v8bf *>(bb + 16 * t * LDH);
                     if constexpr (P == 2) {
                         const v8bf bl = *reinterpret_cast<const v8bf *>(bb + 16 * t * LDH + NCH * LDH);
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], bh, acc[t], 0, 0, 0);
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], bl, acc[t], 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo[s], bh, acc[t], 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi[s], bl, acc[t], 0, 0, 0);
                     }
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], bh, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi[s], bh, acc[t], 0, 0, 0);
                 }
             } else {
 #pragma unroll
@@ -267,53 +235,205 @@ __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(Ge
                         const v4f b = *reinterpret_cast<const v4f *>(bb + 16 * t * LDF);
 #pragma unroll
                         for (int q = 0; q < 4; q++)
-                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s][h][q], b[q], acc[t], 0, 0, 0);
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.f[s][h][q], b[q], acc[t], 0, 0, 0);
                     }
                 }
             }
         }
     }
+}
+
+// Parks the wave's 16 x 128 accumulator tile in LDS (row-major, stride LDC)
+// and returns it.  The epilogue then reads it back by rows, so C (and its
+// second operand) move as whole rows in 16-byte vectors: lane + 64 it covers
+// row (lane + 64 it) / 32, columns 4 ((lane + 64 it) % 32) .. +3.
+__device__ __forceinline__ float *park_tile(char *lds, const v4f *acc) {
+    const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+    __syncthreads();   // every wave is done with the B stages in LDS
+    float *ct = reinterpret_cast<float *>(lds) + (threadIdx.x >> 6) * 16 * LDC;
+#pragma unroll
+    for (int t = 0; t < CT; t++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) ct[(4 * g + r) * LDC + 16 * t + c16] = acc[t][r];
+    __syncthreads();
+    return ct;
+}
+constexpr int EIT = 16 * NCH / 4 / 64;   // epilogue vectors per lane
+
+__device__ __forceinline__ v4f silu4(v4f h) {
+    v4f o;
+#pragma unroll
+    for (int q = 0; q < 4; q++) o[q] = h[q] * g_sigmoid(h[q]);
+    return o;
+}
+__device__ __forceinline__ v4f dsilu4(v4f x, v4f h) {
+    v4f o;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const float sg = g_sigmoid(h[q]);
+        o[q] = x[q] * (sg * (1.0f + h[q] * (1.0f - sg)));
+    }
+    return o;
+}
+
+// The epilogue's second operand of this wave's rows m0 .. m0+15 and columns
+// n0 .. n0 + ncols - 1, in the epilogue's row layout.
+__device__ __forceinline__ void fetch_rows(const float *R, int ldr, long m0, int n0, int ncols, int M, v4f *rr) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int it = 0; it < EIT; it++) {
+        const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
+        const long m = m0 + row;
+        if (m < M && c4 < ncols) rr[it] = gld4(R + m * ldr + n0 + c4);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// C = epilogue(A B), one 128-column chunk (blockIdx.y) per workgroup.
+// ---------------------------------------------------------------------------
+template <int P, int EPI, int KS>
+__global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(GemmWaves<P, KS>::N))) k_gemm(const float *__restrict__ A, int lda, PackedW B, float *C, int ldc,
+                                                  int M, const float *__restrict__ bias, float *__restrict__ C2,
+                                                  int ldc2, const float *R, int ldr) {
+    __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
+    // grid.x is padded to a multiple of 8 (the column chunks of one row block
+    // then run on one XCD and share its L2): padding workgroups leave at once
+    if ((long)blockIdx.x * GW * 16 >= M) return;
+    const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+    const long m0 = ((long)blockIdx.x * GW + (threadIdx.x >> 6)) * 16;
+    const int n0 = blockIdx.y * NCH;
+    const long arow = m0 + c16;
+    const bool rowok = arow < M;
+    const float *Ar = A + (rowok ? arow : 0) * (long)lda;
+    const int K = B.K;
+    // the wave's 16 x K slice of A, loaded at once (all loads in flight together)
+    AOp<P, KS> a;
+    a.load(g, [&](int k) {
+        if (rowok && k + 4 <= K) return gld4(Ar + k);
+        v4f z;
+#pragma unroll
+        for (int q = 0; q < 4; q++) z[q] = (rowok && k + q < K) ? Ar[k + q] : 0.f;
+        return z;
+    });
+    // the epilogue's second operand (R) is fetched now, so its latency
+    // overlaps the products
+    const int ncols = min(NCH, B.N - n0);   // a multiple of 4
+    constexpr bool RPRE = GemmWaves<P, KS>::RPRE && (EPI == GE_DSILU || EPI == GE_ADD);
+    v4f rr[EIT];
+    if constexpr (RPRE) fetch_rows(R, ldr, m0, n0, ncols, M, rr);
+    v4f acc[CT];
+#pragma unroll
+    for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    mma_pass<P, KS>(lds, B, n0, K, a, acc);
+    const float *ct = park_tile(lds, acc);
+#pragma unroll
+    for (int it = 0; it < EIT; it++) {
+        const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
+        const long m = m0 + row;
+        if (m >= M || c4 >= ncols) continue;
+        const int n = n0 + c4;
+        const v4f x = *reinterpret_cast<const v4f *>(ct + row * LDC + c4);
+        v4f o;
+        if constexpr (EPI == GE_STORE) {
+            o = x;
+        } else if constexpr (EPI == GE_BIAS || EPI == GE_BIAS_SILU) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) o[q] = x[q] + bias[n + q];
+            if constexpr (EPI == GE_BIAS_SILU) *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = silu4(o);
+        } else if constexpr (EPI == GE_DSILU) {
+            o = dsilu4(x, RPRE ? rr[it] : gld4(R + m * ldr + n));
+        } else {
+            o = (RPRE ? rr[it] : gld4(R + m * ldr + n)) + x;
+        }
+        *reinterpret_cast<v4f *>(C + m * ldc + n) = o;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two chained products, C2 = epi2(act(A B1) B2), with act the bias + SiLU
+// (E1 = GE_BIAS_SILU; the pre-activation also goes to C1) or the SiLU'
+// gate with the saved pre-activation R1 (E1 = GE_DSILU).  The intermediate
+// (at most 128 columns) stays in the workgroup's LDS tile and becomes the
+// second product's A operand; all column chunks of B2 run in the workgroup.
+// ---------------------------------------------------------------------------
+template <int P, int E1, int E2, int KS>
+__global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(2)))
+k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *C1, int ldc1, const float *__restrict__ bias1,
+             const float *R1, int ldr1, PackedW B2, float *C2, int ldc2, const float *__restrict__ bias2,
+             const float *R2, int ldr2, int M) {
+    __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
+    const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+    const long m0 = ((long)blockIdx.x * GW + (threadIdx.x >> 6)) * 16;
+    const long arow = m0 + c16;
+    const bool rowok = arow < M;
+    const float *Ar = A + (rowok ? arow : 0) * (long)lda;
+    const int K1 = B1.K, N1 = B1.N;
+    float *ct;
     {
-        // Epilogue through LDS: each wave parks its 16 x 128 tile in LDS in the
-        // accumulator layout and reads it back by rows, so C (and R, C2) move
-        // as whole rows in 16-byte vectors (two 512-byte rows per instruction).
-        __syncthreads();   // every wave is done with the B chunk in LDS
-        float *ct = reinterpret_cast<float *>(lds) + (threadIdx.x >> 6) * 16 * LDC;
+        AOp<P, KS> a;
+        a.load(g, [&](int k) {
+            if (rowok && k + 4 <= K1) return gld4(Ar + k);
+            v4f z;
 #pragma unroll
-        for (int t = 0; t < CT; t++)
+            for (int q = 0; q < 4; q++) z[q] = (rowok && k + q < K1) ? Ar[k + q] : 0.f;
+            return z;
+        });
+        v4f rr[EIT];
+        if constexpr (E1 == GE_DSILU) fetch_rows(R1, ldr1, m0, 0, N1, M, rr);
+        v4f acc[CT];
 #pragma unroll
-            for (int r = 0; r < 4; r++) ct[(4 * g + r) * LDC + 16 * t + c16] = acc[t][r];
-        __syncthreads();
+        for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+        mma_pass<P, KS>(lds, B1, 0, K1, a, acc);
+        ct = park_tile(lds, acc);
+        // the activation, written back into the tile (zeros outside the valid
+        // rows and columns, which the second product then reads as padding)
+#pragma unroll
+        for (int it = 0; it < EIT; it++) {
+            const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
+            const long m = m0 + row;
+            v4f y = v4f{0.f, 0.f, 0.f, 0.f};
+            if (m < M && c4 < N1) {
+                const v4f x = *reinterpret_cast<const v4f *>(ct + row * LDC + c4);
+                if constexpr (E1 == GE_BIAS_SILU) {
+                    v4f h;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) h[q] = x[q] + bias1[c4 + q];
+                    *reinterpret_cast<v4f *>(C1 + m * ldc1 + c4) = h;
+                    y = silu4(h);
+                } else {
+                    y = dsilu4(x, rr[it]);
+                }
+            }
+            *reinterpret_cast<v4f *>(ct + row * LDC + c4) = y;
+        }
+        __builtin_amdgcn_wave_barrier();   // each wave reads back only its own tile
+    }
+    AOp<P, 4> a2;   // K2 = N1 <= 128
+    a2.load(g, [&](int k) { return *reinterpret_cast<const v4f *>(ct + c16 * LDC + k); });
+    const int K2 = B2.K;
+    for (int n0 = 0; n0 < B2.N; n0 += NCH) {
+        const int ncols = min(NCH, B2.N - n0);
+        v4f rr[EIT];
+        if constexpr (E2 == GE_ADD) fetch_rows(R2, ldr2, m0, n0, ncols, M, rr);
+        v4f acc[CT];
+#pragma unroll
+        for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+        mma_pass<P, 4>(lds, B2, n0, K2, a2, acc);
+        const float *ct2 = park_tile(lds, acc);
 #pragma unroll
         for (int it = 0; it < EIT; it++) {
             const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
             const long m = m0 + row;
             if (m >= M || c4 >= ncols) continue;
             const int n = n0 + c4;
-            const v4f x = *reinterpret_cast<const v4f *>(ct + row * LDC + c4);
-            v4f o;
-            if (EPI == GE_STORE) {
-                o = x;
-            } else if (EPI == GE_BIAS || EPI == GE_BIAS_SILU) {
+            v4f o = *reinterpret_cast<const v4f *>(ct2 + row * LDC + c4);
+            if constexpr (E2 == GE_BIAS) {
 #pragma unroll
-                for (int q = 0; q < 4; q++) o[q] = x[q] + bias[n + q];
-                if (EPI == GE_BIAS_SILU) {
-                    v4f sl;
-#pragma unroll
-                    for (int q = 0; q < 4; q++) sl[q] = o[q] * g_sigmoid(o[q]);
-                    *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = sl;
-                }
-            } else if (EPI == GE_DSILU) {
-                const v4f h = GemmWaves<P, KS>::RPRE ? rr[it] : gld4(R + m * ldr + n);
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const float sg = g_sigmoid(h[q]);
-                    o[q] = x[q] * (sg * (1.0f + h[q] * (1.0f - sg)));
-                }
-            } else {
-                o = (GemmWaves<P, KS>::RPRE ? rr[it] : gld4(R + m * ldr + n)) + x;
+                for (int q = 0; q < 4; q++) o[q] += bias2[n + q];
+            } else if constexpr (E2 == GE_ADD) {
+                o += rr[it];
             }
-            *reinterpret_cast<v4f *>(C + m * ldc + n) = o;
+            *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = o;
         }
     }
 }
@@ -359,6 +479,40 @@ int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, co
     }
 #undef GE
 #undef GL
+    if (rc) return rc;
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+template <int P, int E1, int E2, int KS>
+static void launch_chain(hipStream_t s, const GemmChain &c) {
+    const unsigned bx = (unsigned)((c.M + 16 * GW - 1) / (16 * GW));
+    k_gemm_chain<P, E1, E2, KS><<<bx, 64 * GW, 0, s>>>(c.A, c.lda, *c.B1, c.C1, c.ldc1, c.bias1, c.R1, c.ldr1, *c.B2,
+                                                        c.C2, c.ldc2, c.bias2, c.R2, c.ldr2, c.M);
+}
+
+template <int P>
+static int chain_p(hipStream_t s, const GemmChain &c) {
+    const int K = c.B1->K;
+    const int ks = K <= 128 ? 4 : (K <= 256 ? 8 : (K <= 384 ? 12 : 0));
+#define CL(E1_, E2_)                                                   \
+    do {                                                               \
+        if (ks == 4) launch_chain<P, E1_, E2_, 4>(s, c);               \
+        else if (ks == 8) launch_chain<P, E1_, E2_, 8>(s, c);          \
+        else launch_chain<P, E1_, E2_, 12>(s, c);                      \
+        return 0;                                                      \
+    } while (0)
+    if (ks == 0) return -1;
+    if (c.e1 == GE_BIAS_SILU && c.e2 == GE_BIAS) CL(GE_BIAS_SILU, GE_BIAS);
+    if (c.e1 == GE_DSILU && c.e2 == GE_STORE) CL(GE_DSILU, GE_STORE);
+    if (c.e1 == GE_DSILU && c.e2 == GE_ADD) CL(GE_DSILU, GE_ADD);
+#undef CL
+    return -1;
+}
+
+int node_gemm_chain(hipStream_t s, int precision, const GemmChain &c) {
+    if (c.M <= 0) return 0;
+    if (c.B1->N > NCH || c.B2->K != c.B1->N) return -1;
+    const int rc = precision == 0 ? chain_p<0>(s, c) : (precision == 1 ? chain_p<1>(s, c) : chain_p<2>(s, c));
     if (rc) return rc;
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }

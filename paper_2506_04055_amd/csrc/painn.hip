@@ -49,6 +49,54 @@ static void gemm(hipStream_t s, int prec, const float *A, int lda, const PackedW
     node_gemm(s, prec, EPI, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr);
 }
 
+// A two-layer MLP (or its adjoint) as one chained GEMM kernel.
+static void gemm2(hipStream_t s, int prec, const GemmChain &c) {
+    if (c.M <= 0) return;
+    ProfScope ps(PK_GEMM, s);
+    node_gemm_chain(s, prec, c);
+}
+
+// phi = W2 silu(W1 s + b1) + b2 and a = W4 silu(W3 [s1; n] + b3) + b4, with
+// the pre-activation h kept for the adjoint
+static GemmChain mlp_fwd(const float *A, int lda, const PackedW &B1, float *h, int F, const float *b1,
+                         const PackedW &B2, float *out, int ldo, const float *b2, int n) {
+    GemmChain c;
+    c.e1 = GE_BIAS_SILU;
+    c.e2 = GE_BIAS;
+    c.A = A;
+    c.lda = lda;
+    c.M = n;
+    c.B1 = &B1;
+    c.C1 = h;
+    c.ldc1 = F;
+    c.bias1 = b1;
+    c.B2 = &B2;
+    c.C2 = out;
+    c.ldc2 = ldo;
+    c.bias2 = b2;
+    return c;
+}
+
+// the adjoint of such an MLP: dx = (silu'(h) * (dout W_out)) W_in (+ R2)
+static GemmChain mlp_bwd(const float *gout, int ldg, const PackedW &B1, const float *h, int F, const PackedW &B2,
+                         float *gx, int ldx, const float *R2, int n) {
+    GemmChain c;
+    c.e1 = GE_DSILU;
+    c.e2 = R2 ? GE_ADD : GE_STORE;
+    c.A = gout;
+    c.lda = ldg;
+    c.M = n;
+    c.B1 = &B1;
+    c.R1 = h;
+    c.ldr1 = F;
+    c.B2 = &B2;
+    c.C2 = gx;
+    c.ldc2 = ldx;
+    c.R2 = R2;
+    c.ldr2 = ldx;
+    return c;
+}
+
 // ---------------------------------------------------------------------------
 // Elementwise node kernels
 // ---------------------------------------------------------------------------
@@ -357,8 +405,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         LayerW L = m->layer(t);
         const int hop_dst = T - 1 - t;
         if (t > 0) {
-            gemm<E_BIAS_SILU>(s, P, A.s[t], F, m->pk[t][WP_W1], A.h1[t], F, n, L.b1, A.tmpF, F);
-            gemm<E_BIAS>(s, P, A.tmpF, F, m->pk[t][WP_W2], A.phi[t], F3, n, L.b2);
+            gemm2(s, P, mlp_fwd(A.s[t], F, m->pk[t][WP_W1], A.h1[t], F, L.b1, m->pk[t][WP_W2], A.phi[t], F3, L.b2, n));
             // u = v * phi_vv: the rows the message pass gathers together with phi_s and phi_vs
             k_vprod<<<nblk((long)n * F / 4, 256), 256, 0, s>>>(A.v[t], A.phi[t], n, F, A.u);
         }
@@ -377,8 +424,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         }
         gemm<E_STORE>(s, P, A.v1[t], F, m->pk[t][WP_UV], A.UV[t], 2 * F, 3 * n);
         k_norm<<<nblk((long)n * F, 256), 256, 0, s>>>(A.UV[t], n, F, m->eps, A.sn[t]);
-        gemm<E_BIAS_SILU>(s, P, A.sn[t], 2 * F, m->pk[t][WP_W3], A.h3[t], F, n, L.b3, A.tmpF, F);
-        gemm<E_BIAS>(s, P, A.tmpF, F, m->pk[t][WP_W4], A.a[t], F3, n, L.b4);
+        gemm2(s, P, mlp_fwd(A.sn[t], 2 * F, m->pk[t][WP_W3], A.h3[t], F, L.b3, m->pk[t][WP_W4], A.a[t], F3, L.b4, n));
         k_update_out<<<nblk((long)n * F, 256), 256, 0, s>>>(A.sn[t], A.v1[t], A.UV[t], A.a[t], n, F, A.s[t + 1],
                                                              A.v[t + 1]);
     }
@@ -398,8 +444,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         const bool last = t == T - 1;   // dE/dv of the last layer's output is zero
         k_update_bwd1<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gs, last ? nullptr : A.gv, A.UV[t], A.a[t], n, F,
                                                              A.ga, A.gUV);
-        gemm<E_DSILU>(s, P, A.ga, F3, m->pk[t][WP_W4T], A.gh3, F, n, nullptr, nullptr, 0, A.h3[t], F);
-        gemm<E_STORE>(s, P, A.gh3, F, m->pk[t][WP_W3T], A.gsn, 2 * F, n);
+        gemm2(s, P, mlp_bwd(A.ga, F3, m->pk[t][WP_W4T], A.h3[t], F, m->pk[t][WP_W3T], A.gsn, 2 * F, nullptr, n));
         k_update_bwd2<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gsn, A.sn[t], A.UV[t], A.gs, n, F, A.gUV, A.gs1);
         // dv1 = [dUv | dVv] [U; V] + dv2 (the residual)
         if (last) gemm<E_STORE>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * n);
@@ -418,8 +463,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             if ((rc = msg_adjoint(s, PF, F, K, ma))) return fail(rc, "adjoint message kernel launch failed");
         }
         if (t == 0) break;   // the embedding carries no gradient
-        gemm<E_DSILU>(s, P, A.gphi, F3, m->pk[t][WP_W2T], A.ga1, F, n, nullptr, nullptr, 0, A.h1[t], F);
-        gemm<E_ADD>(s, P, A.ga1, F, m->pk[t][WP_W1T], A.gs, F, n, nullptr, nullptr, 0, A.gs1, F);
+        gemm2(s, P, mlp_bwd(A.gphi, F3, m->pk[t][WP_W2T], A.h1[t], F, m->pk[t][WP_W1T], A.gs, F, A.gs1, n));
     }
     if ((rc = msg_assemble_G(s, g->rowc.as<int>(), n, ne, g->geom.as<float4>(), g->Gs.as<float4>(), ne, npass * T,
                              g->G.as<float4>())))
