@@ -4,7 +4,7 @@
 
 namespace mlp {
 
-enum { GE_STORE = 0, GE_BIAS = 1, GE_BIAS_SILU = 2, GE_DSILU = 3, GE_ADD = 4 };
+enum { GE_STORE = 0, GE_BIAS = 1, GE_BIAS_SILU = 2, GE_DSILU = 3, GE_ADD = 4, GE_UPDATE = 5, GE_NORM_ADJ = 6 };
 
 // One weight matrix packed as the B operand of C = A B: element (k, n) of B
 // at [n][k] (reduction index contiguous), zero-padded to Np x Kp
@@ -37,6 +37,15 @@ int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, co
 // x + bias1 also stored to C1; e1 = GE_DSILU: act = x * SiLU'(R1).  e2 =
 // GE_BIAS (+ bias2), GE_STORE or GE_ADD (+ R2).  B1 has at most 128 columns and
 // B2 as many rows.  Returns 0, -1 (unsupported shape or combination) or -5.
+// Two further second-stage epilogues apply the gated update of a PaiNN layer
+// (F >= 64, so that the three F-column parts of the output fall in
+// different 128-column chunks, processed in order):
+//   GE_UPDATE (after bias2; the output is a = [a_vv | a_sv | a_ss]):
+//     C2 = a_vv, a_sv (a_ss is not stored), v2 = v1 + a_vv o Uv (if v2),
+//     s2 = s1 + a_sv o <Uv, Vv> + a_ss, with s1 = sn[:, :F];
+//   GE_NORM_ADJ (the output is [ds1 | dn]): C2 = R2 + ds1 (ds1 + ds2, with
+//     R2 = ds2), and dVv += (dn / n) o Vv in gUV, with n = sn[:, F:].
+// UV and gUV hold rows [Uv | Vv] of 2F per (atom, direction).
 struct GemmChain {
     int e1 = GE_BIAS_SILU, e2 = GE_BIAS;
     const float *A = nullptr;
@@ -50,6 +59,9 @@ struct GemmChain {
     int ldc2 = 0;
     const float *bias2 = nullptr, *R2 = nullptr;
     int ldr2 = 0;
+    int F = 0;                                    // feature width of the update epilogues
+    const float *sn = nullptr, *v1 = nullptr, *UV = nullptr;
+    float *s2 = nullptr, *v2 = nullptr, *gUV = nullptr;
 };
 int node_gemm_chain(hipStream_t s, int precision, const GemmChain &c);
 

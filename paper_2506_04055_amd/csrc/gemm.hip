@@ -360,7 +360,8 @@ template <int P, int E1, int E2, int KS>
 __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(2)))
 k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *C1, int ldc1, const float *__restrict__ bias1,
              const float *R1, int ldr1, PackedW B2, float *C2, int ldc2, const float *__restrict__ bias2,
-             const float *R2, int ldr2, int M) {
+             const float *R2, int ldr2, int M, int Fu, const float *sn, const float *v1, const float *UV, float *s2,
+             float *v2, float *gUV) {
     __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
     const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
     const long m0 = ((long)blockIdx.x * GW + (threadIdx.x >> 6)) * 16;
@@ -420,20 +421,73 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *C1, int ld
         for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
         mma_pass<P, 4>(lds, B2, n0, K2, a2, acc);
         const float *ct2 = park_tile(lds, acc);
+        if constexpr (E2 == GE_UPDATE || E2 == GE_NORM_ADJ) {
+            // the update epilogues load several operands per vector: a short
+            // unroll keeps them from being hoisted all at once
+#pragma unroll 2
+            for (int it = 0; it < EIT; it++) {
+                const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
+                const long m = m0 + row;
+                if (m >= M || c4 >= ncols) continue;
+                const int n = n0 + c4;
+                v4f o = *reinterpret_cast<const v4f *>(ct2 + row * LDC + c4);
+                // part of the output: F columns each, features f .. f+3
+                const int part = n / Fu, f = n - part * Fu;
+                if constexpr (E2 == GE_UPDATE) {
+                    // part 0: a_vv, part 1: a_sv, part 2: a_ss
 #pragma unroll
-        for (int it = 0; it < EIT; it++) {
-            const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
-            const long m = m0 + row;
-            if (m >= M || c4 >= ncols) continue;
-            const int n = n0 + c4;
-            v4f o = *reinterpret_cast<const v4f *>(ct2 + row * LDC + c4);
-            if constexpr (E2 == GE_BIAS) {
+                    for (int q = 0; q < 4; q++) o[q] += bias2[n + q];
+                    const float *uv = UV + m * 6 * Fu + f;   // rows (3m + d) of [Uv | Vv]
+                    if (part == 0) {
+                        *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = o;
+                        if (v2)
 #pragma unroll
-                for (int q = 0; q < 4; q++) o[q] += bias2[n + q];
-            } else if constexpr (E2 == GE_ADD) {
-                o += rr[it];
+                            for (int d = 0; d < 3; d++) {
+                                const long b = m * 3 * Fu + d * Fu + f;
+                                *reinterpret_cast<v4f *>(v2 + b) = gld4(v1 + b) + o * gld4(uv + d * 2 * Fu);
+                            }
+                    } else if (part == 1) {
+                        *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = o;
+                        v4f dot = gld4(uv) * gld4(uv + Fu);
+#pragma unroll
+                        for (int d = 1; d < 3; d++) dot += gld4(uv + d * 2 * Fu) * gld4(uv + d * 2 * Fu + Fu);
+                        *reinterpret_cast<v4f *>(s2 + m * Fu + f) = gld4(sn + m * 2 * Fu + f) + o * dot;
+                    } else {
+                        // part 1 of these features was written in an earlier chunk
+                        // (by a thread of this workgroup, before the barrier)
+                        float *sp = s2 + m * Fu + f;
+                        *reinterpret_cast<v4f *>(sp) = gld4(sp) + o;
+                    }
+                } else {
+                    // part 0: ds1, part 1: dn
+                    if (part == 0) {
+                        *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = gld4(R2 + m * ldr2 + n) + o;
+                    } else {
+                        const v4f gn = o / gld4(sn + m * 2 * Fu + Fu + f);
+#pragma unroll
+                        for (int d = 0; d < 3; d++) {
+                            const long b = (3 * m + d) * 2 * Fu + Fu + f;
+                            *reinterpret_cast<v4f *>(gUV + b) = gld4(gUV + b) + gn * gld4(UV + b);
+                        }
+                    }
+                }
             }
-            *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = o;
+        } else {
+#pragma unroll
+            for (int it = 0; it < EIT; it++) {
+                const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
+                const long m = m0 + row;
+                if (m >= M || c4 >= ncols) continue;
+                const int n = n0 + c4;
+                v4f o = *reinterpret_cast<const v4f *>(ct2 + row * LDC + c4);
+                if constexpr (E2 == GE_BIAS) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) o[q] += bias2[n + q];
+                } else if constexpr (E2 == GE_ADD) {
+                    o += rr[it];
+                }
+                *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = o;
+            }
         }
     }
 }
@@ -487,7 +541,8 @@ template <int P, int E1, int E2, int KS>
 static void launch_chain(hipStream_t s, const GemmChain &c) {
     const unsigned bx = (unsigned)((c.M + 16 * GW - 1) / (16 * GW));
     k_gemm_chain<P, E1, E2, KS><<<bx, 64 * GW, 0, s>>>(c.A, c.lda, *c.B1, c.C1, c.ldc1, c.bias1, c.R1, c.ldr1, *c.B2,
-                                                        c.C2, c.ldc2, c.bias2, c.R2, c.ldr2, c.M);
+                                                        c.C2, c.ldc2, c.bias2, c.R2, c.ldr2, c.M, c.F, c.sn, c.v1,
+                                                        c.UV, c.s2, c.v2, c.gUV);
 }
 
 template <int P>
@@ -503,8 +558,10 @@ static int chain_p(hipStream_t s, const GemmChain &c) {
     } while (0)
     if (ks == 0) return -1;
     if (c.e1 == GE_BIAS_SILU && c.e2 == GE_BIAS) CL(GE_BIAS_SILU, GE_BIAS);
+    if (c.e1 == GE_BIAS_SILU && c.e2 == GE_UPDATE) CL(GE_BIAS_SILU, GE_UPDATE);
     if (c.e1 == GE_DSILU && c.e2 == GE_STORE) CL(GE_DSILU, GE_STORE);
     if (c.e1 == GE_DSILU && c.e2 == GE_ADD) CL(GE_DSILU, GE_ADD);
+    if (c.e1 == GE_DSILU && c.e2 == GE_NORM_ADJ) CL(GE_DSILU, GE_NORM_ADJ);
 #undef CL
     return -1;
 }
@@ -512,6 +569,7 @@ static int chain_p(hipStream_t s, const GemmChain &c) {
 int node_gemm_chain(hipStream_t s, int precision, const GemmChain &c) {
     if (c.M <= 0) return 0;
     if (c.B1->N > NCH || c.B2->K != c.B1->N) return -1;
+    if ((c.e2 == GE_UPDATE || c.e2 == GE_NORM_ADJ) && (c.F < 64 || c.F % 4 || c.B2->N % c.F)) return -1;
     const int rc = precision == 0 ? chain_p<0>(s, c) : (precision == 1 ? chain_p<1>(s, c) : chain_p<2>(s, c));
     if (rc) return rc;
     return hipGetLastError() == hipSuccess ? 0 : -5;

@@ -424,9 +424,25 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         }
         gemm<E_STORE>(s, P, A.v1[t], F, m->pk[t][WP_UV], A.UV[t], 2 * F, 3 * n);
         k_norm<<<nblk((long)n * F, 256), 256, 0, s>>>(A.UV[t], n, F, m->eps, A.sn[t]);
-        gemm2(s, P, mlp_fwd(A.sn[t], 2 * F, m->pk[t][WP_W3], A.h3[t], F, L.b3, m->pk[t][WP_W4], A.a[t], F3, L.b4, n));
-        k_update_out<<<nblk((long)n * F, 256), 256, 0, s>>>(A.sn[t], A.v1[t], A.UV[t], A.a[t], n, F, A.s[t + 1],
-                                                             A.v[t + 1]);
+        {
+            GemmChain c = mlp_fwd(A.sn[t], 2 * F, m->pk[t][WP_W3], A.h3[t], F, L.b3, m->pk[t][WP_W4], A.a[t], F3, L.b4, n);
+            if (F >= 64) {
+                // the gated update in the second product's epilogue (the last
+                // layer's v is not needed: the readout takes s only)
+                c.e2 = GE_UPDATE;
+                c.F = F;
+                c.sn = A.sn[t];
+                c.v1 = A.v1[t];
+                c.UV = A.UV[t];
+                c.s2 = A.s[t + 1];
+                c.v2 = t == T - 1 ? nullptr : A.v[t + 1];
+                gemm2(s, P, c);
+            } else {
+                gemm2(s, P, c);
+                k_update_out<<<nblk((long)n * F, 256), 256, 0, s>>>(A.sn[t], A.v1[t], A.UV[t], A.a[t], n, F,
+                                                                     A.s[t + 1], A.v[t + 1]);
+            }
+        }
     }
     // readout and energy
     gemm<E_BIAS>(s, P, A.s[T], F, m->pk_W5, A.h5, Fh, n, m->at(m->off_b5));
@@ -444,8 +460,19 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         const bool last = t == T - 1;   // dE/dv of the last layer's output is zero
         k_update_bwd1<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gs, last ? nullptr : A.gv, A.UV[t], A.a[t], n, F,
                                                              A.ga, A.gUV);
-        gemm2(s, P, mlp_bwd(A.ga, F3, m->pk[t][WP_W4T], A.h3[t], F, m->pk[t][WP_W3T], A.gsn, 2 * F, nullptr, n));
-        k_update_bwd2<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gsn, A.sn[t], A.UV[t], A.gs, n, F, A.gUV, A.gs1);
+        if (F >= 64) {
+            // d[s1 | n] -> ds1 = ds2 + d s1 and dVv += (dn / n) Vv, in the epilogue
+            GemmChain c = mlp_bwd(A.ga, F3, m->pk[t][WP_W4T], A.h3[t], F, m->pk[t][WP_W3T], A.gs1, F, A.gs, n);
+            c.e2 = GE_NORM_ADJ;
+            c.F = F;
+            c.sn = A.sn[t];
+            c.UV = A.UV[t];
+            c.gUV = A.gUV;
+            gemm2(s, P, c);
+        } else {
+            gemm2(s, P, mlp_bwd(A.ga, F3, m->pk[t][WP_W4T], A.h3[t], F, m->pk[t][WP_W3T], A.gsn, 2 * F, nullptr, n));
+            k_update_bwd2<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gsn, A.sn[t], A.UV[t], A.gs, n, F, A.gUV, A.gs1);
+        }
         // dv1 = [dUv | dVv] [U; V] + dv2 (the residual)
         if (last) gemm<E_STORE>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * n);
         else gemm<E_ADD>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * n, nullptr, nullptr, 0, A.gv, F);
