@@ -225,13 +225,14 @@ constexpr int ERED = 1024;
 
 // E_b = sum of U_i over the local atoms of segment b (internal rows
 // [seg[b], seg[b+1]), or [0, n) without segments), in FP64 with a fixed
-// order: one block per segment, strided partial sums, then a tree.  A
+// order: one block per segment, strided partial sums, a butterfly within each
+// wave, then the wave totals in order.  A
 // segment's energy is therefore the same whether it is evaluated alone or
 // packed into a batch.
 __global__ void __launch_bounds__(ERED) k_energy_seg(const float *__restrict__ U, const int *__restrict__ perm,
                                                      const int *__restrict__ seg, int n, int n_local,
                                                      double *__restrict__ E) {
-    __shared__ double sh[ERED];
+    __shared__ double sh[ERED / 64];
     const int b = blockIdx.x;
     const int a = seg ? seg[b] : 0, e = seg ? seg[b + 1] : n;
     // eight interleaved partial sums per thread; the row's energy and its
@@ -250,13 +251,17 @@ __global__ void __launch_bounds__(ERED) k_energy_seg(const float *__restrict__ U
         for (int q = 0; q < 8; q++)
             if (pm[q] < n_local) acc[q] += (double)u[q];
     }
-    sh[threadIdx.x] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    double x = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    // butterfly within each wave, then the waves' totals in wave order
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
     __syncthreads();
-    for (int off = ERED / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < ERED / 64; w++) s += sh[w];
+        E[b] = s;
     }
-    if (threadIdx.x == 0) E[b] = sh[0];
 }
 
 // F_k = sum over in-edges e of (G at rev(e)) - (G at e), scattered to the
