@@ -47,6 +47,9 @@ namespace mlp {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
 template <int P, int K>
 struct Basis {
@@ -163,12 +166,21 @@ struct BOp<1, K> {
 template <int K>
 struct BOp<2, K> {
     v8bf v, lo;
+    // pairs go through the packed conversion, and hi is widened back from
+    // the packed word, so each value costs one conversion half, one shift or
+    // mask and one subtraction
     __device__ __forceinline__ void set(const float *eb) {
+        v4u hv, lv;
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            v[q] = (__bf16)eb[q];
-            lo[q] = (__bf16)(eb[q] - (float)v[q]);
+        for (int q = 0; q < 4; q++) {
+            // element 2q is the low half of word q, element 2q + 1 the high half
+            const unsigned hw = __builtin_bit_cast(unsigned, __builtin_convertvector((v2f){eb[2 * q], eb[2 * q + 1]}, v2bf));
+            const float h0 = __uint_as_float(hw << 16), h1 = __uint_as_float(hw & 0xffff0000u);
+            hv[q] = hw;
+            lv[q] = __builtin_bit_cast(unsigned, __builtin_convertvector((v2f){eb[2 * q] - h0, eb[2 * q + 1] - h1}, v2bf));
         }
+        v = __builtin_bit_cast(v8bf, hv);
+        lo = __builtin_bit_cast(v8bf, lv);
     }
 };
 
@@ -253,6 +265,10 @@ __device__ __forceinline__ float row_sum16(float x) {
     x += dpp<0x124>(x);   // row_ror:4
     x += dpp<0x4E>(x);    // quad_perm [2,3,0,1]
     x += dpp<0xB1>(x);    // quad_perm [1,0,3,2]
+    // materialise the total here: otherwise the last add sinks into the
+    // lane-0 store branch, where it cannot take the DPP operand and costs a
+    // zeroed register, a DPP move and a plain add per value
+    asm volatile("" : "+v"(x));
     return x;
 }
 
