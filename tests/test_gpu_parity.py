@@ -6,12 +6,17 @@ relative (per-atom FP32 energies summed in FP64).  Integer results (neighbour
 sets, hop counts) are compared exactly, with the oracle taking the pair
 decision in float32 by the same formula.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
 from paper_2506_04055_amd import synth
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 F_TOL_FP32 = 1e-5
 E_TOL_FP32 = 2e-6
@@ -72,12 +77,40 @@ def test_neighbor_graph_exact_large_cells(mlp, oracle):
     assert np.array_equal(dst, od) and np.array_equal(src, os_)
 
 
+def test_neighbor_counts_on_fcc_shells(mlp):
+    # perfect fcc (a = 4.05, 6^3 cells): every atom has the textbook shell
+    # counts within rc + skin = 6 A (shells 1-4) and, after pruning, within
+    # rc = 5 A (shells 1-3); lattice sites sit exactly on cell boundaries
+    with open(os.path.join(GOLDEN, "lattice_shells.json")) as f:
+        cnt = json.load(f)["fcc"]["count"]
+    s = synth.fcc_crystal(6, sigma=0.0)
+    hdr, w = synth.make_weights(32, 8, 1, 1, seed=0)
+    model = mlp.Model(hdr, w)
+    d = mlp.System(model, s.pos, s.species, s.box, skin=1.0)
+    dst, src = mlp.mlp_nbr_edges(d.nbr, 0)
+    assert np.all(np.bincount(dst, minlength=s.n_atoms) == sum(cnt[:4]))
+    d.compute()
+    dst, src = mlp.mlp_nbr_edges(d.nbr, 1)
+    assert np.all(np.bincount(dst, minlength=s.n_atoms) == sum(cnt[:3]))
+
+
 def test_water192_energy_forces(mlp, oracle):
     s, hdr, w = synth.workload("water192")
     E_ref, F_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box)
     r = run_gpu(mlp, s, hdr, w)
     assert abs(r["E"] - E_ref) <= E_TOL_FP32 * abs(E_ref)
     assert rel_rms(r["F"], F_ref) <= F_TOL_FP32
+
+
+@pytest.mark.parametrize("precision,e_tol,f_tol", [("fp32", E_TOL_FP32, F_TOL_FP32), ("bf16", 1e-2, 1e-2)])
+def test_water192_against_stored_oracle(mlp, precision, e_tol, f_tol):
+    # the oracle's stored result (tests/golden/oracle_water192.json)
+    with open(os.path.join(GOLDEN, "oracle_water192.json")) as f:
+        ref = json.load(f)
+    s, hdr, w = synth.workload("water192")
+    r = run_gpu(mlp, s, hdr, w, precision=precision)
+    assert abs(r["E"] - ref["energy"]) <= e_tol * abs(ref["energy"])
+    assert rel_rms(r["F"], np.array(ref["forces"], np.float64)) <= f_tol
 
 
 def test_biases_and_three_species(mlp, oracle):

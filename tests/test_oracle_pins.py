@@ -6,7 +6,9 @@ translation, permutation), periodic replication, the ghost-shell statement of
 Eqs. (1)-(2), and special weight choices under which the network reduces to a
 closed form (isolated atoms, an embedded-atom model, a collinear chain).
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -29,15 +31,45 @@ def dsilu(x):
 
 # ---------------------------------------------------------------- neighbours
 
-@pytest.mark.parametrize("cut,expect", [(1.5, 18), (1.8, 26), (2.1, 32)])
-def test_simple_cubic_shell_counts(oracle, cut, expect):
-    # simple cubic, spacing 1: shells 6 @1, 12 @sqrt2, 8 @sqrt3, 6 @2
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _shells(name):
+    with open(os.path.join(GOLDEN, "lattice_shells.json")) as f:
+        d = json.load(f)[name]
+    return np.array(d["squared_length"], np.float64), np.array(d["count"], np.int64)
+
+
+def _cuts_between_shells(sq):
+    # one cutoff between each pair of consecutive shells, and one past the last
+    mids = np.sqrt(0.5 * (sq[:-1] + sq[1:]))
+    return np.append(mids, np.sqrt(sq[-1] + 0.5))
+
+
+def test_simple_cubic_shell_counts(oracle):
+    # simple cubic, spacing 1, in a 5 x 5 x 5 periodic box: every atom's
+    # neighbour count within each cutoff is the cumulative shell count (cutoffs
+    # past L / 2 take several images of one atom)
+    sq, cnt = _shells("simple_cubic")
     n = 5
     g = np.arange(n, dtype=np.float64)
     pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3) + 0.25
-    dst, src, dv = oracle.neighbors(pos, np.array([5.0, 5.0, 5.0]), cut)
-    counts = np.bincount(dst, minlength=n**3)
-    assert np.all(counts == expect)
+    for cut, expect in zip(_cuts_between_shells(sq), np.cumsum(cnt)):
+        dst, src, dv = oracle.neighbors(pos, np.array([5.0, 5.0, 5.0]), cut)
+        assert np.all(np.bincount(dst, minlength=n**3) == expect), (cut, expect)
+
+
+def test_fcc_shell_counts(oracle):
+    # perfect fcc, a = 4.05: shell m at squared distance (a/2)^2 2m; the third
+    # shell (24 at a sqrt(3/2) = 4.96 A) lies inside the 5 A cutoff
+    sq, cnt = _shells("fcc")
+    s = synth.fcc_crystal(3, sigma=0.0)
+    half = 4.05 / 2
+    for cut, expect in zip(_cuts_between_shells(sq), np.cumsum(cnt)):
+        dst, src, dv = oracle.neighbors(s.pos, s.box, half * cut)
+        assert np.all(np.bincount(dst, minlength=s.n_atoms) == expect), (cut, expect)
+    dst, src, dv = oracle.neighbors(s.pos, s.box, 5.0)
+    assert np.all(np.bincount(dst, minlength=s.n_atoms) == cnt[:3].sum())
 
 
 @pytest.mark.parametrize("cut,expect", [(1.5, 18), (2.1, 32)])
@@ -48,13 +80,6 @@ def test_self_images_in_tiny_box(oracle, cut, expect):
     r = np.linalg.norm(dv, axis=1)
     assert np.allclose(np.sort(np.round(r**2)), np.sort(np.round(r**2)))
     assert np.all(np.abs(r**2 - np.round(r**2)) < 1e-12)
-
-
-def test_fcc_shell_count(oracle):
-    # perfect fcc, a = 4.05: 12 @ a/sqrt2, 6 @ a, 24 @ a*sqrt(3/2) = 4.96 < 5
-    s = synth.fcc_crystal(3, sigma=0.0)
-    dst, src, dv = oracle.neighbors(s.pos, s.box, 5.0)
-    assert np.all(np.bincount(dst, minlength=s.n_atoms) == 42)
 
 
 def test_neighbor_symmetry_and_f32_agreement(oracle):
