@@ -48,7 +48,7 @@ def _gpu_domain(mlp, dom, hdr, w, precision, owner):
     return res
 
 
-@pytest.mark.parametrize("precision,ftol,etol", [("fp32", 5e-5, 2e-5), ("bf16", 3e-2, 5e-2)])
+@pytest.mark.parametrize("precision,ftol,etol", [("fp32", 2e-5, 2e-5), ("bf16", 1e-2, 1e-2)])
 def test_fcc_million_atom_domain_sampled(mlp, oracle, fcc_domain, precision, ftol, etol):
     dom = fcc_domain
     T = 3
@@ -65,11 +65,13 @@ def test_fcc_million_atom_domain_sampled(mlp, oracle, fcc_domain, precision, fto
     u_scale = np.abs(U[: dom.n_local]).mean()
     # per-atom energies of sampled local atoms (one deep inside, others random)
     samples = [dom.n_local // 2] + rng.choice(dom.n_local, 2, replace=False).tolist()
+    u_err, f_err = [], []
     for i in samples:
         near = np.nonzero(((p - p[i]) ** 2).sum(1) < (T * 5.0) ** 2)[0]
         order = np.concatenate([[i], near[near != i]])
         Eo, _, Uo = oracle.energy_forces(hdr, w, p[order], dom.species[order], np.zeros(3), n_local=1,
                                          per_atom=True)
+        u_err.append(abs(U[i] - Eo) / u_scale)
         assert abs(U[i] - Eo) <= etol * u_scale
     # partial forces of the local energy on sampled rows (a local and a ghost)
     for k in [samples[1], dom.n_local + int(rng.integers(dom.n_atoms - dom.n_local))]:
@@ -80,7 +82,10 @@ def test_fcc_million_atom_domain_sampled(mlp, oracle, fcc_domain, precision, fto
         order = np.concatenate([loc, rest])
         _, Fo = oracle.energy_forces(hdr, w, p[order], dom.species[order], np.zeros(3), n_local=len(loc))
         kk = int(np.nonzero(order == k)[0][0])
+        f_err.append(np.linalg.norm(F_raw[k] - Fo[kk]) / f_rms)
         assert np.linalg.norm(F_raw[k] - Fo[kk]) <= ftol * f_rms
+    print(f"[measured] fcc 1M domain {precision}: sampled |dU|/mean|U| max {max(u_err):.2e}, "
+          f"sampled |dF_k|/rms|F| max {max(f_err):.2e}")
 
 
 def test_fcc_million_atom_fold_properties(mlp, fcc_domain):
@@ -107,6 +112,9 @@ def test_slab_full_size(mlp, oracle, precision, ftol):
     out = d.compute(stats=True)
     torch.cuda.synchronize()
     F = out["forces"].t().cpu().numpy().astype(np.float64)
+    E = float(out["energy"].item())
+    print(f"[measured] slab 48k {precision}: force rel RMS {np.linalg.norm(F - F_ref) / np.linalg.norm(F_ref):.2e}, "
+          f"energy rel {abs(E - E_ref) / abs(E_ref):.2e}")
     assert np.linalg.norm(F - F_ref) / np.linalg.norm(F_ref) <= ftol
     # vacuum gap: the vapour molecules' neighbourhoods are sparse
     assert out["stats"]["n_edges"] < 60 * s.n_atoms

@@ -139,6 +139,8 @@ def test_full_size_24k_water(mlp, oracle):
     s, hdr, w = synth.workload("water24k")
     E_ref, F_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box)
     r = run_gpu(mlp, s, hdr, w, stats=True)
+    print(f"[measured] water24k fp32: force rel RMS {rel_rms(r['F'], F_ref):.2e}, "
+          f"energy rel {abs(r['E'] - E_ref) / abs(E_ref):.2e}")
     assert abs(r["E"] - E_ref) <= E_TOL_FP32 * abs(E_ref)
     assert rel_rms(r["F"], F_ref) <= F_TOL_FP32
     st = r["stats"]
@@ -271,6 +273,8 @@ def test_bf16_energy_forces(mlp, oracle, name, precision):
     s, hdr, w = synth.workload(name)
     E_ref, F_ref, U_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box, per_atom=True)
     r = run_gpu(mlp, s, hdr, w, precision=precision)
+    print(f"[measured] {name} {precision}: force rel RMS {rel_rms(r['F'], F_ref):.2e}, "
+          f"energy rel {abs(r['E'] - E_ref) / abs(E_ref):.2e}")
     assert abs(r["E"] - E_ref) <= E_TOL_BF16 * np.abs(U_ref).sum()
     assert rel_rms(r["F"], F_ref) <= F_TOL_BF16
 
@@ -281,5 +285,8 @@ def test_bf16_ghost_domain(mlp, oracle):
     E_ref, F_ref, U_ref = oracle.energy_forces(hdr, w, dom.pos, dom.species, np.zeros(3), n_local=dom.n_local,
                                                per_atom=True)
     r = run_gpu(mlp, dom, hdr, w, precision="bf16", skin=0.5)
+    print(f"[measured] fcc ghost domain bf16: force rel RMS "
+          f"{rel_rms(r['F'], oracle.fold_ghost_forces(F_ref, dom.n_local, dom.owner)):.2e}, "
+          f"energy rel {abs(r['E'] - E_ref) / abs(E_ref):.2e}")
     assert abs(r["E"] - E_ref) <= E_TOL_BF16 * np.abs(U_ref[: dom.n_local]).sum()
     assert rel_rms(r["F"], oracle.fold_ghost_forces(F_ref, dom.n_local, dom.owner)) <= F_TOL_BF16

@@ -65,15 +65,22 @@ def test_alone_equals_in_the_mix(mlp, precision):
     server.close()
 
 
-def test_served_result_matches_oracle(mlp, oracle):
-    hdr, w = synth.make_weights(64, 20, 3, 4, seed=6, bias_scale=0.1)
-    model = mlp.Model(hdr, w, "fp32")
+@pytest.mark.parametrize("precision,model_args,e_tol,f_tol", [
+    ("fp32", dict(F=64, K=20, T=3, n_species=4, seed=6, bias_scale=0.1), 2e-6, 1e-5),
+    # the serving benchmark's model and precision
+    ("bf16", dict(F=128, K=20, T=3, n_species=4, seed=0), 1e-2, 1e-2)])
+def test_served_result_matches_oracle(mlp, oracle, precision, model_args, e_tol, f_tol):
+    hdr, w = synth.make_weights(**model_args)
+    model = mlp.Model(hdr, w, precision)
     s = synth.peptide_like(900, seed=7)
     server = mlp.Server(model, hbm_budget_bytes=2 << 30, max_slots=4)
     (E, F, tm), = wait_all(server, [server.submit(s.pos, s.species, s.box)], [s.n_atoms])
     E_ref, F_ref = oracle.energy_forces(hdr, w, s.pos, s.species, s.box)
-    assert abs(E - E_ref) <= 2e-6 * abs(E_ref)
-    assert np.linalg.norm(F - F_ref) / np.linalg.norm(F_ref) <= 1e-5
+    f_err = np.linalg.norm(F - F_ref) / np.linalg.norm(F_ref)
+    print(f"[measured] served 900-atom request {precision}: force rel RMS {f_err:.2e}, "
+          f"energy rel {abs(E - E_ref) / abs(E_ref):.2e}")
+    assert abs(E - E_ref) <= e_tol * abs(E_ref)
+    assert f_err <= f_tol
     server.close()
 
 
