@@ -128,31 +128,35 @@ void fail_req(Req *r, int code, const char *msg) {
     r->errmsg = msg ? msg : "";
 }
 
-// Copy, build and prune one admitted request on the prep stream.
-void prepare(mlp_server *S, Req *r) {
+// Copy, build and prune one admitted request on the prep stream.  Runs
+// without the lock and changes no state a poller reads: the caller publishes
+// the outcome (ready, or failed with the slot released) under the lock, so a
+// poller never sees a failed request while the scheduler still holds it.
+int prepare(mlp_server *S, Req *r, std::string *msg) {
     Slot &sl = S->slots[r->slot];
     int *G = &sl.nbr->n_grows;
-    if (sl.pos.ensure(sizeof(float) * 3 * (size_t)r->n, 1.2, G) || sl.species.ensure(sizeof(int) * (size_t)r->n, 1.2, G)) {
-        fail_req(r, MLP_ERR_OOM, mlp_last_error());
-        return;
-    }
-    hipMemcpyAsync(sl.pos.p, r->h_pos, sizeof(float) * 3 * r->n, hipMemcpyHostToDevice, S->s_prep);
-    hipMemcpyAsync(sl.species.p, r->h_species, sizeof(int) * r->n, hipMemcpyHostToDevice, S->s_prep);
+    int rc = sl.pos.ensure(sizeof(float) * 3 * (size_t)r->n, 1.2, G);
+    if (!rc) rc = sl.species.ensure(sizeof(int) * (size_t)r->n, 1.2, G);
+    if (!rc && (hipMemcpyAsync(sl.pos.p, r->h_pos, sizeof(float) * 3 * r->n, hipMemcpyHostToDevice, S->s_prep) !=
+                    hipSuccess ||
+                hipMemcpyAsync(sl.species.p, r->h_species, sizeof(int) * r->n, hipMemcpyHostToDevice, S->s_prep) !=
+                    hipSuccess))
+        rc = fail(MLP_ERR_DEVICE, "request upload failed");
     mlp_nbr *g = sl.nbr;
-    int rc = build_graph(S->m, g, sl.pos.as<float>(), sl.species.as<int>(), r->n, r->n, r->box, S->skin, S->s_prep);
+    if (!rc) rc = build_graph(S->m, g, sl.pos.as<float>(), sl.species.as<int>(), r->n, r->n, r->box, S->skin, S->s_prep);
     if (!rc) rc = prune_graph(S->m, g, sl.pos.as<float>(), S->s_prep);
-    if (rc) {
-        fail_req(r, rc, mlp_last_error());
-        return;
-    }
     int Ec = 0;
-    if (hipMemcpyAsync(&Ec, g->rowc.as<int>() + r->n, sizeof(int), hipMemcpyDeviceToHost, S->s_prep) != hipSuccess ||
-        hipStreamSynchronize(S->s_prep) != hipSuccess) {
-        fail_req(r, MLP_ERR_DEVICE, "prep stream failed");
-        return;
+    if (!rc && (hipMemcpyAsync(&Ec, g->rowc.as<int>() + r->n, sizeof(int), hipMemcpyDeviceToHost, S->s_prep) !=
+                    hipSuccess ||
+                hipStreamSynchronize(S->s_prep) != hipSuccess))
+        rc = fail(MLP_ERR_DEVICE, "prep stream failed");
+    if (rc) {
+        (void)hipStreamSynchronize(S->s_prep);   // nothing of this request is still in flight on the slot
+        *msg = mlp_last_error();
+        return rc;
     }
     r->n_edges = Ec;
-    r->state = 2;
+    return 0;
 }
 
 // Pack all ready requests and launch one evaluation on the compute stream.
@@ -199,8 +203,13 @@ int launch_wave(mlp_server *S) {
         S->h_seg[b] = (int)aoff;
         aoff += r->n;
         eoff += r->n_edges;
-        r->state = 3;
-        r->batch_size = B;
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (Req *r : W) {
+            r->state = 3;
+            r->batch_size = B;
+        }
     }
     S->h_seg[B] = (int)aoff;
     HIP_TRY(hipMemcpyAsync(S->seg.p, S->h_seg.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, S->s_comp));
@@ -270,21 +279,44 @@ void scheduler(mlp_server *S) {
             }
         }
         for (Req *r : admitted) {
-            prepare(S, r);
+            std::string msg;
+            const int rc = prepare(S, r, &msg);
             std::lock_guard<std::mutex> lk(S->mu);
-            if (r->state == 2) {
+            if (rc == 0) {
+                r->state = 2;
                 S->ready.push_back(r);
             } else {
+                fail_req(r, rc, msg.c_str());
                 S->slots[r->slot].busy = false;
                 S->reserved -= r->bytes;
                 r->slot = -1;
                 r->t_done = clk::now();
             }
         }
-        if (S->wave_in_flight && hipEventQuery(S->ev_wave) == hipSuccess) finish_wave(S);
+        if (S->wave_in_flight) {
+            const hipError_t q = hipEventQuery(S->ev_wave);
+            if (q == hipSuccess) {
+                finish_wave(S);
+            } else if (q != hipErrorNotReady) {
+                // the wave failed on the device: its requests fail instead of waiting forever
+                (void)hipStreamSynchronize(S->s_comp);
+                std::lock_guard<std::mutex> lk(S->mu);
+                for (Req *r : S->running) {
+                    fail_req(r, MLP_ERR_DEVICE, "evaluation failed on the device");
+                    S->slots[r->slot].busy = false;
+                    S->reserved -= r->bytes;
+                    r->slot = -1;
+                    r->t_done = clk::now();
+                }
+                S->running.clear();
+                S->wave_in_flight = false;
+            }
+        }
         if (!S->wave_in_flight && !S->ready.empty()) {
             int rc = launch_wave(S);
             if (rc) {
+                // kernels of the partly launched wave may still read the slots
+                (void)hipStreamSynchronize(S->s_comp);
                 std::lock_guard<std::mutex> lk(S->mu);
                 for (Req *r : S->running) {
                     fail_req(r, rc, mlp_last_error());
