@@ -245,9 +245,12 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
         prc = mlp::first_layer_table(m, nullptr, tab + 3 * (size_t)S * F);
     }
     if (prc == 0 && hipDeviceSynchronize() != hipSuccess) prc = MLP_ERR_DEVICE;
+    // the factorised first layer's species-scaled filter weights (one or two species)
+    if (prc == 0) prc = mlp::first_layer_factor(m);
     if (prc) {
         (void)hipGetLastError();
         if (tab) hipFree(tab);
+        if (m->pk_l0_dev) hipFree(m->pk_l0_dev);
         if (m->pk_dev) hipFree(m->pk_dev);
         hipFree(m->w_dev);
         delete m;
@@ -263,6 +266,7 @@ int mlp_model_destroy(mlp_model *m) {
     if (m->wb_dev) hipFree(m->wb_dev);
     if (m->pk_dev) hipFree(m->pk_dev);
     if (m->phi0_dev) hipFree(m->phi0_dev);
+    if (m->pk_l0_dev) hipFree(m->pk_l0_dev);
     delete m;
     return MLP_OK;
 }

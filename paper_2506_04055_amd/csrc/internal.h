@@ -71,6 +71,12 @@ struct mlp_model {
     // phi of the first layer per species ([S][3F]): s = emb[species] there, so
     // the first message MLP depends on the species alone
     float *phi0_dev = nullptr;
+    // factorised first layer (one or two species): the species-scaled filter
+    // weights packed as B operands: [0] forward s (with the embedding rows),
+    // [1] forward v, [2] adjoint s, [3] adjoint v
+    bool l0f = false;
+    mlp::PackedW pk_l0[4];
+    void *pk_l0_dev = nullptr;
     mlp::LayerW layer(int t) const;
     const float *at(size_t off) const { return w_dev + off; }
     const __hip_bfloat16 *atb(size_t off) const { return wb_dev + off; }
@@ -138,6 +144,10 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
 // Fill m->phi0_dev (device, S x 3F) from the embedding and the first layer's
 // message MLP, in the model's precision; tmp: device scratch of 2 S F floats.
 int first_layer_table(mlp_model *m, hipStream_t s, float *tmp);
+// Pack m->pk_l0 from the first layer's filter, phi0 and the embedding (after
+// first_layer_table); sets m->l0f.  Leaves m->l0f false where the build has
+// no factorised first layer for the model's (F, K, n_species).
+int first_layer_factor(mlp_model *m);
 int verlet_kick_drift(float *pos, float *vel, const float *forces, const float *inv_mass, int n,
                       const double box[3], float dt, hipStream_t s);
 int verlet_kick(float *vel, const float *forces, const float *inv_mass, int n, float dt, hipStream_t s);

@@ -32,6 +32,31 @@ struct MsgArgs {
 int msg_forward(hipStream_t st, int precision, int F, int K, const MsgArgs &a);
 int msg_adjoint(hipStream_t st, int precision, int F, int K, const MsgArgs &a);
 
+// The factorised first layer (msg.hip): per-atom, per-species sums of the
+// radial basis (forward) and the edge sums of the adjoint from the per-atom
+// vectors Q.  Layouts: P rows i of ldp floats, columns Z (K+1) + k then the
+// species one-hot at S (K+1) + Z; R, Q_v rows 3 i + d; Q_s rows i; all with
+// the basis slot k = 0 .. K of species Z at column Z (K+1) + k.
+struct L0Args {
+    const int *rowc, *colc, *revc;
+    const float4 *geom;
+    int n;
+    float rc;
+    const int8_t *hop;
+    int hop_max;
+    const int *species;
+    float *P, *R;             // forward outputs
+    int ldp, ldr;
+    const float *Qs, *Qv;     // adjoint inputs
+    int ldq;
+    float4 *S;                // adjoint output: the layer's single edge-sum slot
+};
+// Whether this build has the factorised first layer for (K, n_species).
+bool l0_factorised(int K, int S);
+// Return 0, -1 (unsupported K, S) or -5 (launch error).
+int msg_l0_basis_sums(hipStream_t st, int K, int S, const L0Args &a);
+int msg_l0_edge_sums(hipStream_t st, int K, int S, const L0Args &a);
+
 // Feature passes of the adjoint (edge-sum slots per layer).
 int msg_passes(int F);
 // G[e] over the pruned edges (count rowc[n], at most ne_max), assembled from

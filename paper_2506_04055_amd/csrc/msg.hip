@@ -693,6 +693,163 @@ __global__ void k_assemble_G(const int *__restrict__ rowc, int n, const float4 *
     }
 }
 
+// ---------------------------------------------------------------------------
+// First layer, factorised.  There v = 0 and phi_j = phi(Z_j) depends on the
+// species alone, while the messages are linear in the radial basis e~, so the
+// sums over neighbours collapse to per-atom, per-species basis sums:
+//   s1_i = s0(Z_i) + sum_Z phi_s(Z) o (A'_s P_i^Z),    P_i^Z   = sum_{j: Z_j = Z} e~(r_ij),
+//   v1_i = sum_Z phi_vs(Z) o (A'_vs R_i^{Z,d}),        R_i^{Z,d} = sum_{j: Z_j = Z} rhat_ij,d e~(r_ij),
+// and the adjoint's edge sums of the message edge (i <- j) need only the
+// per-atom vectors Q_s[i][Z] = A'_s^T (gs1_i o phi_s(Z)) and
+// Q_d[i][Z] = A'_vs^T (gv1_i,d o phi_vs(Z)):
+//   dE/dr = de~ . (Q_s + sum_d rhat_d Q_d),   dE/drhat_d = e~ . Q_d.
+// The products with the species-scaled filter weights (phi(Z) o A') are node
+// GEMMs; the two kernels below do the O(K) work per edge.  Rows of P: the
+// S (K+1) basis sums (column Z (K+1) + k) then the species one-hot (column
+// S (K+1) + Z), which picks s0(Z_i) out of the same GEMM; rows 3 i + d of R
+// and of Q_v, rows i of Q_s: column Z (K+1) + k.  Lane (g, e) = 16 g + e
+// holds basis slots k = 8 g .. 8 g + 7 of edge e, as in the kernels above.
+// ---------------------------------------------------------------------------
+template <int K, int SS>
+__global__ void __launch_bounds__(256) k_l0_basis_sums(const int *__restrict__ rowc, const int *__restrict__ colc,
+                                                       const float4 *__restrict__ geom, int n, float rc,
+                                                       const int8_t *__restrict__ hop, int hop_max,
+                                                       const int *__restrict__ zsp, float *__restrict__ P, int ldp,
+                                                       float *__restrict__ R, int ldr) {
+    constexpr int KS1 = K + 1;
+    const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
+    const float pirc = 3.14159265358979f / rc;
+    const int nw = (int)(gridDim.x * (blockDim.x >> 6));
+    for (int i = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); i < n; i += nw) {
+        const int e0 = rowc[i], e1 = rowc[i + 1];
+        const int deg = hop[i] <= hop_max ? e1 - e0 : 0;
+        float acc[SS][4][8];
+#pragma unroll
+        for (int z = 0; z < SS; z++)
+#pragma unroll
+            for (int t = 0; t < 4; t++)
+#pragma unroll
+                for (int q = 0; q < 8; q++) acc[z][t][q] = 0.f;
+        for (int cb = 0; cb < deg; cb += 16) {
+            const bool valid = cb + e < deg;
+            float4 gm = make_float4(0.f, 0.f, 0.f, rc);
+            int z = 0;
+            if (valid) {
+                gm = geom[e0 + cb + e];
+                z = zsp[colc[e0 + cb + e]];
+            }
+            const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
+            float eb[8];
+            basis_slots<1, K, false>(gm.w, ir, pirc, valid, g, eb, nullptr);
+            const float wt[4] = {1.f, gm.x * ir, gm.y * ir, gm.z * ir};
+#pragma unroll
+            for (int zz = 0; zz < SS; zz++) {
+                const bool on = z == zz;
+#pragma unroll
+                for (int t = 0; t < 4; t++) {
+                    const float w = on ? wt[t] : 0.f;
+#pragma unroll
+                    for (int q = 0; q < 8; q++) acc[zz][t][q] = fmaf(w, eb[q], acc[zz][t][q]);
+                }
+            }
+        }
+#pragma unroll
+        for (int zz = 0; zz < SS; zz++)
+#pragma unroll
+            for (int t = 0; t < 4; t++)
+#pragma unroll
+                for (int q = 0; q < 8; q++) acc[zz][t][q] = row_sum16(acc[zz][t][q]);
+        if (e == 0) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int k = 8 * g + q;
+                if (k > K) continue;
+#pragma unroll
+                for (int zz = 0; zz < SS; zz++) {
+                    P[(long)i * ldp + zz * KS1 + k] = acc[zz][0][q];
+#pragma unroll
+                    for (int d = 0; d < 3; d++) R[(3L * i + d) * ldr + zz * KS1 + k] = acc[zz][1 + d][q];
+                }
+            }
+        }
+        if (lane < SS) P[(long)i * ldp + SS * KS1 + lane] = zsp[i] == lane ? 1.f : 0.f;
+    }
+}
+
+template <int K, int SS>
+__global__ void __launch_bounds__(256) k_l0_edge_sums(const int *__restrict__ rowc, const int *__restrict__ colc,
+                                                      const int *__restrict__ revc, const float4 *__restrict__ geom,
+                                                      int n, float rc, const int8_t *__restrict__ hop, int hop_max,
+                                                      const int *__restrict__ zsp, const float *__restrict__ Qs,
+                                                      const float *__restrict__ Qv, int ldq, float4 *__restrict__ S) {
+    constexpr int KS1 = K + 1;
+    const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
+    const float pirc = 3.14159265358979f / rc;
+    const int nw = (int)(gridDim.x * (blockDim.x >> 6));
+    for (int i = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); i < n; i += nw) {
+        const int e0 = rowc[i], deg = rowc[i + 1] - e0;
+        if (deg == 0) continue;
+        // this lane's slots of Q_i for every species (zeros past K)
+        float qs[SS][8], qv[SS][3][8];
+#pragma unroll
+        for (int zz = 0; zz < SS; zz++)
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int k = 8 * g + q;
+                const bool in = k <= K;
+                qs[zz][q] = in ? Qs[(long)i * ldq + zz * KS1 + k] : 0.f;
+#pragma unroll
+                for (int d = 0; d < 3; d++) qv[zz][d][q] = in ? Qv[(3L * i + d) * ldq + zz * KS1 + k] : 0.f;
+            }
+        for (int cb = 0; cb < deg; cb += 16) {
+            const bool valid = cb + e < deg;
+            float4 gm = make_float4(0.f, 0.f, 0.f, rc);
+            int j = i;
+            if (valid) {
+                gm = geom[e0 + cb + e];
+                j = colc[e0 + cb + e];
+            }
+            const int z = zsp[j];
+            const bool live = valid && hop[j] <= hop_max;
+            const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
+            float eb[8], db[8];
+            basis_slots<1, K, true>(gm.w, ir, pirc, valid, g, eb, db);
+            // direction of the message edge (i <- j): x_j - x_i
+            const float rx = gm.x * ir, ry = gm.y * ir, rz = gm.z * ir;
+            float sr = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                float a = qs[0][q], bx = qv[0][0][q], by = qv[0][1][q], bz = qv[0][2][q];
+#pragma unroll
+                for (int zz = 1; zz < SS; zz++)
+                    if (z == zz) {
+                        a = qs[zz][q];
+                        bx = qv[zz][0][q];
+                        by = qv[zz][1][q];
+                        bz = qv[zz][2][q];
+                    }
+                sr = fmaf(db[q], fmaf(rx, bx, fmaf(ry, by, fmaf(rz, bz, a))), sr);
+                sx = fmaf(eb[q], bx, sx);
+                sy = fmaf(eb[q], by, sy);
+                sz = fmaf(eb[q], bz, sz);
+            }
+            // sum over the four lane rows (all basis slots)
+            sr += __shfl_xor(sr, 16, 64);
+            sx += __shfl_xor(sx, 16, 64);
+            sy += __shfl_xor(sy, 16, 64);
+            sz += __shfl_xor(sz, 16, 64);
+            sr += __shfl_xor(sr, 32, 64);
+            sx += __shfl_xor(sx, 32, 64);
+            sy += __shfl_xor(sy, 32, 64);
+            sz += __shfl_xor(sz, 32, 64);
+            // the sums of edge (i <- j) go to the slot of its reverse (j <- i),
+            // where the adjoint of the later layers keeps them
+            if (g == 0 && valid)
+                S[revc[e0 + cb + e]] = live ? make_float4(sr, sx, sy, sz) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+}
+
 static int grid_x(int n) {
     int b = std::min((n + MW - 1) / MW, 2048);
     if (b >= 8) b -= b % 8;   // keeps blockIdx.x % 8 the XCD in every pass row
@@ -715,6 +872,46 @@ static int launch_bwd(hipStream_t st, const MsgArgs &a) {
     kern<<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.v, a.gs1, a.gv1, a.A, a.c, a.rc, a.hop,
                                    a.hop_max, a.species, a.gv_in, a.gphi, a.S, a.s_stride);
     return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+static unsigned l0_blocks(int n) { return (unsigned)std::max(1, std::min((n + 3) / 4, 8192)); }
+
+template <int K, int SS>
+static int l0_sums(hipStream_t st, const L0Args &a) {
+    k_l0_basis_sums<K, SS><<<l0_blocks(a.n), 256, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.rc, a.hop, a.hop_max,
+                                                           a.species, a.P, a.ldp, a.R, a.ldr);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+template <int K, int SS>
+static int l0_edges(hipStream_t st, const L0Args &a) {
+    k_l0_edge_sums<K, SS><<<l0_blocks(a.n), 256, 0, st>>>(a.rowc, a.colc, a.revc, a.geom, a.n, a.rc, a.hop,
+                                                          a.hop_max, a.species, a.Qs, a.Qv, a.ldq, a.S);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+#define L0_DISPATCH(FN)                                            \
+    do {                                                           \
+        if (K == 20 && S == 1) return FN<20, 1>(st, a);            \
+        if (K == 20 && S == 2) return FN<20, 2>(st, a);            \
+        if (K == 8 && S == 1) return FN<8, 1>(st, a);              \
+        if (K == 8 && S == 2) return FN<8, 2>(st, a);              \
+        if (K == 6 && S == 1) return FN<6, 1>(st, a);              \
+        if (K == 6 && S == 2) return FN<6, 2>(st, a);              \
+    } while (0)
+
+bool l0_factorised(int K, int S) { return (K == 20 || K == 8 || K == 6) && (S == 1 || S == 2); }
+
+int msg_l0_basis_sums(hipStream_t st, int K, int S, const L0Args &a) {
+    if (a.ldp < S * (K + 1) + S || a.ldr < S * (K + 1)) return -1;
+    L0_DISPATCH(l0_sums);
+    return -1;
+}
+
+int msg_l0_edge_sums(hipStream_t st, int K, int S, const L0Args &a) {
+    if (a.ldq < S * (K + 1)) return -1;
+    L0_DISPATCH(l0_edges);
+    return -1;
 }
 
 int msg_passes(int F) { return F < BWD_W ? 1 : F / BWD_W; }

@@ -376,6 +376,33 @@ static MsgArgs msg_args(mlp_nbr *g, mlp_model *m, const LayerW &L, int hop_max) 
     return a;
 }
 
+struct L0Layout {
+    int ldp, ldr, ldq;
+};
+static L0Layout l0_layout(int F, int K, int S) {
+    const int CS = S * (K + 1);
+    L0Layout l;
+    l.ldp = (CS + S + 3) / 4 * 4;
+    l.ldr = (CS + 3) / 4 * 4;
+    l.ldq = l.ldr;
+    (void)F;
+    return l;
+}
+
+static L0Args l0_args(mlp_nbr *g, mlp_model *m, int hop_max) {
+    L0Args a = {};
+    a.rowc = g->rowc.as<int>();
+    a.colc = g->colc.as<int>();
+    a.revc = g->revc.as<int>();
+    a.geom = g->geom.as<float4>();
+    a.n = g->n_atoms;
+    a.rc = m->rc;
+    a.hop = g->hop.as<int8_t>();
+    a.hop_max = hop_max;
+    a.species = g->species.as<int>();
+    return a;
+}
+
 int first_layer_table(mlp_model *m, hipStream_t s, float *tmp) {
     const int F = m->F, S = m->S;
     const int P = m->precision == MLP_PREC_FP32 ? 0 : (m->precision == MLP_PREC_BF16 ? 2 : 1);
@@ -384,6 +411,70 @@ int first_layer_table(mlp_model *m, hipStream_t s, float *tmp) {
     node_gemm(s, P, GE_BIAS_SILU, m->at(m->off_emb), F, m->pk[0][WP_W1], tmp, F, S, L.b1, tmp + (long)S * F, F);
     node_gemm(s, P, GE_BIAS, tmp + (long)S * F, F, m->pk[0][WP_W2], m->phi0_dev, 3 * F, S, L.b2);
     return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+// Species-scaled first-layer filter weights (CS = S (K+1) columns of basis
+// slots, species-major): Wfs[f][z (K+1) + k] = phi_s(z)_f A'_s[f][k] followed
+// by the embedding columns Wfs[f][CS + z] = emb[z][f]; Wbs the same without
+// the embedding; Wv[f][z (K+1) + k] = phi_vs(z)_f A'_vs[f][k]; A'[.][0] = c.
+__global__ void k_l0_weights(const float *__restrict__ A, const float *__restrict__ c,
+                             const float *__restrict__ phi0, const float *__restrict__ emb, int F, int K, int S,
+                             float *__restrict__ Wfs, float *__restrict__ Wbs, float *__restrict__ Wv) {
+    const int CS = S * (K + 1);
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < (long)F * CS) {
+        const int f = (int)(idx / CS), col = (int)(idx % CS), z = col / (K + 1), k = col % (K + 1);
+        const float as = k == 0 ? c[F + f] : A[(long)(F + f) * K + k - 1];
+        const float av = k == 0 ? c[2 * F + f] : A[(long)(2 * F + f) * K + k - 1];
+        const float ws = phi0[(long)z * 3 * F + F + f] * as;
+        Wfs[(long)f * (CS + S) + col] = ws;
+        Wbs[(long)f * CS + col] = ws;
+        Wv[(long)f * CS + col] = phi0[(long)z * 3 * F + 2 * F + f] * av;
+    } else if (idx < (long)F * CS + (long)F * S) {
+        const long r = idx - (long)F * CS;
+        const int f = (int)(r / S), z = (int)(r % S);
+        Wfs[(long)f * (CS + S) + CS + z] = emb[(long)z * F + f];
+    }
+}
+
+int first_layer_factor(mlp_model *m) {
+    m->l0f = false;
+    const int F = m->F, K = m->K, S = m->S, CS = S * (K + 1);
+    if (!l0_factorised(K, S)) return 0;
+    // P and R (forward), Q_s and Q_v (adjoint) must fit the 6 F floats per
+    // atom of the dUV rows they borrow
+    const L0Layout l0 = l0_layout(F, K, S);
+    if (l0.ldp + 3 * l0.ldr > 6 * F || 4 * l0.ldq > 6 * F) return 0;
+    const LayerW L = m->layer(0);
+    float *src = nullptr;
+    const size_t nfs = (size_t)F * (CS + S), nb = (size_t)F * CS;
+    if (hipMalloc(&src, sizeof(float) * (nfs + 2 * nb)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(-2, "first-layer weight allocation failed");
+    }
+    float *Wfs = src, *Wbs = src + nfs, *Wv = Wbs + nb;
+    const long tot = (long)F * CS + (long)F * S;
+    k_l0_weights<<<nblk(tot, 256), 256>>>(L.A, L.c, m->phi0_dev, m->at(m->off_emb), F, K, S, Wfs, Wbs, Wv);
+    const float *Ws[4] = {Wfs, Wv, Wbs, Wv};
+    const int C[4] = {CS + S, CS, CS, CS};
+    const bool tr[4] = {false, false, true, true};
+    size_t bytes = 0;
+    for (int q = 0; q < 4; q++) bytes += packed_bytes(F, C[q], tr[q]);
+    int rc = hipMalloc(&m->pk_l0_dev, bytes) == hipSuccess ? 0 : -2;
+    for (size_t q = 0, o = 0; rc == 0 && q < 4; q++) {
+        if (pack_weight(nullptr, Ws[q], F, C[q], tr[q], (char *)m->pk_l0_dev + o, &m->pk_l0[q])) rc = -5;
+        o += packed_bytes(F, C[q], tr[q]);
+    }
+    if (hipDeviceSynchronize() != hipSuccess && rc == 0) rc = -5;
+    hipFree(src);
+    if (rc) {
+        (void)hipGetLastError();
+        if (m->pk_l0_dev) hipFree(m->pk_l0_dev);
+        m->pk_l0_dev = nullptr;
+        return fail(rc, "first-layer weight packing failed");
+    }
+    m->l0f = true;
+    return 0;
 }
 
 int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
@@ -404,6 +495,12 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     Act A;
     carve(g->act.as<float>(), n, F, T, A);
     const int *perm = g->perm.as<int>();
+    // edge-sum slots: layers 1 .. T-1 take npass each, from slot 0; the first
+    // layer's come last (one slot when it is factorised)
+    const int slot0 = (T - 1) * npass, nslot = slot0 + (m->l0f ? 1 : npass);
+    // factorised first layer: its matrices live in the adjoint's dUV rows
+    // (free in the first layer's forward, and again once dv1 is formed)
+    const L0Layout l0 = l0_layout(F, K, m->S);
 
     // forward
     for (int t = 0; t < T; t++) {
@@ -414,7 +511,18 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             // u = v * phi_vv: the rows the message pass gathers together with phi_s and phi_vs
             k_vprod<<<nblk((long)n * F / 4, 256), 256, 0, s>>>(A.v[t], A.phi[t], n, F, A.u);
         }
-        {
+        if (t == 0 && m->l0f) {
+            // factorised first layer: basis sums per atom and species, then
+            // s1 = [P | one-hot] Wfs^T (s0 included) and v1 = R Wv^T
+            L0Args la = l0_args(g, m, hop_dst);
+            la.P = A.gUV;
+            la.R = A.gUV + (long)n * l0.ldp;
+            la.ldp = l0.ldp;
+            la.ldr = l0.ldr;
+            if ((rc = msg_l0_basis_sums(s, K, m->S, la))) return fail(rc, "first-layer kernel launch failed");
+            gemm<E_STORE>(s, P, la.P, l0.ldp, m->pk_l0[0], A.sn[0], 2 * F, n);
+            gemm<E_STORE>(s, P, la.R, l0.ldr, m->pk_l0[1], A.v1[0], F, 3 * n);
+        } else {
             MsgArgs ma = msg_args(g, m, L, hop_dst);
             ma.layer0 = t == 0;
             // the first layer reads phi and s from the per-species tables
@@ -481,7 +589,19 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         // dv1 = [dUv | dVv] [U; V] + dv2 (the residual)
         if (last) gemm<E_STORE>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * n);
         else gemm<E_ADD>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * n, nullptr, nullptr, 0, A.gv, F);
-        {
+        if (t == 0 && m->l0f) {
+            // factorised first layer: Q_s = gs1 Wbs, Q_v = gv1 Wv, then the
+            // edge sums from Q in one slot
+            L0Args la = l0_args(g, m, hop_src);
+            float *Qs = A.gUV, *Qv = A.gUV + (long)n * l0.ldq;
+            gemm<E_STORE>(s, P, A.gs1, F, m->pk_l0[2], Qs, l0.ldq, n);
+            gemm<E_STORE>(s, P, A.gv1, F, m->pk_l0[3], Qv, l0.ldq, 3 * n);
+            la.Qs = Qs;
+            la.Qv = Qv;
+            la.ldq = l0.ldq;
+            la.S = g->Gs.as<float4>() + (size_t)slot0 * ne;
+            if ((rc = msg_l0_edge_sums(s, K, m->S, la))) return fail(rc, "first-layer adjoint kernel launch failed");
+        } else {
             MsgArgs ma = msg_args(g, m, L, hop_src);
             ma.phi = t == 0 ? m->phi0_dev : A.phi[t];
             ma.v = A.v[t];
@@ -489,7 +609,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             ma.gv1 = A.gv1;
             ma.gv_in = A.gv;
             ma.gphi = A.gphi;
-            ma.S = g->Gs.as<float4>() + (size_t)t * npass * ne;
+            ma.S = g->Gs.as<float4>() + (size_t)(t == 0 ? slot0 : (t - 1) * npass) * ne;
             ma.layer0 = t == 0;
             ProfScope ps(PK_MSG_BWD, s);
             if ((rc = msg_adjoint(s, PF, F, K, ma))) return fail(rc, "adjoint message kernel launch failed");
@@ -497,7 +617,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         if (t == 0) break;   // the embedding carries no gradient
         gemm2(s, P, mlp_bwd(A.gphi, F3, m->pk[t][WP_W2T], A.h1[t], F, m->pk[t][WP_W1T], A.gs, F, A.gs1, n));
     }
-    if ((rc = msg_assemble_G(s, g->rowc.as<int>(), n, ne, g->geom.as<float4>(), g->Gs.as<float4>(), ne, npass * T,
+    if ((rc = msg_assemble_G(s, g->rowc.as<int>(), n, ne, g->geom.as<float4>(), g->Gs.as<float4>(), ne, nslot,
                              g->G.as<float4>())))
         return fail(rc, "edge-gradient kernel launch failed");
     k_forces<<<nblk(16L * n, 256), 256, 0, s>>>(g->rowc.as<int>(), g->revc.as<int>(), g->G.as<float4>(), perm, n,
