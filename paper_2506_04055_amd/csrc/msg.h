@@ -34,9 +34,11 @@ int msg_adjoint(hipStream_t st, int precision, int F, int K, const MsgArgs &a);
 
 // The factorised first layer (msg.hip): per-atom, per-species sums of the
 // radial basis (forward) and the edge sums of the adjoint from the per-atom
-// vectors Q.  Layouts: P rows i of ldp floats, columns Z (K+1) + k then the
-// species one-hot at S (K+1) + Z; R, Q_v rows 3 i + d; Q_s rows i; all with
-// the basis slot k = 0 .. K of species Z at column Z (K+1) + k.
+// vectors Q.  Each species has a block of l0_block(K) columns, basis slot k
+// of species Z at column Z l0_block(K) + k (slots past K meet zero weights).
+// Layouts: P rows i of ldp floats, the S blocks then the species one-hot at
+// column S l0_block(K) + Z; R, Q_v rows 3 i + d; Q_s rows i.  All leading
+// dimensions are multiples of 4.
 struct L0Args {
     const int *rowc, *colc, *revc;
     const float4 *geom;
@@ -53,6 +55,7 @@ struct L0Args {
 };
 // Whether this build has the factorised first layer for (K, n_species).
 bool l0_factorised(int K, int S);
+__host__ __device__ constexpr int l0_block(int K) { return (K + 1 + 7) / 8 * 8; }
 // Return 0, -1 (unsupported K, S) or -5 (launch error).
 int msg_l0_basis_sums(hipStream_t st, int K, int S, const L0Args &a);
 int msg_l0_edge_sums(hipStream_t st, int K, int S, const L0Args &a);

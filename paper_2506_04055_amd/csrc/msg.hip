@@ -704,10 +704,11 @@ __global__ void k_assemble_G(const int *__restrict__ rowc, int n, const float4 *
 // Q_d[i][Z] = A'_vs^T (gv1_i,d o phi_vs(Z)):
 //   dE/dr = de~ . (Q_s + sum_d rhat_d Q_d),   dE/drhat_d = e~ . Q_d.
 // The products with the species-scaled filter weights (phi(Z) o A') are node
-// GEMMs; the two kernels below do the O(K) work per edge.  Rows of P: the
-// S (K+1) basis sums (column Z (K+1) + k) then the species one-hot (column
-// S (K+1) + Z), which picks s0(Z_i) out of the same GEMM; rows 3 i + d of R
-// and of Q_v, rows i of Q_s: column Z (K+1) + k.  Lane (g, e) = 16 g + e
+// GEMMs; the two kernels below do the O(K) work per edge.  Each species has
+// a block of SB = l0_block(K) columns (slot k at Z SB + k; slots past K meet
+// zero weights).  Rows of P: the S SB basis sums, then the species one-hot
+// (column S SB + Z), which picks s0(Z_i) out of the same GEMM; rows 3 i + d
+// of R and of Q_v, rows i of Q_s: the S SB slot columns.  Lane (g, e) = 16 g + e
 // holds basis slots k = 8 g .. 8 g + 7 of edge e, as in the kernels above.
 // ---------------------------------------------------------------------------
 template <int K, int SS>
@@ -716,7 +717,7 @@ __global__ void __launch_bounds__(256) k_l0_basis_sums(const int *__restrict__ r
                                                        const int8_t *__restrict__ hop, int hop_max,
                                                        const int *__restrict__ zsp, float *__restrict__ P, int ldp,
                                                        float *__restrict__ R, int ldr) {
-    constexpr int KS1 = K + 1;
+    constexpr int SB = l0_block(K);
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
     const float pirc = 3.14159265358979f / rc;
     const int nw = (int)(gridDim.x * (blockDim.x >> 6));
@@ -759,20 +760,20 @@ __global__ void __launch_bounds__(256) k_l0_basis_sums(const int *__restrict__ r
             for (int t = 0; t < 4; t++)
 #pragma unroll
                 for (int q = 0; q < 8; q++) acc[zz][t][q] = row_sum16(acc[zz][t][q]);
-        if (e == 0) {
+        // lane row g holds the totals of slots 8 g .. 8 g + 7 (rows past the
+        // species block are not stored; slots past K meet zero weights)
+        if (e == 0 && 8 * g < SB) {
 #pragma unroll
-            for (int q = 0; q < 8; q++) {
-                const int k = 8 * g + q;
-                if (k > K) continue;
+            for (int zz = 0; zz < SS; zz++)
 #pragma unroll
-                for (int zz = 0; zz < SS; zz++) {
-                    P[(long)i * ldp + zz * KS1 + k] = acc[zz][0][q];
-#pragma unroll
-                    for (int d = 0; d < 3; d++) R[(3L * i + d) * ldr + zz * KS1 + k] = acc[zz][1 + d][q];
+                for (int t = 0; t < 4; t++) {
+                    float *dst = t == 0 ? P + (long)i * ldp : R + (3L * i + t - 1) * ldr;
+                    dst += zz * SB + 8 * g;
+                    st4(dst, v4f{acc[zz][t][0], acc[zz][t][1], acc[zz][t][2], acc[zz][t][3]});
+                    st4(dst + 4, v4f{acc[zz][t][4], acc[zz][t][5], acc[zz][t][6], acc[zz][t][7]});
                 }
-            }
         }
-        if (lane < SS) P[(long)i * ldp + SS * KS1 + lane] = zsp[i] == lane ? 1.f : 0.f;
+        if (lane < SS) P[(long)i * ldp + SS * SB + lane] = zsp[i] == lane ? 1.f : 0.f;
     }
 }
 
@@ -782,24 +783,32 @@ __global__ void __launch_bounds__(256) k_l0_edge_sums(const int *__restrict__ ro
                                                       int n, float rc, const int8_t *__restrict__ hop, int hop_max,
                                                       const int *__restrict__ zsp, const float *__restrict__ Qs,
                                                       const float *__restrict__ Qv, int ldq, float4 *__restrict__ S) {
-    constexpr int KS1 = K + 1;
+    constexpr int SB = l0_block(K);
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
     const float pirc = 3.14159265358979f / rc;
     const int nw = (int)(gridDim.x * (blockDim.x >> 6));
+    const bool inb = 8 * g < SB;   // this lane row's slots lie inside a species block
     for (int i = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); i < n; i += nw) {
         const int e0 = rowc[i], deg = rowc[i + 1] - e0;
         if (deg == 0) continue;
-        // this lane's slots of Q_i for every species (zeros past K)
+        // this lane's slots of Q_i for every species (Q is zero past K)
         float qs[SS][8], qv[SS][3][8];
 #pragma unroll
         for (int zz = 0; zz < SS; zz++)
 #pragma unroll
-            for (int q = 0; q < 8; q++) {
-                const int k = 8 * g + q;
-                const bool in = k <= K;
-                qs[zz][q] = in ? Qs[(long)i * ldq + zz * KS1 + k] : 0.f;
+            for (int t = 0; t < 4; t++) {
+                const float *src = (t == 0 ? Qs + (long)i * ldq : Qv + (3L * i + t - 1) * ldq) + zz * SB + 8 * g;
+                v4f lo = v4f{0.f, 0.f, 0.f, 0.f}, hi = lo;
+                if (inb) {
+                    lo = ld4(src);
+                    hi = ld4(src + 4);
+                }
 #pragma unroll
-                for (int d = 0; d < 3; d++) qv[zz][d][q] = in ? Qv[(3L * i + d) * ldq + zz * KS1 + k] : 0.f;
+                for (int q = 0; q < 4; q++) {
+                    float *row = t == 0 ? qs[zz] : qv[zz][t > 0 ? t - 1 : 0];
+                    row[q] = lo[q];
+                    row[q + 4] = hi[q];
+                }
             }
         for (int cb = 0; cb < deg; cb += 16) {
             const bool valid = cb + e < deg;
@@ -817,17 +826,14 @@ __global__ void __launch_bounds__(256) k_l0_edge_sums(const int *__restrict__ ro
             // direction of the message edge (i <- j): x_j - x_i
             const float rx = gm.x * ir, ry = gm.y * ir, rz = gm.z * ir;
             float sr = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+            static_assert(SS == 1 || SS == 2, "one or two species");
+            const bool z1 = SS == 2 && z == 1;   // plain selects: no indexing by z
 #pragma unroll
             for (int q = 0; q < 8; q++) {
-                float a = qs[0][q], bx = qv[0][0][q], by = qv[0][1][q], bz = qv[0][2][q];
-#pragma unroll
-                for (int zz = 1; zz < SS; zz++)
-                    if (z == zz) {
-                        a = qs[zz][q];
-                        bx = qv[zz][0][q];
-                        by = qv[zz][1][q];
-                        bz = qv[zz][2][q];
-                    }
+                const float a = z1 ? qs[SS - 1][q] : qs[0][q];
+                const float bx = z1 ? qv[SS - 1][0][q] : qv[0][0][q];
+                const float by = z1 ? qv[SS - 1][1][q] : qv[0][1][q];
+                const float bz = z1 ? qv[SS - 1][2][q] : qv[0][2][q];
                 sr = fmaf(db[q], fmaf(rx, bx, fmaf(ry, by, fmaf(rz, bz, a))), sr);
                 sx = fmaf(eb[q], bx, sx);
                 sy = fmaf(eb[q], by, sy);
@@ -903,13 +909,14 @@ static int l0_edges(hipStream_t st, const L0Args &a) {
 bool l0_factorised(int K, int S) { return (K == 20 || K == 8 || K == 6) && (S == 1 || S == 2); }
 
 int msg_l0_basis_sums(hipStream_t st, int K, int S, const L0Args &a) {
-    if (a.ldp < S * (K + 1) + S || a.ldr < S * (K + 1)) return -1;
+    const int CS = S * l0_block(K);
+    if (a.ldp < CS + S || a.ldr < CS || a.ldp % 4 || a.ldr % 4) return -1;
     L0_DISPATCH(l0_sums);
     return -1;
 }
 
 int msg_l0_edge_sums(hipStream_t st, int K, int S, const L0Args &a) {
-    if (a.ldq < S * (K + 1)) return -1;
+    if (a.ldq < S * l0_block(K) || a.ldq % 4) return -1;
     L0_DISPATCH(l0_edges);
     return -1;
 }

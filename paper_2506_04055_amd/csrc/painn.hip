@@ -380,11 +380,11 @@ struct L0Layout {
     int ldp, ldr, ldq;
 };
 static L0Layout l0_layout(int F, int K, int S) {
-    const int CS = S * (K + 1);
+    const int CS = S * l0_block(K);
     L0Layout l;
     l.ldp = (CS + S + 3) / 4 * 4;
-    l.ldr = (CS + 3) / 4 * 4;
-    l.ldq = l.ldr;
+    l.ldr = CS;
+    l.ldq = CS;
     (void)F;
     return l;
 }
@@ -413,23 +413,28 @@ int first_layer_table(mlp_model *m, hipStream_t s, float *tmp) {
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
-// Species-scaled first-layer filter weights (CS = S (K+1) columns of basis
-// slots, species-major): Wfs[f][z (K+1) + k] = phi_s(z)_f A'_s[f][k] followed
-// by the embedding columns Wfs[f][CS + z] = emb[z][f]; Wbs the same without
-// the embedding; Wv[f][z (K+1) + k] = phi_vs(z)_f A'_vs[f][k]; A'[.][0] = c.
+// Species-scaled first-layer filter weights (CS = S SB columns of basis
+// slots, one block of SB = l0_block(K) per species, zero past slot K):
+// Wfs[f][z SB + k] = phi_s(z)_f A'_s[f][k] followed by the embedding columns
+// Wfs[f][CS + z] = emb[z][f]; Wbs the same without the embedding;
+// Wv[f][z SB + k] = phi_vs(z)_f A'_vs[f][k]; A'[.][0] = c.
 __global__ void k_l0_weights(const float *__restrict__ A, const float *__restrict__ c,
                              const float *__restrict__ phi0, const float *__restrict__ emb, int F, int K, int S,
                              float *__restrict__ Wfs, float *__restrict__ Wbs, float *__restrict__ Wv) {
-    const int CS = S * (K + 1);
+    const int SB = l0_block(K), CS = S * SB;
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < (long)F * CS) {
-        const int f = (int)(idx / CS), col = (int)(idx % CS), z = col / (K + 1), k = col % (K + 1);
-        const float as = k == 0 ? c[F + f] : A[(long)(F + f) * K + k - 1];
-        const float av = k == 0 ? c[2 * F + f] : A[(long)(2 * F + f) * K + k - 1];
-        const float ws = phi0[(long)z * 3 * F + F + f] * as;
+        const int f = (int)(idx / CS), col = (int)(idx % CS), z = col / SB, k = col % SB;
+        float ws = 0.f, wv = 0.f;
+        if (k <= K) {
+            const float as = k == 0 ? c[F + f] : A[(long)(F + f) * K + k - 1];
+            const float av = k == 0 ? c[2 * F + f] : A[(long)(2 * F + f) * K + k - 1];
+            ws = phi0[(long)z * 3 * F + F + f] * as;
+            wv = phi0[(long)z * 3 * F + 2 * F + f] * av;
+        }
         Wfs[(long)f * (CS + S) + col] = ws;
         Wbs[(long)f * CS + col] = ws;
-        Wv[(long)f * CS + col] = phi0[(long)z * 3 * F + 2 * F + f] * av;
+        Wv[(long)f * CS + col] = wv;
     } else if (idx < (long)F * CS + (long)F * S) {
         const long r = idx - (long)F * CS;
         const int f = (int)(r / S), z = (int)(r % S);
@@ -439,7 +444,7 @@ __global__ void k_l0_weights(const float *__restrict__ A, const float *__restric
 
 int first_layer_factor(mlp_model *m) {
     m->l0f = false;
-    const int F = m->F, K = m->K, S = m->S, CS = S * (K + 1);
+    const int F = m->F, K = m->K, S = m->S, CS = S * l0_block(K);
     if (!l0_factorised(K, S)) return 0;
     // P and R (forward), Q_s and Q_v (adjoint) must fit the 6 F floats per
     // atom of the dUV rows they borrow
