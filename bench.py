@@ -56,8 +56,8 @@ def per_edge_flops(F: int, K: int):
     dE/dx_vs (10), dE/dphi_j (6), dE/dv_j (7), dE/dr (9), dE/drhat (7): 39F.
     First layer: w_vs, dw_s/dr, dw_vs/dr 6(K+1)F; dE/dx_vs (5), dE/dr (6),
     dE/drhat (7): 18F.  (The first-layer figures apply where that layer runs
-    through the message kernels, with more than two species; with one or
-    two it is factorised and not timed with them.)"""
+    through the message kernels, with more than four species; with up to
+    four it is factorised and not timed with them.)"""
     return {"msg_fwd": (4 * (K + 1) * F + 9 * F, 6 * (K + 1) * F + 16 * F),
             "msg_bwd": (6 * (K + 1) * F + 18 * F, 12 * (K + 1) * F + 39 * F)}
 
@@ -110,7 +110,7 @@ def run_md(mlp, synth, torch, precision: str, steps: int, warmup: int, profile: 
     torch.cuda.synchronize()
     if profile:
         # HIP events around the message kernels only (one launch per layer and
-        # direction; with one or two species the first layer is factorised
+        # direction; with up to four species the first layer is factorised
         # into node GEMMs and two O(K)-per-edge kernels, which are not among
         # them), so the timing adds little to the timed region
         mlp.mlp_profile_reset()

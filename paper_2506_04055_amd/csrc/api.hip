@@ -245,7 +245,7 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
         prc = mlp::first_layer_table(m, nullptr, tab + 3 * (size_t)S * F);
     }
     if (prc == 0 && hipDeviceSynchronize() != hipSuccess) prc = MLP_ERR_DEVICE;
-    // the factorised first layer's species-scaled filter weights (one or two species)
+    // the factorised first layer's species-scaled filter weights (up to four species)
     if (prc == 0) prc = mlp::first_layer_factor(m);
     if (prc) {
         (void)hipGetLastError();

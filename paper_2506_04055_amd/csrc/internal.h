@@ -71,7 +71,7 @@ struct mlp_model {
     // phi of the first layer per species ([S][3F]): s = emb[species] there, so
     // the first message MLP depends on the species alone
     float *phi0_dev = nullptr;
-    // factorised first layer (one or two species): the species-scaled filter
+    // factorised first layer (up to four species): the species-scaled filter
     // weights packed as B operands: [0] forward s (with the embedding rows),
     // [1] forward v, [2] adjoint s, [3] adjoint v
     bool l0f = false;

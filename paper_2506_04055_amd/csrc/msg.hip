@@ -791,10 +791,12 @@ __global__ void __launch_bounds__(256) k_l0_edge_sums(const int *__restrict__ ro
     for (int i = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); i < n; i += nw) {
         const int e0 = rowc[i], deg = rowc[i + 1] - e0;
         if (deg == 0) continue;
-        // this lane's slots of Q_i for every species (Q is zero past K)
-        float qs[SS][8], qv[SS][3][8];
+        // one or two species: this lane's slots of Q_i for every species, held
+        // in registers (Q is zero past K); more species: read per edge below
+        constexpr bool REG = SS <= 2;
+        float qs[REG ? SS : 1][8], qv[REG ? SS : 1][3][8];
 #pragma unroll
-        for (int zz = 0; zz < SS; zz++)
+        for (int zz = 0; zz < (REG ? SS : 0); zz++)
 #pragma unroll
             for (int t = 0; t < 4; t++) {
                 const float *src = (t == 0 ? Qs + (long)i * ldq : Qv + (3L * i + t - 1) * ldq) + zz * SB + 8 * g;
@@ -826,14 +828,35 @@ __global__ void __launch_bounds__(256) k_l0_edge_sums(const int *__restrict__ ro
             // direction of the message edge (i <- j): x_j - x_i
             const float rx = gm.x * ir, ry = gm.y * ir, rz = gm.z * ir;
             float sr = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
-            static_assert(SS == 1 || SS == 2, "one or two species");
-            const bool z1 = SS == 2 && z == 1;   // plain selects: no indexing by z
+            float ql[4][8];   // this edge's species: slots of Q_s, Q_x, Q_y, Q_z
+            if constexpr (REG) {
+                const bool z1 = SS == 2 && z == 1;   // plain selects: no indexing by z
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    ql[0][q] = z1 ? qs[REG ? SS - 1 : 0][q] : qs[0][q];
+#pragma unroll
+                    for (int d = 0; d < 3; d++) ql[1 + d][q] = z1 ? qv[REG ? SS - 1 : 0][d][q] : qv[0][d][q];
+                }
+            } else {
+                // the atom's Q rows stay in L1 across its chunks
+#pragma unroll
+                for (int t = 0; t < 4; t++) {
+                    const float *src = (t == 0 ? Qs + (long)i * ldq : Qv + (3L * i + t - 1) * ldq) + z * SB + 8 * g;
+                    v4f lo = v4f{0.f, 0.f, 0.f, 0.f}, hi = lo;
+                    if (inb) {
+                        lo = ld4(src);
+                        hi = ld4(src + 4);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        ql[t][q] = lo[q];
+                        ql[t][q + 4] = hi[q];
+                    }
+                }
+            }
 #pragma unroll
             for (int q = 0; q < 8; q++) {
-                const float a = z1 ? qs[SS - 1][q] : qs[0][q];
-                const float bx = z1 ? qv[SS - 1][0][q] : qv[0][0][q];
-                const float by = z1 ? qv[SS - 1][1][q] : qv[0][1][q];
-                const float bz = z1 ? qv[SS - 1][2][q] : qv[0][2][q];
+                const float a = ql[0][q], bx = ql[1][q], by = ql[2][q], bz = ql[3][q];
                 sr = fmaf(db[q], fmaf(rx, bx, fmaf(ry, by, fmaf(rz, bz, a))), sr);
                 sx = fmaf(eb[q], bx, sx);
                 sy = fmaf(eb[q], by, sy);
@@ -896,17 +919,21 @@ static int l0_edges(hipStream_t st, const L0Args &a) {
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
+#define L0_DISPATCH_K(FN, K_)                                      \
+    do {                                                           \
+        if (S == 1) return FN<K_, 1>(st, a);                       \
+        if (S == 2) return FN<K_, 2>(st, a);                       \
+        if (S == 3) return FN<K_, 3>(st, a);                       \
+        if (S == 4) return FN<K_, 4>(st, a);                       \
+    } while (0)
 #define L0_DISPATCH(FN)                                            \
     do {                                                           \
-        if (K == 20 && S == 1) return FN<20, 1>(st, a);            \
-        if (K == 20 && S == 2) return FN<20, 2>(st, a);            \
-        if (K == 8 && S == 1) return FN<8, 1>(st, a);              \
-        if (K == 8 && S == 2) return FN<8, 2>(st, a);              \
-        if (K == 6 && S == 1) return FN<6, 1>(st, a);              \
-        if (K == 6 && S == 2) return FN<6, 2>(st, a);              \
+        if (K == 20) L0_DISPATCH_K(FN, 20);                        \
+        if (K == 8) L0_DISPATCH_K(FN, 8);                          \
+        if (K == 6) L0_DISPATCH_K(FN, 6);                          \
     } while (0)
 
-bool l0_factorised(int K, int S) { return (K == 20 || K == 8 || K == 6) && (S == 1 || S == 2); }
+bool l0_factorised(int K, int S) { return (K == 20 || K == 8 || K == 6) && S >= 1 && S <= 4; }
 
 int msg_l0_basis_sums(hipStream_t st, int K, int S, const L0Args &a) {
     const int CS = S * l0_block(K);
