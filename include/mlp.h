@@ -235,14 +235,16 @@ int mlp_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of independent periodic systems.
- * mlp_server_create starts a scheduler thread with its own streams.
+ * mlp_server_create starts a scheduler thread and a few preparation threads,
+ *   each with its own stream.
  *   hbm_budget_bytes bounds the device memory of admitted requests; a
  *   request whose estimated footprint exceeds the budget on its own is
  *   rejected with INVALID_ARG at submit.  max_slots bounds the number of
  *   requests resident on the device at once.
  * mlp_submit copies the request's host arrays (pos SoA 3 x n float32,
- *   species int32 [n], box) into library-owned pinned memory, queues it and
- *   returns a ticket without waiting for the GPU.
+ *   species int32 [n], box) into library-owned host memory, queues it and
+ *   returns a ticket without waiting for the GPU (the copies to and from the
+ *   device go through pinned buffers the server keeps per slot).
  * mlp_poll returns MLP_PENDING while the request runs, MLP_OK once energy
  *   (host double) and forces (host SoA 3 x n float32) have been copied out
  *   (the ticket is then retired), or an error.  timing (nullable) receives

@@ -30,14 +30,15 @@
 namespace mlp {
 
 using clk = std::chrono::steady_clock;
+constexpr int PREP_WORKERS = 4;   // preparation threads (and streams) per server
 
 struct Req {
     uint64_t ticket = 0;
     int n = 0;
     double box[3] = {0, 0, 0};
-    float *h_pos = nullptr;      // pinned, SoA 3 x n
-    int *h_species = nullptr;    // pinned
-    float *h_forces = nullptr;   // pinned, SoA 3 x n
+    std::vector<float> pos;      // SoA 3 x n, copied at submit
+    std::vector<int> species;
+    std::vector<float> forces;   // SoA 3 x n, filled when the wave completes
     double energy = 0.0;
     int state = 0;               // 0 queued, 1 admitted, 2 ready, 3 running, 4 done, < 0 error
     int err = 0;
@@ -49,11 +50,36 @@ struct Req {
     int batch_size = 0;
 };
 
+// A slot holds one admitted request: its graph, its device inputs and
+// pinned staging for the host <-> device copies (grown, never per request,
+// so no pinned allocation or release sits on the request path).
 struct Slot {
     mlp_nbr *nbr = nullptr;
     DevBuf pos, species;
+    float *h_pos = nullptr, *h_forces = nullptr;   // pinned, SoA 3 x cap
+    int *h_species = nullptr;                      // pinned, cap
+    int h_cap = 0;
     bool busy = false;
 };
+
+int ensure_staging(Slot &sl, int n) {
+    if (n <= sl.h_cap) return 0;
+    if (sl.h_pos) hipHostFree(sl.h_pos);
+    if (sl.h_forces) hipHostFree(sl.h_forces);
+    if (sl.h_species) hipHostFree(sl.h_species);
+    sl.h_pos = sl.h_forces = nullptr;
+    sl.h_species = nullptr;
+    sl.h_cap = 0;
+    const int cap = n + n / 4;
+    if (hipHostMalloc((void **)&sl.h_pos, sizeof(float) * 3 * (size_t)cap, 0) != hipSuccess ||
+        hipHostMalloc((void **)&sl.h_forces, sizeof(float) * 3 * (size_t)cap, 0) != hipSuccess ||
+        hipHostMalloc((void **)&sl.h_species, sizeof(int) * (size_t)cap, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MLP_ERR_OOM, "pinned staging allocation failed");
+    }
+    sl.h_cap = cap;
+    return 0;
+}
 
 __global__ void k_pack_atoms(const int *__restrict__ rowc, const int *__restrict__ perm, const int *__restrict__ sp,
                              int nb, int aoff, int eoff, int *__restrict__ browc, int *__restrict__ bperm,
@@ -109,7 +135,15 @@ struct mlp_server {
     std::unordered_map<uint64_t, Req *> all;
     std::vector<Req *> ready, running;
     uint64_t next_ticket = 1;
-    hipStream_t s_prep = nullptr, s_comp = nullptr;
+    // admitted requests are prepared (copied, graph built and pruned) by a
+    // few worker threads, each with its own stream, so the host round trips
+    // of one preparation overlap the others and the running wave
+    std::deque<Req *> to_prep;
+    int n_prep_busy = 0;
+    bool stop_workers = false;
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> s_preps;
+    hipStream_t s_comp = nullptr;
     hipEvent_t ev_wave = nullptr;
     bool wave_in_flight = false;
     mlp_nbr batch;              // packed graph + activations of the running wave
@@ -132,26 +166,31 @@ void fail_req(Req *r, int code, const char *msg) {
 // without the lock and changes no state a poller reads: the caller publishes
 // the outcome (ready, or failed with the slot released) under the lock, so a
 // poller never sees a failed request while the scheduler still holds it.
-int prepare(mlp_server *S, Req *r, std::string *msg) {
+int prepare(mlp_server *S, Req *r, hipStream_t sp, std::string *msg) {
     Slot &sl = S->slots[r->slot];
     int *G = &sl.nbr->n_grows;
     int rc = sl.pos.ensure(sizeof(float) * 3 * (size_t)r->n, 1.2, G);
     if (!rc) rc = sl.species.ensure(sizeof(int) * (size_t)r->n, 1.2, G);
-    if (!rc && (hipMemcpyAsync(sl.pos.p, r->h_pos, sizeof(float) * 3 * r->n, hipMemcpyHostToDevice, S->s_prep) !=
+    if (!rc) rc = ensure_staging(sl, r->n);
+    if (!rc) {
+        std::memcpy(sl.h_pos, r->pos.data(), sizeof(float) * 3 * r->n);
+        std::memcpy(sl.h_species, r->species.data(), sizeof(int) * r->n);
+    }
+    if (!rc && (hipMemcpyAsync(sl.pos.p, sl.h_pos, sizeof(float) * 3 * r->n, hipMemcpyHostToDevice, sp) !=
                     hipSuccess ||
-                hipMemcpyAsync(sl.species.p, r->h_species, sizeof(int) * r->n, hipMemcpyHostToDevice, S->s_prep) !=
+                hipMemcpyAsync(sl.species.p, sl.h_species, sizeof(int) * r->n, hipMemcpyHostToDevice, sp) !=
                     hipSuccess))
         rc = fail(MLP_ERR_DEVICE, "request upload failed");
     mlp_nbr *g = sl.nbr;
-    if (!rc) rc = build_graph(S->m, g, sl.pos.as<float>(), sl.species.as<int>(), r->n, r->n, r->box, S->skin, S->s_prep);
-    if (!rc) rc = prune_graph(S->m, g, sl.pos.as<float>(), S->s_prep);
+    if (!rc) rc = build_graph(S->m, g, sl.pos.as<float>(), sl.species.as<int>(), r->n, r->n, r->box, S->skin, sp);
+    if (!rc) rc = prune_graph(S->m, g, sl.pos.as<float>(), sp);
     int Ec = 0;
-    if (!rc && (hipMemcpyAsync(&Ec, g->rowc.as<int>() + r->n, sizeof(int), hipMemcpyDeviceToHost, S->s_prep) !=
+    if (!rc && (hipMemcpyAsync(&Ec, g->rowc.as<int>() + r->n, sizeof(int), hipMemcpyDeviceToHost, sp) !=
                     hipSuccess ||
-                hipStreamSynchronize(S->s_prep) != hipSuccess))
+                hipStreamSynchronize(sp) != hipSuccess))
         rc = fail(MLP_ERR_DEVICE, "prep stream failed");
     if (rc) {
-        (void)hipStreamSynchronize(S->s_prep);   // nothing of this request is still in flight on the slot
+        (void)hipStreamSynchronize(sp);   // nothing of this request is still in flight on the slot
         *msg = mlp_last_error();
         return rc;
     }
@@ -162,8 +201,11 @@ int prepare(mlp_server *S, Req *r, std::string *msg) {
 // Pack all ready requests and launch one evaluation on the compute stream.
 int launch_wave(mlp_server *S) {
     std::vector<Req *> &W = S->running;
-    W = S->ready;
-    S->ready.clear();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        W.swap(S->ready);
+        S->ready.clear();
+    }
     const int B = (int)W.size();
     int64_t Nt = 0, Et = 0;
     for (Req *r : W) {
@@ -225,7 +267,7 @@ int launch_wave(mlp_server *S) {
         Req *r = W[b];
         const float *F = S->forces.as<float>();
         for (int d = 0; d < 3; d++)
-            HIP_TRY(hipMemcpyAsync(r->h_forces + (size_t)d * r->n, F + (size_t)d * Nt + S->h_seg[b],
+            HIP_TRY(hipMemcpyAsync(S->slots[r->slot].h_forces + (size_t)d * r->n, F + (size_t)d * Nt + S->h_seg[b],
                                    sizeof(float) * r->n, hipMemcpyDeviceToHost, S->s_comp));
     }
     HIP_TRY(hipEventRecord(S->ev_wave, S->s_comp));
@@ -239,6 +281,8 @@ void finish_wave(mlp_server *S) {
     for (size_t b = 0; b < S->running.size(); b++) {
         Req *r = S->running[b];
         r->energy = S->h_energies[b];
+        const float *hf = S->slots[r->slot].h_forces;
+        r->forces.assign(hf, hf + 3 * (size_t)r->n);
         r->t_done = now;
         r->state = 4;
         S->slots[r->slot].busy = false;
@@ -250,15 +294,53 @@ void finish_wave(mlp_server *S) {
     S->cv.notify_all();
 }
 
+// One preparation worker: takes admitted requests, prepares them on its own
+// stream and publishes each as ready (or failed, its slot released).
+void prep_worker(mlp_server *S, int k) {
+    hipSetDevice(S->device);
+    for (;;) {
+        Req *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait(lk, [&] { return S->stop_workers || !S->to_prep.empty(); });
+            if (S->to_prep.empty()) break;
+            r = S->to_prep.front();
+            S->to_prep.pop_front();
+            S->n_prep_busy++;
+        }
+        std::string msg;
+        const int rc = prepare(S, r, S->s_preps[k], &msg);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (rc == 0) {
+                r->state = 2;
+                S->ready.push_back(r);
+            } else {
+                fail_req(r, rc, msg.c_str());
+                S->slots[r->slot].busy = false;
+                S->reserved -= r->bytes;
+                r->slot = -1;
+                r->t_done = clk::now();
+            }
+            S->n_prep_busy--;
+        }
+        S->cv.notify_all();
+    }
+}
+
+// The scheduler: admission in arrival order, and waves.  A finished wave is
+// retired and the next one, of every request ready by then, launched.
 void scheduler(mlp_server *S) {
     hipSetDevice(S->device);
     for (;;) {
-        std::vector<Req *> admitted;
+        bool admitted = false, have_ready = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             if (!S->wave_in_flight && S->pending.empty() && S->ready.empty())
                 S->cv.wait_for(lk, std::chrono::microseconds(200));
-            if (S->stop && S->pending.empty() && S->ready.empty() && !S->wave_in_flight) break;
+            if (S->stop && S->pending.empty() && S->to_prep.empty() && S->n_prep_busy == 0 && S->ready.empty() &&
+                !S->wave_in_flight)
+                break;
             // admission in arrival order: a free slot and room in the budget
             while (!S->pending.empty()) {
                 Req *r = S->pending.front();
@@ -275,24 +357,12 @@ void scheduler(mlp_server *S) {
                 r->slot = free_slot;
                 r->state = 1;
                 r->t_admit = clk::now();
-                admitted.push_back(r);
+                S->to_prep.push_back(r);
+                admitted = true;
             }
+            have_ready = !S->ready.empty();
         }
-        for (Req *r : admitted) {
-            std::string msg;
-            const int rc = prepare(S, r, &msg);
-            std::lock_guard<std::mutex> lk(S->mu);
-            if (rc == 0) {
-                r->state = 2;
-                S->ready.push_back(r);
-            } else {
-                fail_req(r, rc, msg.c_str());
-                S->slots[r->slot].busy = false;
-                S->reserved -= r->bytes;
-                r->slot = -1;
-                r->t_done = clk::now();
-            }
-        }
+        if (admitted) S->cv.notify_all();
         if (S->wave_in_flight) {
             const hipError_t q = hipEventQuery(S->ev_wave);
             if (q == hipSuccess) {
@@ -312,7 +382,7 @@ void scheduler(mlp_server *S) {
                 S->wave_in_flight = false;
             }
         }
-        if (!S->wave_in_flight && !S->ready.empty()) {
+        if (!S->wave_in_flight && have_ready) {
             int rc = launch_wave(S);
             if (rc) {
                 // kernels of the partly launched wave may still read the slots
@@ -328,16 +398,11 @@ void scheduler(mlp_server *S) {
                 S->running.clear();
             }
         }
-        if (S->wave_in_flight && admitted.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        if (S->wave_in_flight) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
 
-void free_req(Req *r) {
-    if (r->h_pos) hipHostFree(r->h_pos);
-    if (r->h_species) hipHostFree(r->h_species);
-    if (r->h_forces) hipHostFree(r->h_forces);
-    delete r;
-}
+void free_req(Req *r) { delete r; }
 
 }  // namespace
 
@@ -353,12 +418,21 @@ int mlp_server_create(mlp_model *m, size_t hbm_budget_bytes, int32_t max_slots, 
     hipGetDevice(&S->device);
     S->slots.resize(max_slots);
     for (auto &sl : S->slots) sl.nbr = new mlp_nbr();
-    if (hipStreamCreateWithFlags(&S->s_prep, hipStreamNonBlocking) != hipSuccess ||
+    S->s_preps.assign(PREP_WORKERS, nullptr);
+    bool streams_ok = true;
+    for (hipStream_t &sp : S->s_preps) streams_ok &= hipStreamCreateWithFlags(&sp, hipStreamNonBlocking) == hipSuccess;
+    if (!streams_ok ||
         hipStreamCreateWithFlags(&S->s_comp, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&S->ev_wave, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        for (hipStream_t sp : S->s_preps)
+            if (sp) hipStreamDestroy(sp);
+        if (S->s_comp) hipStreamDestroy(S->s_comp);
+        for (auto &sl : S->slots) mlp_nbr_destroy(sl.nbr);
         delete S;
         return fail(MLP_ERR_DEVICE, "stream creation failed");
     }
+    for (int k = 0; k < PREP_WORKERS; k++) S->workers.emplace_back(prep_worker, S, k);
     S->th = std::thread(scheduler, S);
     *out = S;
     return MLP_OK;
@@ -376,12 +450,23 @@ int mlp_server_destroy(mlp_server *S) {
     }
     S->cv.notify_all();
     if (S->th.joinable()) S->th.join();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop_workers = true;
+    }
+    S->cv.notify_all();
+    for (std::thread &w : S->workers)
+        if (w.joinable()) w.join();
     hipStreamSynchronize(S->s_comp);
-    hipStreamSynchronize(S->s_prep);
+    for (hipStream_t sp : S->s_preps)
+        if (sp) hipStreamSynchronize(sp);
     for (auto &kv : S->all) free_req(kv.second);
     for (auto &sl : S->slots) {
         sl.pos.release();
         sl.species.release();
+        if (sl.h_pos) hipHostFree(sl.h_pos);
+        if (sl.h_forces) hipHostFree(sl.h_forces);
+        if (sl.h_species) hipHostFree(sl.h_species);
         mlp_nbr_destroy(sl.nbr);
     }
     DevBuf *bufs[] = {&S->batch.rowc, &S->batch.perm, &S->batch.species, &S->batch.hop, &S->batch.colc,
@@ -390,7 +475,8 @@ int mlp_server_destroy(mlp_server *S) {
     for (DevBuf *b : bufs) b->release();
     if (S->h_energies) hipHostFree(S->h_energies);
     hipEventDestroy(S->ev_wave);
-    hipStreamDestroy(S->s_prep);
+    for (hipStream_t sp : S->s_preps)
+        if (sp) hipStreamDestroy(sp);
     hipStreamDestroy(S->s_comp);
     delete S;
     return MLP_OK;
@@ -407,14 +493,8 @@ int mlp_submit(mlp_server *S, const mlp_request *q, uint64_t *ticket) {
     r->n = q->n_atoms;
     std::memcpy(r->box, q->box, sizeof(r->box));
     r->bytes = bytes;
-    if (hipHostMalloc((void **)&r->h_pos, sizeof(float) * 3 * r->n, 0) != hipSuccess ||
-        hipHostMalloc((void **)&r->h_species, sizeof(int) * r->n, 0) != hipSuccess ||
-        hipHostMalloc((void **)&r->h_forces, sizeof(float) * 3 * r->n, 0) != hipSuccess) {
-        free_req(r);
-        return fail(MLP_ERR_OOM, "pinned staging allocation failed");
-    }
-    std::memcpy(r->h_pos, q->pos, sizeof(float) * 3 * r->n);
-    std::memcpy(r->h_species, q->species, sizeof(int) * r->n);
+    r->pos.assign(q->pos, q->pos + 3 * (size_t)r->n);
+    r->species.assign(q->species, q->species + (size_t)r->n);
     r->t_submit = clk::now();
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -443,7 +523,7 @@ int mlp_poll(mlp_server *S, uint64_t ticket, double *energy, float *forces, mlp_
         rc = fail(r->err, r->errmsg);
     } else {
         if (energy) *energy = r->energy;
-        if (forces) std::memcpy(forces, r->h_forces, sizeof(float) * 3 * r->n);
+        if (forces) std::memcpy(forces, r->forces.data(), sizeof(float) * 3 * r->n);
         if (timing) {
             timing->latency_us = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
             timing->queue_us = std::chrono::duration<double, std::micro>(r->t_admit - r->t_submit).count();
