@@ -65,6 +65,36 @@ def test_alone_equals_in_the_mix(mlp, precision):
     server.close()
 
 
+def test_concurrent_clients(mlp):
+    # three host threads submit and poll at once while the preparation
+    # workers and the scheduler run: every result equals the system alone
+    import threading
+    hdr, w = synth.make_weights(128, 20, 3, 4, seed=5)
+    model = mlp.Model(hdr, w, "bf16")
+    server = mlp.Server(model, hbm_budget_bytes=8 << 30, max_slots=8)
+    work = [[synth.peptide_like(500 + 137 * (3 * c + k), seed=300 + 10 * c + k) for k in range(8)] for c in range(3)]
+    results, errors = [None] * 3, []
+
+    def client(c):
+        try:
+            tickets = [server.submit(s.pos, s.species, s.box) for s in work[c]]
+            results[c] = wait_all(server, tickets, [s.n_atoms for s in work[c]])
+        except Exception as e:   # reported below, on the main thread
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=client, args=(c,)) for c in range(3)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for c in range(3):
+        for s, (E, F, tm) in zip(work[c], results[c]):
+            E1, F1 = single(mlp, model, s)
+            assert E == E1 and np.array_equal(F, F1)
+    server.close()
+
+
 @pytest.mark.parametrize("precision,model_args,e_tol,f_tol", [
     ("fp32", dict(F=64, K=20, T=3, n_species=4, seed=6, bias_scale=0.1), 2e-6, 1e-5),
     # the serving benchmark's model and precision
