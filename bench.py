@@ -369,6 +369,11 @@ def main():
         "roofline": roof,
         "kernels": {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps}
                     for k, v in head["kt"].items()},
+        "kernels_note": ("msg_fwd / msg_bwd: message kernels of the layers after the first; the first layer is "
+                         "factorised into per-atom basis sums (two O(K)-per-edge kernels, untimed here) and small "
+                         "GEMMs (in node_gemm)"
+                         if head["kt"]["msg_bwd"][1] < (hdr["T"] - 0.5) * args.steps else
+                         "msg_fwd / msg_bwd: message kernels of every layer"),
         "graph": {"n_edges_rc": int(head["n_edges_mean"]), "n_edges_skin": int(head["n_edges_skin"]),
                   "rebuilds_in_timed_steps": int(head["rebuilds"])},
         "md_weights": "N(0,1/fan_in) with radial filter x0.1 and readout x1e-2 (finite 300 K trajectory)",
