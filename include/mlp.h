@@ -53,7 +53,7 @@ enum {
     MLP_ERR_UNKNOWN_TICKET = -6
 };
 
-enum { MLP_FP32 = 0, MLP_BF16 = 1, MLP_BF16_FAST = 2 };
+enum { MLP_FP32 = 0, MLP_BF16 = 1, MLP_BF16_FAST = 2, MLP_BF16_NODE = 3, MLP_BF16_NODE_X3 = 4 };
 
 typedef struct mlp_model mlp_model;
 typedef struct mlp_nbr mlp_nbr;
@@ -73,6 +73,8 @@ typedef struct {
     int32_t n_builds;          /* neighbour builds so far on this handle     */
     int32_t n_grows;           /* capacity growths so far on this handle     */
     int64_t device_bytes;      /* device memory held by the nbr handle       */
+    int64_t n_edges_within_hops[8]; /* pruned edges whose destination atom is
+                                       within <= t hops of a local atom      */
 } mlp_stats;
 
 /* Message describing the last error of the calling thread. */
@@ -92,14 +94,18 @@ const char *mlp_last_error(void);
  *   W5 [F/2][F] b5 [F/2] w6 [F/2] b6 [1]); matrices are [out][in] row-major;
  *   3F blocks are split [vv | s | vs] (message) and [vv | sv | ss] (update).
  *   Copied to the device; the caller keeps ownership of its array.
- * precision: the operand form of the matrix-core contractions (node-feature
- *   GEMMs and the radial filter):
- *   MLP_FP32      FP32 operands (v_mfma_f32_16x16x4_f32);
- *   MLP_BF16      split bfloat16 operands x = hi + lo, three products per
- *                 tile on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16);
- *   MLP_BF16_FAST plain bfloat16 operands (one product; bfloat16 rounding of
- *                 activations and weights, ~3e-2 force error with random
- *                 N(0, 1/fan_in) weights at F = 128, T = 3).
+ * precision: the operand forms of the two matrix-core contractions, the
+ *   node-feature GEMMs (node) and the radial filter of the message kernels
+ *   (filter):
+ *   MLP_FP32         node FP32, filter FP32 (v_mfma_f32_16x16x4_f32);
+ *   MLP_BF16         node and filter split bfloat16 ("bf16x3"): x = hi + lo,
+ *                    three bf16 products per tile (v_mfma_f32_16x16x32_bf16),
+ *                    about 16 significant bits per operand;
+ *   MLP_BF16_FAST    node and filter plain bfloat16 (one product; bfloat16
+ *                    rounding of activations, weights and basis);
+ *   MLP_BF16_NODE    node plain bfloat16, filter FP32: bfloat16 node GEMMs with
+ *                    FP32 accumulation, everything else FP32;
+ *   MLP_BF16_NODE_X3 node plain bfloat16, filter split bfloat16.
  *   Accumulation is FP32 in every mode; geometry, cutoff envelope, message
  *   and force accumulation stay FP32; the energy sum is FP64.
  * Errors: INVALID_ARG (header or weight count), OOM, DEVICE.
@@ -156,7 +162,12 @@ int mlp_nbr_edges(mlp_nbr *nbr, int32_t which, int32_t *dst, int32_t *src, int64
  * ghost_owner: NULL, or device int32 [n_atoms - n_local] with the local
  *   index each ghost copies; then each ghost row's force is also added into
  *   its owner's row (the reverse summation of partial forces) while ghost
- *   rows keep their own partial forces.
+ *   rows keep their own partial forces.  The owner -> ghosts map is built and
+ *   validated at the first call after each neighbour build (or when a
+ *   different ghost_owner pointer is passed), with one synchronisation of the
+ *   stream; an owner outside [0, n_local) then fails with INVALID_ARG before
+ *   anything is computed.  Later calls reuse the map, so the array's contents
+ *   must not change between neighbour builds.
  * energy: device double [1] (written on the stream).
  * forces: device SoA 3 x n_atoms float32 (written on the stream).
  * atom_energy: NULL or device float [n_atoms] receiving U_i (ghost rows too).
@@ -166,6 +177,20 @@ int mlp_nbr_edges(mlp_nbr *nbr, int32_t which, int32_t *dst, int32_t *src, int64
 int mlp_energy_forces(mlp_model *model, mlp_nbr *nbr, const float *pos, int32_t n_atoms,
                       int32_t n_local, const int32_t *ghost_owner, void *stream, double *energy,
                       float *forces, float *atom_energy, mlp_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * mlp_nbr_check_displacement — whether the graph of the last build is still
+ * exact at the given positions: *exceeds (host) is set to 1 when some atom
+ * has moved more than skin/2 from its position at the last build (then a
+ * pair may have entered rc unseen and mlp_build_neighbors must run before
+ * mlp_energy_forces), else 0.  The list-with-skin scheme of Results,
+ * "Distributed potential computation".
+ * pos: device SoA 3 x n_atoms, same atoms and order as the build; periodic
+ *   displacements are taken under the minimum image.
+ * Synchronises the stream.  Errors: INVALID_ARG, DEVICE, OOM (pinned word).
+ * ------------------------------------------------------------------------- */
+int mlp_nbr_check_displacement(mlp_nbr *nbr, const float *pos, int32_t n_atoms, void *stream,
+                               int32_t *exceeds);
 
 /* ---------------------------------------------------------------------------
  * mlp_md_step — one velocity-Verlet step (kick, drift, wrap into [0, L),
@@ -235,6 +260,14 @@ int mlp_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of independent periodic systems.
+ * The paper's runtime keeps device buffers of fixed shape and reuses them
+ * across calls, growing them (with headroom) only when a system no longer
+ * fits, and reports the statistics that decide it (Results, "Runtime
+ * optimizations and buffering").  The server applies the same rule to a
+ * stream of requests: each slot's buffers only grow, requests are admitted
+ * by their device footprint against a fixed budget, and the admitted systems
+ * of one wave are evaluated together as one ragged batch (one energy segment
+ * per system, the per-system sum of Eq. 1).
  * mlp_server_create starts a scheduler thread and a few preparation threads,
  *   each with its own stream.
  *   hbm_budget_bytes bounds the device memory of admitted requests; a

@@ -13,7 +13,7 @@
 
 namespace mlp {
 const char *last_error_cstr();
-int hop_histogram(mlp_model *m, mlp_nbr *g, hipStream_t s, int *hist_host);
+int hop_histogram(mlp_model *m, mlp_nbr *g, hipStream_t s, int *hist_host, int64_t *ehist_host);
 int export_edges(mlp_nbr *g, const int *row, const int *col, int32_t *dst, int32_t *src, hipStream_t s);
 }
 
@@ -173,7 +173,8 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
         if (!found) return fail(MLP_ERR_INVALID_ARG, "(F, K) combination is not compiled in this build");
     }
     if (!(rc > 0.0) || !(eps > 0.0)) return fail(MLP_ERR_INVALID_ARG, "r_c and eps must be positive");
-    if (precision != MLP_FP32 && precision != MLP_BF16 && precision != MLP_BF16_FAST)
+    if (precision != MLP_FP32 && precision != MLP_BF16 && precision != MLP_BF16_FAST &&
+        precision != MLP_BF16_NODE && precision != MLP_BF16_NODE_X3)
         return fail(MLP_ERR_INVALID_ARG, "unknown precision");
     mlp_model *m = new mlp_model();
     m->F = (int)F; m->K = (int)K; m->T = (int)T; m->S = (int)S;
@@ -329,29 +330,33 @@ int mlp_energy_forces(mlp_model *m, mlp_nbr *g, const float *pos, int32_t n_atom
         return fail(MLP_ERR_INVALID_ARG, "atom counts differ from the last neighbour build");
     hipStream_t s = (hipStream_t)stream;
     int rc;
+    const bool fold = forces && ghost_owner && n_atoms > n_local;
+    // the owner map is validated before anything is computed
+    if (fold && (rc = prepare_owner_map(g, ghost_owner, s))) return rc;
     if ((rc = prune_graph(m, g, pos, s))) return rc;
     if ((rc = compute_hops(m, g, s))) return rc;
     if ((rc = evaluate(m, g, s, energy, forces, atom_energy))) return rc;
-    if (forces && ghost_owner && n_atoms > n_local)
-        if ((rc = fold_ghosts(g, ghost_owner, forces, s))) return rc;
+    if (fold && (rc = fold_ghosts(g, forces, s))) return rc;
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         int hist[MLP_MAX_LAYERS + 2] = {0};
-        if ((rc = hop_histogram(m, g, s, hist))) return rc;
-        int Ec = 0, flag1 = 0;
+        int64_t ehist[MLP_MAX_LAYERS + 2] = {0};
+        if ((rc = hop_histogram(m, g, s, hist, ehist))) return rc;
+        int Ec = 0;
         if (hipMemcpyAsync(&Ec, g->rowc.as<int>() + g->n_atoms, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipMemcpyAsync(&flag1, g->flags.as<int>() + 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return fail(MLP_ERR_DEVICE, "statistics readback failed");
-        if (flag1) return fail(MLP_ERR_INVALID_ARG, "ghost owner index out of range");
         stats->n_edges_skin = g->n_edges_skin;
         stats->n_edges = Ec;
         stats->n_atoms = g->n_atoms;
         stats->n_local = g->n_local;
         int run = 0;
+        int64_t erun = 0;
         for (int t = 0; t <= m->T && t < 8; t++) {
             run += hist[t];
+            erun += ehist[t];
             stats->n_within_hops[t] = run;
+            stats->n_edges_within_hops[t] = erun;
         }
         for (int d = 0; d < 3; d++) stats->n_cells[d] = g->nc[d];
         stats->max_cell_occupancy = g->max_occ;
@@ -359,6 +364,17 @@ int mlp_energy_forces(mlp_model *m, mlp_nbr *g, const float *pos, int32_t n_atom
         stats->n_grows = g->n_grows;
         stats->device_bytes = held_bytes(g);
     }
+    return MLP_OK;
+}
+
+int mlp_nbr_check_displacement(mlp_nbr *g, const float *pos, int32_t n_atoms, void *stream, int32_t *exceeds) {
+    if (!g || !pos || !exceeds) return fail(MLP_ERR_INVALID_ARG, "null argument");
+    if (g->n_builds == 0) return fail(MLP_ERR_INVALID_ARG, "neighbour handle was never built");
+    if (n_atoms != g->n_atoms) return fail(MLP_ERR_INVALID_ARG, "atom count differs from the last neighbour build");
+    bool ex = false;
+    int rc = max_displacement_exceeds(g, pos, 0.5f * g->skin, (hipStream_t)stream, &ex);
+    if (rc) return rc;
+    *exceeds = ex ? 1 : 0;
     return MLP_OK;
 }
 

@@ -10,12 +10,30 @@
 
 #define MLP_MAX_LAYERS 7
 #define MLP_MAX_K 32
-// precision modes (values of the C ABI's MLP_FP32 / MLP_BF16 / MLP_BF16_FAST)
+// precision modes (values of the C ABI's MLP_FP32 / MLP_BF16 / MLP_BF16_FAST /
+// MLP_BF16_NODE / MLP_BF16_NODE_X3)
 #define MLP_PREC_FP32 0
 #define MLP_PREC_BF16 1
 #define MLP_PREC_BF16_FAST 2
+#define MLP_PREC_BF16_NODE 3
+#define MLP_PREC_BF16_NODE_X3 4
 
 namespace mlp {
+
+// MFMA operand forms: 0 FP32, 1 plain bfloat16, 2 split bfloat16 (hi + lo,
+// three products).  A precision mode fixes one form for the node-feature
+// GEMMs and one for the radial-filter contraction of the message kernels.
+inline int node_operands(int precision) {
+    return precision == MLP_PREC_FP32 ? 0 : (precision == MLP_PREC_BF16 ? 2 : 1);
+}
+inline int filter_operands(int precision) {
+    switch (precision) {
+    case MLP_PREC_BF16: return 2;
+    case MLP_PREC_BF16_FAST: return 1;
+    case MLP_PREC_BF16_NODE_X3: return 2;
+    default: return 0;   // FP32 and MLP_PREC_BF16_NODE
+    }
+}
 
 // Status carried through host code; converted to the C return codes at the boundary.
 struct Error {
@@ -102,6 +120,8 @@ struct mlp_nbr {
     mlp::DevBuf pos4;          // float4 positions at evaluation (internal order)
     mlp::DevBuf scan_tmp, flags, red;
     mlp::DevBuf ghost_ptr, ghost_list, ghost_cnt;  // owner -> ghosts (user indices)
+    const int32_t *owner_key = nullptr;   // ghost_owner array the map was built from
+    int owner_build = -1;      // n_builds when it was built (-1: no valid map)
     // model activations
     mlp::DevBuf act;           // one arena for per-layer activations
     size_t act_bytes = 0;
@@ -133,7 +153,12 @@ int build_graph(mlp_model *m, mlp_nbr *g, const float *pos, const int32_t *speci
                 const double box[3], float skin, hipStream_t s);
 int prune_graph(mlp_model *m, mlp_nbr *g, const float *pos, hipStream_t s);
 int compute_hops(mlp_model *m, mlp_nbr *g, hipStream_t s);
-int fold_ghosts(mlp_nbr *g, const int32_t *owner, float *forces, hipStream_t s);
+// Build and validate the owner -> ghosts map unless the one from the same
+// owner array since the last neighbour build is at hand (one stream
+// synchronisation when it is built); INVALID_ARG for an owner out of range.
+int prepare_owner_map(mlp_nbr *g, const int32_t *owner, hipStream_t s);
+// Add each ghost row of forces into its owner's row (after prepare_owner_map).
+int fold_ghosts(mlp_nbr *g, float *forces, hipStream_t s);
 int max_displacement_exceeds(mlp_nbr *g, const float *pos, float limit, hipStream_t s, bool *exceeds);
 
 // ---- model (painn.hip) ----

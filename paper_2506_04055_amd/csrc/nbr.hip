@@ -463,14 +463,26 @@ __global__ void k_hop_round(const int *__restrict__ rowc, const int *__restrict_
     }
 }
 
-__global__ void k_hop_hist(const int8_t *__restrict__ hop, int n, int *__restrict__ hist) {
-    // per-workgroup counts in LDS, then one global add per bin and workgroup
+__global__ void k_hop_hist(const int8_t *__restrict__ hop, const int *__restrict__ rowc, int n,
+                           int *__restrict__ hist, unsigned long long *__restrict__ ehist) {
+    // per-workgroup counts of atoms and of their pruned in-edges per hop
+    // distance in LDS, then one global add per bin and workgroup
     __shared__ int h[MLP_MAX_LAYERS + 2];
-    if (threadIdx.x < MLP_MAX_LAYERS + 2) h[threadIdx.x] = 0;
+    __shared__ unsigned long long eh[MLP_MAX_LAYERS + 2];
+    if (threadIdx.x < MLP_MAX_LAYERS + 2) {
+        h[threadIdx.x] = 0;
+        eh[threadIdx.x] = 0ull;
+    }
     __syncthreads();
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) atomicAdd(&h[hop[i]], 1);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        atomicAdd(&h[hop[i]], 1);
+        atomicAdd(&eh[hop[i]], (unsigned long long)(rowc[i + 1] - rowc[i]));
+    }
     __syncthreads();
-    if (threadIdx.x < MLP_MAX_LAYERS + 2 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < MLP_MAX_LAYERS + 2 && h[threadIdx.x]) {
+        atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+        atomicAdd(&ehist[threadIdx.x], eh[threadIdx.x]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -498,12 +510,13 @@ __global__ void k_owner_fill(const int *__restrict__ owner, int ng, int n_local,
     list[ptr[o] + slot] = n_local + g;
 }
 
-__global__ void k_fold(const int *__restrict__ ptr, int *__restrict__ list, int n_local, int n,
-                       float *__restrict__ F) {
+// Each owner's ghosts in ascending index (a fixed summation order for the
+// fold), sorted once per map.
+__global__ void k_owner_sort(const int *__restrict__ ptr, int *__restrict__ list, int n_local) {
     int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n_local) return;
     int a = ptr[u], b = ptr[u + 1];
-    for (int i = a + 1; i < b; i++) {  // ascending ghost index: fixed summation order
+    for (int i = a + 1; i < b; i++) {
         int key = list[i], j = i - 1;
         while (j >= a && list[j] > key) {
             list[j + 1] = list[j];
@@ -511,6 +524,13 @@ __global__ void k_fold(const int *__restrict__ ptr, int *__restrict__ list, int 
         }
         list[j + 1] = key;
     }
+}
+
+__global__ void k_fold(const int *__restrict__ ptr, const int *__restrict__ list, int n_local, int n,
+                       float *__restrict__ F) {
+    int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_local) return;
+    int a = ptr[u], b = ptr[u + 1];
     for (int d = 0; d < 3; d++) {
         float acc = F[(long)d * n + u];
         for (int q = a; q < b; q++) acc += F[(long)d * n + list[q]];
@@ -559,7 +579,9 @@ int build_graph(mlp_model *m, mlp_nbr *g, const float *pos, const int32_t *speci
     }
     int ng = 0;
     auto &err_grows = g->n_grows;
-    if (int rc = g->flags.ensure(64, 1.0, &err_grows)) return rc;
+    // status words: 0 build errors, 1 ghost owners, 2 displacement tag,
+    // 8 cell sort, 16..31 hop histogram, 32..63 per-hop edge counts (64-bit)
+    if (int rc = g->flags.ensure(256, 1.0, &err_grows)) return rc;
     int *flag = g->flags.as<int>();
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     if (any_open) {
@@ -708,31 +730,59 @@ int compute_hops(mlp_model *m, mlp_nbr *g, hipStream_t s) {
     return 0;
 }
 
-int hop_histogram(mlp_model *m, mlp_nbr *g, hipStream_t s, int *hist_host /* T+2 */) {
+int hop_histogram(mlp_model *m, mlp_nbr *g, hipStream_t s, int *hist_host /* T+2 */,
+                  int64_t *ehist_host /* T+2 */) {
+    // flags words 16..31 hold the atom counts, 32..63 the edge counts (64-bit)
     int *flag = g->flags.as<int>();
-    HIP_TRY(hipMemsetAsync(flag + 16, 0, sizeof(int) * 16, s));
-    k_hop_hist<<<std::max(1, std::min(nblk(g->n_atoms, 256), 1024)), 256, 0, s>>>(g->hop.as<int8_t>(), g->n_atoms,
-                                                                                  flag + 16);
+    unsigned long long *eh = reinterpret_cast<unsigned long long *>(flag + 32);
+    HIP_TRY(hipMemsetAsync(flag + 16, 0, sizeof(int) * 48, s));
+    k_hop_hist<<<std::max(1, std::min(nblk(g->n_atoms, 256), 1024)), 256, 0, s>>>(
+        g->hop.as<int8_t>(), g->rowc.as<int>(), g->n_atoms, flag + 16, eh);
     HIP_TRY(hipMemcpyAsync(hist_host, flag + 16, sizeof(int) * (m->T + 2), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ehist_host, eh, sizeof(int64_t) * (m->T + 2), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return 0;
 }
 
-int fold_ghosts(mlp_nbr *g, const int32_t *owner, float *forces, hipStream_t s) {
+int prepare_owner_map(mlp_nbr *g, const int32_t *owner, hipStream_t s) {
     const int n = g->n_atoms, nl = g->n_local, ng = n - nl;
     if (ng <= 0) return 0;
+    if (g->owner_key == owner && g->owner_build == g->n_builds) return 0;
+    g->owner_build = -1;
     int *G = &g->n_grows;
     int rc;
     if ((rc = g->ghost_ptr.ensure(sizeof(int) * (nl + 1), 1.2, G)) ||
         (rc = g->ghost_cnt.ensure(sizeof(int) * (nl + 1) * 2, 1.2, G)) ||
         (rc = g->ghost_list.ensure(sizeof(int) * ng + 4, 1.2, G)))
         return rc;
+    if (!g->h_flag) {
+        if (hipHostMalloc((void **)&g->h_flag, sizeof(int)) != hipSuccess) {
+            (void)hipGetLastError();
+            g->h_flag = nullptr;
+            return fail(-2, "pinned host allocation failed");
+        }
+    }
     int *cnt = g->ghost_cnt.as<int>(), *fill = cnt + nl + 1;
+    int *flag = g->flags.as<int>() + 1;
     HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int) * (nl + 1) * 2, s));
-    int *flag = g->flags.as<int>();
-    k_owner_count<<<nblk(ng, 256), 256, 0, s>>>(owner, ng, nl, cnt, flag + 1);
+    HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+    k_owner_count<<<nblk(ng, 256), 256, 0, s>>>(owner, ng, nl, cnt, flag);
     if ((rc = scan_exclusive(cnt, g->ghost_ptr.as<int>(), nl, g->scan_tmp, G, s))) return rc;
     k_owner_fill<<<nblk(ng, 256), 256, 0, s>>>(owner, ng, nl, g->ghost_ptr.as<int>(), fill, g->ghost_list.as<int>());
+    k_owner_sort<<<nblk(nl, 256), 256, 0, s>>>(g->ghost_ptr.as<int>(), g->ghost_list.as<int>(), nl);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(g->h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (*g->h_flag) return fail(-1, "ghost owner index out of range [0, n_local)");
+    g->owner_key = owner;
+    g->owner_build = g->n_builds;
+    return 0;
+}
+
+int fold_ghosts(mlp_nbr *g, float *forces, hipStream_t s) {
+    const int n = g->n_atoms, nl = g->n_local;
+    if (n <= nl) return 0;
+    if (g->owner_build != g->n_builds) return fail(-1, "ghost owner map missing");
     k_fold<<<nblk(nl, 256), 256, 0, s>>>(g->ghost_ptr.as<int>(), g->ghost_list.as<int>(), nl, n, forces);
     HIP_TRY(hipGetLastError());
     return 0;

@@ -405,7 +405,7 @@ static L0Args l0_args(mlp_nbr *g, mlp_model *m, int hop_max) {
 
 int first_layer_table(mlp_model *m, hipStream_t s, float *tmp) {
     const int F = m->F, S = m->S;
-    const int P = m->precision == MLP_PREC_FP32 ? 0 : (m->precision == MLP_PREC_BF16 ? 2 : 1);
+    const int P = node_operands(m->precision);
     const LayerW L = m->layer(0);
     // the same GEMMs as the later layers' node MLPs, on the S embedding rows
     node_gemm(s, P, GE_BIAS_SILU, m->at(m->off_emb), F, m->pk[0][WP_W1], tmp, F, S, L.b1, tmp + (long)S * F, F);
@@ -485,10 +485,10 @@ int first_layer_factor(mlp_model *m) {
 int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
              float *atom_energy_user, int n_seg, const int *seg_dev) {
     const int n = g->n_atoms, F = m->F, K = m->K, T = m->T, F3 = 3 * F, Fh = F / 2;
-    // MFMA operand form of the mode (node GEMMs and radial filter alike):
-    // 0 FP32, 1 plain bfloat16, 2 split bfloat16 (hi + lo)
-    const int P = m->precision == MLP_PREC_FP32 ? 0 : (m->precision == MLP_PREC_BF16 ? 2 : 1);
-    const int PF = P;
+    // MFMA operand forms of the mode for the node GEMMs (P) and for the
+    // radial filter (PF): 0 FP32, 1 plain bfloat16, 2 split bfloat16 (hi + lo)
+    const int P = node_operands(m->precision);
+    const int PF = filter_operands(m->precision);
     int *Gr = &g->n_grows;
     int rc;
     const size_t need = act_floats(n, F, T) * sizeof(float);

@@ -19,7 +19,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmlp.so")
 
 MLP_OK, MLP_PENDING = 0, 1
-MLP_FP32, MLP_BF16, MLP_BF16_FAST = 0, 1, 2
+MLP_FP32, MLP_BF16, MLP_BF16_FAST, MLP_BF16_NODE, MLP_BF16_NODE_X3 = 0, 1, 2, 3, 4
+# precision names: operand forms of the node GEMMs / the radial filter
+PRECISIONS = {"fp32": MLP_FP32,            # FP32 / FP32
+              "bf16": MLP_BF16,            # split bf16 ("bf16x3") / split bf16
+              "bf16x3": MLP_BF16,
+              "bf16_fast": MLP_BF16_FAST,  # plain bf16 / plain bf16
+              "bf16_node": MLP_BF16_NODE,  # plain bf16 / FP32
+              "bf16_node_x3": MLP_BF16_NODE_X3}   # plain bf16 / split bf16
 _ERRORS = {-1: "INVALID_ARG", -2: "OOM", -3: "CAPACITY", -4: "BOX_TOO_SMALL", -5: "DEVICE", -6: "UNKNOWN_TICKET"}
 
 
@@ -36,6 +43,7 @@ class Stats(ctypes.Structure):
         ("n_within_hops", ctypes.c_int32 * 8), ("n_cells", ctypes.c_int32 * 3),
         ("max_cell_occupancy", ctypes.c_int32), ("n_builds", ctypes.c_int32),
         ("n_grows", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+        ("n_edges_within_hops", ctypes.c_int64 * 8),
     ]
 
     def as_dict(self):
@@ -44,6 +52,7 @@ class Stats(ctypes.Structure):
             "n_local": self.n_local, "n_within_hops": list(self.n_within_hops),
             "n_cells": list(self.n_cells), "max_cell_occupancy": self.max_cell_occupancy,
             "n_builds": self.n_builds, "n_grows": self.n_grows, "device_bytes": self.device_bytes,
+            "n_edges_within_hops": list(self.n_edges_within_hops),
         }
 
 
@@ -76,6 +85,7 @@ def lib():
     L.mlp_nbr_destroy.argtypes = [P]
     L.mlp_nbr_edges.argtypes = [P, I32, P, P, I64, ctypes.POINTER(I64), P]
     L.mlp_energy_forces.argtypes = [P, P, P, I32, I32, P, P, P, P, P, ctypes.POINTER(Stats)]
+    L.mlp_nbr_check_displacement.argtypes = [P, P, I32, P, ctypes.POINTER(I32)]
     L.mlp_md_step.argtypes = [P, P, P, P, P, P, P, I32, P, ctypes.c_float, ctypes.c_float, P, P,
                               ctypes.POINTER(I32)]
     L.mlp_nvt_create.argtypes = [I32, ctypes.c_double, ctypes.c_double, I32, ctypes.POINTER(P)]
@@ -92,7 +102,7 @@ def lib():
     L.mlp_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
     for name in ("mlp_profile_enable", "mlp_profile_reset", "mlp_profile_read",
                  "mlp_model_create", "mlp_model_destroy", "mlp_build_neighbors", "mlp_nbr_destroy", "mlp_nbr_edges",
-                 "mlp_energy_forces", "mlp_md_step", "mlp_server_create", "mlp_server_destroy",
+                 "mlp_energy_forces", "mlp_nbr_check_displacement", "mlp_md_step", "mlp_server_create", "mlp_server_destroy",
                  "mlp_submit", "mlp_poll", "mlp_nvt_create", "mlp_nvt_destroy", "mlp_nvt_read", "mlp_md_step_nvt"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -160,6 +170,14 @@ def mlp_nbr_edges(nbr, which: int = 0, stream=None):
     s_ = src[:E].cpu().numpy().astype(np.int64)
     order = np.lexsort((s_, d))
     return d[order], s_[order]
+
+
+def mlp_nbr_check_displacement(nbr, pos_soa, stream=None) -> bool:
+    """True when some atom moved more than skin/2 since the last build."""
+    ex = ctypes.c_int32(0)
+    _check(lib().mlp_nbr_check_displacement(nbr, _ptr(pos_soa), pos_soa.shape[1], _stream(stream),
+                                            ctypes.byref(ex)))
+    return bool(ex.value)
 
 
 def mlp_md_step(model, nbr, pos, vel, forces, inv_mass, species, box, skin, dt, energy, stream=None):
@@ -230,7 +248,7 @@ class Model:
 
     def __init__(self, header: dict, weights: np.ndarray, precision: str | int = "fp32"):
         if isinstance(precision, str):
-            precision = {"fp32": MLP_FP32, "bf16": MLP_BF16, "bf16_fast": MLP_BF16_FAST}[precision]
+            precision = PRECISIONS[precision]
         self.header = header
         self.precision = precision
         self.handle = mlp_model_create(json.dumps(header, sort_keys=True), weights, precision)
@@ -266,6 +284,14 @@ class System:
         self.nbr = mlp_build_neighbors(self.model.handle, self.pos, self.species, self.n_local, self.box,
                                        self.skin, self.nbr)
 
+    def rebuild_if_needed(self) -> bool:
+        """Rebuild the graph when an atom moved more than skin/2 since the
+        last build (the graph is exact only below that)."""
+        if mlp_nbr_check_displacement(self.nbr, self.pos):
+            self.build()
+            return True
+        return False
+
     def set_positions(self, pos_aos):
         self.pos.copy_(torch.as_tensor(pos_aos, dtype=torch.float32, device=self.pos.device).t())
 
@@ -290,11 +316,14 @@ class MLPEnergy(torch.autograd.Function):
     """E(pos) with dE/dpos = -F from the library's adjoint pass.
 
     forward(pos_soa (3, N) float32 on the device, system) -> energy (float64).
+    The graph is rebuilt first when the positions moved more than skin/2 from
+    those of the last build, so any displacement gives the exact result.
     First derivatives only: a double backward raises."""
 
     @staticmethod
     def forward(ctx, pos_soa, system: System):
         system.pos.copy_(pos_soa.detach())
+        system.rebuild_if_needed()
         system.compute(forces=True)
         ctx.save_for_backward(system.forces.clone())
         return system.energy.clone()

@@ -19,60 +19,77 @@ def bench():
     return B
 
 
-def fake_md(kt, T=3, F=128, K=20, n=24000, edges=1_000_000.0):
-    return {"hdr": {"F": F, "K": K, "T": T}, "n": n, "kt": kt, "n_edges_mean": edges}
+def fake_stats(T=3):
+    # hop sets of a domain share: atoms and pruned in-edges within <= h hops
+    return {"n_within_hops": [1000, 1100, 1200, 1300] + [0] * 4,
+            "n_edges_within_hops": [35000, 38500, 42000, 45500] + [0] * 4}
 
 
-def test_roofline_over_the_layers_after_the_first(bench):
-    # 10 steps, 2 adjoint launches per step of 0.5 ms each: the first layer is
-    # factorised and not among the timed launches
-    steps = 10
-    kt = {"msg_fwd": (3.0, 20), "msg_bwd": (10.0, 20)}
-    r = bench.roofline(fake_md(kt), "bf16", steps)
-    later = bench.per_edge_flops(128, 20)["msg_bwd"][1]
-    assert r["kernel"] == "msg_bwd" and r["bound"] == "mfma"
-    assert r["avg_launch_us"] == pytest.approx(500.0)
-    assert r["achieved"] == pytest.approx(later * 1e6 / 500e-6 / 1e12, rel=1e-3)
-    assert r["frac"] == pytest.approx(r["achieved"] / 2500.0, rel=1e-3)
-    assert "after the first" in r["work_per_launch"]
+def test_layer_work_follows_the_hop_sets(bench):
+    w = bench.layer_work(fake_stats(), 3, factorised=True)
+    # forward layer t reaches destinations within T-1-t hops, the adjoint of
+    # layer t the sources within T-t hops; the factorised first layer is absent
+    assert w["msg_fwd"] == [(1, 38500, 1100), (2, 35000, 1000)]
+    assert w["msg_bwd"] == [(2, 38500, 1100), (1, 42000, 1200)]
+    w = bench.layer_work(fake_stats(), 3, factorised=False)
+    assert w["msg_fwd"][0] == (0, 42000, 1200) and w["msg_bwd"][-1] == (0, 45500, 1300)
 
 
-def test_roofline_over_every_layer(bench):
-    # 3 launches per step: the first layer's work enters the average
-    steps = 10
-    kt = {"msg_fwd": (3.0, 30), "msg_bwd": (15.0, 30)}
-    r = bench.roofline(fake_md(kt), "fp32", steps)
-    first, later = bench.per_edge_flops(128, 20)["msg_bwd"]
-    assert r["achieved"] == pytest.approx((first + 2 * later) / 3 * 1e6 / 500e-6 / 1e12, rel=1e-3)
-    assert r["peak"] == pytest.approx(157.3)
+def test_roofline_entry_picks_the_binding_roof(bench):
+    F, K = 128, 20
+    work = bench.layer_work(fake_stats(), 3, factorised=True)["msg_bwd"]
+    later = bench.per_edge_flops(F, K)["msg_bwd"][1]
+    eb, ab = bench.per_pass_bytes(F)["msg_bwd"]
+    flops = (later * 38500 + later * 42000) / 2
+    byts = (eb * 38500 + ab * 1100 + eb * 42000 + ab * 1200) / 2
+    avg = 1e-4
+    # split bf16: bytes / 8 TB/s exceed flops / 2.5 PF, so HBM binds
+    r = bench.roofline_entry("msg_bwd", work, F, K, avg, "bf16", "fcc1m")
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert r["achieved"] == pytest.approx(byts / avg / 1e9, rel=1e-3)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, rel=1e-3)
+    assert r["other_roof"]["achieved"] == pytest.approx(flops / avg / 1e12, rel=1e-3)
+    # FP32 filter: the matrix cores' FP32 rate binds
+    r = bench.roofline_entry("msg_bwd", work, F, K, avg, "fp32", "fcc1m")
+    assert r["bound"] == "mfma" and r["peak"] == pytest.approx(157.3)
+    assert r["achieved"] == pytest.approx(flops / avg / 1e12, rel=1e-3)
+    # the bf16-node form keeps the filter in FP32: same roof as fp32
+    assert bench.roofline_entry("msg_bwd", work, F, K, avg, "bf16_node", "fcc1m")["bound"] == "mfma"
 
 
-def test_per_edge_flops_counts(bench):
-    # one filter output is K + 1 multiply-adds (2 flops each)
+def test_per_edge_counts(bench):
     pe = bench.per_edge_flops(128, 20)
-    assert pe["msg_fwd"] == (4 * 21 * 128 + 9 * 128, 6 * 21 * 128 + 16 * 128)
-    assert pe["msg_bwd"] == (6 * 21 * 128 + 18 * 128, 12 * 21 * 128 + 39 * 128)
+    assert pe["msg_fwd"][1] == 6 * 20 * 128 + 12 * 128
+    assert pe["msg_bwd"][1] == 12 * 20 * 128 + 28 * 128
+    assert bench.per_pass_bytes(128)["msg_bwd"] == (36, 19 * 128 * 4 + 8)
+
+
+def test_node_flops_with_active_sets(bench):
+    hops = [1000, 1100, 1200, 1300]
+    F, T = 128, 3
+    f = bench.node_flops_per_step(hops, F, T, 1000)
+    fwd = 22 * F * F * 1200 + (8 * F * F * 1200 + 22 * F * F * 1100) + (8 * F * F * 1100 + 22 * F * F * 1000)
+    assert f == 2 * fwd + 2 * F * F * 1000
 
 
 def test_traffic_figure_is_gated_on_the_kernel_source(bench, tmp_path, monkeypatch):
-    src = os.path.join(ROOT, "profiles", "traffic_msg_bwd_bf16.json")
-    d = json.load(open(src))
+    d = {"kernel": "msg_bwd", "precision": "bf16", "source_file": "msg.hip", "hbm_bytes_per_launch": 123456789}
     (tmp_path / "profiles").mkdir()
     (tmp_path / "paper_2506_04055_amd" / "csrc").mkdir(parents=True)
     shutil.copy(os.path.join(ROOT, "paper_2506_04055_amd", "csrc", "msg.hip"),
                 tmp_path / "paper_2506_04055_amd" / "csrc" / "msg.hip")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    dst = tmp_path / "profiles" / "traffic_msg_bwd_bf16.json"
+    dst = tmp_path / "profiles" / "traffic_msg_bwd_fcc1m_bf16.json"
     # the stored hash of the current source: the figure is used
     d_ok = dict(d, source_sha256_16=bench.source_hash("msg.hip"))
     dst.write_text(json.dumps(d_ok))
-    assert bench.load_traffic("msg_bwd", "bf16") == d["hbm_bytes_per_launch"]
+    assert bench.load_traffic("msg_bwd", "bf16", "fcc1m") == d["hbm_bytes_per_launch"]
     # any other source: the figure is withheld
     dst.write_text(json.dumps(dict(d, source_sha256_16="0" * 16)))
-    assert bench.load_traffic("msg_bwd", "bf16") is None
+    assert bench.load_traffic("msg_bwd", "bf16", "fcc1m") is None
     # no file: withheld
     dst.unlink()
-    assert bench.load_traffic("msg_bwd", "bf16") is None
+    assert bench.load_traffic("msg_bwd", "bf16", "fcc1m") is None
 
 
 def test_more_than_one_gpu_is_refused():
