@@ -1,6 +1,7 @@
 // C ABI of libmlp: model and neighbour handles, evaluation, MD step.
 #include "../../include/mlp.h"
 #include "internal.h"
+#include "header_json.h"
 
 #include <vector>
 
@@ -19,119 +20,12 @@ int export_edges(mlp_nbr *g, const int *row, const int *col, int32_t *dst, int32
 
 using namespace mlp;
 
-// ---------------------------------------------------------------------------
 // Minimal reader for the flat top-level JSON object of the model header.
-// Values: numbers and strings are kept; nested objects/arrays are skipped.
-// ---------------------------------------------------------------------------
 namespace {
-struct JsonTop {
-    std::map<std::string, std::string> kv;
-    bool ok = false;
-};
-
-void skip_ws(const char *&p) {
-    while (*p && std::isspace((unsigned char)*p)) p++;
-}
-
-bool read_string(const char *&p, std::string &out) {
-    if (*p != '"') return false;
-    p++;
-    out.clear();
-    while (*p && *p != '"') {
-        if (*p == '\\' && p[1]) p++;
-        out.push_back(*p++);
-    }
-    if (*p != '"') return false;
-    p++;
-    return true;
-}
-
-bool skip_value(const char *&p, std::string *scalar) {
-    skip_ws(p);
-    if (*p == '"') {
-        std::string s;
-        if (!read_string(p, s)) return false;
-        if (scalar) *scalar = s;
-        return true;
-    }
-    if (*p == '{' || *p == '[') {
-        int depth = 0;
-        bool in_str = false;
-        do {
-            char c = *p;
-            if (!c) return false;
-            if (in_str) {
-                if (c == '\\' && p[1]) p++;
-                else if (c == '"') in_str = false;
-            } else if (c == '"') {
-                in_str = true;
-            } else if (c == '{' || c == '[') {
-                depth++;
-            } else if (c == '}' || c == ']') {
-                depth--;
-            }
-            p++;
-        } while (depth > 0);
-        return true;
-    }
-    const char *b = p;
-    while (*p && *p != ',' && *p != '}' && !std::isspace((unsigned char)*p)) p++;
-    if (scalar) scalar->assign(b, p);
-    return p > b;
-}
-
-JsonTop parse_top(const char *s) {
-    JsonTop r;
-    const char *p = s;
-    skip_ws(p);
-    if (*p != '{') return r;
-    p++;
-    for (;;) {
-        skip_ws(p);
-        if (*p == '}') {
-            r.ok = true;
-            return r;
-        }
-        std::string key, val;
-        if (!read_string(p, key)) return r;
-        skip_ws(p);
-        if (*p != ':') return r;
-        p++;
-        if (!skip_value(p, &val)) return r;
-        r.kv[key] = val;
-        skip_ws(p);
-        if (*p == ',') {
-            p++;
-            continue;
-        }
-        if (*p == '}') {
-            r.ok = true;
-            return r;
-        }
-        return r;
-    }
-}
-
-bool get_int(const JsonTop &j, const char *k, long *out) {
-    auto it = j.kv.find(k);
-    if (it == j.kv.end()) return false;
-    char *end = nullptr;
-    long v = std::strtol(it->second.c_str(), &end, 10);
-    if (end == it->second.c_str() || *end) return false;
-    *out = v;
-    return true;
-}
-
-bool get_num(const JsonTop &j, const char *k, double *out) {
-    auto it = j.kv.find(k);
-    if (it == j.kv.end()) return false;
-    char *end = nullptr;
-    double v = std::strtod(it->second.c_str(), &end);
-    if (end == it->second.c_str() || *end) return false;
-    *out = v;
-    return true;
-}
-
+using mlp_json::JsonTop;
+using mlp_json::get_int;
+using mlp_json::get_num;
+using mlp_json::parse_top;
 int status(int rc) { return rc; }
 }  // namespace
 
