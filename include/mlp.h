@@ -179,6 +179,35 @@ int mlp_energy_forces(mlp_model *model, mlp_nbr *nbr, const float *pos, int32_t 
                       float *forces, float *atom_energy, mlp_stats *stats);
 
 /* ---------------------------------------------------------------------------
+ * mlp_energy_forces_noalloc — mlp_energy_forces for callers that cannot
+ * allocate device memory while they run (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, result
+ * and kernels as mlp_energy_forces without stats; it calls no hipMalloc,
+ * hipFree or allocating library routine.  Every per-evaluation buffer (the
+ * pruned graph, hop marks, activations, edge gradients and edge sums) is a
+ * slice of one static device array of MLP_NOALLOC_SCRATCH_BYTES (256 MiB),
+ * which each GPU the library runs on holds until the process ends.
+ * Limits: the buffers of the system must fit that array (roughly 3,000
+ * atoms at F = 128, T = 3, fewer with a larger skin); a larger system fails
+ * with CAPACITY, naming the bytes it needs, before anything is enqueued.
+ * The neighbour handle must have been built (mlp_build_neighbors allocates;
+ * call it outside the allocation-free region).  With ghost_owner, the
+ * owner map must already be prepared for this build and this array (one
+ * mlp_energy_forces call with it after the build), else INVALID_ARG.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other threads, other handles) race and must be
+ * serialised by the caller; results are complete once the stream has
+ * reached the end of the call's work.  The array keeps the last call's
+ * contents; nothing in it is assumed to start at zero.
+ * mlp_nbr_edges(which = 1) keeps describing the last mlp_energy_forces call.
+ * Errors: INVALID_ARG, CAPACITY, DEVICE.
+ * ------------------------------------------------------------------------- */
+#define MLP_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int mlp_energy_forces_noalloc(mlp_model *model, mlp_nbr *nbr, const float *pos, int32_t n_atoms,
+                              int32_t n_local, const int32_t *ghost_owner, void *stream, double *energy,
+                              float *forces, float *atom_energy);
+
+/* ---------------------------------------------------------------------------
  * mlp_nbr_check_displacement — whether the graph of the last build is still
  * exact at the given positions: *exceeds (host) is set to 1 when some atom
  * has moved more than skin/2 from its position at the last build (then a

@@ -51,10 +51,13 @@ int fail(int code, const std::string &msg);
             return ::mlp::fail(-5, std::string(#expr) + ": " + hipGetErrorString(_e)); \
     } while (0)
 
-// Grow-only device buffer.
+// Grow-only device buffer.  A borrowed buffer is a view of memory the
+// library does not own (a slice of the static scratch array): it is never
+// grown or freed, and ensure() on one that is too small fails with CAPACITY.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;
     // Ensure at least `need` bytes; grows to need * headroom.  Returns 0 or error code.
     int ensure(size_t need, double headroom, int *n_grows);
     void release();
@@ -152,6 +155,11 @@ int scan_exclusive(const int *in, int *out, int n, DevBuf &tmp, int *n_grows, hi
 int build_graph(mlp_model *m, mlp_nbr *g, const float *pos, const int32_t *species, int n, int n_local,
                 const double box[3], float skin, hipStream_t s);
 int prune_graph(mlp_model *m, mlp_nbr *g, const float *pos, hipStream_t s);
+// Bytes each per-evaluation graph buffer needs (the sizes prune_graph and
+// compute_hops ensure), in the order pos4, rowc, colc, revc, geom, map,
+// oldidx, hop, scan_tmp.
+enum { EN_POS4 = 0, EN_ROWC, EN_COLC, EN_REVC, EN_GEOM, EN_MAP, EN_OLDIDX, EN_HOP, EN_SCAN, EN_GRAPH_COUNT };
+void eval_graph_needs(const mlp_nbr *g, size_t need[EN_GRAPH_COUNT]);
 int compute_hops(mlp_model *m, mlp_nbr *g, hipStream_t s);
 // Build and validate the owner -> ghosts map unless the one from the same
 // owner array since the last neighbour build is at hand (one stream
@@ -166,6 +174,9 @@ int max_displacement_exceeds(mlp_nbr *g, const float *pos, float limit, hipStrea
 // offsets, or nullptr for one segment covering all rows), forces of all rows.
 int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
              float *atom_energy_user, int n_seg = 1, const int *seg_dev = nullptr);
+// Bytes of the buffers evaluate() ensures: the activation arena, the edge
+// gradients G and the adjoint's edge-sum slots Gs.
+void eval_model_needs(const mlp_model *m, const mlp_nbr *g, size_t *act, size_t *G, size_t *Gs);
 // Fill m->phi0_dev (device, S x 3F) from the embedding and the first layer's
 // message MLP, in the model's precision; tmp: device scratch of 2 S F floats.
 int first_layer_table(mlp_model *m, hipStream_t s, float *tmp);

@@ -28,6 +28,9 @@ const char *last_error_cstr() { return g_err.msg.c_str(); }
 
 int DevBuf::ensure(size_t need, double headroom, int *n_grows) {
     if (p && need <= bytes) return 0;
+    if (borrowed)
+        return fail(-3, "scratch slice of " + std::to_string(bytes) + " bytes is below the " + std::to_string(need) +
+                            " bytes needed");
     size_t nb = (size_t)((double)(need ? need : 1) * headroom) + 256;
     nb = (nb + 255) & ~(size_t)255;
     if (p) {
@@ -48,7 +51,8 @@ int DevBuf::ensure(size_t need, double headroom, int *n_grows) {
 }
 
 void DevBuf::release() {
-    if (p) hipFree(p);
+    if (p && !borrowed) hipFree(p);
+    borrowed = false;
     p = nullptr;
     bytes = 0;
 }
@@ -117,10 +121,16 @@ __global__ void k_scan_add(int *__restrict__ out, const int *__restrict__ bsum, 
     if (i < n) out[i] += bsum[i / SCAN_B];
 }
 
+static size_t scan_tmp_bytes(int n) {
+    int nb = (n + SCAN_B - 1) / SCAN_B;
+    if (nb < 1) nb = 1;
+    return sizeof(int) * (size_t)(nb + 1);
+}
+
 int scan_exclusive(const int *in, int *out, int n, DevBuf &tmp, int *n_grows, hipStream_t s) {
     int nb = (n + SCAN_B - 1) / SCAN_B;
     if (nb < 1) nb = 1;
-    if (int rc = tmp.ensure(sizeof(int) * (nb + 1), 1.5, n_grows)) return rc;
+    if (int rc = tmp.ensure(scan_tmp_bytes(n), 1.5, n_grows)) return rc;
     int *bs = tmp.as<int>();
     if (n == 0) {
         HIP_TRY(hipMemsetAsync(out, 0, sizeof(int), s));
@@ -691,15 +701,29 @@ int build_graph(mlp_model *m, mlp_nbr *g, const float *pos, const int32_t *speci
     return 0;
 }
 
+void eval_graph_needs(const mlp_nbr *g, size_t need[EN_GRAPH_COUNT]) {
+    const size_t n = (size_t)g->n_atoms, E = (size_t)g->n_edges_skin;
+    need[EN_POS4] = sizeof(float4) * n;
+    need[EN_ROWC] = sizeof(int) * (n + 1);
+    need[EN_COLC] = sizeof(int) * E + 4;
+    need[EN_REVC] = sizeof(int) * E + 4;
+    need[EN_GEOM] = sizeof(float4) * E + 16;
+    need[EN_MAP] = sizeof(int) * E + 4;
+    need[EN_OLDIDX] = sizeof(int) * E + 4;
+    need[EN_HOP] = n + 16;
+    need[EN_SCAN] = scan_tmp_bytes((int)n);
+}
+
 int prune_graph(mlp_model *m, mlp_nbr *g, const float *pos, hipStream_t s) {
     const int n = g->n_atoms;
-    const size_t E = (size_t)g->n_edges_skin;
     int *G = &g->n_grows;
     int rc;
-    if ((rc = g->pos4.ensure(sizeof(float4) * n, 1.2, G)) || (rc = g->rowc.ensure(sizeof(int) * (n + 1), 1.2, G)) ||
-        (rc = g->colc.ensure(sizeof(int) * E + 4, 1.2, G)) || (rc = g->revc.ensure(sizeof(int) * E + 4, 1.2, G)) ||
-        (rc = g->geom.ensure(sizeof(float4) * E + 16, 1.2, G)) || (rc = g->map.ensure(sizeof(int) * E + 4, 1.2, G)) ||
-        (rc = g->oldidx.ensure(sizeof(int) * E + 4, 1.2, G)) || (rc = g->hop.ensure(n + 16, 1.2, G)))
+    size_t nd[EN_GRAPH_COUNT];
+    eval_graph_needs(g, nd);
+    if ((rc = g->pos4.ensure(nd[EN_POS4], 1.2, G)) || (rc = g->rowc.ensure(nd[EN_ROWC], 1.2, G)) ||
+        (rc = g->colc.ensure(nd[EN_COLC], 1.2, G)) || (rc = g->revc.ensure(nd[EN_REVC], 1.2, G)) ||
+        (rc = g->geom.ensure(nd[EN_GEOM], 1.2, G)) || (rc = g->map.ensure(nd[EN_MAP], 1.2, G)) ||
+        (rc = g->oldidx.ensure(nd[EN_OLDIDX], 1.2, G)) || (rc = g->hop.ensure(nd[EN_HOP], 1.2, G)))
         return rc;
     const float rcut = m->rc;
     const float rc2 = rcut * rcut;

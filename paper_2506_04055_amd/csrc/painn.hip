@@ -482,6 +482,13 @@ int first_layer_factor(mlp_model *m) {
     return 0;
 }
 
+void eval_model_needs(const mlp_model *m, const mlp_nbr *g, size_t *act, size_t *G, size_t *Gs) {
+    const size_t ne = (size_t)g->n_edges_skin;
+    *act = act_floats(g->n_atoms, m->F, m->T) * sizeof(float);
+    *G = sizeof(float4) * ne + 64;
+    *Gs = sizeof(float4) * ne * (size_t)msg_passes(m->F) * (size_t)m->T + 64;
+}
+
 int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
              float *atom_energy_user, int n_seg, const int *seg_dev) {
     const int n = g->n_atoms, F = m->F, K = m->K, T = m->T, F3 = 3 * F, Fh = F / 2;
@@ -491,12 +498,13 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     const int PF = filter_operands(m->precision);
     int *Gr = &g->n_grows;
     int rc;
-    const size_t need = act_floats(n, F, T) * sizeof(float);
-    if ((rc = g->act.ensure(need, 1.2, Gr))) return rc;
+    size_t need_act, need_G, need_Gs;
+    eval_model_needs(m, g, &need_act, &need_G, &need_Gs);
+    if ((rc = g->act.ensure(need_act, 1.2, Gr))) return rc;
     const int npass = msg_passes(F);
     const long ne = g->n_edges_skin;
-    if ((rc = g->G.ensure(sizeof(float4) * (size_t)ne + 64, 1.2, Gr))) return rc;
-    if ((rc = g->Gs.ensure(sizeof(float4) * (size_t)ne * npass * T + 64, 1.2, Gr))) return rc;
+    if ((rc = g->G.ensure(need_G, 1.2, Gr))) return rc;
+    if ((rc = g->Gs.ensure(need_Gs, 1.2, Gr))) return rc;
     Act A;
     carve(g->act.as<float>(), n, F, T, A);
     const int *perm = g->perm.as<int>();

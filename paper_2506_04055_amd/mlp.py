@@ -85,6 +85,7 @@ def lib():
     L.mlp_nbr_destroy.argtypes = [P]
     L.mlp_nbr_edges.argtypes = [P, I32, P, P, I64, ctypes.POINTER(I64), P]
     L.mlp_energy_forces.argtypes = [P, P, P, I32, I32, P, P, P, P, P, ctypes.POINTER(Stats)]
+    L.mlp_energy_forces_noalloc.argtypes = [P, P, P, I32, I32, P, P, P, P, P]
     L.mlp_nbr_check_displacement.argtypes = [P, P, I32, P, ctypes.POINTER(I32)]
     L.mlp_md_step.argtypes = [P, P, P, P, P, P, P, I32, P, ctypes.c_float, ctypes.c_float, P, P,
                               ctypes.POINTER(I32)]
@@ -102,7 +103,7 @@ def lib():
     L.mlp_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
     for name in ("mlp_profile_enable", "mlp_profile_reset", "mlp_profile_read",
                  "mlp_model_create", "mlp_model_destroy", "mlp_build_neighbors", "mlp_nbr_destroy", "mlp_nbr_edges",
-                 "mlp_energy_forces", "mlp_nbr_check_displacement", "mlp_md_step", "mlp_server_create", "mlp_server_destroy",
+                 "mlp_energy_forces", "mlp_energy_forces_noalloc", "mlp_nbr_check_displacement", "mlp_md_step", "mlp_server_create", "mlp_server_destroy",
                  "mlp_submit", "mlp_poll", "mlp_nvt_create", "mlp_nvt_destroy", "mlp_nvt_read", "mlp_md_step_nvt"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -153,6 +154,13 @@ def mlp_energy_forces(model, nbr, pos_soa, n_local, energy, forces=None, ghost_o
                                    _ptr(ghost_owner), _stream(stream), _ptr(energy), _ptr(forces),
                                    _ptr(atom_energy), ctypes.byref(st) if st is not None else None))
     return st.as_dict() if st is not None else None
+
+
+def mlp_energy_forces_noalloc(model, nbr, pos_soa, n_local, energy, forces=None, ghost_owner=None,
+                              atom_energy=None, stream=None):
+    _check(lib().mlp_energy_forces_noalloc(model, nbr, _ptr(pos_soa), int(pos_soa.shape[1]), int(n_local),
+                                           _ptr(ghost_owner), _stream(stream), _ptr(energy), _ptr(forces),
+                                           _ptr(atom_energy)))
 
 
 def mlp_nbr_edges(nbr, which: int = 0, stream=None):
