@@ -432,21 +432,22 @@ def cpu_baseline(synth, reps: int = 3):
     from oracle import oracle as O
     out = {}
 
-    def med(fn):
+    def med(fn, label=""):
         ts = []
         for _ in range(reps):
             t = time.perf_counter()
             fn()
             ts.append(time.perf_counter() - t)
+            print(f"bench: CPU baseline {label} {ts[-1]:.2f} s", file=sys.stderr, flush=True)
         return float(np.median(ts))
 
     dom = synth.fcc_crystal(16, seed=0, ghost_depth=15.0)
     hdr, w = synth.make_weights(128, 20, 3, 1, seed=0)
-    t = med(lambda: O.energy_forces(hdr, w, dom.pos, dom.species, np.zeros(3), n_local=dom.n_local))
+    t = med(lambda: O.energy_forces(hdr, w, dom.pos, dom.species, np.zeros(3), n_local=dom.n_local), "fcc16")
     out["fcc_domain_share"] = {"n_local": dom.n_local, "n_atoms": dom.n_atoms, "s_per_eval": round(t, 3),
                                "local_atom_steps_per_s": round(dom.n_local / t, 1)}
     s1, h1, w1 = synth.workload("water192")
-    t = med(lambda: O.energy_forces(h1, w1, s1.pos, s1.species, s1.box))
+    t = med(lambda: O.energy_forces(h1, w1, s1.pos, s1.species, s1.box), "water192")
     out["water192"] = {"s_per_eval": round(t, 4), "atom_steps_per_s": round(s1.n_atoms / t, 1)}
     h5, w5 = synth.make_weights(128, 20, 3, 4, seed=0)
     sizes, seeds = synth.serving_requests(2000, seed=1)
@@ -455,7 +456,7 @@ def cpu_baseline(synth, reps: int = 3):
     tot_atoms, tot_t = 0, 0.0
     for k in pick:
         s = synth.peptide_like(int(sizes[k]), int(seeds[k]))
-        tot_t += med(lambda: O.energy_forces(h5, w5, s.pos, s.species, s.box))
+        tot_t += med(lambda: O.energy_forces(h5, w5, s.pos, s.species, s.box), f"request {s.n_atoms}")
         tot_atoms += s.n_atoms
     out["serving_sample"] = {"requests": [int(sizes[k]) for k in pick], "atoms_per_s": round(tot_atoms / tot_t, 1)}
     return out, O.num_threads()

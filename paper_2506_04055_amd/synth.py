@@ -343,6 +343,60 @@ def header_json(header: dict) -> str:
     return json.dumps(header, sort_keys=True)
 
 
+# Allegro (single tensor-product layer): the widths the paper gives for its
+# water and aluminium models (a 5 A cutoff, 8 radial functions, polynomial
+# envelope of order 2, l_max = 3, two-body MLP [8, 16, 32] into a 64-wide
+# latent, hidden MLP width 64), with per-degree channel counts (32, 16, 8, 8)
+# for l = 0..3 and a 32-wide output MLP.
+ALLEGRO_DEFAULTS = {"n_basis": 8, "envelope_p": 2, "mlp_2b": [8, 16, 32, 64], "channels": [32, 16, 8, 8],
+                    "latent_hidden": 64, "out_hidden": 32}
+
+
+def allegro_layout(h: dict):
+    """Ordered (name, shape, fan_in) of every Allegro parameter block;
+    fan_in = 0 marks biases.  Matrices are [out][in] row-major."""
+    S, nb = h["n_species"], h["n_basis"]
+    d = list(h["mlp_2b"])
+    NC, D, L, O = sum(h["channels"]), d[-1], h["latent_hidden"], h["out_hidden"]
+    out, prev = [], 2 * S + nb
+    for q, w in enumerate(d):
+        out += [(f"2b_W{q + 1}", (w, prev), prev), (f"2b_b{q + 1}", (w,), 0)]
+        prev = w
+    out += [("Wv", (NC, D), D), ("We", (NC, D), D),
+            ("lat_W1", (L, D + NC), D + NC), ("lat_b1", (L,), 0), ("lat_W2", (D, L), L), ("lat_b2", (D,), 0),
+            ("out_W1", (O, D), D), ("out_b1", (O,), 0), ("out_w2", (O,), O), ("out_b2", (1,), 0)]
+    return out
+
+
+def allegro_header(n_species: int, r_c: float = 5.0, env_scale: float | None = None, **kw) -> dict:
+    h = dict(ALLEGRO_DEFAULTS, **kw)
+    h.update({"model": "allegro", "n_species": n_species, "r_c": r_c, "l_max": len(h["channels"]) - 1,
+              "basis": "bessel", "envelope": "polynomial",
+              "units": {"length": "angstrom", "energy": "eV"}, "graph": "full_directed_csr_by_destination"})
+    # 1 / sqrt(mean neighbour count) of a liquid or fcc metal at r_c = 5 A
+    h["env_scale"] = float(np.float32(1.0 / math.sqrt(40.0) if env_scale is None else env_scale))
+    lay = allegro_layout(h)
+    h["layout"] = [[n, list(s)] for n, s, _ in lay]
+    h["n_weights"] = int(sum(int(np.prod(s)) for _, s, _ in lay))
+    return h
+
+
+def make_allegro_weights(n_species: int, seed: int = 0, bias_scale: float = 0.0, **kw):
+    """Flat float32 Allegro weights: matrices ~ N(0, 1/fan_in), biases 0 (or
+    N(0, bias_scale^2)); draw order = layout order, float64 draws cast to
+    float32."""
+    h = allegro_header(n_species, **kw)
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape, fan_in in allegro_layout(h):
+        n = int(np.prod(shape))
+        if fan_in == 0:
+            parts.append(rng.standard_normal(n) * bias_scale if bias_scale > 0 else np.zeros(n))
+        else:
+            parts.append(rng.standard_normal(n) / math.sqrt(fan_in))
+    return h, np.concatenate(parts).astype(np.float32)
+
+
 MD_FILTER_SCALE = 0.1
 MD_READOUT_SCALE = 1e-2
 
