@@ -94,6 +94,21 @@ const char *mlp_last_error(void);
  *   W5 [F/2][F] b5 [F/2] w6 [F/2] b6 [1]); matrices are [out][in] row-major;
  *   3F blocks are split [vv | s | vs] (message) and [vv | sv | ss] (update).
  *   Copied to the device; the caller keeps ownership of its array.
+ * header_json may instead describe an Allegro model with one tensor-product
+ *   layer (Methods, "Chosen Architectures" and "Training Details": the
+ *   strictly local, edge-centric model, one layer, l_max = 3, 8 radial
+ *   functions, polynomial envelope of order 2):
+ *   {"model":"allegro","n_species":..,"r_c":..,"n_basis":..,"envelope_p":..,
+ *    "mlp_2b":[..],"channels":[n_0,..,n_lmax],"latent_hidden":..,
+ *    "out_hidden":..,"env_scale":..,"basis":"bessel","envelope":"polynomial"}
+ *   with l_max <= 3, channels totalling at most 64 (a multiple of 4), the
+ *   last two-body width (the latent width D) at most 64, every width a
+ *   multiple of 4.  Weights (matrices [out][in]): for each two-body layer q
+ *   W_q [d_q][d_(q-1)] b_q [d_q] (d_0's input: onehot(Z_i) | onehot(Z_j) |
+ *   radial functions); Wv [NC][D]; We [NC][D]; lat_W1 [LH][D + NC]
+ *   lat_b1 [LH] lat_W2 [D][LH] lat_b2 [D]; out_W1 [OH][D] out_b1 [OH]
+ *   out_w2 [OH] out_b2 [1].  An Allegro model is strictly local: its graph
+ *   needs ghosts within rc only, and the serving calls do not take it.
  * precision: the operand forms of the two matrix-core contractions, the
  *   node-feature GEMMs (node) and the radial filter of the message kernels
  *   (filter):

@@ -24,6 +24,7 @@ using namespace mlp;
 namespace {
 using mlp_json::JsonTop;
 using mlp_json::get_int;
+using mlp_json::get_int_list;
 using mlp_json::get_num;
 using mlp_json::parse_top;
 int status(int rc) { return rc; }
@@ -38,6 +39,62 @@ mlp::LayerW mlp_model::layer(int t) const {
     return L;
 }
 
+// An Allegro model (single tensor-product layer): header fields n_species,
+// r_c, n_basis, envelope_p, mlp_2b, channels (per degree l = 0..l_max),
+// latent_hidden, out_hidden, env_scale; basis "bessel", envelope
+// "polynomial".  The neighbour graph treats it as one layer (strictly local).
+static int create_allegro(const JsonTop &j, const float *weights, size_t n_weights, int precision, mlp_model **out) {
+    long S, NB, p, LH, OH;
+    double rc, nu;
+    std::vector<long> d2b, ch;
+    if (!get_int(j, "n_species", &S) || !get_int(j, "n_basis", &NB) || !get_int(j, "envelope_p", &p) ||
+        !get_int(j, "latent_hidden", &LH) || !get_int(j, "out_hidden", &OH) || !get_num(j, "r_c", &rc) ||
+        !get_num(j, "env_scale", &nu) || !get_int_list(j, "mlp_2b", &d2b) || !get_int_list(j, "channels", &ch))
+        return fail(MLP_ERR_INVALID_ARG, "allegro header lacks n_species, n_basis, envelope_p, mlp_2b, channels, "
+                                         "latent_hidden, out_hidden, r_c or env_scale");
+    auto str = [&](const char *k) { auto it = j.kv.find(k); return it == j.kv.end() ? std::string() : it->second; };
+    if (str("basis") != "bessel" || str("envelope") != "polynomial")
+        return fail(MLP_ERR_INVALID_ARG, "allegro: basis must be bessel and envelope polynomial");
+    if (d2b.size() > 6 || ch.size() > 4 || ch.empty())
+        return fail(MLP_ERR_INVALID_ARG, "allegro: at most 6 two-body widths and degrees 0..3");
+    if (precision != MLP_FP32 && precision != MLP_BF16 && precision != MLP_BF16_FAST &&
+        precision != MLP_BF16_NODE && precision != MLP_BF16_NODE_X3)
+        return fail(MLP_ERR_INVALID_ARG, "unknown precision");
+    AlDims d;
+    d.S = (int)S;
+    d.NB = (int)NB;
+    d.p = (int)p;
+    d.n2b = (int)d2b.size();
+    for (size_t q = 0; q < d2b.size(); q++) d.d2b[q] = (int)d2b[q];
+    d.lmax = (int)ch.size() - 1;
+    d.NC = 0;
+    for (size_t q = 0; q < ch.size(); q++) {
+        if (ch[q] < 0 || ch[q] > 64) return fail(MLP_ERR_INVALID_ARG, "allegro: channel count out of range");
+        d.ch[q] = (int)ch[q];
+        d.NC += (int)ch[q];
+    }
+    d.D = d.d2b[d.n2b - 1];
+    d.LH = (int)LH;
+    d.OH = (int)OH;
+    d.rc = (float)rc;
+    d.nu = (float)nu;
+    mlp_model *m = new mlp_model();
+    m->F = 0;
+    m->K = 0;
+    m->T = 1;
+    m->S = (int)S;
+    m->rc = (float)rc;
+    m->eps = 0.f;
+    m->precision = precision;
+    m->n_weights = n_weights;
+    if (int rc2 = allegro_create(m, d, weights, n_weights)) {
+        delete m;
+        return rc2;
+    }
+    *out = m;
+    return MLP_OK;
+}
+
 extern "C" {
 
 const char *mlp_last_error(void) { return last_error_cstr(); }
@@ -48,6 +105,10 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
     *out = nullptr;
     JsonTop j = parse_top(header_json);
     if (!j.ok) return fail(MLP_ERR_INVALID_ARG, "model header is not a JSON object");
+    {
+        auto it = j.kv.find("model");
+        if (it != j.kv.end() && it->second == "allegro") return create_allegro(j, weights, n_weights, precision, out);
+    }
     long F, K, T, S;
     double rc, eps;
     if (!get_int(j, "F", &F) || !get_int(j, "K", &K) || !get_int(j, "T", &T) || !get_int(j, "n_species", &S) ||
@@ -157,6 +218,7 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
 
 int mlp_model_destroy(mlp_model *m) {
     if (!m) return MLP_OK;
+    allegro_destroy(m);
     if (m->w_dev) hipFree(m->w_dev);
     if (m->wb_dev) hipFree(m->wb_dev);
     if (m->pk_dev) hipFree(m->pk_dev);

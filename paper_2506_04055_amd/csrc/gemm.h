@@ -24,13 +24,15 @@ size_t packed_bytes(int R, int C, bool transpose);
 // stored [out][in]), transpose = true gives B = W (adjoint).  Returns 0 or -5.
 int pack_weight(hipStream_t s, const float *W, int R, int C, bool transpose, void *arena, PackedW *out);
 
-// C = epilogue(A B) for A (M x K, row stride lda, FP32).
+// C = epilogue(A B) for A (M x K, row stride lda, FP32).  Mc (device, may be
+// null): a row count known only on the device; rows at or past it are not
+// computed (the grid is sized for M, its workgroups past the count leave).
 // precision: 0 = FP32 operands, 1 = bfloat16 operands, 2 = split bfloat16
 // operands (hi + lo, three products); FP32 accumulation in all.
 // Returns 0 or -5 (launch error).
 int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, const PackedW &B, float *C, int ldc,
               int M, const float *bias = nullptr, float *C2 = nullptr, int ldc2 = 0, const float *R = nullptr,
-              int ldr = 0);
+              int ldr = 0, const int *Mc = nullptr);
 
 // Two chained products C2 = e2(act(A B1) B2) in one kernel, the intermediate
 // kept on chip.  e1 = GE_BIAS_SILU: act = SiLU(x + bias1), the pre-activation
@@ -62,6 +64,7 @@ struct GemmChain {
     int F = 0;                                    // feature width of the update epilogues
     const float *sn = nullptr, *v1 = nullptr, *UV = nullptr;
     float *s2 = nullptr, *v2 = nullptr, *gUV = nullptr;
+    const int *Mc = nullptr;                      // device row count bounding M (may be null)
 };
 int node_gemm_chain(hipStream_t s, int precision, const GemmChain &c);
 

@@ -294,8 +294,10 @@ __device__ __forceinline__ void fetch_rows(const float *R, int ldr, long m0, int
 template <int P, int EPI, int KS>
 __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(GemmWaves<P, KS>::N))) k_gemm(const float *__restrict__ A, int lda, PackedW B, float *C, int ldc,
                                                   int M, const float *__restrict__ bias, float *__restrict__ C2,
-                                                  int ldc2, const float *R, int ldr) {
+                                                  int ldc2, const float *R, int ldr, const int *Mc) {
     __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
+    // a row count on the device (Mc) bounds M: the grid is sized for M
+    if (Mc) M = min(M, *Mc);
     // grid.x is padded to a multiple of 8 (the column chunks of one row block
     // then run on one XCD and share its L2): padding workgroups leave at once
     if ((long)blockIdx.x * GW * 16 >= M) return;
@@ -361,8 +363,10 @@ __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(2)
 k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *C1, int ldc1, const float *__restrict__ bias1,
              const float *R1, int ldr1, PackedW B2, float *C2, int ldc2, const float *__restrict__ bias2,
              const float *R2, int ldr2, int M, int Fu, const float *sn, const float *v1, const float *UV, float *s2,
-             float *v2, float *gUV) {
+             float *v2, float *gUV, const int *Mc) {
     __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
+    if (Mc) M = min(M, *Mc);
+    if ((long)blockIdx.x * GW * 16 >= M) return;   // the whole workgroup leaves
     const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
     const long m0 = ((long)blockIdx.x * GW + (threadIdx.x >> 6)) * 16;
     const long arow = m0 + c16;
@@ -494,28 +498,28 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *C1, int ld
 
 template <int P, int EPI, int KS>
 static void launch(hipStream_t s, const float *A, int lda, const PackedW &B, float *C, int ldc, int M,
-                   const float *bias, float *C2, int ldc2, const float *R, int ldr) {
+                   const float *bias, float *C2, int ldc2, const float *R, int ldr, const int *Mc) {
     unsigned bx = (unsigned)((M + 16 * GW - 1) / (16 * GW));
     const unsigned by = (unsigned)(B.Np / NCH);
     if (by > 1) bx = (bx + 7) / 8 * 8;
-    k_gemm<P, EPI, KS><<<dim3(bx, by), 64 * GW, 0, s>>>(A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr);
+    k_gemm<P, EPI, KS><<<dim3(bx, by), 64 * GW, 0, s>>>(A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr, Mc);
 }
 
 template <int P, int EPI>
 static int launch_k(hipStream_t s, const float *A, int lda, const PackedW &B, float *C, int ldc, int M,
-                    const float *bias, float *C2, int ldc2, const float *R, int ldr) {
-    if (B.K <= 128) launch<P, EPI, 4>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr);
-    else if (B.K <= 256) launch<P, EPI, 8>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr);
-    else if (B.K <= 384) launch<P, EPI, 12>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr);
+                    const float *bias, float *C2, int ldc2, const float *R, int ldr, const int *Mc) {
+    if (B.K <= 128) launch<P, EPI, 4>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr, Mc);
+    else if (B.K <= 256) launch<P, EPI, 8>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr, Mc);
+    else if (B.K <= 384) launch<P, EPI, 12>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr, Mc);
     else return -1;
     return 0;
 }
 
 int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, const PackedW &B, float *C, int ldc,
-              int M, const float *bias, float *C2, int ldc2, const float *R, int ldr) {
+              int M, const float *bias, float *C2, int ldc2, const float *R, int ldr, const int *Mc) {
     if (M <= 0 || B.N <= 0 || B.K <= 0) return 0;
     int rc = 0;
-#define GL(P_, E_) rc = launch_k<P_, E_>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr)
+#define GL(P_, E_) rc = launch_k<P_, E_>(s, A, lda, B, C, ldc, M, bias, C2, ldc2, R, ldr, Mc)
 #define GE(P_)                                   \
     switch (epi) {                               \
         case GE_STORE: GL(P_, GE_STORE); break;   \
@@ -542,7 +546,7 @@ static void launch_chain(hipStream_t s, const GemmChain &c) {
     const unsigned bx = (unsigned)((c.M + 16 * GW - 1) / (16 * GW));
     k_gemm_chain<P, E1, E2, KS><<<bx, 64 * GW, 0, s>>>(c.A, c.lda, *c.B1, c.C1, c.ldc1, c.bias1, c.R1, c.ldr1, *c.B2,
                                                         c.C2, c.ldc2, c.bias2, c.R2, c.ldr2, c.M, c.F, c.sn, c.v1,
-                                                        c.UV, c.s2, c.v2, c.gUV);
+                                                        c.UV, c.s2, c.v2, c.gUV, c.Mc);
 }
 
 template <int P>

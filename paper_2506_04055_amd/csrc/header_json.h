@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <map>
 #include <string>
+#include <vector>
 
 namespace mlp_json {
 // Values: numbers and strings are kept; nested objects/arrays are skipped.
@@ -40,6 +41,7 @@ inline bool skip_value(const char *&p, std::string *scalar) {
         return true;
     }
     if (*p == '{' || *p == '[') {
+        const char *b0 = p;
         int depth = 0;
         bool in_str = false;
         do {
@@ -57,6 +59,7 @@ inline bool skip_value(const char *&p, std::string *scalar) {
             }
             p++;
         } while (depth > 0);
+        if (scalar) scalar->assign(b0, p);   // the raw text of the nested value
         return true;
     }
     const char *b = p;
@@ -117,4 +120,28 @@ inline bool get_num(const JsonTop &j, const char *k, double *out) {
     return true;
 }
 
+// A flat list of integers, "[8, 16, 32]"; false unless every element is an
+// integer and the list is non-empty.
+inline bool get_int_list(const JsonTop &j, const char *k, std::vector<long> *out) {
+    auto it = j.kv.find(k);
+    if (it == j.kv.end()) return false;
+    const std::string &v = it->second;
+    if (v.size() < 2 || v.front() != '[' || v.back() != ']') return false;
+    out->clear();
+    const char *p = v.c_str() + 1;
+    for (;;) {
+        skip_ws(p);
+        char *end = nullptr;
+        long x = std::strtol(p, &end, 10);
+        if (end == p) return false;
+        out->push_back(x);
+        p = end;
+        skip_ws(p);
+        if (*p == ',') {
+            p++;
+            continue;
+        }
+        return *p == ']' && p[1] == '\0' && !out->empty();
+    }
+}
 }  // namespace mlp_json

@@ -73,10 +73,23 @@ struct LayerW {
 // UV is the stacked [U; V] (2F x F, adjacent in the weight layout).
 enum { WP_W1 = 0, WP_W2, WP_UV, WP_W3, WP_W4, WP_W1T, WP_W2T, WP_UVT, WP_W3T, WP_W4T, WP_COUNT };
 
+// Dimensions of a single-layer Allegro model (allegro.hip): species, radial
+// functions, envelope order, the two-body MLP widths, channel counts per
+// degree l = 0..lmax (NC in all), latent width D (= the last two-body
+// width), latent hidden width LH, output hidden width OH; cutoff and the
+// environment normalisation nu.
+struct AlDims {
+    int S = 0, NB = 0, p = 0, n2b = 0, d2b[6] = {0, 0, 0, 0, 0, 0}, lmax = 0, ch[4] = {0, 0, 0, 0}, NC = 0, D = 0,
+        LH = 0, OH = 0;
+    float rc = 0.f, nu = 0.f;
+};
+struct AlModel;
+
 }  // namespace mlp
 
 struct mlp_model {
     int F, K, T, S, precision;
+    mlp::AlModel *al = nullptr;          // set for an Allegro model (then T = 1; F, K unused)
     float rc, eps;
     size_t n_weights;
     float *w_dev = nullptr;              // flat weights on the device
@@ -177,6 +190,24 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
 // Bytes of the buffers evaluate() ensures: the activation arena, the edge
 // gradients G and the adjoint's edge-sum slots Gs.
 void eval_model_needs(const mlp_model *m, const mlp_nbr *g, size_t *act, size_t *G, size_t *Gs);
+// Energy of each segment (FP64, fixed order) from per-atom energies U in
+// internal order, and U scattered to the caller's order if atom_energy_user.
+int launch_energy(hipStream_t s, const float *U, const int *perm, int n, int n_local, double *energy,
+                  float *atom_energy_user, int n_seg, const int *seg_dev);
+// F_k = sum over in-edges e of (G at rev(e)) - (G at e), G_e = dE/d(x_dst - x_src),
+// written to the caller's order (SoA).
+int launch_forces(hipStream_t s, const int *rowc, const int *revc, const float4 *G, const int *perm, int n,
+                  float *forces_user);
+
+// ---- Allegro (allegro.hip) ----
+// Validates the dimensions and the weight count, copies and packs the weights
+// (host array in the layout of the model header); sets m->al.
+int allegro_create(mlp_model *m, const AlDims &d, const float *weights, size_t n_weights);
+void allegro_destroy(mlp_model *m);
+int allegro_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
+                     float *atom_energy_user, int n_seg, const int *seg_dev);
+// Bytes of the per-evaluation arena (per-edge and per-atom activations).
+size_t allegro_arena_bytes(const mlp_model *m, long n_atoms, long n_edges);
 // Fill m->phi0_dev (device, S x 3F) from the embedding and the first layer's
 // message MLP, in the model's precision; tmp: device scratch of 2 S F floats.
 int first_layer_table(mlp_model *m, hipStream_t s, float *tmp);

@@ -484,13 +484,35 @@ int first_layer_factor(mlp_model *m) {
 
 void eval_model_needs(const mlp_model *m, const mlp_nbr *g, size_t *act, size_t *G, size_t *Gs) {
     const size_t ne = (size_t)g->n_edges_skin;
+    if (m->al) {
+        *act = allegro_arena_bytes(m, g->n_atoms, (long)ne);
+        *G = sizeof(float4) * ne + 64;
+        *Gs = 64;
+        return;
+    }
     *act = act_floats(g->n_atoms, m->F, m->T) * sizeof(float);
     *G = sizeof(float4) * ne + 64;
     *Gs = sizeof(float4) * ne * (size_t)msg_passes(m->F) * (size_t)m->T + 64;
 }
 
+int launch_energy(hipStream_t s, const float *U, const int *perm, int n, int n_local, double *energy,
+                  float *atom_energy_user, int n_seg, const int *seg_dev) {
+    k_energy_seg<<<std::max(1, n_seg), ERED, 0, s>>>(U, perm, seg_dev, n, n_local, energy);
+    if (atom_energy_user) k_scatter_energy<<<nblk(n, 256), 256, 0, s>>>(U, perm, n, atom_energy_user);
+    HIP_TRY(hipGetLastError());
+    return 0;
+}
+
+int launch_forces(hipStream_t s, const int *rowc, const int *revc, const float4 *G, const int *perm, int n,
+                  float *forces_user) {
+    k_forces<<<nblk(16L * n, 256), 256, 0, s>>>(rowc, revc, G, perm, n, forces_user);
+    HIP_TRY(hipGetLastError());
+    return 0;
+}
+
 int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
              float *atom_energy_user, int n_seg, const int *seg_dev) {
+    if (m->al) return allegro_evaluate(m, g, s, energy, forces_user, atom_energy_user, n_seg, seg_dev);
     const int n = g->n_atoms, F = m->F, K = m->K, T = m->T, F3 = 3 * F, Fh = F / 2;
     // MFMA operand forms of the mode for the node GEMMs (P) and for the
     // radial filter (PF): 0 FP32, 1 plain bfloat16, 2 split bfloat16 (hi + lo)

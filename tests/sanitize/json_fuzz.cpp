@@ -42,6 +42,13 @@ int main() {
             bad++;
         }
         if (mlp_json::get_int(j, "r_c", &F)) { std::printf("5.0 read as an integer\n"); bad++; }
+        std::vector<long> lv;
+        mlp_json::JsonTop j2 = mlp_json::parse_top("{\"mlp_2b\": [8, 16 ,32,64], \"bad\": [1, x], \"e\": []}");
+        if (!mlp_json::get_int_list(j2, "mlp_2b", &lv) || lv.size() != 4 || lv[3] != 64 ||
+            mlp_json::get_int_list(j2, "bad", &lv) || mlp_json::get_int_list(j2, "e", &lv)) {
+            std::printf("integer lists misread\n");
+            bad++;
+        }
     }
     const char alphabet[] = "{}[]\":,\\ \t\nabcFKT0123456789.eE-+";
     long n_ok = 0;
@@ -70,6 +77,8 @@ int main() {
             n_ok++;
             for (const char *k : {"F", "K", "T", "n_species"}) (void)mlp_json::get_int(j, k, &iv);
             for (const char *k : {"r_c", "eps"}) (void)mlp_json::get_num(j, k, &dv);
+            std::vector<long> lv;
+            for (const char *k : {"graph", "units", "F"}) (void)mlp_json::get_int_list(j, k, &lv);
         }
     }
     std::printf("json_fuzz: %d failures, %ld of 200000 inputs parsed as objects\n", bad, n_ok);
