@@ -8,9 +8,9 @@ The paper deploys Allegro (Methods, "Chosen Architectures": an edge-centric,
 strictly local equivariant model whose messages pass only between directed
 edges that share their central atom) with one tensor-product layer,
 l_max = 3, 8 radial basis functions, a polynomial envelope of order 2 and a
-5 A cutoff for water and aluminium ("Training Details"), and a two-body MLP
-of widths [8, 16, 32] into a 64-wide latent ("hidden MLP layer dimension of
-64 and embedding dimensions of [8, 16, 32]").  The layer equations are those
+5 A cutoff for water and aluminium ("Training Details"), and gives 64 as the
+hidden MLP width and 8, 16, 32 as the embedding widths, read here as a
+two-body MLP of widths [8, 16, 32] into a 64-wide latent.  The layer equations are those
 of the cited Allegro paper, which the paper does not print; the reading used
 here, per directed edge e = (i <- j) with 0 < r = |r_j - r_i| < r_c and
 rhat = (r_j - r_i) / r:

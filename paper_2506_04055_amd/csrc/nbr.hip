@@ -148,8 +148,41 @@ int scan_exclusive(const int *in, int *out, int n, DevBuf &tmp, int *n_grows, hi
 // ---------------------------------------------------------------------------
 struct Grid {
     int nc[3];
+    int bits[3];                  // bits of each cell coordinate in the cell key
     float lo[3], inv_w[3], L[3];  // L[d] > 0: periodic dimension
 };
+
+// Cell key: the bits of (cx, cy, cz) interleaved from the least significant
+// one (a Morton order; a coordinate whose bits are used up drops out).
+// Cells close in space get close keys, so the atoms sorted by key, and the
+// contiguous slices of them one XCD's workgroups take, are compact regions
+// whose neighbours' rows stay in that XCD's L2; a row-major order would
+// place the atoms of the adjacent plane a whole plane of cells away.
+__host__ __device__ inline int cell_key(const Grid &g, int cx, int cy, int cz) {
+    int key = 0, o = 0;
+    for (int b = 0; b < 10; b++) {
+        if (b < g.bits[0]) key |= ((cx >> b) & 1) << o++;
+        if (b < g.bits[1]) key |= ((cy >> b) & 1) << o++;
+        if (b < g.bits[2]) key |= ((cz >> b) & 1) << o++;
+    }
+    return key;
+}
+
+__device__ __forceinline__ void cell_coords(const Grid &g, int key, int &cx, int &cy, int &cz) {
+    cx = cy = cz = 0;
+    int o = 0;
+    for (int b = 0; b < 10; b++) {
+        if (b < g.bits[0]) cx |= ((key >> o++) & 1) << b;
+        if (b < g.bits[1]) cy |= ((key >> o++) & 1) << b;
+        if (b < g.bits[2]) cz |= ((key >> o++) & 1) << b;
+    }
+}
+
+static int bits_for(int n) {
+    int b = 0;
+    while ((1 << b) < n) b++;
+    return b;
+}
 
 __device__ __forceinline__ float wrap_coord(float x, float L) {
     // x - L floor(x / L), then one fold into [0, L); the identity on [0, L).
@@ -205,7 +238,7 @@ __global__ void k_bin(const float *__restrict__ pos, int n, Grid g, float4 *__re
         c[d] = min(max(ci, 0), g.nc[d] - 1);
     }
     posw[i] = make_float4(p[0], p[1], p[2], 0.f);
-    int cell = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
+    int cell = cell_key(g, c[0], c[1], c[2]);
     cell_of[i] = cell;
     atomicAdd(&cell_cnt[cell], 1);
 }
@@ -296,12 +329,12 @@ __device__ __forceinline__ float fold_once(float d, float L) {
     return d;
 }
 
-// Neighbours within rc + skin of row i, one wave per row.  The stencil cells
-// are visited in ascending order, runs of consecutive cells (z-neighbours
-// without a wrap) form one contiguous range of the cell-sorted rows, and each
-// range is tested 64 candidates at a time; a ballot and a prefix popcount
-// place the hits, so the columns of a row come out ascending, as from a
-// sequential scan.
+// Neighbours within rc + skin of row i, one wave per row.  The (at most 27)
+// stencil cells are visited in ascending key order, runs of consecutive keys
+// form one contiguous range of the cell-sorted rows, and each range is
+// tested 64 candidates at a time; a ballot and a prefix popcount place the
+// hits, so the columns of a row come out ascending, as from a sequential
+// scan.
 template <bool FILL>
 __global__ void __launch_bounds__(256) k_nbr(const float4 *__restrict__ pb, const int *__restrict__ cell_int,
                                              const int *__restrict__ cell_start, int n, Grid g, float cut2,
@@ -311,41 +344,54 @@ __global__ void __launch_bounds__(256) k_nbr(const float4 *__restrict__ pb, cons
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
     const float4 pi = pb[i];
-    const int cell = cell_int[i];
-    const int cz = cell % g.nc[2];
-    const int cy = (cell / g.nc[2]) % g.nc[1];
-    const int cx = cell / (g.nc[2] * g.nc[1]);
+    int cx, cy, cz;
+    cell_coords(g, cell_int[i], cx, cy, cz);
     int lx[3], ly[3], lz[3];
     const int nx = stencil_list(cx, g.nc[0], g.L[0] > 0.f, lx);
     const int ny = stencil_list(cy, g.nc[1], g.L[1] > 0.f, ly);
     const int nz = stencil_list(cz, g.nc[2], g.L[2] > 0.f, lz);
+    // the stencil's keys, sorted (unused slots hold INT_MAX and sort last)
+    int key[27];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+#pragma unroll
+            for (int q = 0; q < 3; q++)
+                key[9 * a + 3 * b + q] =
+                    (a < nx && b < ny && q < nz) ? cell_key(g, lx[a], ly[b], lz[q]) : 0x7fffffff;
+#pragma unroll
+    for (int a = 0; a < 26; a++)
+#pragma unroll
+        for (int b = 0; b < 26 - a; b++) {
+            const int lo = min(key[b], key[b + 1]), hi = max(key[b], key[b + 1]);
+            key[b] = lo;
+            key[b + 1] = hi;
+        }
+    const int nk = nx * ny * nz;
     int c = 0;
     const int o = FILL ? row[i] : 0;
     const unsigned long long below = (1ull << lane) - 1ull;
-    for (int a = 0; a < nx; a++)
-        for (int b = 0; b < ny; b++) {
-            const int base = (lx[a] * g.nc[1] + ly[b]) * g.nc[2];
-            for (int q = 0; q < nz;) {
-                int q1 = q;
-                while (q1 + 1 < nz && lz[q1 + 1] == lz[q1] + 1) q1++;
-                const int j0 = cell_start[base + lz[q]], j1 = cell_start[base + lz[q1] + 1];
-                q = q1 + 1;
-                for (int jb = j0; jb < j1; jb += 64) {
-                    const int j = jb + lane;
-                    bool hit = false;
-                    if (j < j1 && j != i) {
-                        const float4 pj = pb[j];
-                        const float dx = fold_once(pj.x - pi.x, g.L[0]);
-                        const float dy = fold_once(pj.y - pi.y, g.L[1]);
-                        const float dz = fold_once(pj.z - pi.z, g.L[2]);
-                        hit = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < cut2;
-                    }
-                    const unsigned long long m = __ballot(hit);
-                    if (FILL && hit) col[o + c + __popcll(m & below)] = j;
-                    c += __popcll(m);
-                }
+    for (int q = 0; q < nk;) {
+        int q1 = q;
+        while (q1 + 1 < nk && key[q1 + 1] == key[q1] + 1) q1++;
+        const int j0 = cell_start[key[q]], j1 = cell_start[key[q1] + 1];
+        q = q1 + 1;
+        for (int jb = j0; jb < j1; jb += 64) {
+            const int j = jb + lane;
+            bool hit = false;
+            if (j < j1 && j != i) {
+                const float4 pj = pb[j];
+                const float dx = fold_once(pj.x - pi.x, g.L[0]);
+                const float dy = fold_once(pj.y - pi.y, g.L[1]);
+                const float dz = fold_once(pj.z - pi.z, g.L[2]);
+                hit = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < cut2;
             }
+            const unsigned long long m = __ballot(hit);
+            if (FILL && hit) col[o + c + __popcll(m & below)] = j;
+            c += __popcll(m);
         }
+    }
     if (!FILL && lane == 0) cnt[i] = c;
 }
 
@@ -612,7 +658,16 @@ int build_graph(mlp_model *m, mlp_nbr *g, const float *pos, const int32_t *speci
         }
     }
     const float margin = cut * (1.0f + 1e-5f);
-    long ncell = 1;
+    // the cell arrays are indexed by cell key, whose range is 2^(bits of the
+    // three coordinates): at most 8x the cell count
+    auto key_space = [&]() {
+        long t = 1;
+        for (int d = 0; d < 3; d++) {
+            gr.bits[d] = bits_for(gr.nc[d]);
+            t <<= gr.bits[d];
+        }
+        return t;
+    };
     for (int d = 0; d < 3; d++) {
         float ext = L[d] > 0.f ? L[d] : (hi[d] - lo[d]) * (1.0f + 1e-6f) + 1e-3f;
         int ncd = std::max(1, (int)std::floor(ext / margin));
@@ -620,17 +675,16 @@ int build_graph(mlp_model *m, mlp_nbr *g, const float *pos, const int32_t *speci
         gr.nc[d] = ncd;
         gr.lo[d] = L[d] > 0.f ? 0.f : lo[d];
         gr.inv_w[d] = (float)ncd / ext;
-        ncell *= ncd;
     }
-    // keep the grid modest: coarsen if the cell count is extreme (cells stay >= cut)
+    long ncell = key_space();
+    // keep the grid modest: coarsen if the key range is extreme (cells stay >= cut)
     while (ncell > (1L << 24)) {
-        ncell = 1;
         for (int d = 0; d < 3; d++) {
             float ext = L[d] > 0.f ? L[d] : (hi[d] - lo[d]) * (1.0f + 1e-6f) + 1e-3f;
             gr.nc[d] = std::max(1, gr.nc[d] / 2);
             gr.inv_w[d] = (float)gr.nc[d] / ext;
-            ncell *= gr.nc[d];
         }
+        ncell = key_space();
     }
     const int nc = (int)ncell;
     int *G = &err_grows;

@@ -73,21 +73,24 @@ def test_node_flops_with_active_sets(bench):
 
 
 def test_traffic_figure_is_gated_on_the_kernel_source(bench, tmp_path, monkeypatch):
-    d = {"kernel": "msg_bwd", "precision": "bf16", "source_file": "msg.hip", "hbm_bytes_per_launch": 123456789}
+    d = {"kernel": "msg_bwd", "precision": "bf16", "hbm_bytes_per_launch": 123456789}
     (tmp_path / "profiles").mkdir()
     (tmp_path / "paper_2506_04055_amd" / "csrc").mkdir(parents=True)
-    shutil.copy(os.path.join(ROOT, "paper_2506_04055_amd", "csrc", "msg.hip"),
-                tmp_path / "paper_2506_04055_amd" / "csrc" / "msg.hip")
+    for f in ("msg.hip", "nbr.hip"):
+        shutil.copy(os.path.join(ROOT, "paper_2506_04055_amd", "csrc", f), tmp_path / "paper_2506_04055_amd" / "csrc" / f)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     dst = tmp_path / "profiles" / "traffic_msg_bwd_fcc1m_bf16.json"
-    # the stored hash of the current source: the figure is used
-    d_ok = dict(d, source_sha256_16=bench.source_hash("msg.hip"))
-    dst.write_text(json.dumps(d_ok))
+    # the stored hashes of the current sources: the figure is used
+    ok = {"msg.hip": bench.source_hash("msg.hip"), "nbr.hip": bench.source_hash("nbr.hip")}
+    dst.write_text(json.dumps(dict(d, source_sha256_16=ok)))
     assert bench.load_traffic("msg_bwd", "bf16", "fcc1m") == d["hbm_bytes_per_launch"]
-    # any other source: the figure is withheld
-    dst.write_text(json.dumps(dict(d, source_sha256_16="0" * 16)))
+    # the kernel or the atom order changed since: the figure is withheld
+    for f in ok:
+        dst.write_text(json.dumps(dict(d, source_sha256_16=dict(ok, **{f: "0" * 16}))))
+        assert bench.load_traffic("msg_bwd", "bf16", "fcc1m") is None
+    # a single hash (the old form) or no file: withheld
+    dst.write_text(json.dumps(dict(d, source_sha256_16=ok["msg.hip"])))
     assert bench.load_traffic("msg_bwd", "bf16", "fcc1m") is None
-    # no file: withheld
     dst.unlink()
     assert bench.load_traffic("msg_bwd", "bf16", "fcc1m") is None
 
