@@ -30,6 +30,7 @@
 // forces by gathering through the reverse-edge index (no atomics).
 #include "internal.h"
 #include "gemm.h"
+#include "sh.h"
 
 #include <cmath>
 #include <vector>
@@ -61,88 +62,20 @@ struct AlModel {
 };
 
 // ---------------------------------------------------------------------------
-// Spherical harmonics, component normalisation, degree <= 3, as polynomials
-// of the unit vector (x, y, z), and the tangential gradient of sum_m g_m Y_m.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void sh16(float x, float y, float z, float *Y) {
-    const float s3 = 1.7320508075688772f, s15 = 3.872983346207417f, s5 = 2.23606797749979f;
-    const float s70 = 8.366600265340756f, s105 = 10.246950765959598f, s42 = 6.48074069840786f,
-                s7 = 2.6457513110645907f;
-    Y[0] = 1.f;
-    Y[1] = s3 * y;
-    Y[2] = s3 * z;
-    Y[3] = s3 * x;
-    Y[4] = s15 * x * y;
-    Y[5] = s15 * y * z;
-    Y[6] = 0.5f * s5 * (3.f * z * z - 1.f);
-    Y[7] = s15 * x * z;
-    Y[8] = 0.5f * s15 * (x * x - y * y);
-    Y[9] = 0.25f * s70 * y * (3.f * x * x - y * y);
-    Y[10] = s105 * x * y * z;
-    Y[11] = 0.25f * s42 * y * (5.f * z * z - 1.f);
-    Y[12] = 0.5f * s7 * z * (5.f * z * z - 3.f);
-    Y[13] = 0.25f * s42 * x * (5.f * z * z - 1.f);
-    Y[14] = 0.5f * s105 * z * (x * x - y * y);
-    Y[15] = 0.25f * s70 * x * (x * x - 3.f * y * y);
-}
-
-// sum_m g[m] grad Y_m, the gradient of the polynomial forms above (the
-// caller projects it onto the tangent plane)
-__device__ __forceinline__ void sh16_grad(float x, float y, float z, const float *g, float &ox, float &oy,
-                                          float &oz) {
-    const float s3 = 1.7320508075688772f, s15 = 3.872983346207417f, s5 = 2.23606797749979f;
-    const float s70 = 8.366600265340756f, s105 = 10.246950765959598f, s42 = 6.48074069840786f,
-                s7 = 2.6457513110645907f;
-    float gx = 0.f, gy = 0.f, gz = 0.f;
-    gx += s3 * g[3];
-    gy += s3 * g[1];
-    gz += s3 * g[2];
-    gx += s15 * (g[4] * y + g[7] * z + g[8] * x);
-    gy += s15 * (g[4] * x + g[5] * z - g[8] * y);
-    gz += s15 * (g[5] * y + g[7] * x) + 3.f * s5 * z * g[6];
-    const float a9 = 0.25f * s70 * g[9], a15 = 0.25f * s70 * g[15];
-    gx += a9 * 6.f * x * y + a15 * (3.f * x * x - 3.f * y * y);
-    gy += a9 * (3.f * x * x - 3.f * y * y) - a15 * 6.f * x * y;
-    gx += s105 * g[10] * y * z;
-    gy += s105 * g[10] * x * z;
-    gz += s105 * g[10] * x * y;
-    const float a11 = 0.25f * s42 * g[11], a13 = 0.25f * s42 * g[13];
-    gy += a11 * (5.f * z * z - 1.f);
-    gz += a11 * 10.f * y * z + a13 * 10.f * x * z;
-    gx += a13 * (5.f * z * z - 1.f);
-    gz += 0.5f * s7 * g[12] * (15.f * z * z - 3.f);
-    const float a14 = 0.5f * s105 * g[14];
-    gx += a14 * 2.f * x * z;
-    gy -= a14 * 2.f * y * z;
-    gz += a14 * (x * x - y * y);
-    ox = gx;
-    oy = gy;
-    oz = gz;
-}
-
-// Envelope u(x) and du/dx for order p.
-__device__ __forceinline__ void envelope(float x, int p, float &u, float &du) {
-    const float a = 0.5f * (p + 1) * (p + 2), b = (float)(p * (p + 2)), c = 0.5f * p * (p + 1);
-    float xp1 = 1.f;  // x^(p-1)
-    for (int q = 1; q < p; q++) xp1 *= x;
-    const float xp = xp1 * x;
-    u = 1.f - a * xp + b * xp * x - c * xp * x * x;
-    du = -a * p * xp1 + b * (p + 1) * xp - c * (p + 2) * xp * x;
-}
-
-// ---------------------------------------------------------------------------
 // Forward, per edge: envelope, radial functions, harmonics, two-body input.
 // One wave per destination atom, lanes over its edges.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_al_edge_in(const int *__restrict__ rowc, const int *__restrict__ colc,
                                                     const float4 *__restrict__ geom, const int *__restrict__ zsp,
-                                                    int n, int S, int NB, int p, int KIN, float rc,
-                                                    float *__restrict__ H0, float *__restrict__ U,
-                                                    float *__restrict__ Y) {
+                                                    const int *__restrict__ perm, int n, int n_local, int S, int NB,
+                                                    int p, int KIN, float rc, float *__restrict__ H0,
+                                                    float *__restrict__ U, float *__restrict__ Y,
+                                                    float *__restrict__ GL) {
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
     const int zi = zsp[i];
+    const float loc = perm[i] < n_local ? 1.f : 0.f;   // dE/dE_e: the edge's atom is local
     const float c0 = sqrtf(2.0f / rc), th = 3.14159265358979f / rc;
     for (int e = rowc[i] + lane; e < rowc[i + 1]; e += 64) {
         const float4 gm = geom[e];
@@ -164,6 +97,7 @@ __global__ void __launch_bounds__(256) k_al_edge_in(const int *__restrict__ rowc
         h[NB + zi] = 1.f;
         h[NB + S + zj] = 1.f;
         U[e] = u;
+        GL[e] = loc;
         float Ye[16];
         sh16(gm.x * ir, gm.y * ir, gm.z * ir, Ye);
         float4 *y4 = reinterpret_cast<float4 *>(Y + (long)e * 16);
@@ -217,6 +151,8 @@ __global__ void __launch_bounds__(256) k_al_tp(const int *__restrict__ rowc, int
     const AlChan ch(lane, d);
     const int e0 = rowc[i], e1 = rowc[i + 1];
     float env[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // unrolled so that several edges' loads are in flight together
+#pragma unroll 4
     for (int e = e0; e < e1; e++) {
         const float we = WV[(long)e * ldwv + NC + lane];
         const float *ye = Y + (long)e * 16 + ch.m0;
@@ -230,6 +166,7 @@ __global__ void __launch_bounds__(256) k_al_tp(const int *__restrict__ rowc, int
         env[m] *= d.nu;
         en[m] = env[m];
     }
+#pragma unroll 4
     for (int e = e0; e < e1; e++) {
         const float *ye = Y + (long)e * 16 + ch.m0;
         float dot = 0.f;
@@ -255,20 +192,30 @@ __global__ void k_al_x1(const float *__restrict__ LIN, int ldl, const float *__r
         make_float4(r2 * fmaf(s, m.x, x.x), r2 * fmaf(s, m.y, x.y), r2 * fmaf(s, m.z, x.z), r2 * fmaf(s, m.w, x.w));
 }
 
-// E_e = u (w2 . HO_e + b2) summed over each atom's edges (fixed order: lane
-// partial sums over edges q, q + 64, ..., then a wave butterfly).
+// E_e = u (w2 . HO_e + b2) summed over each atom's edges.  One wave per atom:
+// eight lane groups take the edges q, q + 8, ..., the eight lanes of a group
+// the row's features four at a time (a row is read as whole 16-byte pieces);
+// the sums run in a fixed order (group totals, then a butterfly).
 __global__ void __launch_bounds__(256) k_al_energy(const int *__restrict__ rowc, int n, int OH,
                                                    const float *__restrict__ HO, const float *__restrict__ u,
                                                    const float *__restrict__ w2, float b2, float *__restrict__ Uat) {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, q = lane & 7, grp = lane >> 3;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
+    const int e1 = rowc[i + 1];
     float acc = 0.f;
-    for (int e = rowc[i] + lane; e < rowc[i + 1]; e += 64) {
-        const float *h = HO + (long)e * OH;
-        float dot = b2;
-        for (int f = 0; f < OH; f++) dot = fmaf(h[f], w2[f], dot);
-        acc = fmaf(u[e], dot, acc);
+    for (int eb = rowc[i]; eb < e1; eb += 8) {
+        const int e = eb + grp;
+        float dot = 0.f;
+        if (e < e1)
+            for (int f = 4 * q; f < OH; f += 32) {
+                const float4 h = *reinterpret_cast<const float4 *>(HO + (long)e * OH + f);
+                dot += h.x * w2[f] + h.y * w2[f + 1] + h.z * w2[f + 2] + h.w * w2[f + 3];
+            }
+        dot += __shfl_xor(dot, 1, 64);
+        dot += __shfl_xor(dot, 2, 64);
+        dot += __shfl_xor(dot, 4, 64);
+        if (e < e1 && q == 0) acc = fmaf(u[e], dot + b2, acc);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -279,26 +226,32 @@ __global__ void __launch_bounds__(256) k_al_energy(const int *__restrict__ rowc,
 // Adjoint
 // ---------------------------------------------------------------------------
 
-// dE/dE_e = 1 for edges into a local atom, 0 otherwise.  Through
+// dE/dE_e = GL[e] (1 for edges into a local atom, 0 otherwise).  Through
 // E_e = u (w2 . silu(PO) + b2): GU[e] = dE/du (first part) and the gradient of
-// the output layer's pre-activation, written over HO.
-__global__ void __launch_bounds__(256) k_al_out_bwd(const int *__restrict__ rowc, const int *__restrict__ perm,
-                                                    int n, int n_local, int OH, const float *__restrict__ PO,
-                                                    float *__restrict__ HO, const float *__restrict__ u,
-                                                    const float *__restrict__ w2, float b2, float *__restrict__ GU) {
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= n) return;
-    const float gE = perm[i] < n_local ? 1.f : 0.f;
-    for (int e = rowc[i] + lane; e < rowc[i + 1]; e += 64) {
-        float *h = HO + (long)e * OH;
-        const float *pp = PO + (long)e * OH;
-        float dot = b2;
-        for (int f = 0; f < OH; f++) dot = fmaf(h[f], w2[f], dot);
-        GU[e] = gE * dot;
-        const float s = gE * u[e];
-        for (int f = 0; f < OH; f++) h[f] = s * w2[f] * al_dsilu(pp[f]);
+// the output layer's pre-activation, written over HO.  Eight lanes per edge,
+// four features each.
+__global__ void k_al_out_bwd(const int *__restrict__ cnt, int OH, const float *__restrict__ PO,
+                             float *__restrict__ HO, const float *__restrict__ u, const float *__restrict__ GL,
+                             const float *__restrict__ w2, float b2, float *__restrict__ GU) {
+    const long ne = *cnt;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long e = t >> 3;
+    const int q = (int)(t & 7);
+    float dot = 0.f;
+    if (e < ne) {
+        const float gE = GL[e], s = gE * u[e];
+        for (int f = 4 * q; f < OH; f += 32) {
+            float4 *hp = reinterpret_cast<float4 *>(HO + e * OH + f);
+            const float4 h = *hp, pp = *reinterpret_cast<const float4 *>(PO + e * OH + f);
+            dot += h.x * w2[f] + h.y * w2[f + 1] + h.z * w2[f + 2] + h.w * w2[f + 3];
+            *hp = make_float4(s * w2[f] * al_dsilu(pp.x), s * w2[f + 1] * al_dsilu(pp.y),
+                              s * w2[f + 2] * al_dsilu(pp.z), s * w2[f + 3] * al_dsilu(pp.w));
+        }
     }
+    dot += __shfl_xor(dot, 1, 8);
+    dot += __shfl_xor(dot, 2, 8);
+    dot += __shfl_xor(dot, 4, 8);
+    if (e < ne && q == 0) GU[e] = GL[e] * (dot + b2);
 }
 
 // Through x1 = (x0 + u m) / sqrt(2): with GX = dE/dx1 (in X), GU += GX . m / sqrt(2),
@@ -370,6 +323,7 @@ __global__ void __launch_bounds__(256) k_al_tp_bwd(const int *__restrict__ rowc,
         genv[m] = 0.f;
     }
     const int e0 = rowc[i], e1 = rowc[i + 1];
+#pragma unroll 2
     for (int e = e0; e < e1; e++) {
         float q[7];
         if (act) {
@@ -400,6 +354,7 @@ __global__ void __launch_bounds__(256) k_al_tp_bwd(const int *__restrict__ rowc,
     }
 #pragma unroll
     for (int m = 0; m < 7; m++) genv[m] *= d.nu;
+#pragma unroll 2
     for (int e = e0; e < e1; e++) {
         float q[7];
         if (act) {
@@ -505,7 +460,7 @@ __global__ void k_al_geom_bwd(const int *__restrict__ rowc, int n, const float4 
 
 // Offsets (floats) of the per-evaluation arrays in the arena.
 struct AlArena {
-    long H0, u, Y, P[6], A[6], Yo, LIN, WV, PL, M, X1, PO, HO, GU, GWV, GY, GB, ENV, Uat, total;
+    long H0, u, GL, Y, P[6], A[6], Yo, LIN, WV, PL, M, X1, PO, HO, GU, GWV, GY, GB, ENV, Uat, total;
 };
 
 static AlArena al_layout(const AlModel &a, long N, long E) {
@@ -519,6 +474,7 @@ static AlArena al_layout(const AlModel &a, long N, long E) {
     };
     L.H0 = take(E * a.KIN);
     L.u = take(E);
+    L.GL = take(E);
     L.Y = take(E * 16);
     for (int q = 0; q < 6; q++) L.P[q] = L.A[q] = 0;
     for (int q = 0; q + 1 < d.n2b; q++) {
@@ -717,7 +673,7 @@ int allegro_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, fl
     if ((rc = g->G.ensure(sizeof(float4) * (size_t)E + 64, 1.2, &g->n_grows))) return rc;
     const AlArena L = al_layout(a, n, E);
     float *base = g->act.as<float>();
-    float *H0 = base + L.H0, *u = base + L.u, *Y = base + L.Y, *Yo = base + L.Yo, *LIN = base + L.LIN,
+    float *H0 = base + L.H0, *u = base + L.u, *GLc = base + L.GL, *Y = base + L.Y, *Yo = base + L.Yo, *LIN = base + L.LIN,
           *WV = base + L.WV, *PL = base + L.PL, *M = base + L.M, *X1 = base + L.X1, *PO = base + L.PO,
           *HO = base + L.HO, *GU = base + L.GU, *GWV = base + L.GWV, *GY = base + L.GY, *GB = base + L.GB,
           *ENV = base + L.ENV, *Uat = base + L.Uat;
@@ -730,8 +686,8 @@ int allegro_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, fl
     const int *cnt = rowc + n;
 
     // forward
-    k_al_edge_in<<<nblk(n, 4), 256, 0, s>>>(rowc, colc, geom, g->species.as<int>(), n, d.S, d.NB, d.p, a.KIN, d.rc,
-                                            H0, u, Y);
+    k_al_edge_in<<<nblk(n, 4), 256, 0, s>>>(rowc, colc, geom, g->species.as<int>(), perm, n, g->n_local, d.S, d.NB,
+                                            d.p, a.KIN, d.rc, H0, u, Y, GLc);
     const float *in = H0;
     int ldin = a.KIN;
     for (int q = 0; q + 1 < d.n2b; q++) {
@@ -770,8 +726,7 @@ int allegro_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, fl
     if (!forces_user) return 0;
 
     // adjoint
-    k_al_out_bwd<<<nblk(n, 4), 256, 0, s>>>(rowc, perm, n, g->n_local, d.OH, PO, HO, u, a.out_w2, a.out_b2_host,
-                                            GU);
+    k_al_out_bwd<<<nblk(ne * 8, 256), 256, 0, s>>>(cnt, d.OH, PO, HO, u, GLc, a.out_w2, a.out_b2_host, GU);
     if ((rc = gm(s, P, GE_STORE, HO, d.OH, a.aO1, X1, D, ne, cnt))) return rc;
     k_al_x1_bwd<<<nblk(ne * 16, 256), 256, 0, s>>>(cnt, D, u, X1, M, GU);
     {

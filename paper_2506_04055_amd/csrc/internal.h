@@ -133,6 +133,12 @@ struct mlp_nbr {
     mlp::DevBuf row, col, rev; // skin graph CSR
     mlp::DevBuf rowc, colc, revc, geom, map, oldidx, cnt;  // pruned graph
     mlp::DevBuf hop;           // int8 hop distance (capped T+1)
+    // With ghosts the internal order is hop-major: atoms within h hops of the
+    // locals (over the rc + skin graph) are rows [0, nhop[h]), so a layer's
+    // node work runs on a prefix (nhop[T + 1] = n_atoms).  Without ghosts
+    // every nhop[h] = n_atoms.
+    int nhop[MLP_MAX_LAYERS + 2] = {0};
+    mlp::DevBuf ro_perm, ro_pos, ro_spec, ro_row, ro_col, ro_newpos, ro_rank, ro_base;  // reorder scratch
     mlp::DevBuf pos4;          // float4 positions at evaluation (internal order)
     mlp::DevBuf scan_tmp, flags, red;
     mlp::DevBuf ghost_ptr, ghost_list, ghost_cnt;  // owner -> ghosts (user indices)

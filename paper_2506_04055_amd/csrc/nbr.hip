@@ -519,6 +519,71 @@ __global__ void k_hop_round(const int *__restrict__ rowc, const int *__restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Hop-major internal order (domains with ghosts).  Hop levels over the
+// rc + skin graph bound those over any pruned graph of the same build from
+// below (more edges, fewer hops), so the rows within h hops of the locals at
+// any evaluation before the next build lie in the prefix of level <= h.
+// Atoms are stably partitioned by level (cell order kept inside a level),
+// the CSR relabelled and each row's columns emitted level by level, which
+// keeps them ascending.
+// ---------------------------------------------------------------------------
+__global__ void k_level_flag(const int8_t *__restrict__ hop, int n, int L, int *__restrict__ flag) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) flag[k] = hop[k] == L ? 1 : 0;
+}
+
+// newpos of the level-L atoms: base[L] + their rank among level L; base[L + 1]
+// = base[L] + the level's count (rank[n], the scan total).
+__global__ void k_level_assign(const int8_t *__restrict__ hop, int n, int L, const int *__restrict__ rank,
+                               int *__restrict__ base, int *__restrict__ newpos) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = base[L];
+    if (k < n && hop[k] == L) newpos[k] = b + rank[k];
+    if (k == 0) base[L + 1] = b + rank[n];
+}
+
+__global__ void k_reorder_atoms(const int *__restrict__ newpos, int n, const int *__restrict__ perm,
+                                const float4 *__restrict__ pos, const int *__restrict__ spec,
+                                const int *__restrict__ row, int *__restrict__ perm2, float4 *__restrict__ pos2,
+                                int *__restrict__ spec2, int *__restrict__ cnt2, int *__restrict__ iperm) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int q = newpos[k];
+    perm2[q] = perm[k];
+    pos2[q] = pos[k];
+    spec2[q] = spec[k];
+    cnt2[q] = row[k + 1] - row[k];
+    iperm[perm[k]] = q;
+}
+
+// One wave per old row: its columns relabelled, level by level (ballot
+// compaction keeps the old, ascending order inside a level).
+__global__ void __launch_bounds__(256) k_relabel_rows(const int *__restrict__ row, const int *__restrict__ col,
+                                                      const int8_t *__restrict__ hop, const int *__restrict__ newpos,
+                                                      const int *__restrict__ row2, int n, int nlev,
+                                                      int *__restrict__ col2) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= n) return;
+    const int a = row[k], b = row[k + 1];
+    int o = row2[newpos[k]];
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int L = 0; L < nlev; L++)
+        for (int e0 = a; e0 < b; e0 += 64) {
+            const int e = e0 + lane;
+            int j = 0;
+            bool hit = false;
+            if (e < b) {
+                j = col[e];
+                hit = hop[j] == L;
+            }
+            const unsigned long long m = __ballot(hit);
+            if (hit) col2[o + __popcll(m & below)] = newpos[j];
+            o += __popcll(m);
+        }
+}
+
 __global__ void k_hop_hist(const int8_t *__restrict__ hop, const int *__restrict__ rowc, int n,
                            int *__restrict__ hist, unsigned long long *__restrict__ ehist) {
     // per-workgroup counts of atoms and of their pruned in-edges per hop
@@ -738,6 +803,54 @@ int build_graph(mlp_model *m, mlp_nbr *g, const float *pos, const int32_t *speci
     HIP_TRY(hipMemcpyAsync(hostv, flag, sizeof(int) * 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (hostv[0] & 4) return fail(-5, "neighbour graph is not symmetric");
+    const int T = m->T;
+    for (int h = 0; h < MLP_MAX_LAYERS + 2; h++) g->nhop[h] = n;
+    if (ghosts) {
+        // hop levels over the rc + skin graph, then the hop-major order
+        const int nlev = T + 2;
+        if ((rc = g->hop.ensure(n + 16, 1.2, G)) || (rc = g->ro_perm.ensure(sizeof(int) * n, 1.2, G)) ||
+            (rc = g->ro_pos.ensure(sizeof(float4) * n, 1.2, G)) || (rc = g->ro_spec.ensure(sizeof(int) * n, 1.2, G)) ||
+            (rc = g->ro_row.ensure(sizeof(int) * (n + 1), 1.2, G)) ||
+            (rc = g->ro_col.ensure(sizeof(int) * (size_t)E + 4, 1.2, G)) ||
+            (rc = g->ro_newpos.ensure(sizeof(int) * n, 1.2, G)) ||
+            (rc = g->ro_rank.ensure(sizeof(int) * (n + 1) * 2, 1.2, G)) ||
+            (rc = g->ro_base.ensure(sizeof(int) * (nlev + 2), 1.0, G)))
+            return rc;
+        int8_t *hop = g->hop.as<int8_t>();
+        int *flg = g->ro_rank.as<int>(), *rank = flg + n + 1, *base = g->ro_base.as<int>();
+        k_hop_init<<<nblk(n, 256), 256, 0, s>>>(g->perm.as<int>(), n, n_local, T, hop);
+        for (int t = 1; t <= T; t++)
+            k_hop_round<<<nblk(n, 256), 256, 0, s>>>(g->row.as<int>(), g->col.as<int>(), n, t, T, hop);
+        HIP_TRY(hipMemsetAsync(base, 0, sizeof(int), s));
+        for (int L = 0; L < nlev; L++) {
+            k_level_flag<<<nblk(n, 256), 256, 0, s>>>(hop, n, L, flg);
+            if ((rc = scan_exclusive(flg, rank, n, g->scan_tmp, G, s))) return rc;
+            k_level_assign<<<nblk(n, 256), 256, 0, s>>>(hop, n, L, rank, base, g->ro_newpos.as<int>());
+        }
+        int *cnt2 = g->cnt.as<int>();
+        k_reorder_atoms<<<nblk(n, 256), 256, 0, s>>>(g->ro_newpos.as<int>(), n, g->perm.as<int>(),
+                                                       g->pos_build.as<float4>(), g->species.as<int>(),
+                                                       g->row.as<int>(), g->ro_perm.as<int>(), g->ro_pos.as<float4>(),
+                                                       g->ro_spec.as<int>(), cnt2, g->iperm.as<int>());
+        if ((rc = scan_exclusive(cnt2, g->ro_row.as<int>(), n, g->scan_tmp, G, s))) return rc;
+        k_relabel_rows<<<nblk(n, 4), 256, 0, s>>>(g->row.as<int>(), g->col.as<int>(), hop, g->ro_newpos.as<int>(),
+                                                  g->ro_row.as<int>(), n, nlev, g->ro_col.as<int>());
+        std::swap(g->perm, g->ro_perm);
+        std::swap(g->pos_build, g->ro_pos);
+        std::swap(g->species, g->ro_spec);
+        std::swap(g->row, g->ro_row);
+        std::swap(g->col, g->ro_col);
+        HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+        k_rev<<<nblk(n, 4), 256, 0, s>>>(g->row.as<int>(), g->col.as<int>(), n, g->rev.as<int>(), flag);
+        HIP_TRY(hipGetLastError());
+        int lev[MLP_MAX_LAYERS + 4];
+        HIP_TRY(hipMemcpyAsync(lev, base, sizeof(int) * (nlev + 1), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hostv, flag, sizeof(int) * 16, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (hostv[0] & 4) return fail(-5, "reordered neighbour graph is not symmetric");
+        if (lev[nlev] != n) return fail(-5, "hop-level partition lost atoms");
+        for (int h = 0; h < MLP_MAX_LAYERS + 2; h++) g->nhop[h] = lev[std::min(h + 1, nlev)];
+    }
     g->n_atoms = n;
     g->n_local = n_local;
     g->open = ghosts;

@@ -115,6 +115,16 @@ __global__ void k_vprod(const float *__restrict__ v, const float *__restrict__ p
     }
 }
 
+// p[0 .. count) = 0.
+__global__ void k_fill_zero(float *__restrict__ p, long count) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) p[t] = 0.f;
+}
+
+static void fill_zero(hipStream_t s, float *p, long count) {
+    if (count > 0) k_fill_zero<<<nblk(count, 256), 256, 0, s>>>(p, count);
+}
+
 // UV holds rows [Uv | Vv] of 2F for each (atom, direction): Uv(i, d, f) at
 // UV[(3 i + d) 2F + f], Vv(i, d, f) at UV[(3 i + d) 2F + F + f]; gUV likewise.
 __global__ void k_norm(const float *__restrict__ UV, int n, int F, float eps, float *__restrict__ sn) {
@@ -537,14 +547,28 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     // (free in the first layer's forward, and again once dv1 is formed)
     const L0Layout l0 = l0_layout(F, K, m->S);
 
+    // Per-layer active sets (Results, "Distributed potential computation",
+    // pruning): layer t's outputs are needed within T - 1 - t hops of the
+    // locals and its message MLP within T - t hops.  With ghosts the internal
+    // order is hop-major (the neighbour build), so those sets are the row
+    // prefixes NH(h) and every node kernel runs on its prefix; the message
+    // kernels skip atoms by the exact hop marks of this evaluation, which the
+    // prefixes contain.  Rows past a prefix hold values that no needed row
+    // reads, except the gradients a message adjoint gathers from its
+    // destinations: those rows are zeroed (their gradient is zero).
+    const bool ho = g->nhop[0] > 0 && g->nhop[std::min(T + 1, MLP_MAX_LAYERS + 1)] == n;
+    auto NH = [&](int h) { return ho ? g->nhop[std::max(0, std::min(h, T + 1))] : n; };
+
     // forward
     for (int t = 0; t < T; t++) {
         LayerW L = m->layer(t);
         const int hop_dst = T - 1 - t;
+        const int nsrc = NH(T - t), ndst = NH(T - 1 - t);
         if (t > 0) {
-            gemm2(s, P, mlp_fwd(A.s[t], F, m->pk[t][WP_W1], A.h1[t], F, L.b1, m->pk[t][WP_W2], A.phi[t], F3, L.b2, n));
+            gemm2(s, P, mlp_fwd(A.s[t], F, m->pk[t][WP_W1], A.h1[t], F, L.b1, m->pk[t][WP_W2], A.phi[t], F3, L.b2,
+                                nsrc));
             // u = v * phi_vv: the rows the message pass gathers together with phi_s and phi_vs
-            k_vprod<<<nblk((long)n * F / 4, 256), 256, 0, s>>>(A.v[t], A.phi[t], n, F, A.u);
+            k_vprod<<<nblk((long)nsrc * F / 4, 256), 256, 0, s>>>(A.v[t], A.phi[t], nsrc, F, A.u);
         }
         if (t == 0 && m->l0f) {
             // factorised first layer: basis sums per atom and species, then
@@ -555,8 +579,8 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             la.ldp = l0.ldp;
             la.ldr = l0.ldr;
             if ((rc = msg_l0_basis_sums(s, K, m->S, la))) return fail(rc, "first-layer kernel launch failed");
-            gemm<E_STORE>(s, P, la.P, l0.ldp, m->pk_l0[0], A.sn[0], 2 * F, n);
-            gemm<E_STORE>(s, P, la.R, l0.ldr, m->pk_l0[1], A.v1[0], F, 3 * n);
+            gemm<E_STORE>(s, P, la.P, l0.ldp, m->pk_l0[0], A.sn[0], 2 * F, ndst);
+            gemm<E_STORE>(s, P, la.R, l0.ldr, m->pk_l0[1], A.v1[0], F, 3 * ndst);
         } else {
             MsgArgs ma = msg_args(g, m, L, hop_dst);
             ma.layer0 = t == 0;
@@ -570,10 +594,11 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             ProfScope ps(PK_MSG_FWD, s);
             if ((rc = msg_forward(s, PF, F, K, ma))) return fail(rc, "message kernel launch failed");
         }
-        gemm<E_STORE>(s, P, A.v1[t], F, m->pk[t][WP_UV], A.UV[t], 2 * F, 3 * n);
-        k_norm<<<nblk((long)n * F, 256), 256, 0, s>>>(A.UV[t], n, F, m->eps, A.sn[t]);
+        gemm<E_STORE>(s, P, A.v1[t], F, m->pk[t][WP_UV], A.UV[t], 2 * F, 3 * ndst);
+        k_norm<<<nblk((long)ndst * F, 256), 256, 0, s>>>(A.UV[t], ndst, F, m->eps, A.sn[t]);
         {
-            GemmChain c = mlp_fwd(A.sn[t], 2 * F, m->pk[t][WP_W3], A.h3[t], F, L.b3, m->pk[t][WP_W4], A.a[t], F3, L.b4, n);
+            GemmChain c = mlp_fwd(A.sn[t], 2 * F, m->pk[t][WP_W3], A.h3[t], F, L.b3, m->pk[t][WP_W4], A.a[t], F3, L.b4,
+                                  ndst);
             if (F >= 64) {
                 // the gated update in the second product's epilogue (the last
                 // layer's v is not needed: the readout takes s only)
@@ -587,30 +612,34 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
                 gemm2(s, P, c);
             } else {
                 gemm2(s, P, c);
-                k_update_out<<<nblk((long)n * F, 256), 256, 0, s>>>(A.sn[t], A.v1[t], A.UV[t], A.a[t], n, F,
-                                                                     A.s[t + 1], A.v[t + 1]);
+                k_update_out<<<nblk((long)ndst * F, 256), 256, 0, s>>>(A.sn[t], A.v1[t], A.UV[t], A.a[t], ndst, F,
+                                                                        A.s[t + 1], A.v[t + 1]);
             }
         }
     }
-    // readout and energy
-    gemm<E_BIAS>(s, P, A.s[T], F, m->pk_W5, A.h5, Fh, n, m->at(m->off_b5));
-    k_readout<<<nblk(16L * n, 256), 256, 0, s>>>(A.h5, n, Fh, m->at(m->off_w6), m->at(m->off_b6), perm,
-                                                 g->n_local, A.U, A.g5);
+    // readout and energy (the locals are the prefix NH(0); U of the other
+    // rows, reported to the caller as per-atom energies, is zero)
+    const int nloc = NH(0);
+    gemm<E_BIAS>(s, P, A.s[T], F, m->pk_W5, A.h5, Fh, nloc, m->at(m->off_b5));
+    k_readout<<<nblk(16L * nloc, 256), 256, 0, s>>>(A.h5, nloc, Fh, m->at(m->off_w6), m->at(m->off_b6), perm,
+                                                    g->n_local, A.U, A.g5);
+    fill_zero(s, A.U + nloc, (long)(n - nloc));
     k_energy_seg<<<std::max(1, n_seg), ERED, 0, s>>>(A.U, perm, seg_dev, n, g->n_local, energy);
     if (atom_energy_user) k_scatter_energy<<<nblk(n, 256), 256, 0, s>>>(A.U, perm, n, atom_energy_user);
     if (!forces_user) return 0;
 
     // adjoint
-    gemm<E_STORE>(s, P, A.g5, Fh, m->pk_W5t, A.gs, F, n);
+    gemm<E_STORE>(s, P, A.g5, Fh, m->pk_W5t, A.gs, F, nloc);
     for (int t = T - 1; t >= 0; t--) {
         LayerW L = m->layer(t);
         const int hop_src = T - t;
         const bool last = t == T - 1;   // dE/dv of the last layer's output is zero
-        k_update_bwd1<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gs, last ? nullptr : A.gv, A.UV[t], A.a[t], n, F,
-                                                             A.ga, A.gUV);
+        const int ndst = NH(T - 1 - t), nsrc = NH(T - t), nfar = NH(T - t + 1);
+        k_update_bwd1<<<nblk((long)ndst * F, 256), 256, 0, s>>>(A.gs, last ? nullptr : A.gv, A.UV[t], A.a[t], ndst,
+                                                                F, A.ga, A.gUV);
         if (F >= 64) {
             // d[s1 | n] -> ds1 = ds2 + d s1 and dVv += (dn / n) Vv, in the epilogue
-            GemmChain c = mlp_bwd(A.ga, F3, m->pk[t][WP_W4T], A.h3[t], F, m->pk[t][WP_W3T], A.gs1, F, A.gs, n);
+            GemmChain c = mlp_bwd(A.ga, F3, m->pk[t][WP_W4T], A.h3[t], F, m->pk[t][WP_W3T], A.gs1, F, A.gs, ndst);
             c.e2 = GE_NORM_ADJ;
             c.F = F;
             c.sn = A.sn[t];
@@ -618,19 +647,27 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             c.gUV = A.gUV;
             gemm2(s, P, c);
         } else {
-            gemm2(s, P, mlp_bwd(A.ga, F3, m->pk[t][WP_W4T], A.h3[t], F, m->pk[t][WP_W3T], A.gsn, 2 * F, nullptr, n));
-            k_update_bwd2<<<nblk((long)n * F, 256), 256, 0, s>>>(A.gsn, A.sn[t], A.UV[t], A.gs, n, F, A.gUV, A.gs1);
+            gemm2(s, P, mlp_bwd(A.ga, F3, m->pk[t][WP_W4T], A.h3[t], F, m->pk[t][WP_W3T], A.gsn, 2 * F, nullptr,
+                                ndst));
+            k_update_bwd2<<<nblk((long)ndst * F, 256), 256, 0, s>>>(A.gsn, A.sn[t], A.UV[t], A.gs, ndst, F, A.gUV,
+                                                                    A.gs1);
         }
         // dv1 = [dUv | dVv] [U; V] + dv2 (the residual)
-        if (last) gemm<E_STORE>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * n);
-        else gemm<E_ADD>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * n, nullptr, nullptr, 0, A.gv, F);
+        if (last) gemm<E_STORE>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * ndst);
+        else gemm<E_ADD>(s, P, A.gUV, 2 * F, m->pk[t][WP_UVT], A.gv1, F, 3 * ndst, nullptr, nullptr, 0, A.gv, F);
+        // destinations past this layer's set carry no gradient; the message
+        // adjoint gathers them up to one hop beyond its sources
+        fill_zero(s, A.gs1 + (long)ndst * F, (long)(nfar - ndst) * F);
+        fill_zero(s, A.gv1 + 3L * ndst * F, 3L * (nfar - ndst) * F);
         if (t == 0 && m->l0f) {
             // factorised first layer: Q_s = gs1 Wbs, Q_v = gv1 Wv, then the
-            // edge sums from Q in one slot
+            // edge sums from Q in one slot.  The edge kernel reads Q of every
+            // destination of a live source (one hop past the sources), so Q
+            // covers the rows through nfar (zero past ndst, as gs1 and gv1).
             L0Args la = l0_args(g, m, hop_src);
             float *Qs = A.gUV, *Qv = A.gUV + (long)n * l0.ldq;
-            gemm<E_STORE>(s, P, A.gs1, F, m->pk_l0[2], Qs, l0.ldq, n);
-            gemm<E_STORE>(s, P, A.gv1, F, m->pk_l0[3], Qv, l0.ldq, 3 * n);
+            gemm<E_STORE>(s, P, A.gs1, F, m->pk_l0[2], Qs, l0.ldq, nfar);
+            gemm<E_STORE>(s, P, A.gv1, F, m->pk_l0[3], Qv, l0.ldq, 3 * nfar);
             la.Qs = Qs;
             la.Qv = Qv;
             la.ldq = l0.ldq;
@@ -650,7 +687,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             if ((rc = msg_adjoint(s, PF, F, K, ma))) return fail(rc, "adjoint message kernel launch failed");
         }
         if (t == 0) break;   // the embedding carries no gradient
-        gemm2(s, P, mlp_bwd(A.gphi, F3, m->pk[t][WP_W2T], A.h1[t], F, m->pk[t][WP_W1T], A.gs, F, A.gs1, n));
+        gemm2(s, P, mlp_bwd(A.gphi, F3, m->pk[t][WP_W2T], A.h1[t], F, m->pk[t][WP_W1T], A.gs, F, A.gs1, nsrc));
     }
     if ((rc = msg_assemble_G(s, g->rowc.as<int>(), n, ne, g->geom.as<float4>(), g->Gs.as<float4>(), ne, nslot,
                              g->G.as<float4>())))
