@@ -397,6 +397,84 @@ def make_allegro_weights(n_species: int, seed: int = 0, bias_scale: float = 0.0,
     return h, np.concatenate(parts).astype(np.float32)
 
 
+# MACE at the paper's settings: two interaction layers, correlation order 3,
+# l_max = 3, 32 channels (hidden irreps 32x0e + 32x1o), 8 radial basis
+# functions, polynomial envelope of order 6, 5 A cutoff; a 64-wide radial MLP
+# (the paper's node embedding width read as the width of the radial network)
+# and a 16-wide readout MLP.
+MACE_DEFAULTS = {"n_basis": 8, "envelope_p": 6, "l_max": 3, "channels": 32, "correlation": 3,
+                 "radial_hidden": [64, 64, 64], "readout_hidden": 16, "avg_neighbors": 40.0}
+
+
+def _mace_couples(l1, l2, L):
+    return abs(l1 - l2) <= L <= l1 + l2 and (l1 + l2 + L) % 2 == 0
+
+
+def mace_layout(h: dict):
+    """Ordered (name, shape, fan_in) of every MACE parameter block (fan_in = 0:
+    bias).  Conv paths (l1, l2, L) and contraction paths are enumerated in the
+    order the model header documents (see include/mlp.h)."""
+    S, K, nb, lmax, corr = h["n_species"], h["channels"], h["n_basis"], h["l_max"], h["correlation"]
+    rh = list(h["radial_hidden"])
+    lin, lout = ([0], [0, 1]), ([0, 1], [0])
+    out = [("W_emb", (K, S), 1)]
+    for t in range(2):
+        conv = [(l1, l2, L) for l2 in lin[t] for l1 in range(lmax + 1) for L in range(lmax + 1)
+                if _mace_couples(l1, l2, L)]
+        for l2 in lin[t]:
+            out.append((f"l{t}.W_up{l2}", (K, K), K))
+        prev = nb
+        for q, wdt in enumerate(rh):
+            out.append((f"l{t}.rad{q}", (wdt, prev), prev))
+            prev = wdt
+        out.append((f"l{t}.rad{len(rh)}", (len(conv) * K, prev), prev))
+        for L in range(lmax + 1):
+            nL = sum(1 for c in conv if c[2] == L)
+            if nL:
+                out.append((f"l{t}.W_A{L}", (K, nL * K), nL * K))
+        for Lo in lout[t]:
+            npth = (1 if Lo <= lmax else 0)
+            if corr >= 2:
+                npth += sum(1 for l1 in range(lmax + 1) for l2 in range(l1, lmax + 1) if _mace_couples(l1, l2, Lo))
+            if corr >= 3:
+                npth += sum(1 for l1 in range(lmax + 1) for l2 in range(l1, lmax + 1) for lam in range(lmax + 1)
+                            if _mace_couples(l1, l2, lam) for l3 in range(lmax + 1) if _mace_couples(lam, l3, Lo))
+            out.append((f"l{t}.W_sym{Lo}", (S, K, npth), npth))
+        for Lo in lout[t]:
+            out.append((f"l{t}.W_out{Lo}", (K, K), K))
+        for Lo in lout[t]:
+            if Lo in lin[t]:
+                out.append((f"l{t}.W_sc{Lo}", (S, K, K), K))
+    RH = h["readout_hidden"]
+    out += [("w_r1", (K,), K), ("W_r2", (RH, K), K), ("b_r2", (RH,), 0), ("w_r2", (RH,), RH), ("b_r3", (1,), 0)]
+    return out
+
+
+def mace_header(n_species: int, r_c: float = 5.0, **kw) -> dict:
+    h = dict(MACE_DEFAULTS, **kw)
+    h.update({"model": "mace", "n_species": n_species, "r_c": r_c, "basis": "bessel", "envelope": "polynomial",
+              "units": {"length": "angstrom", "energy": "eV"}, "graph": "full_directed_csr_by_destination"})
+    lay = mace_layout(h)
+    h["layout"] = [[n, list(s)] for n, s, _ in lay]
+    h["n_weights"] = int(sum(int(np.prod(s)) for _, s, _ in lay))
+    return h
+
+
+def make_mace_weights(n_species: int, seed: int = 0, bias_scale: float = 0.0, **kw):
+    """Flat float32 MACE weights: matrices ~ N(0, 1/fan_in) (the embedding
+    ~ N(0, 1)), biases 0 (or N(0, bias_scale^2)); draw order = layout order."""
+    h = mace_header(n_species, **kw)
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape, fan_in in mace_layout(h):
+        n = int(np.prod(shape))
+        if fan_in == 0:
+            parts.append(rng.standard_normal(n) * bias_scale if bias_scale > 0 else np.zeros(n))
+        else:
+            parts.append(rng.standard_normal(n) / math.sqrt(fan_in))
+    return h, np.concatenate(parts).astype(np.float32)
+
+
 MD_FILTER_SCALE = 0.1
 MD_READOUT_SCALE = 1e-2
 
