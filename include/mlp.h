@@ -109,6 +109,30 @@ const char *mlp_last_error(void);
  *   lat_b1 [LH] lat_W2 [D][LH] lat_b2 [D]; out_W1 [OH][D] out_b1 [OH]
  *   out_w2 [OH] out_b2 [1].  An Allegro model is strictly local: its graph
  *   needs ghosts within rc only, and the serving calls do not take it.
+ * header_json may instead describe a MACE model with two interaction layers
+ *   (Methods, "Chosen Architectures" and "Training Details": correlation
+ *   order 3, l_max = 3, 32 scalar and 32 vector channels, 8 radial functions,
+ *   polynomial envelope of order 6):
+ *   {"model":"mace","n_species":..,"r_c":..,"n_basis":..,"envelope_p":..,
+ *    "l_max":3,"channels":32,"correlation":3,"radial_hidden":[..],
+ *    "readout_hidden":..,"avg_neighbors":..,"basis":"bessel",
+ *    "envelope":"polynomial"}
+ *   with 1..4 radial widths (multiples of 4, at most 256) and a readout
+ *   width of at most 32.  Layer 1 takes degree 0 and produces degrees 0
+ *   and 1, layer 2 takes 0 and 1 and produces 0; a coupling l1 x l2 -> L is
+ *   used only where |l1 - l2| <= L <= l1 + l2 and l1 + l2 + L is even.
+ *   Conv paths (l1, l2, L) of a layer in order: l2 over its input degrees,
+ *   then l1 = 0..3, then L = 0..3.  Contraction paths onto an output
+ *   degree L_o in order: (A_Lo); the pairs (l1 <= l2) coupled to L_o; the
+ *   triples (l1 <= l2, lambda, l3) with l1 x l2 -> lambda and
+ *   lambda x l3 -> L_o, looped l1, l2, lambda, l3.  Weights (K = 32,
+ *   matrices [out][in]): W_emb [K][S]; per layer: W_up [K][K] per input
+ *   degree; the radial matrices [r_1][n_basis], [r_q][r_(q-1)], and
+ *   [P K][r_last] (P conv paths, output column p K + k); W_A [K][n_L K] for
+ *   L = 0..3 (n_L paths onto L, columns in path order); W_sym [S][K][paths]
+ *   per output degree; W_out [K][K] per output degree; W_sc [S][K][K] for
+ *   degree 0; then w_r1 [K], W_r2 [RH][K], b_r2 [RH], w_r2 [RH], b_r3 [1].
+ *   Its graph needs ghosts within 2 rc; the serving calls do not take it.
  * precision: the operand forms of the two matrix-core contractions, the
  *   node-feature GEMMs (node) and the radial filter of the message kernels
  *   (filter):

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmlp.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "nbr.hip", "painn.hip", "prof.hip", "gemm.hip", "msg.hip", "server.hip", "md.hip", "noalloc.hip", "allegro.hip"]
+SOURCES = ["api.hip", "nbr.hip", "painn.hip", "prof.hip", "gemm.hip", "msg.hip", "server.hip", "md.hip", "noalloc.hip", "allegro.hip",
+           "mace.hip"]
 ARCH = os.environ.get("MLP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -95,6 +95,63 @@ static int create_allegro(const JsonTop &j, const float *weights, size_t n_weigh
     return MLP_OK;
 }
 
+// A MACE model (two layers): header fields n_species, r_c, n_basis,
+// envelope_p, l_max, channels, correlation, radial_hidden, readout_hidden,
+// avg_neighbors; basis "bessel", envelope "polynomial".  The neighbour graph
+// treats it as two layers (receptive field 2 r_c).
+static int create_mace(const JsonTop &j, const float *weights, size_t n_weights, int precision, mlp_model **out) {
+    long S, NB, p, lmax, K, corr, RH;
+    double rc, navg;
+    std::vector<long> rh;
+    if (!get_int(j, "n_species", &S) || !get_int(j, "n_basis", &NB) || !get_int(j, "envelope_p", &p) ||
+        !get_int(j, "l_max", &lmax) || !get_int(j, "channels", &K) || !get_int(j, "correlation", &corr) ||
+        !get_int(j, "readout_hidden", &RH) || !get_num(j, "r_c", &rc) || !get_num(j, "avg_neighbors", &navg) ||
+        !get_int_list(j, "radial_hidden", &rh))
+        return fail(MLP_ERR_INVALID_ARG, "mace header lacks n_species, n_basis, envelope_p, l_max, channels, "
+                                         "correlation, radial_hidden, readout_hidden, r_c or avg_neighbors");
+    auto str = [&](const char *k) { auto it = j.kv.find(k); return it == j.kv.end() ? std::string() : it->second; };
+    if (str("basis") != "bessel" || str("envelope") != "polynomial")
+        return fail(MLP_ERR_INVALID_ARG, "mace: basis must be bessel and envelope polynomial");
+    if (rh.empty() || rh.size() > 4) return fail(MLP_ERR_INVALID_ARG, "mace: radial_hidden needs 1..4 widths");
+    if (precision != MLP_FP32 && precision != MLP_BF16 && precision != MLP_BF16_FAST &&
+        precision != MLP_BF16_NODE && precision != MLP_BF16_NODE_X3)
+        return fail(MLP_ERR_INVALID_ARG, "unknown precision");
+    auto in = [](long v, long lo, long hi) { return v >= lo && v <= hi; };
+    if (!in(S, 1, 64) || !in(NB, 1, 16) || !in(p, 1, 8) || !in(lmax, 0, 8) || !in(K, 1, 1024) || !in(corr, 1, 8) ||
+        !in(RH, 1, 1024))
+        return fail(MLP_ERR_INVALID_ARG, "mace: header value out of range");
+    McDims d;
+    d.S = (int)S;
+    d.NB = (int)NB;
+    d.p = (int)p;
+    d.lmax = (int)lmax;
+    d.K = (int)K;
+    d.corr = (int)corr;
+    d.nrad = (int)rh.size();
+    for (size_t q = 0; q < rh.size(); q++) {
+        if (!in(rh[q], 1, 4096)) return fail(MLP_ERR_INVALID_ARG, "mace: radial width out of range");
+        d.rh[q] = (int)rh[q];
+    }
+    d.RH = (int)RH;
+    d.rc = (float)rc;
+    d.navg = (float)navg;
+    mlp_model *m = new mlp_model();
+    m->F = 0;
+    m->K = 0;
+    m->T = 2;
+    m->S = (int)S;
+    m->rc = (float)rc;
+    m->eps = 0.f;
+    m->precision = precision;
+    m->n_weights = n_weights;
+    if (int rc2 = mace_create(m, d, weights, n_weights)) {
+        delete m;
+        return rc2;
+    }
+    *out = m;
+    return MLP_OK;
+}
+
 extern "C" {
 
 const char *mlp_last_error(void) { return last_error_cstr(); }
@@ -108,6 +165,7 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
     {
         auto it = j.kv.find("model");
         if (it != j.kv.end() && it->second == "allegro") return create_allegro(j, weights, n_weights, precision, out);
+        if (it != j.kv.end() && it->second == "mace") return create_mace(j, weights, n_weights, precision, out);
     }
     long F, K, T, S;
     double rc, eps;
@@ -219,6 +277,7 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
 int mlp_model_destroy(mlp_model *m) {
     if (!m) return MLP_OK;
     allegro_destroy(m);
+    mace_destroy(m);
     if (m->w_dev) hipFree(m->w_dev);
     if (m->wb_dev) hipFree(m->wb_dev);
     if (m->pk_dev) hipFree(m->pk_dev);

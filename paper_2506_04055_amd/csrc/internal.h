@@ -85,11 +85,22 @@ struct AlDims {
 };
 struct AlModel;
 
+// Dimensions of a two-layer MACE model (mace.hip): species, radial
+// functions, envelope order, l_max, channels, correlation order, the radial
+// MLP's hidden widths, the readout MLP's hidden width; cutoff and the
+// average neighbour count that normalises the convolution.
+struct McDims {
+    int S = 0, NB = 0, p = 0, lmax = 0, K = 0, corr = 0, nrad = 0, rh[4] = {0, 0, 0, 0}, RH = 0;
+    float rc = 0.f, navg = 0.f;
+};
+struct McModel;
+
 }  // namespace mlp
 
 struct mlp_model {
     int F, K, T, S, precision;
     mlp::AlModel *al = nullptr;          // set for an Allegro model (then T = 1; F, K unused)
+    mlp::McModel *mc = nullptr;          // set for a MACE model (then T = 2; F, K unused)
     float rc, eps;
     size_t n_weights;
     float *w_dev = nullptr;              // flat weights on the device
@@ -214,6 +225,15 @@ int allegro_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, fl
                      float *atom_energy_user, int n_seg, const int *seg_dev);
 // Bytes of the per-evaluation arena (per-edge and per-atom activations).
 size_t allegro_arena_bytes(const mlp_model *m, long n_atoms, long n_edges);
+
+// ---- MACE (mace.hip) ----
+// Validates the dimensions and the weight count, builds the coupling and
+// contraction tables, copies, transposes and packs the weights; sets m->mc.
+int mace_create(mlp_model *m, const McDims &d, const float *weights, size_t n_weights);
+void mace_destroy(mlp_model *m);
+int mace_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
+                  float *atom_energy_user, int n_seg, const int *seg_dev);
+size_t mace_arena_bytes(const mlp_model *m, long n_atoms, long n_edges);
 // Fill m->phi0_dev (device, S x 3F) from the embedding and the first layer's
 // message MLP, in the model's precision; tmp: device scratch of 2 S F floats.
 int first_layer_table(mlp_model *m, hipStream_t s, float *tmp);

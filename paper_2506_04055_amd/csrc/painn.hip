@@ -494,8 +494,8 @@ int first_layer_factor(mlp_model *m) {
 
 void eval_model_needs(const mlp_model *m, const mlp_nbr *g, size_t *act, size_t *G, size_t *Gs) {
     const size_t ne = (size_t)g->n_edges_skin;
-    if (m->al) {
-        *act = allegro_arena_bytes(m, g->n_atoms, (long)ne);
+    if (m->al || m->mc) {
+        *act = m->al ? allegro_arena_bytes(m, g->n_atoms, (long)ne) : mace_arena_bytes(m, g->n_atoms, (long)ne);
         *G = sizeof(float4) * ne + 64;
         *Gs = 64;
         return;
@@ -523,6 +523,7 @@ int launch_forces(hipStream_t s, const int *rowc, const int *revc, const float4 
 int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *forces_user,
              float *atom_energy_user, int n_seg, const int *seg_dev) {
     if (m->al) return allegro_evaluate(m, g, s, energy, forces_user, atom_energy_user, n_seg, seg_dev);
+    if (m->mc) return mace_evaluate(m, g, s, energy, forces_user, atom_energy_user, n_seg, seg_dev);
     const int n = g->n_atoms, F = m->F, K = m->K, T = m->T, F3 = 3 * F, Fh = F / 2;
     // MFMA operand forms of the mode for the node GEMMs (P) and for the
     // radial filter (PF): 0 FP32, 1 plain bfloat16, 2 split bfloat16 (hi + lo)

@@ -410,7 +410,7 @@ extern "C" {
 
 int mlp_server_create(mlp_model *m, size_t hbm_budget_bytes, int32_t max_slots, mlp_server **out) {
     if (!m || !out || max_slots < 1 || hbm_budget_bytes == 0) return fail(MLP_ERR_INVALID_ARG, "bad argument");
-    if (m->al) return fail(MLP_ERR_INVALID_ARG, "the server's admission model is PaiNN's; serve a PaiNN model");
+    if (m->al || m->mc) return fail(MLP_ERR_INVALID_ARG, "the server's admission model is PaiNN's; serve a PaiNN model");
     mlp_server *S = new mlp_server();
     S->m = m;
     S->budget = hbm_budget_bytes;
