@@ -452,6 +452,35 @@ def measure_allegro(mlp, synth, torch, precision: str, n_cells: int = 49, reps: 
     return res
 
 
+def measure_mace(mlp, synth, torch, precision: str, n_cells: int = 33, reps: int = 5):
+    """MACE with two layers (the paper's setting: correlation order 3,
+    l_max = 3, 32 scalar and 32 vector channels, 8 radial functions,
+    polynomial envelope p = 6, 5 A cutoff) on a periodic fcc aluminium crystal
+    of 4 n_cells^3 atoms (33 gives 143,748, the per-GPU load of the paper's
+    MACE aluminium weak-scaling runs), a = 4.065 A, sigma = 0.1 A: energy +
+    forces per call on a graph built with a 0.5 A skin."""
+    import gc
+    s = synth.fcc_crystal(n_cells, a=4.065, sigma=0.1, seed=0)
+    h, w = synth.make_mace_weights(1, seed=0)
+    model = mlp.Model(h, w, precision)
+    d = mlp.System(model, s.pos, s.species, s.box, skin=0.5)
+    st = d.compute(stats=True)["stats"]
+    d.compute()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        d.compute()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    res = {"atoms": s.n_atoms, "precision": precision, "ms_per_eval": round(1e3 * el, 3),
+           "atom_steps_per_s": round(s.n_atoms / el, 1), "n_edges_rc": int(st["n_edges"]),
+           "device_GB": round(st["device_bytes"] / 2**30, 2)}
+    del d, model
+    gc.collect()
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -514,6 +543,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the water MD, slab, NVT, capacity and Allegro timings")
     ap.add_argument("--allegro-only", action="store_true", help="time only the Allegro workload (a quick check)")
+    ap.add_argument("--mace-only", action="store_true", help="time only the MACE workload (a quick check)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device to device (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -529,6 +559,9 @@ def main():
 
     if args.allegro_only:
         print(json.dumps({p: measure_allegro(mlp, synth, torch, p) for p in (args.precision, "fp32")}), flush=True)
+        return
+    if args.mace_only:
+        print(json.dumps({p: measure_mace(mlp, synth, torch, p) for p in (args.precision, "fp32")}), flush=True)
         return
     if args.copy_probe:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -581,6 +614,7 @@ def main():
             "al_fcc_nvt_171500": measure_al_nvt(mlp, synth, torch, args.precision),
             "max_atoms_one_gpu_al_fcc_painn_T4_F64": measure_capacity(mlp, synth, torch),
             "allegro_al_fcc_470596": {p: measure_allegro(mlp, synth, torch, p) for p in [args.precision, "fp32"]},
+            "mace_al_fcc_143748": {p: measure_mace(mlp, synth, torch, p) for p in [args.precision, "fp32"]},
         }
 
     if not args.no_serving:

@@ -12,7 +12,7 @@ namespace mlp {
 // of the unit vector (x, y, z), and the tangential gradient of sum_m g_m Y_m.
 // ---------------------------------------------------------------------------
 template <class T>
-__host__ __device__ inline void sh16(T x, T y, T z, T *Y) {
+__host__ __device__ constexpr inline void sh16(T x, T y, T z, T *Y) {
     const T s3 = (T)1.7320508075688772, s15 = (T)3.872983346207417, s5 = (T)2.23606797749979;
     const T s70 = (T)8.366600265340756, s105 = (T)10.246950765959598, s42 = (T)6.48074069840786,
             s7 = (T)2.6457513110645907;
