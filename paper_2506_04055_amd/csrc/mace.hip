@@ -22,40 +22,45 @@
 //   E_i       = w_r1 . h1_i,0 + w_r2 . silu(W_r2 h2_i,0 + b_r2) + b_r3
 // Layer 1 takes degree 0 and gives degrees 0 and 1; layer 2 takes 0 and 1 and
 // gives 0.  Y are the component-normalised real harmonics of sh.h; the
-// couplings are computed once on the host by an exact quadrature of the same
-// harmonics, so the kernels and the tables share one basis.
+// couplings are constant expressions of the same harmonics (gaunt.h), so the
+// kernels unroll over the nonzero couplings only.
 //
 // Layout of the work: the radial MLPs are GEMMs over edges and the W_A
 // channel mixes GEMMs over (atom, m) rows, on the matrix cores (gemm.hip).
 // The convolution, the symmetric contraction and the small per-atom channel
 // mixes (W_out, W_sc, W_up, the readouts) run with one half-wave per atom and
-// one lane per channel.  The symmetric contraction walks a host-built list of
-// expanded product terms (uniform over the wave, read through the scalar
-// cache) against the lane's A' held in LDS.  Forces come from a hand-written
-// adjoint: the same kernels reversed, the gradient of each source's hb
-// collected from per-edge partials through the reverse-edge index (no
-// atomics), and per edge G_e = dE/d(r_i - r_j), assembled into forces by
-// launch_forces.
+// one lane per channel:
+// * the l2 = 1 conv paths accumulate per atom the moments
+//   M_p[a][b] = sum_e R_e,p Y_l1a hb_j,1b and couple them once per atom
+//   (A_p,c = sum_ab G[a][b][c] M_p[a][b]); the adjoint contracts G with the
+//   atom's dE/dA once (X_p[a][b] = sum_c G[a][b][c] dE/dA_p,c) and then works
+//   per edge on X;
+// * the symmetric contraction is factorised: the pair products
+//   P(l1, l2 -> lambda) = sum_ab G A'_l1a A'_l2b of a channel are formed once
+//   in registers and serve both the two-body paths and, coupled with one
+//   more A', the three-body paths.
+// Forces come from a hand-written adjoint: the same kernels reversed, the
+// gradient of each source's hb collected from per-edge partials through the
+// reverse-edge index (no atomics), per-edge sums over channels by DPP
+// exchanges within the half-wave, and per edge G_e = dE/d(r_i - r_j),
+// assembled into forces by launch_forces.
 #include "internal.h"
 #include "gemm.h"
+#include "gaunt.h"
 #include "sh.h"
 
 #include <algorithm>
 #include <cmath>
-#include <cstring>
-#include <map>
 #include <string>
-#include <tuple>
 #include <vector>
+
+#define MC_INLINE __attribute__((always_inline))
 
 namespace mlp {
 
 namespace {
 
 constexpr int MK = 32;     // channels: one lane each, a half-wave per atom
-constexpr int NT = 72;     // coupled harmonics per edge of the l2 = 1 paths
-constexpr int NGC = 318;   // coupling entries of the l2 = 1 paths
-constexpr int ONE = 16;    // the LDS slot holding 1 (lower body orders of the contraction)
 constexpr int APB = 8;     // atoms per workgroup (256 threads)
 
 inline int nblk(long n, int t) { return (int)((n + t - 1) / t); }
@@ -87,20 +92,139 @@ __host__ __device__ constexpr int cp_nL(int L, int np) {
     for (int q = 0; q < np; q++) c += cp_L(q) == L;
     return c;
 }
-// offsets of an l2 = 1 path in the per-edge table (3 (2L + 1) entries, [b][c])
-// and in the coupling table ((2 l1 + 1) 3 (2L + 1) entries, [a][b][c])
-__host__ __device__ constexpr int cp_toff(int p) {
+// first moment M_p[a][b] of an l2 = 1 path ((2 l1 + 1) x 3 per path)
+__host__ __device__ constexpr int cp_moff(int p) {
     int o = 0;
-    for (int q = 4; q < p; q++) o += 3 * (2 * cp_L(q) + 1);
+    for (int q = 4; q < p; q++) o += 3 * (2 * cp_l1(q) + 1);
     return o;
 }
-__host__ __device__ constexpr int cp_goff(int p) {
-    int o = 0;
-    for (int q = 4; q < p; q++) o += (2 * cp_l1(q) + 1) * 3 * (2 * cp_L(q) + 1);
-    return o;
+constexpr int NMOM = cp_moff(10);
+static_assert(cp_off(4) == 16 && cp_off(10) == 40 && NMOM == 72, "accumulator layout");
+
+// ---- compile-time couplings of the conv paths with l2 = 1 ----
+struct CEnt {
+    int a, b, c;
+    float v;
+};
+struct ConvTab {
+    CEnt e[320] = {};
+    int beg[11] = {};   // entries of path p: [beg[p], beg[p + 1]), p = 4..9
+};
+constexpr ConvTab make_conv() {
+    ConvTab t{};
+    int n = 0;
+    for (int p = 4; p < 10; p++) {
+        t.beg[p] = n;
+        const int l1 = cp_l1(p), L = cp_L(p);
+        for (int a = 0; a < 2 * l1 + 1; a++)
+            for (int b = 0; b < 3; b++)
+                for (int c = 0; c < 2 * L + 1; c++) {
+                    const double v = cg::coupling(l1, a, 1, b, L, c);
+                    if (v != 0.0) t.e[n++] = CEnt{a, b, c, (float)v};
+                }
+    }
+    t.beg[10] = n;
+    return t;
 }
-static_assert(cp_off(4) == 16 && cp_off(10) == 40, "accumulator layout");
-static_assert(cp_toff(10) == NT && cp_goff(10) == NGC, "coupling tables");
+inline constexpr ConvTab kConv = make_conv();
+
+// ---- compile-time structure of the symmetric contraction (l_max 3, correlation 3) ----
+// Pair products P(l1 <= l2 -> lambda)[mu] = sum_ab G(l1, l2, lambda)[a][b][mu] A_l1a A_l2b.
+struct PEnt {
+    int i, j, q;   // A slots l1^2 + a, l2^2 + b; P index
+    float v;
+};
+struct PairTab {
+    int nc = 0, l1[16] = {}, l2[16] = {}, lam[16] = {}, off[17] = {};
+    PEnt e[400] = {};
+    int n = 0;
+};
+constexpr PairTab make_pairs() {
+    PairTab t{};
+    int q = 0;
+    for (int l1 = 0; l1 <= 3; l1++)
+        for (int l2 = l1; l2 <= 3; l2++)
+            for (int lam = 0; lam <= 3; lam++) {
+                if (!cg::couples(l1, l2, lam)) continue;
+                const int c = t.nc++;
+                t.l1[c] = l1;
+                t.l2[c] = l2;
+                t.lam[c] = lam;
+                t.off[c] = q;
+                for (int a = 0; a < 2 * l1 + 1; a++)
+                    for (int b = 0; b < 2 * l2 + 1; b++)
+                        for (int mu = 0; mu < 2 * lam + 1; mu++) {
+                            const double v = cg::coupling(l1, a, l2, b, lam, mu);
+                            if (v != 0.0) t.e[t.n++] = PEnt{l1 * l1 + a, l2 * l2 + b, q + mu, (float)v};
+                        }
+                q += 2 * lam + 1;
+            }
+    t.off[t.nc] = q;
+    return t;
+}
+inline constexpr PairTab kPair = make_pairs();
+constexpr int NPP = kPair.off[kPair.nc];
+
+constexpr int pair_off(int l1, int l2, int lam) {
+    for (int c = 0; c < kPair.nc; c++)
+        if (kPair.l1[c] == l1 && kPair.l2[c] == l2 && kPair.lam[c] == lam) return kPair.off[c];
+    return -1;
+}
+
+// Contraction paths onto degree Lo in weight order: kind 1 (A'_Lo), kind 2
+// (a pair product onto Lo, P index q0), kind 3 (a pair product onto lambda
+// coupled with A'_l3 to Lo: entries (P index, A slot, output component)).
+struct SEnt {
+    int q, s, d;
+    float v;
+};
+struct SymTab {
+    int np = 0, kind[32] = {}, q0[32] = {}, beg[33] = {};
+    SEnt e[400] = {};
+    int n = 0;
+};
+constexpr SymTab make_sym(int Lo) {
+    SymTab t{};
+    t.kind[t.np] = 1;
+    t.beg[t.np] = t.n;
+    t.np++;
+    for (int l1 = 0; l1 <= 3; l1++)
+        for (int l2 = l1; l2 <= 3; l2++)
+            if (cg::couples(l1, l2, Lo)) {
+                t.kind[t.np] = 2;
+                t.q0[t.np] = pair_off(l1, l2, Lo);
+                t.beg[t.np] = t.n;
+                t.np++;
+            }
+    for (int l1 = 0; l1 <= 3; l1++)
+        for (int l2 = l1; l2 <= 3; l2++)
+            for (int lam = 0; lam <= 3; lam++) {
+                if (!cg::couples(l1, l2, lam)) continue;
+                for (int l3 = 0; l3 <= 3; l3++) {
+                    if (!cg::couples(lam, l3, Lo)) continue;
+                    const int q0 = pair_off(l1, l2, lam);
+                    t.kind[t.np] = 3;
+                    t.q0[t.np] = q0;
+                    t.beg[t.np] = t.n;
+                    for (int mu = 0; mu < 2 * lam + 1; mu++)
+                        for (int c = 0; c < 2 * l3 + 1; c++)
+                            for (int d = 0; d < 2 * Lo + 1; d++) {
+                                const double v = cg::coupling(lam, mu, l3, c, Lo, d);
+                                if (v != 0.0) t.e[t.n++] = SEnt{q0 + mu, l3 * l3 + c, d, (float)v};
+                            }
+                    t.np++;
+                }
+            }
+    t.beg[t.np] = t.n;
+    return t;
+}
+inline constexpr SymTab kSym0 = make_sym(0), kSym1 = make_sym(1);
+template <int LO>
+constexpr const SymTab &sym_tab() {
+    if constexpr (LO == 0) return kSym0;
+    else return kSym1;
+}
+static_assert(kSym0.np == 20 && kSym1.np == 27 && NPP == 59, "contraction paths");
 
 __device__ __forceinline__ float mc_sigmoid(float x) { return 1.0f / (1.0f + __expf(-x)); }
 __device__ __forceinline__ float mc_silu(float x) { return x * mc_sigmoid(x); }
@@ -121,19 +245,30 @@ __device__ __forceinline__ void load16(const float *p, float *v) {
     }
 }
 
-// Sum of 16 values over the 32 lanes of a half-wave: lane k ends with the
-// total of value k >> 1 (each exchange hands over the half the lane drops).
-__device__ __forceinline__ float halfwave_sum16(float *v, int k) {
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+// One exchange of a reduce-scatter: the lane whose bit is set keeps the
+// upper W values and hands its lower W to the partner, which keeps the lower.
+template <int W, int CTRL>
+__device__ __forceinline__ void rs_stage(float *v, bool up) {
 #pragma unroll
-    for (int w = 8, sh = 16; w >= 1; w >>= 1, sh >>= 1) {
-        const bool up = (k & sh) != 0;
-#pragma unroll
-        for (int q = 0; q < w; q++) {
-            const float send = up ? v[q] : v[q + w], keep = up ? v[q + w] : v[q];
-            v[q] = keep + __shfl_xor(send, sh, 64);
-        }
+    for (int q = 0; q < W; q++) {
+        const float send = up ? v[q] : v[q + W], keep = up ? v[q + W] : v[q];
+        v[q] = keep + dpp_mov<CTRL>(send);
     }
-    return v[0] + __shfl_xor(v[0], 1, 64);
+}
+// Sum of 16 values over the 32 lanes of a half-wave; lane k returns the total
+// of value k & 15.  Partners within a row of 16 lanes: lane i and 15 - i
+// (row mirror, bit 3 differs), i and 7 - i (half-row mirror, bit 2), i ^ 2 and
+// i ^ 1 (quad permutations); then the two rows.
+__device__ __forceinline__ float halfwave_sum16(float *v, int k) {
+    rs_stage<8, 0x140>(v, (k & 8) != 0);
+    rs_stage<4, 0x141>(v, (k & 4) != 0);
+    rs_stage<2, 0x4E>(v, (k & 2) != 0);
+    rs_stage<1, 0xB1>(v, (k & 1) != 0);
+    return v[0] + __shfl_xor(v[0], 16, 64);
 }
 
 __device__ __forceinline__ float halfwave_sum(float v) {
@@ -142,51 +277,85 @@ __device__ __forceinline__ float halfwave_sum(float v) {
     return v;
 }
 
-// T_p[b][c] = sum_a G_p[a][b][c] Y_l1a for one l2 = 1 path (compile-time shape)
-template <int p>
-__device__ __forceinline__ void edge_tpath(const float *__restrict__ Gc, const float *y, float *t) {
-    constexpr int l1 = cp_l1(p), na = 2 * l1 + 1, nc = 2 * cp_L(p) + 1, to = cp_toff(p), go = cp_goff(p);
+// ---- symmetric contraction of one channel (A: 16 slots l^2 + m) ----
+__device__ __forceinline__ void pair_fwd(const float *A, float *P) {
 #pragma unroll
-    for (int b = 0; b < 3; b++)
-#pragma unroll
-        for (int c = 0; c < nc; c++) {
-            float s = 0.f;
-#pragma unroll
-            for (int a = 0; a < na; a++) s = fmaf(Gc[go + (a * 3 + b) * nc + c], y[l1 * l1 + a], s);
-            t[to + b * nc + c] = s;
-        }
+    for (int q = 0; q < NPP; q++) P[q] = 0.f;
+    cg::sfor<kPair.n>([&](auto t) MC_INLINE {
+        constexpr PEnt E = kPair.e[decltype(t)::value];
+        P[E.q] = fmaf(E.v, A[E.i] * A[E.j], P[E.q]);
+    });
 }
 
-// Adjoint of one l2 = 1 path of the second layer's convolution for one edge
-// and channel: dE/dR_p, the source's hb gradient (gh[1..3]) and dE/dY_l1a.
-template <int p>
-__device__ __forceinline__ void conv1_bwd_path(const float *gA, const float *t, const float *h1,
-                                               const float *__restrict__ Gc, float rp, float *gy, float *gh,
-                                               float *gR) {
-    constexpr int l1 = cp_l1(p), na = 2 * l1 + 1, nc = 2 * cp_L(p) + 1, to = cp_toff(p), go = cp_goff(p),
-                  ao = cp_off(p);
-    float d = 0.f;
+__device__ __forceinline__ void pair_bwd(const float *A, const float *gP, float *gA) {
+    cg::sfor<kPair.n>([&](auto t) MC_INLINE {
+        constexpr PEnt E = kPair.e[decltype(t)::value];
+        const float g = E.v * gP[E.q];
+        gA[E.i] = fmaf(g, A[E.j], gA[E.i]);
+        gA[E.j] = fmaf(g, A[E.i], gA[E.j]);
+    });
+}
+
+// m[d] += sum_eta W[eta] B_eta,d for output degree LO; W: this species' and
+// channel's weights, path eta at W[eta * MK]
+template <int LO>
+__device__ __forceinline__ void sym_fwd(const float *A, const float *P, const float *__restrict__ W, float *m) {
+    constexpr int NO = 2 * LO + 1;
+    cg::sfor<sym_tab<LO>().np>([&](auto eta) MC_INLINE {
+        constexpr int h = decltype(eta)::value;
+        constexpr int kind = sym_tab<LO>().kind[h];
+        const float w = W[h * MK];
+        if constexpr (kind == 1) {
 #pragma unroll
-    for (int b = 0; b < 3; b++) {
-        float tb = 0.f;
+            for (int d = 0; d < NO; d++) m[d] = fmaf(w, A[LO * LO + d], m[d]);
+        } else if constexpr (kind == 2) {
+            constexpr int q0 = sym_tab<LO>().q0[h];
 #pragma unroll
-        for (int c = 0; c < nc; c++) tb = fmaf(gA[ao + c], t[to + b * nc + c], tb);
-        d = fmaf(tb, h1[b], d);
-        gh[1 + b] = fmaf(rp, tb, gh[1 + b]);
-    }
-    gR[p] = d;
+            for (int d = 0; d < NO; d++) m[d] = fmaf(w, P[q0 + d], m[d]);
+        } else {
+            constexpr int e0 = sym_tab<LO>().beg[h], ne = sym_tab<LO>().beg[h + 1] - e0;
+            float b[NO];
 #pragma unroll
-    for (int a = 0; a < na; a++) {
-        float s = 0.f;
+            for (int d = 0; d < NO; d++) b[d] = 0.f;
+            cg::sfor<ne>([&](auto t) MC_INLINE {
+                constexpr SEnt E = sym_tab<LO>().e[e0 + decltype(t)::value];
+                b[E.d] = fmaf(E.v, P[E.q] * A[E.s], b[E.d]);
+            });
 #pragma unroll
-        for (int b = 0; b < 3; b++) {
-            float sb = 0.f;
-#pragma unroll
-            for (int c = 0; c < nc; c++) sb = fmaf(Gc[go + (a * 3 + b) * nc + c], gA[ao + c], sb);
-            s = fmaf(sb, h1[b], s);
+            for (int d = 0; d < NO; d++) m[d] = fmaf(w, b[d], m[d]);
         }
-        gy[l1 * l1 + a] = fmaf(rp, s, gy[l1 * l1 + a]);
-    }
+    });
+}
+
+// adjoint of sym_fwd: gm = dE/dm; adds dE/dA (direct) into gA and dE/dP into gP
+template <int LO>
+__device__ __forceinline__ void sym_bwd(const float *A, const float *P, const float *__restrict__ W, const float *gm,
+                                        float *gA, float *gP) {
+    constexpr int NO = 2 * LO + 1;
+    cg::sfor<sym_tab<LO>().np>([&](auto eta) MC_INLINE {
+        constexpr int h = decltype(eta)::value;
+        constexpr int kind = sym_tab<LO>().kind[h];
+        const float w = W[h * MK];
+        float gb[NO];
+#pragma unroll
+        for (int d = 0; d < NO; d++) gb[d] = w * gm[d];
+        if constexpr (kind == 1) {
+#pragma unroll
+            for (int d = 0; d < NO; d++) gA[LO * LO + d] += gb[d];
+        } else if constexpr (kind == 2) {
+            constexpr int q0 = sym_tab<LO>().q0[h];
+#pragma unroll
+            for (int d = 0; d < NO; d++) gP[q0 + d] += gb[d];
+        } else {
+            constexpr int e0 = sym_tab<LO>().beg[h], ne = sym_tab<LO>().beg[h + 1] - e0;
+            cg::sfor<ne>([&](auto t) MC_INLINE {
+                constexpr SEnt E = sym_tab<LO>().e[e0 + decltype(t)::value];
+                const float g = E.v * gb[E.d];
+                gP[E.q] = fmaf(g, A[E.s], gP[E.q]);
+                gA[E.s] = fmaf(g, P[E.q], gA[E.s]);
+            });
+        }
+    });
 }
 
 }  // namespace
@@ -196,19 +365,6 @@ struct McBlk {
     float *p[4];
 };
 
-// One layer's symmetric contraction: segments (path, output component, first
-// term, end term) grouped by output degree (segments [sb[q], sb[q + 1]) for
-// the q-th output degree), terms (a1 | a2 << 5 | a3 << 10, coefficient bits)
-// with a the (l, m) slot l^2 + m of A' or ONE, and W_sym per output degree
-// as [species][path][K].
-struct McSym {
-    const int4 *seg;
-    const int2 *term;
-    int sb[3];
-    const float *W[2];
-    int np[2];
-};
-
 // ---------------------------------------------------------------------------
 // Model
 // ---------------------------------------------------------------------------
@@ -216,26 +372,23 @@ struct McModel {
     int S = 0, NB = 0, NBP = 0, pe = 0, nrad = 0, rh[4] = {0, 0, 0, 0}, RH = 0;
     float rc = 0.f, navg = 1.f, b_r3 = 0.f;
     float *dev = nullptr;     // weights, transposed copies, tables (device)
-    int *sym_dev = nullptr;   // segments and terms of both layers (device)
     void *pk_dev = nullptr;   // packed GEMM operands
     PackedW radF[2][5], radA[2][5], waF[2][4], waA[2][4];
-    const float *zero = nullptr, *Gc = nullptr, *hb0tab = nullptr, *skip0tab = nullptr;
+    const float *zero = nullptr, *hb0tab = nullptr, *skip0tab = nullptr;
     const float *w_r1 = nullptr, *W_r2 = nullptr, *b_r2 = nullptr, *w_r2 = nullptr;
     const float *WoutT[2][2] = {}, *Wout[2][2] = {};   // [layer][output degree index]
     const float *WupT1[2] = {}, *Wup1[2] = {};         // second layer's W_up for l2 = 0, 1
     const float *WscT1 = nullptr, *Wsc1 = nullptr;     // second layer's skip (degree 0), [S][K][K]
-    McSym sym[2] = {};
+    const float *Wsym[2][2] = {};                      // [layer][output degree index]: [S][paths][K]
 };
 
 // ---------------------------------------------------------------------------
-// Forward, per edge: radial functions with the envelope, harmonics, and the
-// harmonics coupled to the l2 = 1 paths: T_p[b][c] = sum_a G_p[a][b][c] Y_l1a.
+// Forward, per edge: radial functions with the envelope, and the harmonics.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_mc_edge(const int *__restrict__ rowc, int n, const float4 *__restrict__ geom,
-                                                 int NB, int NBP, int pe, float rc, const int *__restrict__ e1,
-                                                 const float *__restrict__ Gc, float *__restrict__ X0,
-                                                 float *__restrict__ Y, float *__restrict__ TT) {
-    const long ne = rowc[n], ne1 = *e1;
+                                                 int NB, int NBP, int pe, float rc, float *__restrict__ X0,
+                                                 float *__restrict__ Y) {
+    const long ne = rowc[n];
     const float c0 = sqrtf(2.0f / rc), th = 3.14159265358979f / rc;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (long)gridDim.x * blockDim.x) {
         const float4 gm = geom[e];
@@ -258,18 +411,6 @@ __global__ void __launch_bounds__(256) k_mc_edge(const int *__restrict__ rowc, i
         float4 *y4 = reinterpret_cast<float4 *>(Y + e * 16);
 #pragma unroll
         for (int q = 0; q < 4; q++) y4[q] = make_float4(y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]);
-        if (e < ne1) {
-            float t[NT];
-            edge_tpath<4>(Gc, y, t);
-            edge_tpath<5>(Gc, y, t);
-            edge_tpath<6>(Gc, y, t);
-            edge_tpath<7>(Gc, y, t);
-            edge_tpath<8>(Gc, y, t);
-            edge_tpath<9>(Gc, y, t);
-            float4 *t4 = reinterpret_cast<float4 *>(TT + e * NT);
-#pragma unroll
-            for (int q = 0; q < NT / 4; q++) t4[q] = make_float4(t[4 * q], t[4 * q + 1], t[4 * q + 2], t[4 * q + 3]);
-        }
     }
 }
 
@@ -281,17 +422,18 @@ __global__ void __launch_bounds__(256) k_mc_edge(const int *__restrict__ rowc, i
 // ---------------------------------------------------------------------------
 template <int LAY>
 __global__ void __launch_bounds__(256) k_mc_conv(const int *__restrict__ rowc, const int *__restrict__ colc, int nd,
-                                                 const float *__restrict__ Y, const float *__restrict__ TT,
-                                                 const float *__restrict__ R, const float *__restrict__ HB,
-                                                 const int *__restrict__ zsp, const float *__restrict__ hb0,
-                                                 float scale, McBlk AR) {
-    constexpr int NP = LAY == 0 ? 4 : 10, NA = cp_off(NP);
+                                                 const float *__restrict__ Y, const float *__restrict__ R,
+                                                 const float *__restrict__ HB, const int *__restrict__ zsp,
+                                                 const float *__restrict__ hb0, float scale, McBlk AR) {
+    constexpr int NP = LAY == 0 ? 4 : 10, NM = LAY == 0 ? 1 : NMOM;
     const int k = threadIdx.x & 31;
     const int i = blockIdx.x * APB + (threadIdx.x >> 5);
     if (i >= nd) return;
-    float acc[NA];
+    float acc[16], mom[NM];
 #pragma unroll
-    for (int q = 0; q < NA; q++) acc[q] = 0.f;
+    for (int q = 0; q < 16; q++) acc[q] = 0.f;
+#pragma unroll
+    for (int q = 0; q < NM; q++) mom[q] = 0.f;
     const int eend = rowc[i + 1];
     for (int e = rowc[i]; e < eend; e++) {
         const int j = colc[e];
@@ -305,63 +447,68 @@ __global__ void __launch_bounds__(256) k_mc_conv(const int *__restrict__ rowc, c
             h1[1] = hb[2 * MK];
             h1[2] = hb[3 * MK];
         }
-        float y[16];
+        float y[16], r[NP];
         load16(Y + (long)e * 16, y);
         const float *rr = R + (long)e * NP * MK + k;
-        float r[NP];
 #pragma unroll
         for (int p = 0; p < NP; p++) r[p] = rr[p * MK];
 #pragma unroll
         for (int p = 0; p < 4; p++) {
             const float s = r[p] * h0;
 #pragma unroll
-            for (int c = 0; c < 2 * p + 1; c++) acc[cp_off(p) + c] = fmaf(s, y[p * p + c], acc[cp_off(p) + c]);
+            for (int c = 0; c < 2 * p + 1; c++) acc[p * p + c] = fmaf(s, y[p * p + c], acc[p * p + c]);
         }
         if constexpr (LAY == 1) {
-            float t[NT];
-            const float4 *t4 = reinterpret_cast<const float4 *>(TT + (long)e * NT);
-#pragma unroll
-            for (int q = 0; q < NT / 4; q++) {
-                const float4 x = t4[q];
-                t[4 * q] = x.x;
-                t[4 * q + 1] = x.y;
-                t[4 * q + 2] = x.z;
-                t[4 * q + 3] = x.w;
-            }
 #pragma unroll
             for (int p = 4; p < NP; p++) {
-                const int nc = 2 * cp_L(p) + 1, to = cp_toff(p);
+                const int l1 = cp_l1(p), mo = cp_moff(p);
+                const float rb[3] = {r[p] * h1[0], r[p] * h1[1], r[p] * h1[2]};
 #pragma unroll
-                for (int c = 0; c < nc; c++) {
-                    const float v = t[to + c] * h1[0] + t[to + nc + c] * h1[1] + t[to + 2 * nc + c] * h1[2];
-                    acc[cp_off(p) + c] = fmaf(r[p], v, acc[cp_off(p) + c]);
-                }
+                for (int a = 0; a < 2 * l1 + 1; a++)
+#pragma unroll
+                    for (int b = 0; b < 3; b++) mom[mo + a * 3 + b] = fmaf(y[l1 * l1 + a], rb[b], mom[mo + a * 3 + b]);
             }
         }
     }
 #pragma unroll
-    for (int p = 0; p < NP; p++) {
-        const int L = cp_L(p), nc = 2 * L + 1, ld = cp_nL(L, NP) * MK;
+    for (int p = 0; p < 4; p++) {
+        const int L = p, nc = 2 * L + 1, ld = cp_nL(L, NP) * MK;
         float *o = AR.p[L] + (long)i * nc * ld + cp_loc(p) * MK + k;
 #pragma unroll
-        for (int c = 0; c < nc; c++) o[(long)c * ld] = acc[cp_off(p) + c] * scale;
+        for (int c = 0; c < nc; c++) o[(long)c * ld] = acc[p * p + c] * scale;
+    }
+    if constexpr (LAY == 1) {
+        cg::sfor<6>([&](auto pi) MC_INLINE {
+            constexpr int p = 4 + decltype(pi)::value, L = cp_L(p), nc = 2 * L + 1, ld = cp_nL(L, 10) * MK,
+                          mo = cp_moff(p), e0 = kConv.beg[p];
+            float v[nc];
+#pragma unroll
+            for (int c = 0; c < nc; c++) v[c] = 0.f;
+            cg::sfor<kConv.beg[p + 1] - e0>([&](auto t) MC_INLINE {
+                constexpr CEnt E = kConv.e[e0 + decltype(t)::value];
+                v[E.c] = fmaf(E.v, mom[mo + E.a * 3 + E.b], v[E.c]);
+            });
+            float *o = AR.p[L] + (long)i * nc * ld + cp_loc(p) * MK + k;
+#pragma unroll
+            for (int c = 0; c < nc; c++) o[(long)c * ld] = v[c] * scale;
+        });
     }
 }
 
 // ---------------------------------------------------------------------------
 // Per-atom kernels: one half-wave per atom, lane = channel; the lane's A'
-// (16 values and the constant 1) in an LDS column of its own, the channel
-// mixes through a per-atom LDS row.  Every thread of a workgroup reaches the
-// barriers (rows past nd compute on zeros and write nothing).
+// (16 values) and pair products in registers, the channel mixes through a
+// per-atom LDS row.  Every thread of a workgroup reaches the barriers (rows
+// past nd compute on zeros and write nothing).
 // ---------------------------------------------------------------------------
 struct McNodeArgs {
     McBlk AP;                      // A' [row][2L + 1][K] per L
-    McSym sym;
+    const float *Wsym[2];          // per output degree index: [S][paths][K]
+    int np[2];
     const float *WoutT[2];         // [k'][k] per output degree index
-    const float *Wout[2];          // [k][k'] (adjoint)
     const float *skip0tab;         // first layer: W_sc[Z] h0 per species [S][K]
-    const float *WupT1[2], *Wup1[2];
-    const float *WscT1, *Wsc1;     // second layer's skip [S][K][K] (transposed / as stored)
+    const float *WupT1[2];
+    const float *WscT1;            // second layer's skip [S][k'][k]
     const float *w_r1, *W_r2, *b_r2, *w_r2;
     float b_r3;
     int RH;
@@ -371,49 +518,18 @@ struct McNodeArgs {
     int nloc;                      // rows the second layer covers
 };
 
-__device__ __forceinline__ void sym_forward(const McSym &sy, int q, const float *sA, int tid, int z, int k, float *m) {
-    const float *W = sy.W[q] + (long)z * sy.np[q] * MK + k;
-    for (int sg = sy.sb[q]; sg < sy.sb[q + 1]; sg++) {
-        const int4 S = sy.seg[sg];
-        float s = 0.f;
-        for (int t = S.z; t < S.w; t++) {
-            const int2 T = sy.term[t];
-            const float p = sA[(T.x & 31) * 256 + tid] * sA[((T.x >> 5) & 31) * 256 + tid] * sA[(T.x >> 10) * 256 + tid];
-            s = fmaf(__int_as_float(T.y), p, s);
-        }
-        const float v = W[S.x * MK] * s;
-        if (q == 0) m[0] += v;
-        else if (S.y == 0) m[1] += v;
-        else if (S.y == 1) m[2] += v;
-        else m[3] += v;
-    }
-}
-
-__device__ __forceinline__ void sym_adjoint(const McSym &sy, int q, const float *sA, float *sG, int tid, int z, int k,
-                                            const float *gm) {
-    const float *W = sy.W[q] + (long)z * sy.np[q] * MK + k;
-    for (int sg = sy.sb[q]; sg < sy.sb[q + 1]; sg++) {
-        const int4 S = sy.seg[sg];
-        const float g = W[S.x * MK] * (q == 0 ? gm[0] : (S.y == 0 ? gm[1] : (S.y == 1 ? gm[2] : gm[3])));
-        for (int t = S.z; t < S.w; t++) {
-            const int2 T = sy.term[t];
-            const int a1 = (T.x & 31) * 256 + tid, a2 = ((T.x >> 5) & 31) * 256 + tid, a3 = (T.x >> 10) * 256 + tid;
-            const float c = __int_as_float(T.y) * g;
-            const float p1 = sA[a1], p2 = sA[a2], p3 = sA[a3];
-            sG[a1] += c * p2 * p3;
-            sG[a2] += c * p1 * p3;
-            sG[a3] += c * p1 * p2;
-        }
-    }
-}
-
-__device__ __forceinline__ void load_ap(const McBlk &AP, bool act, int i, int k, int tid, float *sA) {
+__device__ __forceinline__ void load_ap(const McBlk &AP, bool act, int i, int k, float *A) {
 #pragma unroll
     for (int L = 0; L < 4; L++)
 #pragma unroll
-        for (int m = 0; m < 2 * L + 1; m++)
-            sA[(L * L + m) * 256 + tid] = act ? AP.p[L][((long)i * (2 * L + 1) + m) * MK + k] : 0.f;
-    sA[ONE * 256 + tid] = 1.f;
+        for (int m = 0; m < 2 * L + 1; m++) A[L * L + m] = act ? AP.p[L][((long)i * (2 * L + 1) + m) * MK + k] : 0.f;
+}
+
+__device__ __forceinline__ void store_gap(const McBlk &GAP, int i, int k, const float *gA) {
+#pragma unroll
+    for (int L = 0; L < 4; L++)
+#pragma unroll
+        for (int m = 0; m < 2 * L + 1; m++) GAP.p[L][((long)i * (2 * L + 1) + m) * MK + k] = gA[L * L + m];
 }
 
 // x[c] = sum_k' W[c][k' * K + k] xs[c][k'] for c < NC (W per component, [k'][k])
@@ -432,16 +548,17 @@ __device__ __forceinline__ void mix(const float *const *W, const float *xs, int 
 
 template <int LAY>
 __global__ void __launch_bounds__(256) k_mc_node(int nd, const int *__restrict__ zsp, McNodeArgs a) {
-    __shared__ float sA[17 * 256];
     __shared__ float sx[APB * 4 * MK];
     const int tid = threadIdx.x, k = tid & 31, ai = tid >> 5;
     const int i = blockIdx.x * APB + ai;
     const bool act = i < nd;
     const int z = act ? zsp[i] : 0;
-    load_ap(a.AP, act, i, k, tid, sA);
+    float A[16], P[NPP];
+    load_ap(a.AP, act, i, k, A);
+    pair_fwd(A, P);
     float m[4] = {0.f, 0.f, 0.f, 0.f};
-    sym_forward(a.sym, 0, sA, tid, z, k, m);
-    if constexpr (LAY == 0) sym_forward(a.sym, 1, sA, tid, z, k, m);
+    sym_fwd<0>(A, P, a.Wsym[0] + (long)z * a.np[0] * MK + k, m);
+    if constexpr (LAY == 0) sym_fwd<1>(A, P, a.Wsym[1] + (long)z * a.np[1] * MK + k, m + 1);
     float *xs = sx + ai * 4 * MK;
     constexpr int NC = LAY == 0 ? 4 : 1;
 #pragma unroll
@@ -501,7 +618,8 @@ __global__ void __launch_bounds__(256) k_mc_node(int nd, const int *__restrict__
 // ---------------------------------------------------------------------------
 struct McNodeBwdArgs {
     McBlk AP, GAP;                 // A' of the layer and dE/dA' (output)
-    McSym sym;
+    const float *Wsym[2];
+    int np[2];
     const float *Wout[2];          // [k][k'] per output degree index
     const float *Wup1[2];          // second layer's W_up [k][k'] for l2 = 0, 1
     const float *Wsc1;             // [S][K][K]
@@ -518,8 +636,6 @@ struct McNodeBwdArgs {
 };
 
 __global__ void __launch_bounds__(256) k_mc_node1_bwd(int nd, const int *__restrict__ zsp, McNodeBwdArgs a) {
-    __shared__ float sA[17 * 256];
-    __shared__ float sG[17 * 256];
     __shared__ float sx[APB * 4 * MK];
     const int tid = threadIdx.x, k = tid & 31, ai = tid >> 5;
     const int i = blockIdx.x * APB + ai;
@@ -542,7 +658,7 @@ __global__ void __launch_bounds__(256) k_mc_node1_bwd(int nd, const int *__restr
     for (int q = 0; q < a.RH; q++) gh = fmaf(a.W_r2[q * MK + k], xs[MK + q], gh);
     xs[2 * MK + k] = gh;
     __syncthreads();
-    float gm[4] = {0.f, 0.f, 0.f, 0.f}, gs = 0.f;
+    float gm[1] = {0.f}, gs = 0.f;
     {
         const float *wo = a.Wout[0] + k, *ws = a.Wsc1 + (long)z * MK * MK + k;
         const float *v = xs + 2 * MK;
@@ -553,21 +669,20 @@ __global__ void __launch_bounds__(256) k_mc_node1_bwd(int nd, const int *__restr
         }
     }
     if (act) a.GH1S[(long)i * MK + k] = gs;
-    load_ap(a.AP, act, i, k, tid, sA);
+    float A[16], P[NPP], gA[16], gP[NPP];
+    load_ap(a.AP, act, i, k, A);
+    pair_fwd(A, P);
 #pragma unroll
-    for (int q = 0; q < 17; q++) sG[q * 256 + tid] = 0.f;
-    sym_adjoint(a.sym, 0, sA, sG, tid, z, k, gm);
-    if (act)
+    for (int q = 0; q < 16; q++) gA[q] = 0.f;
 #pragma unroll
-        for (int L = 0; L < 4; L++)
-#pragma unroll
-            for (int m = 0; m < 2 * L + 1; m++)
-                a.GAP.p[L][((long)i * (2 * L + 1) + m) * MK + k] = sG[(L * L + m) * 256 + tid];
+    for (int q = 0; q < NPP; q++) gP[q] = 0.f;
+    sym_bwd<0>(A, P, a.Wsym[0] + (long)z * a.np[0] * MK + k, gm, gA, gP);
+    pair_bwd(A, gP, gA);
+    if (act) store_gap(a.GAP, i, k, gA);
 }
 
-__global__ void __launch_bounds__(256) k_mc_node0_bwd(int nd, const int *__restrict__ zsp, McNodeBwdArgs a) {
-    __shared__ float sA[17 * 256];
-    __shared__ float sG[17 * 256];
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_mc_node0_bwd(int nd, const int *__restrict__ zsp,
+                                                                                         McNodeBwdArgs a) {
     __shared__ float sx[APB * 4 * MK];
     const int tid = threadIdx.x, k = tid & 31, ai = tid >> 5;
     const int i = blockIdx.x * APB + ai;
@@ -604,88 +719,103 @@ __global__ void __launch_bounds__(256) k_mc_node0_bwd(int nd, const int *__restr
         const float *W[4] = {a.Wout[0], a.Wout[1], a.Wout[1], a.Wout[1]};
         mix<4>(W, xs, k, gm);
     }
-    load_ap(a.AP, act, i, k, tid, sA);
+    float A[16], P[NPP], gA[16], gP[NPP];
+    load_ap(a.AP, act, i, k, A);
+    pair_fwd(A, P);
 #pragma unroll
-    for (int q = 0; q < 17; q++) sG[q * 256 + tid] = 0.f;
-    sym_adjoint(a.sym, 0, sA, sG, tid, z, k, gm);
-    sym_adjoint(a.sym, 1, sA, sG, tid, z, k, gm);
-    if (act)
+    for (int q = 0; q < 16; q++) gA[q] = 0.f;
 #pragma unroll
-        for (int L = 0; L < 4; L++)
-#pragma unroll
-            for (int m = 0; m < 2 * L + 1; m++)
-                a.GAP.p[L][((long)i * (2 * L + 1) + m) * MK + k] = sG[(L * L + m) * 256 + tid];
+    for (int q = 0; q < NPP; q++) gP[q] = 0.f;
+    sym_bwd<0>(A, P, a.Wsym[0] + (long)z * a.np[0] * MK + k, gm, gA, gP);
+    sym_bwd<1>(A, P, a.Wsym[1] + (long)z * a.np[1] * MK + k, gm + 1, gA, gP);
+    pair_bwd(A, gP, gA);
+    if (act) store_gap(a.GAP, i, k, gA);
 }
 
 // ---------------------------------------------------------------------------
 // Adjoint of the second layer's convolution, by destination: dE/dR per edge
-// (written over R), dE/dY per edge (half-wave sums), and per edge the
+// (written over R), dE/dY per edge (sums over the channels), and per edge the
 // gradient its source's hb receives (MSG[e][4][K]), collected later by the
-// source through the reverse edge.
+// source through the reverse edge.  The l2 = 1 paths work on
+// X_p[a][b] = sum_c G_p[a][b][c] dE/dA_p,c, formed once per atom.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_mc_conv1_bwd(const int *__restrict__ rowc, const int *__restrict__ colc, int nd,
-                                                      const float *__restrict__ Y, const float *__restrict__ TT,
-                                                      float *__restrict__ R, const float *__restrict__ HB,
-                                                      const float *__restrict__ Gc, float scale, McBlk GAR,
+                                                      const float *__restrict__ Y, float *__restrict__ R,
+                                                      const float *__restrict__ HB, float scale, McBlk GAR,
                                                       float *__restrict__ GY, float *__restrict__ MSG) {
-    constexpr int NP = 10, NA = 40;
+    constexpr int NP = 10;
     const int k = threadIdx.x & 31;
     const int i = blockIdx.x * APB + (threadIdx.x >> 5);
     if (i >= nd) return;
-    float gA[NA];
+    float gA0[16], X[NMOM];
 #pragma unroll
-    for (int p = 0; p < NP; p++) {
-        const int L = cp_L(p), nc = 2 * L + 1, ld = cp_nL(L, NP) * MK;
+    for (int p = 0; p < 4; p++) {
+        const int L = p, nc = 2 * L + 1, ld = cp_nL(L, NP) * MK;
         const float *o = GAR.p[L] + (long)i * nc * ld + cp_loc(p) * MK + k;
 #pragma unroll
-        for (int c = 0; c < nc; c++) gA[cp_off(p) + c] = o[(long)c * ld] * scale;
+        for (int c = 0; c < nc; c++) gA0[p * p + c] = o[(long)c * ld] * scale;
     }
+#pragma unroll
+    for (int q = 0; q < NMOM; q++) X[q] = 0.f;
+    cg::sfor<6>([&](auto pi) MC_INLINE {
+        constexpr int p = 4 + decltype(pi)::value, L = cp_L(p), nc = 2 * L + 1, ld = cp_nL(L, NP) * MK,
+                      mo = cp_moff(p), e0 = kConv.beg[p];
+        const float *o = GAR.p[L] + (long)i * nc * ld + cp_loc(p) * MK + k;
+        float g[nc];
+#pragma unroll
+        for (int c = 0; c < nc; c++) g[c] = o[(long)c * ld] * scale;
+        cg::sfor<kConv.beg[p + 1] - e0>([&](auto t) MC_INLINE {
+            constexpr CEnt E = kConv.e[e0 + decltype(t)::value];
+            X[mo + E.a * 3 + E.b] = fmaf(E.v, g[E.c], X[mo + E.a * 3 + E.b]);
+        });
+    });
     const int eend = rowc[i + 1];
     for (int e = rowc[i]; e < eend; e++) {
         const int j = colc[e];
         const float *hb = HB + (long)j * 4 * MK + k;
         const float h0 = hb[0], h1[3] = {hb[MK], hb[2 * MK], hb[3 * MK]};
-        float y[16], t[NT], r[NP];
+        float y[16], r[NP];
         load16(Y + (long)e * 16, y);
-        const float4 *t4 = reinterpret_cast<const float4 *>(TT + (long)e * NT);
-#pragma unroll
-        for (int q = 0; q < NT / 4; q++) {
-            const float4 x = t4[q];
-            t[4 * q] = x.x;
-            t[4 * q + 1] = x.y;
-            t[4 * q + 2] = x.z;
-            t[4 * q + 3] = x.w;
-        }
         float *rr = R + (long)e * NP * MK + k;
 #pragma unroll
         for (int p = 0; p < NP; p++) r[p] = rr[p * MK];
         float gy[16], gh[4] = {0.f, 0.f, 0.f, 0.f}, gR[NP];
 #pragma unroll
-        for (int q = 0; q < 16; q++) gy[q] = 0.f;
-#pragma unroll
         for (int p = 0; p < 4; p++) {
             float d = 0.f;
 #pragma unroll
             for (int c = 0; c < 2 * p + 1; c++) {
-                d = fmaf(gA[p * p + c], y[p * p + c], d);
-                gy[p * p + c] = fmaf(gA[p * p + c], r[p] * h0, gy[p * p + c]);
+                d = fmaf(gA0[p * p + c], y[p * p + c], d);
+                gy[p * p + c] = gA0[p * p + c] * (r[p] * h0);
             }
             gR[p] = d * h0;
             gh[0] = fmaf(r[p], d, gh[0]);
         }
-        conv1_bwd_path<4>(gA, t, h1, Gc, r[4], gy, gh, gR);
-        conv1_bwd_path<5>(gA, t, h1, Gc, r[5], gy, gh, gR);
-        conv1_bwd_path<6>(gA, t, h1, Gc, r[6], gy, gh, gR);
-        conv1_bwd_path<7>(gA, t, h1, Gc, r[7], gy, gh, gR);
-        conv1_bwd_path<8>(gA, t, h1, Gc, r[8], gy, gh, gR);
-        conv1_bwd_path<9>(gA, t, h1, Gc, r[9], gy, gh, gR);
+#pragma unroll
+        for (int p = 4; p < NP; p++) {
+            const int l1 = cp_l1(p), mo = cp_moff(p);
+            float u[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int a = 0; a < 2 * l1 + 1; a++) {
+                float wa = 0.f;
+#pragma unroll
+                for (int b = 0; b < 3; b++) {
+                    u[b] = fmaf(X[mo + a * 3 + b], y[l1 * l1 + a], u[b]);
+                    wa = fmaf(X[mo + a * 3 + b], h1[b], wa);
+                }
+                gy[l1 * l1 + a] = fmaf(r[p], wa, gy[l1 * l1 + a]);
+            }
+            gR[p] = u[0] * h1[0] + u[1] * h1[1] + u[2] * h1[2];
+#pragma unroll
+            for (int b = 0; b < 3; b++) gh[1 + b] = fmaf(r[p], u[b], gh[1 + b]);
+        }
 #pragma unroll
         for (int p = 0; p < NP; p++) rr[p * MK] = gR[p];
         float *mp = MSG + (long)e * 4 * MK + k;
 #pragma unroll
         for (int c = 0; c < 4; c++) mp[c * MK] = gh[c];
         const float s = halfwave_sum16(gy, k);
-        if ((k & 1) == 0) GY[(long)e * 16 + (k >> 1)] = s;
+        if (k < 16) GY[(long)e * 16 + k] = s;
     }
 }
 
@@ -719,13 +849,13 @@ __global__ void __launch_bounds__(256) k_mc_conv0_bwd(const int *__restrict__ ro
 #pragma unroll
             for (int c = 0; c < 2 * p + 1; c++) {
                 d = fmaf(gA[p * p + c], y[p * p + c], d);
-                gy[p * p + c] = gA[p * p + c] * rp * h0;
+                gy[p * p + c] = gA[p * p + c] * (rp * h0);
             }
             rr[p * MK] = d * h0;
         }
         const float s = halfwave_sum16(gy, k);
-        if ((k & 1) == 0) {
-            float *g = GY + (long)e * 16 + (k >> 1);
+        if (k < 16) {
+            float *g = GY + (long)e * 16 + k;
             *g = add ? *g + s : s;
         }
     }
@@ -797,136 +927,10 @@ __global__ void k_mc_species(int S, const float *__restrict__ Wemb, const float 
 }
 
 // ---------------------------------------------------------------------------
-// Host side: couplings, expanded contraction terms, weights
+// Host side
 // ---------------------------------------------------------------------------
-namespace {
-
-constexpr double kPi = 3.14159265358979323846;
-
-bool couples(int l1, int l2, int L) { return std::abs(l1 - l2) <= L && L <= l1 + l2 && (l1 + l2 + L) % 2 == 0; }
-
-// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
-void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
-    x.resize(n);
-    w.resize(n);
-    for (int i = 0; i < n; i++) {
-        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
-        for (int it = 0; it < 100; it++) {
-            double p1 = 1.0, p2 = 0.0;
-            for (int j = 1; j <= n; j++) {
-                const double p3 = p2;
-                p2 = p1;
-                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
-            }
-            const double pp = n * (z * p1 - p2) / (z * z - 1.0), dz = p1 / pp;
-            z -= dz;
-            if (std::fabs(dz) < 1e-15) break;
-        }
-        double p1 = 1.0, p2 = 0.0;
-        for (int j = 1; j <= n; j++) {
-            const double p3 = p2;
-            p2 = p1;
-            p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
-        }
-        const double pp = n * (z * p1 - p2) / (z * z - 1.0);
-        x[i] = z;
-        w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
-    }
-}
-
-// G(l1, l2, L)[a][b][c] = (1 / 4 pi) int Y_l1a Y_l2b Y_Lc over the sphere, by a
-// product rule (Gauss-Legendre in z, uniform in phi) exact for the degrees
-// involved (at most 9).
-struct Gaunt {
-    std::map<std::tuple<int, int, int>, std::vector<double>> cache;
-    std::vector<std::vector<double>> Yq;   // harmonics at the nodes
-    std::vector<double> wq;
-    Gaunt() {
-        const int nz = 8, nphi = 16;
-        std::vector<double> zx, zw;
-        gauss_legendre(nz, zx, zw);
-        for (int a = 0; a < nz; a++)
-            for (int b = 0; b < nphi; b++) {
-                const double ph = 2.0 * kPi * b / nphi, s = std::sqrt(std::max(0.0, 1.0 - zx[a] * zx[a]));
-                std::vector<double> y(16);
-                sh16<double>(s * std::cos(ph), s * std::sin(ph), zx[a], y.data());
-                Yq.push_back(y);
-                wq.push_back(zw[a] / (2.0 * nphi));   // (2 pi / nphi) / (4 pi)
-            }
-    }
-    const std::vector<double> &get(int l1, int l2, int L) {
-        auto key = std::make_tuple(l1, l2, L);
-        auto it = cache.find(key);
-        if (it != cache.end()) return it->second;
-        const int n1 = 2 * l1 + 1, n2 = 2 * l2 + 1, n3 = 2 * L + 1;
-        std::vector<double> g((size_t)n1 * n2 * n3, 0.0);
-        for (size_t q = 0; q < wq.size(); q++)
-            for (int a = 0; a < n1; a++)
-                for (int b = 0; b < n2; b++)
-                    for (int c = 0; c < n3; c++)
-                        g[((size_t)a * n2 + b) * n3 + c] += wq[q] * Yq[q][l1 * l1 + a] * Yq[q][l2 * l2 + b] * Yq[q][L * L + c];
-        return cache[key] = g;
-    }
-};
-
-struct Term {
-    int c, a1, a2, a3;
-    double coef;
-};
-
-// Contraction paths onto degree Lo (l_max 3, correlation 3) in weight order,
-// each expanded into product terms of A' slots per output component.
-std::vector<std::vector<Term>> contraction_paths(Gaunt &G, int Lo) {
-    std::vector<std::vector<Term>> paths;
-    const int lmax = 3;
-    const double tol = 1e-12;
-    {
-        std::vector<Term> t;
-        for (int c = 0; c < 2 * Lo + 1; c++) t.push_back({c, Lo * Lo + c, ONE, ONE, 1.0});
-        paths.push_back(t);
-    }
-    for (int l1 = 0; l1 <= lmax; l1++)
-        for (int l2 = l1; l2 <= lmax; l2++) {
-            if (!couples(l1, l2, Lo)) continue;
-            const auto &g = G.get(l1, l2, Lo);
-            const int n2 = 2 * l2 + 1, n3 = 2 * Lo + 1;
-            std::vector<Term> t;
-            for (int c = 0; c < n3; c++)
-                for (int a = 0; a < 2 * l1 + 1; a++)
-                    for (int b = 0; b < n2; b++) {
-                        const double v = g[((size_t)a * n2 + b) * n3 + c];
-                        if (std::fabs(v) > tol) t.push_back({c, l1 * l1 + a, l2 * l2 + b, ONE, v});
-                    }
-            paths.push_back(t);
-        }
-    for (int l1 = 0; l1 <= lmax; l1++)
-        for (int l2 = l1; l2 <= lmax; l2++)
-            for (int lam = 0; lam <= lmax; lam++) {
-                if (!couples(l1, l2, lam)) continue;
-                for (int l3 = 0; l3 <= lmax; l3++) {
-                    if (!couples(lam, l3, Lo)) continue;
-                    const auto &g1 = G.get(l1, l2, lam), &g2 = G.get(lam, l3, Lo);
-                    const int n1 = 2 * l1 + 1, n2 = 2 * l2 + 1, nl = 2 * lam + 1, n3 = 2 * l3 + 1, no = 2 * Lo + 1;
-                    std::vector<Term> t;
-                    for (int d = 0; d < no; d++)
-                        for (int a = 0; a < n1; a++)
-                            for (int b = 0; b < n2; b++)
-                                for (int c = 0; c < n3; c++) {
-                                    double v = 0.0;
-                                    for (int mu = 0; mu < nl; mu++)
-                                        v += g1[((size_t)a * n2 + b) * nl + mu] * g2[((size_t)mu * n3 + c) * no + d];
-                                    if (std::fabs(v) > tol) t.push_back({d, l1 * l1 + a, l2 * l2 + b, l3 * l3 + c, v});
-                                }
-                    paths.push_back(t);
-                }
-            }
-    return paths;
-}
-
-}  // namespace
-
 struct McArena {
-    long X0, Y, TT, P[2][4], A[2][4], R[2], GY, GX0, MSG, AR[2], AP[2], GAP, H1, HB1, H2, GH1S, U, total;
+    long X0, Y, P[2][4], A[2][4], R[2], GY, GX0, MSG, AR[2], AP[2], GAP, H1, HB1, H2, GH1S, U, total;
 };
 
 static McArena mc_layout(const McModel &a, long N, long E) {
@@ -939,7 +943,6 @@ static McArena mc_layout(const McModel &a, long N, long E) {
     };
     L.X0 = take(E * a.NBP);
     L.Y = take(E * 16);
-    L.TT = take(E * NT);
     for (int t = 0; t < 2; t++) {
         for (int q = 0; q < 4; q++) L.P[t][q] = L.A[t][q] = 0;
         for (int q = 0; q < a.nrad; q++) {
@@ -981,17 +984,12 @@ int mace_create(mlp_model *m, const McDims &d, const float *w, size_t n_weights)
     if (d.RH < 1 || d.RH > MK) return fail(-1, "mace: readout_hidden must be 1..32");
     if (!(d.rc > 0.f) || !(d.navg > 0.f)) return fail(-1, "mace: r_c and avg_neighbors must be positive");
     const int S = d.S, K = MK, NB = d.NB;
-    // host-side contraction terms and the weight layout they fix
-    Gaunt gnt;
-    std::vector<std::vector<std::vector<Term>>> paths[2];   // [layer][output degree index][path]
-    const int LOUT[2][2] = {{0, 1}, {0, -1}};
-    for (int t = 0; t < 2; t++)
-        for (int q = 0; q < 2; q++)
-            if (LOUT[t][q] >= 0) paths[t].push_back(contraction_paths(gnt, LOUT[t][q]));
+    // contraction paths per layer and output degree (layer 1: degrees 0 and 1; layer 2: degree 0)
+    const int npath[2][2] = {{kSym0.np, kSym1.np}, {kSym0.np, 0}}, nout[2] = {2, 1};
     // storage order (matrices [out][in]): W_emb (K x S); per layer: W_up per
     // input degree, radial matrices, W_A per L, W_sym per output degree,
-    // W_out per output degree, W_sc per output degree that is an input
-    // degree; then w_r1, W_r2, b_r2, w_r2, b_r3
+    // W_out per output degree, W_sc for degree 0 (the one output degree both
+    // layers also take); then w_r1, W_r2, b_r2, w_r2, b_r3
     size_t off = 0;
     auto take = [&](size_t cnt) {
         const size_t r = off;
@@ -1010,9 +1008,9 @@ int mace_create(mlp_model *m, const McDims &d, const float *w, size_t n_weights)
         }
         oRad[t][d.nrad] = take((size_t)NPt[t] * K * prev);
         for (int L = 0; L < 4; L++) oWA[t][L] = take((size_t)K * cp_nL(L, NPt[t]) * K);
-        for (size_t q = 0; q < paths[t].size(); q++) oSym[t][q] = take((size_t)S * K * paths[t][q].size());
-        for (size_t q = 0; q < paths[t].size(); q++) oOut[t][q] = take((size_t)K * K);
-        oSc[t] = take((size_t)S * K * K);   // degree 0 is the one output degree both layers also take
+        for (int q = 0; q < nout[t]; q++) oSym[t][q] = take((size_t)S * K * npath[t][q]);
+        for (int q = 0; q < nout[t]; q++) oOut[t][q] = take((size_t)K * K);
+        oSc[t] = take((size_t)S * K * K);
     }
     const size_t oR1 = take(K), oWR2 = take((size_t)d.RH * K), oBR2 = take(d.RH), oWr2 = take(d.RH), oBR3 = take(1);
     if (off != n_weights)
@@ -1031,12 +1029,12 @@ int mace_create(mlp_model *m, const McDims &d, const float *w, size_t n_weights)
     a->navg = d.navg;
     a->b_r3 = w[oBR3];
 
-    // device floats: the weights as given, then transposed copies, tables
+    // device floats: the weights as given, then transposed copies and tables
     std::vector<float> host(w, w + n_weights);
     auto push = [&](const std::vector<float> &v) {
+        while (host.size() % 64) host.push_back(0.f);
         const size_t r = host.size();
         host.insert(host.end(), v.begin(), v.end());
-        while (host.size() % 64) host.push_back(0.f);
         return r;
     };
     auto transpose = [&](size_t o) {   // K x K, [k][k'] -> [k'][k]
@@ -1045,9 +1043,9 @@ int mace_create(mlp_model *m, const McDims &d, const float *w, size_t n_weights)
             for (int c = 0; c < K; c++) t[(size_t)c * K + r] = w[o + (size_t)r * K + c];
         return t;
     };
-    size_t oWoutT[2][2], oWupT1[2], oWscT1, oSymT[2][2];
+    size_t oWoutT[2][2] = {}, oWupT1[2], oWscT1, oSymT[2][2] = {};
     for (int t = 0; t < 2; t++)
-        for (size_t q = 0; q < paths[t].size(); q++) oWoutT[t][q] = push(transpose(oOut[t][q]));
+        for (int q = 0; q < nout[t]; q++) oWoutT[t][q] = push(transpose(oOut[t][q]));
     for (int l2 = 0; l2 < 2; l2++) oWupT1[l2] = push(transpose(oUp[1][l2]));
     {
         std::vector<float> t((size_t)S * K * K);
@@ -1057,92 +1055,35 @@ int mace_create(mlp_model *m, const McDims &d, const float *w, size_t n_weights)
         oWscT1 = push(t);
     }
     for (int t = 0; t < 2; t++)
-        for (size_t q = 0; q < paths[t].size(); q++) {
-            const size_t np = paths[t][q].size();
+        for (int q = 0; q < nout[t]; q++) {
+            const int np = npath[t][q];
             std::vector<float> v((size_t)S * np * K);
             for (int z = 0; z < S; z++)
                 for (int k = 0; k < K; k++)
-                    for (size_t e = 0; e < np; e++) v[((size_t)z * np + e) * K + k] = w[oSym[t][q] + ((size_t)z * K + k) * np + e];
+                    for (int e = 0; e < np; e++) v[((size_t)z * np + e) * K + k] = w[oSym[t][q] + ((size_t)z * K + k) * np + e];
             oSymT[t][q] = push(v);
         }
-    std::vector<float> gc(NGC);
-    for (int p = 4; p < 10; p++) {
-        const auto &g = gnt.get(cp_l1(p), 1, cp_L(p));
-        for (size_t q = 0; q < g.size(); q++) gc[cp_goff(p) + q] = (float)g[q];
-    }
-    const size_t oGc = push(gc);
     const size_t oZero = push(std::vector<float>(512, 0.f));
     const size_t oHb0 = push(std::vector<float>((size_t)S * K, 0.f));
     const size_t oSkip0 = push(std::vector<float>((size_t)S * K, 0.f));
-    // segments and terms
-    std::vector<int> ints;
-    int segoff[2] = {0, 0}, termoff[2] = {0, 0};
-    std::vector<int4> segs[2];
-    std::vector<int2> terms[2];
-    for (int t = 0; t < 2; t++) {
-        a->sym[t].sb[0] = 0;
-        for (size_t q = 0; q < paths[t].size(); q++) {
-            const int Lo = LOUT[t][q];
-            for (size_t e = 0; e < paths[t][q].size(); e++)
-                for (int c = 0; c < 2 * Lo + 1; c++) {
-                    const int tb = (int)terms[t].size();
-                    for (const Term &x : paths[t][q][e])
-                        if (x.c == c) {
-                            float cf = (float)x.coef;
-                            int bits;
-                            std::memcpy(&bits, &cf, 4);
-                            terms[t].push_back(make_int2(x.a1 | (x.a2 << 5) | (x.a3 << 10), bits));
-                        }
-                    if ((int)terms[t].size() > tb) segs[t].push_back(make_int4((int)e, c, tb, (int)terms[t].size()));
-                }
-            a->sym[t].sb[q + 1] = (int)segs[t].size();
-            a->sym[t].np[q] = (int)paths[t][q].size();
-        }
-        if (paths[t].size() < 2) a->sym[t].sb[2] = a->sym[t].sb[1];
-    }
-    for (int t = 0; t < 2; t++) {
-        segoff[t] = (int)ints.size();
-        for (const int4 &s : segs[t]) {
-            ints.push_back(s.x);
-            ints.push_back(s.y);
-            ints.push_back(s.z);
-            ints.push_back(s.w);
-        }
-        while (ints.size() % 64) ints.push_back(0);
-        termoff[t] = (int)ints.size();
-        for (const int2 &x : terms[t]) {
-            ints.push_back(x.x);
-            ints.push_back(x.y);
-        }
-        while (ints.size() % 64) ints.push_back(0);
-    }
     float *dev = nullptr;
-    int *idev = nullptr;
-    if (hipMalloc(&dev, sizeof(float) * host.size()) != hipSuccess ||
-        hipMalloc(&idev, sizeof(int) * ints.size()) != hipSuccess) {
+    if (hipMalloc(&dev, sizeof(float) * host.size()) != hipSuccess) {
         (void)hipGetLastError();
-        if (dev) hipFree(dev);
         delete a;
         return fail(-2, "mace: weight allocation failed");
     }
-    if (hipMemcpy(dev, host.data(), sizeof(float) * host.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(idev, ints.data(), sizeof(int) * ints.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(dev, host.data(), sizeof(float) * host.size(), hipMemcpyHostToDevice) != hipSuccess) {
         hipFree(dev);
-        hipFree(idev);
         delete a;
         return fail(-5, "mace: weight copy failed");
     }
     a->dev = dev;
-    a->sym_dev = idev;
-    for (int t = 0; t < 2; t++) {
-        a->sym[t].seg = reinterpret_cast<const int4 *>(idev + segoff[t]);
-        a->sym[t].term = reinterpret_cast<const int2 *>(idev + termoff[t]);
-        for (size_t q = 0; q < paths[t].size(); q++) {
-            a->sym[t].W[q] = dev + oSymT[t][q];
+    for (int t = 0; t < 2; t++)
+        for (int q = 0; q < nout[t]; q++) {
+            a->Wsym[t][q] = dev + oSymT[t][q];
             a->WoutT[t][q] = dev + oWoutT[t][q];
             a->Wout[t][q] = dev + oOut[t][q];
         }
-    }
     for (int l2 = 0; l2 < 2; l2++) {
         a->WupT1[l2] = dev + oWupT1[l2];
         a->Wup1[l2] = dev + oUp[1][l2];
@@ -1150,7 +1091,6 @@ int mace_create(mlp_model *m, const McDims &d, const float *w, size_t n_weights)
     a->WscT1 = dev + oWscT1;
     a->Wsc1 = dev + oSc[1];
     a->zero = dev + oZero;
-    a->Gc = dev + oGc;
     a->hb0tab = dev + oHb0;
     a->skip0tab = dev + oSkip0;
     a->w_r1 = dev + oR1;
@@ -1194,7 +1134,6 @@ int mace_create(mlp_model *m, const McDims &d, const float *w, size_t n_weights)
         (void)hipGetLastError();
         if (a->pk_dev) hipFree(a->pk_dev);
         hipFree(dev);
-        hipFree(idev);
         delete a;
         return fail(rc, "mace: weight packing failed");
     }
@@ -1205,7 +1144,6 @@ int mace_create(mlp_model *m, const McDims &d, const float *w, size_t n_weights)
 void mace_destroy(mlp_model *m) {
     if (!m || !m->mc) return;
     if (m->mc->pk_dev) hipFree(m->mc->pk_dev);
-    if (m->mc->sym_dev) hipFree(m->mc->sym_dev);
     if (m->mc->dev) hipFree(m->mc->dev);
     delete m->mc;
     m->mc = nullptr;
@@ -1230,9 +1168,8 @@ int mace_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float
     if ((rc = g->G.ensure(sizeof(float4) * (size_t)E + 64, 1.2, &g->n_grows))) return rc;
     const McArena L = mc_layout(a, n, E);
     float *base = g->act.as<float>();
-    float *X0 = base + L.X0, *Y = base + L.Y, *TT = base + L.TT, *GY = base + L.GY, *GX0 = base + L.GX0,
-          *MSG = base + L.MSG, *H1 = base + L.H1, *HB1 = base + L.HB1, *H2 = base + L.H2, *GH1S = base + L.GH1S,
-          *U = base + L.U;
+    float *X0 = base + L.X0, *Y = base + L.Y, *GY = base + L.GY, *GX0 = base + L.GX0, *MSG = base + L.MSG,
+          *H1 = base + L.H1, *HB1 = base + L.HB1, *H2 = base + L.H2, *GH1S = base + L.GH1S, *U = base + L.U;
     const int *rowc = g->rowc.as<int>(), *colc = g->colc.as<int>(), *revc = g->revc.as<int>(),
               *perm = g->perm.as<int>(), *zsp = g->species.as<int>();
     const float4 *geom = g->geom.as<float4>();
@@ -1260,7 +1197,7 @@ int mace_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float
 
     // forward
     k_mc_zero<<<nblk(n + 64, 256), 256, 0, s>>>(U, n + 64);
-    k_mc_edge<<<eg, 256, 0, s>>>(rowc, n, geom, a.NB, a.NBP, a.pe, a.rc, e1, a.Gc, X0, Y, TT);
+    k_mc_edge<<<eg, 256, 0, s>>>(rowc, n, geom, a.NB, a.NBP, a.pe, a.rc, X0, Y);
     for (int t = 0; t < 2; t++) {
         const float *in = X0;
         int ldin = a.NBP;
@@ -1278,10 +1215,7 @@ int mace_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float
     na.skip0tab = a.skip0tab;
     na.WupT1[0] = a.WupT1[0];
     na.WupT1[1] = a.WupT1[1];
-    na.Wup1[0] = a.Wup1[0];
-    na.Wup1[1] = a.Wup1[1];
     na.WscT1 = a.WscT1;
-    na.Wsc1 = a.Wsc1;
     na.w_r1 = a.w_r1;
     na.W_r2 = a.W_r2;
     na.b_r2 = a.b_r2;
@@ -1294,27 +1228,27 @@ int mace_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float
     na.H2 = H2;
     na.U = U;
     na.nloc = nd1;
+    na.np[0] = kSym0.np;
+    na.np[1] = kSym1.np;
     for (int t = 0; t < 2; t++) {
         const int nd = t ? nd1 : nd0;
         if (nd <= 0) continue;
         const McBlk &AR = t ? AR1 : AR0, &AP = t ? AP1 : AP0;
         if (t == 0)
-            k_mc_conv<0><<<nblk(nd, APB), 256, 0, s>>>(rowc, colc, nd, Y, TT, base + L.R[0], nullptr, zsp, a.hb0tab,
-                                                       scale, AR);
+            k_mc_conv<0><<<nblk(nd, APB), 256, 0, s>>>(rowc, colc, nd, Y, base + L.R[0], nullptr, zsp, a.hb0tab, scale,
+                                                       AR);
         else
-            k_mc_conv<1><<<nblk(nd, APB), 256, 0, s>>>(rowc, colc, nd, Y, TT, base + L.R[1], HB1, zsp, a.hb0tab,
-                                                       scale, AR);
+            k_mc_conv<1><<<nblk(nd, APB), 256, 0, s>>>(rowc, colc, nd, Y, base + L.R[1], HB1, zsp, a.hb0tab, scale, AR);
         for (int Lq = 0; Lq < 4; Lq++) {
             const int ld = cp_nL(Lq, NPt[t]) * MK;
             if ((rc = mgm(s, P, GE_STORE, AR.p[Lq], ld, a.waF[t][Lq], AP.p[Lq], MK, (long)nd * (2 * Lq + 1), nullptr)))
                 return rc;
         }
         na.AP = AP;
-        na.sym = a.sym[t];
+        na.Wsym[0] = a.Wsym[t][0];
+        na.Wsym[1] = a.Wsym[t][1];
         na.WoutT[0] = a.WoutT[t][0];
         na.WoutT[1] = a.WoutT[t][1];
-        na.Wout[0] = a.Wout[t][0];
-        na.Wout[1] = a.Wout[t][1];
         if (t == 0) k_mc_node<0><<<nblk(nd, APB), 256, 0, s>>>(nd, zsp, na);
         else k_mc_node<1><<<nblk(nd, APB), 256, 0, s>>>(nd, zsp, na);
     }
@@ -1342,9 +1276,12 @@ int mace_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float
     nb.perm = perm;
     nb.n_local = g->n_local;
     nb.GAP = GAP;
+    nb.np[0] = kSym0.np;
+    nb.np[1] = kSym1.np;
     if (nd1 > 0) {
         nb.AP = AP1;
-        nb.sym = a.sym[1];
+        nb.Wsym[0] = a.Wsym[1][0];
+        nb.Wsym[1] = nullptr;
         nb.Wout[0] = a.Wout[1][0];
         nb.Wout[1] = a.Wout[1][0];
         k_mc_node1_bwd<<<nblk(nd1, APB), 256, 0, s>>>(nd1, zsp, nb);
@@ -1354,12 +1291,12 @@ int mace_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float
             if ((rc = mgm(s, P, GE_STORE, GAP.p[Lq], MK, a.waA[1][Lq], AR1.p[Lq], ld, (long)nd1 * (2 * Lq + 1), nullptr)))
                 return rc;
         }
-        k_mc_conv1_bwd<<<nblk(nd1, APB), 256, 0, s>>>(rowc, colc, nd1, Y, TT, base + L.R[1], HB1, a.Gc, scale, AR1,
-                                                      GY, MSG);
+        k_mc_conv1_bwd<<<nblk(nd1, APB), 256, 0, s>>>(rowc, colc, nd1, Y, base + L.R[1], HB1, scale, AR1, GY, MSG);
     }
     if (nd0 > 0) {
         nb.AP = AP0;
-        nb.sym = a.sym[0];
+        nb.Wsym[0] = a.Wsym[0][0];
+        nb.Wsym[1] = a.Wsym[0][1];
         nb.Wout[0] = a.Wout[0][0];
         nb.Wout[1] = a.Wout[0][1];
         k_mc_node0_bwd<<<nblk(nd0, APB), 256, 0, s>>>(nd0, zsp, nb);
