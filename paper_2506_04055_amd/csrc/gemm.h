@@ -68,4 +68,22 @@ struct GemmChain {
 };
 int node_gemm_chain(hipStream_t s, int precision, const GemmChain &c);
 
+// A bias-free SiLU MLP over rows (edges) with every hidden layer kept on
+// chip: f[q] (B = W_q^T) and a[q] (B = W_q) for the hidden matrices
+// q < nh and the output matrix q = nh.  This build takes nh = 3, an input
+// of at most 32 columns, hidden widths of at most 64, an output of at most
+// 384 columns and (adjoint) an input gradient of at most 16 columns.
+struct EdgeMlp {
+    int nh = 0;
+    PackedW f[5], a[5];
+};
+// C = h_nh Wo^T with h_q = silu(h_(q-1) W_q^T), h_0 = X (rows bounded by the
+// device count Mc when given).  Returns 0, -1 (unsupported shape) or -5.
+int edge_mlp_forward(hipStream_t s, int precision, const EdgeMlp &W, const float *X, int ldx, float *C, int ldc,
+                     int M, const int *Mc = nullptr);
+// GX (+)= dE/dX given GC = dE/dC, recomputing the hidden layers.  Returns
+// 0, -1 or -5.
+int edge_mlp_adjoint(hipStream_t s, int precision, const EdgeMlp &W, const float *X, int ldx, const float *GC,
+                     int ldgc, float *GX, int ldgx, bool add, int M, const int *Mc = nullptr);
+
 }  // namespace mlp

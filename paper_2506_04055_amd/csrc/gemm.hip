@@ -159,7 +159,9 @@ struct AOp {
 // stage are loaded from L2 while the current stage is multiplied.  Each
 // thread takes a fixed, unrolled share, so all loads of a stage are in
 // flight together.  Starts with a workgroup barrier (LDS may still be read).
-template <int P, int KS>
+// NT: the number of 16-column tiles computed (the leading ones; a product
+// whose B has at most 16 NT columns needs no more).
+template <int P, int KS, int NT = CT>
 __device__ __forceinline__ void mma_pass(char *lds, const PackedW &B, int n0, int K, const AOp<P, KS> &a,
                                          v4f *acc) {
     constexpr int KC = Stage<P>::KC, LDH = Stage<P>::LDH, LDF = Stage<P>::LDF;
@@ -217,7 +219,7 @@ __device__ __forceinline__ void mma_pass(char *lds, const PackedW &B, int n0, in
             if constexpr (P >= 1) {
                 const __bf16 *bb = reinterpret_cast<const __bf16 *>(lds) + c16 * LDH + 32 * j + 8 * g;
 #pragma unroll
-                for (int t = 0; t < CT; t++) {
+                for (int t = 0; t < NT; t++) {
                     const v8bf bh = *reinterpret_cast<const v8bf *>(bb + 16 * t * LDH);
                     if constexpr (P == 2) {
                         const v8bf bl = *reinterpret_cast<const v8bf *>(bb + 16 * t * LDH + NCH * LDH);
@@ -231,7 +233,7 @@ __device__ __forceinline__ void mma_pass(char *lds, const PackedW &B, int n0, in
                 for (int h = 0; h < 2; h++) {
                     const float *bb = reinterpret_cast<const float *>(lds) + c16 * LDF + 32 * j + 16 * h + 4 * g;
 #pragma unroll
-                    for (int t = 0; t < CT; t++) {
+                    for (int t = 0; t < NT; t++) {
                         const v4f b = *reinterpret_cast<const v4f *>(bb + 16 * t * LDF);
 #pragma unroll
                         for (int q = 0; q < 4; q++)
@@ -247,12 +249,13 @@ __device__ __forceinline__ void mma_pass(char *lds, const PackedW &B, int n0, in
 // and returns it.  The epilogue then reads it back by rows, so C (and its
 // second operand) move as whole rows in 16-byte vectors: lane + 64 it covers
 // row (lane + 64 it) / 32, columns 4 ((lane + 64 it) % 32) .. +3.
+template <int NT = CT>
 __device__ __forceinline__ float *park_tile(char *lds, const v4f *acc) {
     const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
     __syncthreads();   // every wave is done with the B stages in LDS
     float *ct = reinterpret_cast<float *>(lds) + (threadIdx.x >> 6) * 16 * LDC;
 #pragma unroll
-    for (int t = 0; t < CT; t++)
+    for (int t = 0; t < NT; t++)
 #pragma unroll
         for (int r = 0; r < 4; r++) ct[(4 * g + r) * LDC + 16 * t + c16] = acc[t][r];
     __syncthreads();
@@ -494,6 +497,236 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *C1, int ld
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// A bias-free SiLU MLP over rows with every hidden layer kept on chip:
+//   forward  C = h_n Wo^T,  h_q = silu(h_(q-1) W_q^T),  h_0 = X
+//   adjoint  dE/dX from dE/dC, the hidden layers recomputed per tile and
+//            their pre-activations held in registers (in the MFMA output
+//            layout, so the SiLU' gates are elementwise on the accumulators)
+// Hidden widths are at most 16 HT (HT tiles, HT / 2 32-wide k-blocks; this
+// build instantiates HT = 4, widths up to 64), the input at most 32 wide.  Each wave owns 16 rows; the tile parked in LDS
+// between layers becomes the next product's A operand.
+// ---------------------------------------------------------------------------
+template <int P, int HT>
+__device__ __forceinline__ void silu_tile(float *ct, int N) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int it = 0; it < EIT; it++) {
+        const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
+        if (c4 >= 16 * HT) continue;
+        v4f *p = reinterpret_cast<v4f *>(ct + row * LDC + c4);
+        *p = c4 < N ? silu4(*p) : v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    __builtin_amdgcn_wave_barrier();   // each wave reads back only its own tile
+}
+
+template <int P, int NH, int HT>
+__global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(2)))
+k_mlp_fwd(const float *__restrict__ X, int ldx, EdgeMlp W, float *__restrict__ C, int ldc, int M, const int *Mc) {
+    __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
+    if (Mc) M = min(M, *Mc);
+    if ((long)blockIdx.x * GW * 16 >= M) return;   // the whole workgroup leaves
+    const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+    const long m0 = ((long)blockIdx.x * GW + (threadIdx.x >> 6)) * 16;
+    const long arow = m0 + c16;
+    const bool rowok = arow < M;
+    const float *Xr = X + (rowok ? arow : 0) * (long)ldx;
+    constexpr int KH = HT / 2;
+    AOp<P, KH> a;
+    {
+        const int K0 = W.f[0].K;
+        AOp<P, 1> x;
+        x.load(g, [&](int k) {
+            v4f z;
+#pragma unroll
+            for (int q = 0; q < 4; q++) z[q] = (rowok && k + q < K0) ? Xr[k + q] : 0.f;
+            return z;
+        });
+        v4f acc[HT];
+#pragma unroll
+        for (int t = 0; t < HT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+        mma_pass<P, 1, HT>(lds, W.f[0], 0, K0, x, acc);
+        float *ct = park_tile<HT>(lds, acc);
+        silu_tile<P, HT>(ct, W.f[0].N);
+        a.load(g, [&](int k) { return *reinterpret_cast<const v4f *>(ct + c16 * LDC + k); });
+    }
+#pragma unroll
+    for (int q = 1; q < NH; q++) {
+        v4f acc[HT];
+#pragma unroll
+        for (int t = 0; t < HT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+        mma_pass<P, KH, HT>(lds, W.f[q], 0, W.f[q].K, a, acc);
+        float *ct = park_tile<HT>(lds, acc);
+        silu_tile<P, HT>(ct, W.f[q].N);
+        a.load(g, [&](int k) { return *reinterpret_cast<const v4f *>(ct + c16 * LDC + k); });
+    }
+    const PackedW &Wo = W.f[NH];
+    for (int n0 = 0; n0 < Wo.N; n0 += NCH) {
+        const int ncols = min(NCH, Wo.N - n0);
+        v4f acc[CT];
+#pragma unroll
+        for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+        mma_pass<P, KH>(lds, Wo, n0, Wo.K, a, acc);
+        const float *ct = park_tile(lds, acc);
+#pragma unroll
+        for (int it = 0; it < EIT; it++) {
+            const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
+            const long m = m0 + row;
+            if (m >= M || c4 >= ncols) continue;
+            *reinterpret_cast<v4f *>(C + m * ldc + n0 + c4) = *reinterpret_cast<const v4f *>(ct + row * LDC + c4);
+        }
+    }
+}
+
+// acc *= SiLU'(pre), elementwise in the MFMA output layout
+template <int HT>
+__device__ __forceinline__ void dsilu_acc(v4f *acc, const v4f *pre) {
+#pragma unroll
+    for (int t = 0; t < HT; t++) acc[t] = dsilu4(acc[t], pre[t]);
+}
+
+template <int P, int NH, int HT, int KSG>
+__global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(2)))
+k_mlp_bwd(const float *__restrict__ X, int ldx, EdgeMlp W, const float *__restrict__ GC, int ldgc, float *GX,
+          int ldgx, int add, int M, const int *Mc) {
+    __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
+    if (Mc) M = min(M, *Mc);
+    if ((long)blockIdx.x * GW * 16 >= M) return;
+    const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+    const long m0 = ((long)blockIdx.x * GW + (threadIdx.x >> 6)) * 16;
+    const long arow = m0 + c16;
+    const bool rowok = arow < M;
+    constexpr int KH = HT / 2;
+    // dE/dC of the wave's rows, loaded first so that its latency overlaps the recompute
+    AOp<P, KSG> ga;
+    {
+        const float *Gr = GC + (rowok ? arow : 0) * (long)ldgc;
+        const int NO = W.f[NH].N;
+        ga.load(g, [&](int k) {
+            if (rowok && k + 4 <= NO) return gld4(Gr + k);
+            v4f z;
+#pragma unroll
+            for (int q = 0; q < 4; q++) z[q] = (rowok && k + q < NO) ? Gr[k + q] : 0.f;
+            return z;
+        });
+    }
+    // forward recompute: pre-activations of every hidden layer
+    v4f pre[NH][HT];
+    AOp<P, KH> a;
+    {
+        const float *Xr = X + (rowok ? arow : 0) * (long)ldx;
+        const int K0 = W.f[0].K;
+        AOp<P, 1> x;
+        x.load(g, [&](int k) {
+            v4f z;
+#pragma unroll
+            for (int q = 0; q < 4; q++) z[q] = (rowok && k + q < K0) ? Xr[k + q] : 0.f;
+            return z;
+        });
+#pragma unroll
+        for (int t = 0; t < HT; t++) pre[0][t] = v4f{0.f, 0.f, 0.f, 0.f};
+        mma_pass<P, 1, HT>(lds, W.f[0], 0, K0, x, pre[0]);
+    }
+#pragma unroll
+    for (int q = 1; q < NH; q++) {
+        float *ct = park_tile<HT>(lds, pre[q - 1]);
+        silu_tile<P, HT>(ct, W.f[q - 1].N);
+        a.load(g, [&](int k) { return *reinterpret_cast<const v4f *>(ct + c16 * LDC + k); });
+#pragma unroll
+        for (int t = 0; t < HT; t++) pre[q][t] = v4f{0.f, 0.f, 0.f, 0.f};
+        mma_pass<P, KH, HT>(lds, W.f[q], 0, W.f[q].K, a, pre[q]);
+    }
+    // dE/dh of the last hidden layer through the output matrix, then down
+    v4f acc[HT];
+#pragma unroll
+    for (int t = 0; t < HT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    mma_pass<P, KSG, HT>(lds, W.a[NH], 0, W.a[NH].K, ga, acc);
+    dsilu_acc<HT>(acc, pre[NH - 1]);
+#pragma unroll
+    for (int q = NH - 1; q >= 1; q--) {
+        float *ct = park_tile<HT>(lds, acc);
+        __builtin_amdgcn_wave_barrier();
+        a.load(g, [&](int k) { return *reinterpret_cast<const v4f *>(ct + c16 * LDC + k); });
+#pragma unroll
+        for (int t = 0; t < HT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+        mma_pass<P, KH, HT>(lds, W.a[q], 0, W.a[q].K, a, acc);
+        dsilu_acc<HT>(acc, pre[q - 1]);
+    }
+    // dE/dX = dE/dP_0 W_0 (at most 16 columns)
+    float *ct = park_tile<HT>(lds, acc);
+    __builtin_amdgcn_wave_barrier();
+    a.load(g, [&](int k) { return *reinterpret_cast<const v4f *>(ct + c16 * LDC + k); });
+    v4f gx[1] = {v4f{0.f, 0.f, 0.f, 0.f}};
+    mma_pass<P, KH, 1>(lds, W.a[0], 0, W.a[0].K, a, gx);
+    const float *cx = park_tile<1>(lds, gx);
+    const int NX = W.a[0].N;
+    // 16 rows x 16 columns: lane (row, 4-column group) = (lane / 4, lane % 4)
+    const int row = lane >> 2, c4 = 4 * (lane & 3);
+    const long m = m0 + row;
+    if (m < M && c4 < NX) {
+        v4f o = *reinterpret_cast<const v4f *>(cx + row * LDC + c4);
+        float *d = GX + m * ldgx + c4;
+        if (add) o += gld4(d);
+        *reinterpret_cast<v4f *>(d) = o;
+    }
+}
+
+template <int P, int NH, int HT>
+static int mlp_fwd_launch(hipStream_t s, const EdgeMlp &W, const float *X, int ldx, float *C, int ldc, int M,
+                          const int *Mc) {
+    const unsigned bx = (unsigned)((M + 16 * GW - 1) / (16 * GW));
+    k_mlp_fwd<P, NH, HT><<<bx, 64 * GW, 0, s>>>(X, ldx, W, C, ldc, M, Mc);
+    return 0;
+}
+
+template <int P, int NH, int HT, int KSG>
+static int mlp_bwd_launch(hipStream_t s, const EdgeMlp &W, const float *X, int ldx, const float *GC, int ldgc,
+                          float *GX, int ldgx, bool add, int M, const int *Mc) {
+    const unsigned bx = (unsigned)((M + 16 * GW - 1) / (16 * GW));
+    k_mlp_bwd<P, NH, HT, KSG><<<bx, 64 * GW, 0, s>>>(X, ldx, W, GC, ldgc, GX, ldgx, add ? 1 : 0, M, Mc);
+    return 0;
+}
+
+static bool mlp_shape_ok(const EdgeMlp &W, int *HT) {
+    if (W.nh != 3 || W.f[0].K > 32 || W.a[0].N > 16) return false;
+    for (int q = 0; q < W.nh; q++)
+        if (W.f[q].N > 64) return false;
+    *HT = 4;
+    return W.f[W.nh].N <= 384;
+}
+
+int edge_mlp_forward(hipStream_t s, int precision, const EdgeMlp &W, const float *X, int ldx, float *C, int ldc,
+                     int M, const int *Mc) {
+    int HT;
+    if (M <= 0) return 0;
+    if (!mlp_shape_ok(W, &HT)) return -1;
+#define MF(P_) mlp_fwd_launch<P_, 3, 4>(s, W, X, ldx, C, ldc, M, Mc)
+    if (precision == 0) MF(0);
+    else if (precision == 1) MF(1);
+    else MF(2);
+#undef MF
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+int edge_mlp_adjoint(hipStream_t s, int precision, const EdgeMlp &W, const float *X, int ldx, const float *GC,
+                     int ldgc, float *GX, int ldgx, bool add, int M, const int *Mc) {
+    int HT;
+    if (M <= 0) return 0;
+    if (!mlp_shape_ok(W, &HT)) return -1;
+    const int NO = W.f[W.nh].N;
+#define MB2(P_, HT_)                                                                                          \
+    (NO <= 128 ? mlp_bwd_launch<P_, 3, HT_, 4>(s, W, X, ldx, GC, ldgc, GX, ldgx, add, M, Mc)                    \
+               : (NO <= 256 ? mlp_bwd_launch<P_, 3, HT_, 8>(s, W, X, ldx, GC, ldgc, GX, ldgx, add, M, Mc)       \
+                            : mlp_bwd_launch<P_, 3, HT_, 12>(s, W, X, ldx, GC, ldgc, GX, ldgx, add, M, Mc)))
+#define MB(P_) MB2(P_, 4)
+    if (precision == 0) MB(0);
+    else if (precision == 1) MB(1);
+    else MB(2);
+#undef MB
+#undef MB2
+    return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
 template <int P, int EPI, int KS>

@@ -374,6 +374,8 @@ struct McModel {
     float *dev = nullptr;     // weights, transposed copies, tables (device)
     void *pk_dev = nullptr;   // packed GEMM operands
     PackedW radF[2][5], radA[2][5], waF[2][4], waA[2][4];
+    EdgeMlp rmlp[2];          // the radial MLPs as fused kernels (when their shape allows)
+    bool fused = false;
     const float *zero = nullptr, *hb0tab = nullptr, *skip0tab = nullptr;
     const float *w_r1 = nullptr, *W_r2 = nullptr, *b_r2 = nullptr, *w_r2 = nullptr;
     const float *WoutT[2][2] = {}, *Wout[2][2] = {};   // [layer][output degree index]
@@ -945,10 +947,11 @@ static McArena mc_layout(const McModel &a, long N, long E) {
     L.Y = take(E * 16);
     for (int t = 0; t < 2; t++) {
         for (int q = 0; q < 4; q++) L.P[t][q] = L.A[t][q] = 0;
-        for (int q = 0; q < a.nrad; q++) {
-            L.P[t][q] = take(E * a.rh[q]);
-            L.A[t][q] = take(E * a.rh[q]);
-        }
+        if (!a.fused)
+            for (int q = 0; q < a.nrad; q++) {
+                L.P[t][q] = take(E * a.rh[q]);
+                L.A[t][q] = take(E * a.rh[q]);
+            }
         L.R[t] = take(E * (t == 0 ? 4 : 10) * MK);
     }
     L.GY = take(E * 16);
@@ -1137,6 +1140,17 @@ int mace_create(mlp_model *m, const McDims &d, const float *w, size_t n_weights)
         delete a;
         return fail(rc, "mace: weight packing failed");
     }
+    // the radial MLPs run as one fused kernel each way where the shape allows
+    // (three hidden layers of at most 64, at most 32 radial functions)
+    a->fused = d.nrad == 3 && NB <= 16;
+    for (int q = 0; q < d.nrad; q++) a->fused = a->fused && d.rh[q] <= 64;
+    for (int t = 0; t < 2; t++) {
+        a->rmlp[t].nh = d.nrad;
+        for (int q = 0; q <= d.nrad; q++) {
+            a->rmlp[t].f[q] = a->radF[t][q];
+            a->rmlp[t].a[q] = a->radA[t][q];
+        }
+    }
     m->mc = a;
     return 0;
 }
@@ -1199,6 +1213,12 @@ int mace_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float
     k_mc_zero<<<nblk(n + 64, 256), 256, 0, s>>>(U, n + 64);
     k_mc_edge<<<eg, 256, 0, s>>>(rowc, n, geom, a.NB, a.NBP, a.pe, a.rc, X0, Y);
     for (int t = 0; t < 2; t++) {
+        if (a.fused) {
+            ProfScope ps(PK_GEMM, s);
+            if (edge_mlp_forward(s, P, a.rmlp[t], X0, a.NBP, base + L.R[t], NPt[t] * MK, (int)E, t ? e1 : e0))
+                return fail(-5, "mace radial MLP failed");
+            continue;
+        }
         const float *in = X0;
         int ldin = a.NBP;
         for (int q = 0; q < a.nrad; q++) {
@@ -1310,6 +1330,12 @@ int mace_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float
     // edges first (stored), then the second layer's added on its prefix
     for (int t = 0; t < 2; t++) {
         const int *cnt = t ? e1 : e0;
+        if (a.fused) {
+            ProfScope ps(PK_GEMM, s);
+            if (edge_mlp_adjoint(s, P, a.rmlp[t], X0, a.NBP, base + L.R[t], NPt[t] * MK, GX0, a.NBP, t != 0, (int)E, cnt))
+                return fail(-5, "mace radial MLP adjoint failed");
+            continue;
+        }
         const float *gin = base + L.R[t];
         int ldg = NPt[t] * MK;
         for (int q = a.nrad - 1; q >= 0; q--) {
