@@ -254,21 +254,34 @@ __global__ void k_cell_fill(const int *__restrict__ cell_of, int n, const int *_
 
 // Ascending user index inside each cell: makes the internal order, and hence
 // every result, independent of atomic scheduling.
-__global__ void k_cell_sort(const int *__restrict__ cell_start, int ncell, int *__restrict__ idx,
-                            int *__restrict__ max_occ) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per cell: lane l holds the cell's l-th entry and moves it to its
+// rank among the entries (user indices are distinct); a cell of more than
+// 64 atoms falls back to an insertion sort by its first lane.
+__global__ void __launch_bounds__(256) k_cell_sort(const int *__restrict__ cell_start, int ncell,
+                                                   int *__restrict__ idx, int *__restrict__ max_occ) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (c >= ncell) return;
-    int a = cell_start[c], b = cell_start[c + 1];
-    for (int i = a + 1; i < b; i++) {
-        int key = idx[i];
-        int j = i - 1;
-        while (j >= a && idx[j] > key) {
-            idx[j + 1] = idx[j];
-            j--;
+    const int a = cell_start[c], b = cell_start[c + 1], occ = b - a;
+    if (occ <= 64) {
+        const int v = lane < occ ? idx[a + lane] : 0x7fffffff;
+        int rank = 0;
+        for (int p = 0; p < occ; p++) rank += __builtin_amdgcn_readlane(v, p) < v;
+        if (lane < occ) idx[a + rank] = v;
+    } else if (lane == 0) {
+        for (int i = a + 1; i < b; i++) {
+            int key = idx[i];
+            int j = i - 1;
+            while (j >= a && idx[j] > key) {
+                idx[j + 1] = idx[j];
+                j--;
+            }
+            idx[j + 1] = key;
         }
-        idx[j + 1] = key;
     }
-    atomicMax(max_occ, b - a);
+    // the largest occupancy; the plain read (never above the true maximum)
+    // skips most of the atomics on the one shared word
+    if (lane == 0 && occ > 0 && occ > *(volatile int *)max_occ) atomicMax(max_occ, occ);
 }
 
 __global__ void k_gather_build(const int *__restrict__ perm, int n, const float4 *__restrict__ posw,
@@ -329,20 +342,24 @@ __device__ __forceinline__ float fold_once(float d, float L) {
     return d;
 }
 
-// Neighbours within rc + skin of row i, one wave per row.  The (at most 27)
-// stencil cells are visited in ascending key order, runs of consecutive keys
-// form one contiguous range of the cell-sorted rows, and each range is
-// tested 64 candidates at a time; a ballot and a prefix popcount place the
-// hits, so the columns of a row come out ascending, as from a sequential
-// scan.
+// Neighbours within rc + skin of row i, one wave per row.  Lane q (< 27)
+// computes the key of stencil cell q and its rank among the stencil keys
+// (distinct cells have distinct keys); lane r then holds the r-th cell in
+// ascending key order, its row range in the cell-sorted order and the
+// exclusive prefix of the range lengths.  The candidates of all ranges are
+// tested as one concatenated sequence, 64 at a time (lane l takes candidate
+// cb + l, found in the few ranges that overlap the chunk); a ballot and a
+// prefix popcount place the hits, so the columns of a row come out
+// ascending, as from a sequential scan of the cells in key order.
 template <bool FILL>
 __global__ void __launch_bounds__(256) k_nbr(const float4 *__restrict__ pb, const int *__restrict__ cell_int,
                                              const int *__restrict__ cell_start, int n, Grid g, float cut2,
                                              int *__restrict__ cnt, const int *__restrict__ row,
                                              int *__restrict__ col) {
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= n) return;
+    __shared__ int skey[4][32];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 4 + w;
+    if (i >= n) return;   // wave-local LDS only: no workgroup barrier below
     const float4 pi = pb[i];
     int cx, cy, cz;
     cell_coords(g, cell_int[i], cx, cy, cz);
@@ -350,47 +367,58 @@ __global__ void __launch_bounds__(256) k_nbr(const float4 *__restrict__ pb, cons
     const int nx = stencil_list(cx, g.nc[0], g.L[0] > 0.f, lx);
     const int ny = stencil_list(cy, g.nc[1], g.L[1] > 0.f, ly);
     const int nz = stencil_list(cz, g.nc[2], g.L[2] > 0.f, lz);
-    // the stencil's keys, sorted (unused slots hold INT_MAX and sort last)
-    int key[27];
-#pragma unroll
-    for (int a = 0; a < 3; a++)
-#pragma unroll
-        for (int b = 0; b < 3; b++)
-#pragma unroll
-            for (int q = 0; q < 3; q++)
-                key[9 * a + 3 * b + q] =
-                    (a < nx && b < ny && q < nz) ? cell_key(g, lx[a], ly[b], lz[q]) : 0x7fffffff;
-#pragma unroll
-    for (int a = 0; a < 26; a++)
-#pragma unroll
-        for (int b = 0; b < 26 - a; b++) {
-            const int lo = min(key[b], key[b + 1]), hi = max(key[b], key[b + 1]);
-            key[b] = lo;
-            key[b + 1] = hi;
-        }
     const int nk = nx * ny * nz;
+    int kq = 0x7fffffff;
+    if (lane < nk) {
+        const int a = lane / (ny * nz), b = (lane / nz) % ny, q = lane % nz;
+        const int x = a == 0 ? lx[0] : (a == 1 ? lx[1] : lx[2]);
+        const int y = b == 0 ? ly[0] : (b == 1 ? ly[1] : ly[2]);
+        const int z = q == 0 ? lz[0] : (q == 1 ? lz[1] : lz[2]);
+        kq = cell_key(g, x, y, z);
+    }
+    int rank = 0;
+    for (int p = 0; p < nk; p++) rank += __builtin_amdgcn_readlane(kq, p) < kq;
+    if (lane < nk) skey[w][rank] = kq;
+    __builtin_amdgcn_wave_barrier();   // the reads below see the whole wave's writes
+    int rb = 0, len = 0;
+    if (lane < nk) {
+        const int k = skey[w][lane];
+        rb = cell_start[k];
+        len = cell_start[k + 1] - rb;
+    }
+    // exclusive prefix of the range lengths over the lanes
+    int pre = len;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+        const int v = __shfl_up(pre, d, 64);
+        if (lane >= d) pre += v;
+    }
+    const int total = __builtin_amdgcn_readlane(pre, nk - 1);
+    pre -= len;
     int c = 0;
     const int o = FILL ? row[i] : 0;
     const unsigned long long below = (1ull << lane) - 1ull;
-    for (int q = 0; q < nk;) {
-        int q1 = q;
-        while (q1 + 1 < nk && key[q1 + 1] == key[q1] + 1) q1++;
-        const int j0 = cell_start[key[q]], j1 = cell_start[key[q1] + 1];
-        q = q1 + 1;
-        for (int jb = j0; jb < j1; jb += 64) {
-            const int j = jb + lane;
-            bool hit = false;
-            if (j < j1 && j != i) {
-                const float4 pj = pb[j];
-                const float dx = fold_once(pj.x - pi.x, g.L[0]);
-                const float dy = fold_once(pj.y - pi.y, g.L[1]);
-                const float dz = fold_once(pj.z - pi.z, g.L[2]);
-                hit = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < cut2;
-            }
-            const unsigned long long m = __ballot(hit);
-            if (FILL && hit) col[o + c + __popcll(m & below)] = j;
-            c += __popcll(m);
+    int r0 = 0;   // first range that can still hold candidates (uniform)
+    for (int cb = 0; cb < total; cb += 64) {
+        while (r0 < nk && __builtin_amdgcn_readlane(pre, r0) + __builtin_amdgcn_readlane(len, r0) <= cb) r0++;
+        const int t = cb + lane;
+        int j = 0;
+        for (int r = r0; r < nk; r++) {
+            const int pr = __builtin_amdgcn_readlane(pre, r);
+            if (pr >= cb + 64) break;
+            if (t >= pr) j = __builtin_amdgcn_readlane(rb, r) + (t - pr);
         }
+        bool hit = false;
+        if (t < total && j != i) {
+            const float4 pj = pb[j];
+            const float dx = fold_once(pj.x - pi.x, g.L[0]);
+            const float dy = fold_once(pj.y - pi.y, g.L[1]);
+            const float dz = fold_once(pj.z - pi.z, g.L[2]);
+            hit = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < cut2;
+        }
+        const unsigned long long m = __ballot(hit);
+        if (FILL && hit) col[o + c + __popcll(m & below)] = j;
+        c += __popcll(m);
     }
     if (!FILL && lane == 0) cnt[i] = c;
 }
@@ -775,7 +803,7 @@ int build_graph(mlp_model *m, mlp_nbr *g, const float *pos, const int32_t *speci
     // perm is filled through iperm's storage as scratch, then sorted in place
     int *perm = g->perm.as<int>();
     k_cell_fill<<<nblk(n, 256), 256, 0, s>>>(cell_user, n, g->cell_start.as<int>(), g->cell_fill.as<int>(), perm);
-    k_cell_sort<<<nblk(nc, 256), 256, 0, s>>>(g->cell_start.as<int>(), nc, perm, flag + 8);
+    k_cell_sort<<<nblk(nc, 4), 256, 0, s>>>(g->cell_start.as<int>(), nc, perm, flag + 8);
     k_gather_build<<<nblk(n, 256), 256, 0, s>>>(perm, n, posw, species, m->S, cell_user,
                                                   g->pos_build.as<float4>(), g->species.as<int>(), cell_int,
                                                   g->iperm.as<int>(), flag);
