@@ -422,6 +422,35 @@ def measure_capacity(mlp, synth, torch, n_cells: int = 110):
     return res
 
 
+def measure_capacity_eq(mlp, synth, torch, kind: str, n_cells: int):
+    """One energy + force evaluation of a large fcc-Al system with an
+    equivariant model at the paper's settings (Allegro: one layer, l_max 3;
+    MACE: two layers, correlation 3, l_max 3), split bf16, skin 2.0 A: the
+    analogue of the paper's "maximum atoms on one GPU" (Table 2) for these
+    models."""
+    import gc
+    s = synth.fcc_crystal(n_cells, a=4.065, sigma=0.1, seed=0)
+    h, w = (synth.make_allegro_weights if kind == "allegro" else synth.make_mace_weights)(1, seed=0)
+    try:
+        model = mlp.Model(h, w, "bf16")
+        d = mlp.System(model, s.pos, s.species, s.box, skin=2.0)
+        st = d.compute(stats=True)["stats"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d.compute()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res = {"atoms": s.n_atoms, "device_GB": round(st["device_bytes"] / 2**30, 2),
+               "ms_per_eval": round(1e3 * el, 1), "n_edges_rc": int(st["n_edges"]),
+               "finite": bool(np.isfinite(d.energy.item()))}
+        del d, model
+    except mlp.MLPError as e:
+        res = {"atoms": s.n_atoms, "error": str(e)[:300]}
+    gc.collect()
+    torch.cuda.empty_cache()
+    return res
+
+
 def measure_allegro(mlp, synth, torch, precision: str, n_cells: int = 49, reps: int = 5):
     """Allegro with one tensor-product layer (the paper's setting for water and
     aluminium: l_max = 3, 8 radial functions, polynomial envelope p = 2,
@@ -613,6 +642,10 @@ def main():
                                for p in [args.precision] + others},
             "al_fcc_nvt_171500": measure_al_nvt(mlp, synth, torch, args.precision),
             "max_atoms_one_gpu_al_fcc_painn_T4_F64": measure_capacity(mlp, synth, torch),
+            # 4 n^3 atoms near the device's capacity at skin 2.0 A (measured
+            # footprints: MACE 259.6 KiB, Allegro 323 KiB per atom)
+            "max_atoms_one_gpu_al_fcc_mace": measure_capacity_eq(mlp, synth, torch, "mace", 64),
+            "max_atoms_one_gpu_al_fcc_allegro": measure_capacity_eq(mlp, synth, torch, "allegro", 59),
             "allegro_al_fcc_470596": {p: measure_allegro(mlp, synth, torch, p) for p in [args.precision, "fp32"]},
             "mace_al_fcc_143748": {p: measure_mace(mlp, synth, torch, p) for p in [args.precision, "fp32"]},
         }
