@@ -161,13 +161,13 @@ struct AOp {
 // flight together.  Starts with a workgroup barrier (LDS may still be read).
 // NT: the number of 16-column tiles computed (the leading ones; a product
 // whose B has at most 16 NT columns needs no more).
-template <int P, int KS, int NT = CT>
+template <int P, int KS, int NT = CT, int G = GW>
 __device__ __forceinline__ void mma_pass(char *lds, const PackedW &B, int n0, int K, const AOp<P, KS> &a,
                                          v4f *acc) {
     constexpr int KC = Stage<P>::KC, LDH = Stage<P>::LDH, LDF = Stage<P>::LDF;
     constexpr int VR = P >= 1 ? KC / 8 : KC / 4;   // 16-byte vectors per row of a stage
-    constexpr int IT = NCH * VR / (64 * GW);
-    static_assert(IT * 64 * GW == NCH * VR, "stage split");
+    constexpr int IT = NCH * VR / (64 * G);
+    static_assert(IT * 64 * G == NCH * VR, "stage split");
     constexpr int EV = P >= 1 ? 8 : 4;             // k-elements per vector
     const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
     v8bf sh[IT], sl[IT];
@@ -176,7 +176,7 @@ __device__ __forceinline__ void mma_pass(char *lds, const PackedW &B, int n0, in
         const int kcl = min(KC, B.Kp - kc);
 #pragma unroll
         for (int it = 0; it < IT; it++) {
-            const int idx = threadIdx.x + 64 * GW * it, n = idx / VR, q = idx % VR;
+            const int idx = threadIdx.x + 64 * G * it, n = idx / VR, q = idx % VR;
             if (EV * q < kcl) {
                 const long go = (long)(n0 + n) * B.Kp + kc + EV * q;
                 if constexpr (P >= 1) {
@@ -192,7 +192,7 @@ __device__ __forceinline__ void mma_pass(char *lds, const PackedW &B, int n0, in
         const int kcl = min(KC, B.Kp - kc);
 #pragma unroll
         for (int it = 0; it < IT; it++) {
-            const int idx = threadIdx.x + 64 * GW * it, n = idx / VR, q = idx % VR;
+            const int idx = threadIdx.x + 64 * G * it, n = idx / VR, q = idx % VR;
             if (EV * q < kcl) {
                 if constexpr (P >= 1) {
                     __bf16 *h = reinterpret_cast<__bf16 *>(lds) + n * LDH + 8 * q;
@@ -509,6 +509,17 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *C1, int ld
 // build instantiates HT = 4, widths up to 64), the input at most 32 wide.  Each wave owns 16 rows; the tile parked in LDS
 // between layers becomes the next product's A operand.
 // ---------------------------------------------------------------------------
+#ifndef MLP_GW
+#define MLP_GW 4
+#endif
+constexpr int MG = MLP_GW;   // waves per workgroup of the fused MLP kernels (rows 16 MG per workgroup;
+                             // eight measured slower than four on MACE's radial MLPs)
+template <int P>
+struct MlpLds {
+    static constexpr int C_BYTES = MG * 16 * LDC * 4;
+    static constexpr int BYTES = GemmLds<P>::B_BYTES > C_BYTES ? GemmLds<P>::B_BYTES : C_BYTES;
+};
+
 template <int P, int HT>
 __device__ __forceinline__ void silu_tile(float *ct, int N) {
     const int lane = threadIdx.x & 63;
@@ -523,13 +534,13 @@ __device__ __forceinline__ void silu_tile(float *ct, int N) {
 }
 
 template <int P, int NH, int HT>
-__global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(64 * MG) __attribute__((amdgpu_waves_per_eu(2)))
 k_mlp_fwd(const float *__restrict__ X, int ldx, EdgeMlp W, float *__restrict__ C, int ldc, int M, const int *Mc) {
-    __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
+    __shared__ __attribute__((aligned(16))) char lds[MlpLds<P>::BYTES];
     if (Mc) M = min(M, *Mc);
-    if ((long)blockIdx.x * GW * 16 >= M) return;   // the whole workgroup leaves
+    if ((long)blockIdx.x * MG * 16 >= M) return;   // the whole workgroup leaves
     const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
-    const long m0 = ((long)blockIdx.x * GW + (threadIdx.x >> 6)) * 16;
+    const long m0 = ((long)blockIdx.x * MG + (threadIdx.x >> 6)) * 16;
     const long arow = m0 + c16;
     const bool rowok = arow < M;
     const float *Xr = X + (rowok ? arow : 0) * (long)ldx;
@@ -547,7 +558,7 @@ k_mlp_fwd(const float *__restrict__ X, int ldx, EdgeMlp W, float *__restrict__ C
         v4f acc[HT];
 #pragma unroll
         for (int t = 0; t < HT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-        mma_pass<P, 1, HT>(lds, W.f[0], 0, K0, x, acc);
+        mma_pass<P, 1, HT, MG>(lds, W.f[0], 0, K0, x, acc);
         float *ct = park_tile<HT>(lds, acc);
         silu_tile<P, HT>(ct, W.f[0].N);
         a.load(g, [&](int k) { return *reinterpret_cast<const v4f *>(ct + c16 * LDC + k); });
@@ -557,7 +568,7 @@ k_mlp_fwd(const float *__restrict__ X, int ldx, EdgeMlp W, float *__restrict__ C
         v4f acc[HT];
 #pragma unroll
         for (int t = 0; t < HT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-        mma_pass<P, KH, HT>(lds, W.f[q], 0, W.f[q].K, a, acc);
+        mma_pass<P, KH, HT, MG>(lds, W.f[q], 0, W.f[q].K, a, acc);
         float *ct = park_tile<HT>(lds, acc);
         silu_tile<P, HT>(ct, W.f[q].N);
         a.load(g, [&](int k) { return *reinterpret_cast<const v4f *>(ct + c16 * LDC + k); });
@@ -568,7 +579,7 @@ k_mlp_fwd(const float *__restrict__ X, int ldx, EdgeMlp W, float *__restrict__ C
         v4f acc[CT];
 #pragma unroll
         for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-        mma_pass<P, KH>(lds, Wo, n0, Wo.K, a, acc);
+        mma_pass<P, KH, CT, MG>(lds, Wo, n0, Wo.K, a, acc);
         const float *ct = park_tile(lds, acc);
 #pragma unroll
         for (int it = 0; it < EIT; it++) {
@@ -588,14 +599,14 @@ __device__ __forceinline__ void dsilu_acc(v4f *acc, const v4f *pre) {
 }
 
 template <int P, int NH, int HT, int KSG>
-__global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(64 * MG) __attribute__((amdgpu_waves_per_eu(2)))
 k_mlp_bwd(const float *__restrict__ X, int ldx, EdgeMlp W, const float *__restrict__ GC, int ldgc, float *GX,
           int ldgx, int add, int M, const int *Mc) {
-    __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
+    __shared__ __attribute__((aligned(16))) char lds[MlpLds<P>::BYTES];
     if (Mc) M = min(M, *Mc);
-    if ((long)blockIdx.x * GW * 16 >= M) return;
+    if ((long)blockIdx.x * MG * 16 >= M) return;
     const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
-    const long m0 = ((long)blockIdx.x * GW + (threadIdx.x >> 6)) * 16;
+    const long m0 = ((long)blockIdx.x * MG + (threadIdx.x >> 6)) * 16;
     const long arow = m0 + c16;
     const bool rowok = arow < M;
     constexpr int KH = HT / 2;
@@ -627,7 +638,7 @@ k_mlp_bwd(const float *__restrict__ X, int ldx, EdgeMlp W, const float *__restri
         });
 #pragma unroll
         for (int t = 0; t < HT; t++) pre[0][t] = v4f{0.f, 0.f, 0.f, 0.f};
-        mma_pass<P, 1, HT>(lds, W.f[0], 0, K0, x, pre[0]);
+        mma_pass<P, 1, HT, MG>(lds, W.f[0], 0, K0, x, pre[0]);
     }
 #pragma unroll
     for (int q = 1; q < NH; q++) {
@@ -636,13 +647,13 @@ k_mlp_bwd(const float *__restrict__ X, int ldx, EdgeMlp W, const float *__restri
         a.load(g, [&](int k) { return *reinterpret_cast<const v4f *>(ct + c16 * LDC + k); });
 #pragma unroll
         for (int t = 0; t < HT; t++) pre[q][t] = v4f{0.f, 0.f, 0.f, 0.f};
-        mma_pass<P, KH, HT>(lds, W.f[q], 0, W.f[q].K, a, pre[q]);
+        mma_pass<P, KH, HT, MG>(lds, W.f[q], 0, W.f[q].K, a, pre[q]);
     }
     // dE/dh of the last hidden layer through the output matrix, then down
     v4f acc[HT];
 #pragma unroll
     for (int t = 0; t < HT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-    mma_pass<P, KSG, HT>(lds, W.a[NH], 0, W.a[NH].K, ga, acc);
+    mma_pass<P, KSG, HT, MG>(lds, W.a[NH], 0, W.a[NH].K, ga, acc);
     dsilu_acc<HT>(acc, pre[NH - 1]);
 #pragma unroll
     for (int q = NH - 1; q >= 1; q--) {
@@ -651,7 +662,7 @@ k_mlp_bwd(const float *__restrict__ X, int ldx, EdgeMlp W, const float *__restri
         a.load(g, [&](int k) { return *reinterpret_cast<const v4f *>(ct + c16 * LDC + k); });
 #pragma unroll
         for (int t = 0; t < HT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-        mma_pass<P, KH, HT>(lds, W.a[q], 0, W.a[q].K, a, acc);
+        mma_pass<P, KH, HT, MG>(lds, W.a[q], 0, W.a[q].K, a, acc);
         dsilu_acc<HT>(acc, pre[q - 1]);
     }
     // dE/dX = dE/dP_0 W_0 (at most 16 columns)
@@ -659,7 +670,7 @@ k_mlp_bwd(const float *__restrict__ X, int ldx, EdgeMlp W, const float *__restri
     __builtin_amdgcn_wave_barrier();
     a.load(g, [&](int k) { return *reinterpret_cast<const v4f *>(ct + c16 * LDC + k); });
     v4f gx[1] = {v4f{0.f, 0.f, 0.f, 0.f}};
-    mma_pass<P, KH, 1>(lds, W.a[0], 0, W.a[0].K, a, gx);
+    mma_pass<P, KH, 1, MG>(lds, W.a[0], 0, W.a[0].K, a, gx);
     const float *cx = park_tile<1>(lds, gx);
     const int NX = W.a[0].N;
     // 16 rows x 16 columns: lane (row, 4-column group) = (lane / 4, lane % 4)
@@ -676,16 +687,16 @@ k_mlp_bwd(const float *__restrict__ X, int ldx, EdgeMlp W, const float *__restri
 template <int P, int NH, int HT>
 static int mlp_fwd_launch(hipStream_t s, const EdgeMlp &W, const float *X, int ldx, float *C, int ldc, int M,
                           const int *Mc) {
-    const unsigned bx = (unsigned)((M + 16 * GW - 1) / (16 * GW));
-    k_mlp_fwd<P, NH, HT><<<bx, 64 * GW, 0, s>>>(X, ldx, W, C, ldc, M, Mc);
+    const unsigned bx = (unsigned)((M + 16 * MG - 1) / (16 * MG));
+    k_mlp_fwd<P, NH, HT><<<bx, 64 * MG, 0, s>>>(X, ldx, W, C, ldc, M, Mc);
     return 0;
 }
 
 template <int P, int NH, int HT, int KSG>
 static int mlp_bwd_launch(hipStream_t s, const EdgeMlp &W, const float *X, int ldx, const float *GC, int ldgc,
                           float *GX, int ldgx, bool add, int M, const int *Mc) {
-    const unsigned bx = (unsigned)((M + 16 * GW - 1) / (16 * GW));
-    k_mlp_bwd<P, NH, HT, KSG><<<bx, 64 * GW, 0, s>>>(X, ldx, W, GC, ldgc, GX, ldgx, add ? 1 : 0, M, Mc);
+    const unsigned bx = (unsigned)((M + 16 * MG - 1) / (16 * MG));
+    k_mlp_bwd<P, NH, HT, KSG><<<bx, 64 * MG, 0, s>>>(X, ldx, W, GC, ldgc, GX, ldgx, add ? 1 : 0, M, Mc);
     return 0;
 }
 
