@@ -60,6 +60,23 @@ def test_noalloc_equals_entry_point_two_calls(mlp, oracle, precision):
         del d
 
 
+@pytest.mark.parametrize("kind", ["allegro", "mace"])
+def test_noalloc_equivariant_models_two_calls(mlp, kind):
+    # the Allegro and MACE paths through the allocation-free entry point: a
+    # 192-atom water box, then a smaller 108-atom crystal on the same GPU
+    import torch
+    make = synth.make_allegro_weights if kind == "allegro" else synth.make_mace_weights
+    hdr, w = make(2, seed=4, bias_scale=0.1)
+    model = mlp.Model(hdr, w, "fp32")
+    for s in (synth.water_box(4, 3.105, seed=3), synth.fcc_crystal(3, seed=5, sigma=0.1)):
+        d = mlp.System(model, s.pos, s.species, s.box, skin=1.0)
+        print(f"[case] noalloc {kind} n={s.n_atoms}", flush=True)
+        ref, got = _both(mlp, d)
+        for a, b, name in zip(ref, got, ("energy", "forces", "atom energies")):
+            assert torch.equal(a, b), f"{kind}: {name} differ from mlp_energy_forces (n={s.n_atoms})"
+        del d
+
+
 def test_noalloc_ghost_domain_fold(mlp, oracle):
     import torch
     hdr, w = synth.make_weights(32, 8, 2, 1, seed=3)
