@@ -137,14 +137,29 @@ struct AlChan {
     }
 };
 
+// The edge's 16 harmonics (the same address in every lane of the wave, so
+// they come through the scalar cache) and the lane's own components
+// ym[m] = Y_(l, m) for m < 2l + 1, zero above.
+__device__ __forceinline__ void al_lane_harm(const float *__restrict__ ye, int l, float *ym) {
+    float y[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) y[q] = ye[q];
+#pragma unroll
+    for (int m = 0; m < 7; m++) {
+        const float a = m < 1 ? y[m] : 0.f, b = m < 3 ? y[1 + m] : 0.f, c = m < 5 ? y[4 + m] : 0.f, dd = y[9 + m];
+        ym[m] = l == 0 ? a : (l == 1 ? b : (l == 2 ? c : dd));
+    }
+}
+
 // The environment of each atom and the scalar outputs of its edges.  One
-// wave per atom, lane = channel: pass 1 sums env[c][m] over the atom's
-// edges, pass 2 contracts each edge's harmonics against it.
+// wave per atom (its index made wave-uniform, so the edge loop and the
+// harmonic loads are scalar), lane = channel: pass 1 sums env[c][m] over the
+// atom's edges, pass 2 contracts each edge's harmonics against it.
 __global__ void __launch_bounds__(256) k_al_tp(const int *__restrict__ rowc, int n, AlDims d,
                                                const float *__restrict__ Y, const float *__restrict__ WV,
                                                float *__restrict__ ENV, float *__restrict__ LIN) {
     const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (i >= n) return;
     const int NC = d.NC, ldwv = 2 * d.NC, ldl = d.D + d.NC;
     if (lane >= NC) return;
@@ -155,10 +170,10 @@ __global__ void __launch_bounds__(256) k_al_tp(const int *__restrict__ rowc, int
 #pragma unroll 4
     for (int e = e0; e < e1; e++) {
         const float we = WV[(long)e * ldwv + NC + lane];
-        const float *ye = Y + (long)e * 16 + ch.m0;
+        float ym[7];
+        al_lane_harm(Y + (long)e * 16, ch.l, ym);
 #pragma unroll
-        for (int m = 0; m < 7; m++)
-            if (m < ch.nm) env[m] = fmaf(we, ye[m], env[m]);
+        for (int m = 0; m < 7; m++) env[m] = fmaf(we, ym[m], env[m]);
     }
     float *en = ENV + ((long)i * NC + lane) * 8;
 #pragma unroll
@@ -168,11 +183,11 @@ __global__ void __launch_bounds__(256) k_al_tp(const int *__restrict__ rowc, int
     }
 #pragma unroll 4
     for (int e = e0; e < e1; e++) {
-        const float *ye = Y + (long)e * 16 + ch.m0;
+        float ym[7];
+        al_lane_harm(Y + (long)e * 16, ch.l, ym);
         float dot = 0.f;
 #pragma unroll
-        for (int m = 0; m < 7; m++)
-            if (m < ch.nm) dot = fmaf(ye[m], env[m], dot);
+        for (int m = 0; m < 7; m++) dot = fmaf(ym[m], env[m], dot);
         LIN[(long)e * ldl + d.D + lane] = WV[(long)e * ldwv + lane] * ch.inv * dot;
     }
 }
@@ -281,13 +296,62 @@ __global__ void k_al_x1_bwd(const int *__restrict__ cnt, int D, const float *__r
     if (e < ne && q == 0) GU[e] += r2 * part;
 }
 
-// Adjoint of the tensor-product contraction and of the environment, one
-// wave per atom, lane = channel.  With t = dE/dS_e[c] / (2l+1):
+template <int CTRL>
+__device__ __forceinline__ float al_dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// The sums over the channels of each degree of q[m] (m < 2l + 1), stored as
+// GY[slot l^2 + m] (add: accumulate).  STD: the channel layout (32, 16, 8, 8)
+// of degrees 0..3 over the 64 lanes, summed by DPP exchanges (8-lane groups
+// by quad permutations and the half-row mirror, 16-lane rows by a row
+// rotation, the two rows of degree 0 by one cross-row exchange); otherwise
+// through the wave's LDS rows.
+template <bool STD>
+__device__ __forceinline__ void al_channel_sums(const float *q, int lane, int ny, int kc0, int kc1, int km,
+                                                float (*red)[8], float *__restrict__ gy, bool add) {
+    if constexpr (STD) {
+        float v8[7], v16[3], v32 = 0.f;
+#pragma unroll
+        for (int m = 0; m < 7; m++) {
+            float v = q[m];
+            v += al_dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+            v += al_dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+            v += al_dpp<0x141>(v);   // row_half_mirror: the other quad of the 8
+            v8[m] = v;
+        }
+#pragma unroll
+        for (int m = 0; m < 3; m++) v16[m] = v8[m] + al_dpp<0x128>(v8[m]);   // row_ror:8
+        v32 = v16[0] + __shfl_xor(v16[0], 16, 64);
+        if (lane == 0) gy[0] = add ? gy[0] + v32 : v32;
+        if (lane == 32)
+#pragma unroll
+            for (int m = 0; m < 3; m++) gy[1 + m] = add ? gy[1 + m] + v16[m] : v16[m];
+        if (lane == 48)
+#pragma unroll
+            for (int m = 0; m < 5; m++) gy[4 + m] = add ? gy[4 + m] + v8[m] : v8[m];
+        if (lane == 56)
+#pragma unroll
+            for (int m = 0; m < 7; m++) gy[9 + m] = add ? gy[9 + m] + v8[m] : v8[m];
+    } else {
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int m = 0; m < 7; m++) red[lane][m] = q[m];
+        __builtin_amdgcn_wave_barrier();
+        if (lane < ny) {
+            float s = 0.f;
+            for (int c = kc0; c < kc1; c++) s += red[c][km];
+            gy[lane] = add ? gy[lane] + s : s;
+        }
+    }
+}
+
+// Adjoint of k_al_tp, one wave per atom, lane = channel.  With t = dE/dS_e:
 //   pass 1: dE/dw0_e[c] = t Y_e . env[c],  genv[c] += t w0_e[c] Y_e,
 //           dE/dY_e[m] += sum_c t w0_e[c] env[c][m];   also X <- X + GLIN[:, :D]
 //   pass 2 (genv scaled by nu): dE/dwe_e[c] = genv[c] . Y_e,
 //           dE/dY_e[m] += sum_c genv[c][m] we_e[c]
-// The sums over the channels of one degree go through the wave's LDS rows.
+template <bool STD>
 __global__ void __launch_bounds__(256) k_al_tp_bwd(const int *__restrict__ rowc, int n, AlDims d,
                                                    const float *__restrict__ Y, const float *__restrict__ WV,
                                                    const float *__restrict__ ENV, const float *__restrict__ GLIN,
@@ -295,13 +359,13 @@ __global__ void __launch_bounds__(256) k_al_tp_bwd(const int *__restrict__ rowc,
                                                    float *__restrict__ GY) {
     __shared__ float red[4][64][8];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i = blockIdx.x * 4 + w;
+    const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
     if (i >= n) return;
     const int NC = d.NC, ldwv = 2 * d.NC, ldl = d.D + d.NC, D = d.D;
     const bool act = lane < NC;
     const AlChan ch(act ? lane : 0, d);
-    // the harmonic a lane sums in the reductions (lanes 0..15): degree, order,
-    // and the channel range of that degree
+    // the harmonic a lane sums in the LDS reductions (lanes 0..15): degree,
+    // order, and the channel range of that degree
     int kl = 0, kc0 = 0, kc1 = 0;
     {
         int off = 0;
@@ -325,60 +389,42 @@ __global__ void __launch_bounds__(256) k_al_tp_bwd(const int *__restrict__ rowc,
     const int e0 = rowc[i], e1 = rowc[i + 1];
 #pragma unroll 2
     for (int e = e0; e < e1; e++) {
-        float q[7];
+        float q[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float ym[7];
+        al_lane_harm(Y + (long)e * 16, ch.l, ym);
         if (act) {
-            const float *ye = Y + (long)e * 16 + ch.m0;
             const float t = GLIN[(long)e * ldl + D + lane] * ch.inv;
             const float w0 = WV[(long)e * ldwv + lane];
             float dot = 0.f;
 #pragma unroll
             for (int m = 0; m < 7; m++) {
-                const float ym = m < ch.nm ? ye[m] : 0.f;
-                dot = fmaf(ym, env[m], dot);
-                genv[m] = fmaf(t * w0, ym, genv[m]);
+                dot = fmaf(ym[m], env[m], dot);
+                genv[m] = fmaf(t * w0, ym[m], genv[m]);
                 q[m] = t * w0 * env[m];
             }
             GWV[(long)e * ldwv + lane] = t * dot;
         }
         for (int f = lane; f < D; f += 64) X[(long)e * D + f] += GLIN[(long)e * ldl + f];
-        __builtin_amdgcn_wave_barrier();
-        if (act)
-#pragma unroll
-            for (int m = 0; m < 7; m++) red[w][lane][m] = q[m];
-        __builtin_amdgcn_wave_barrier();
-        if (lane < ny) {
-            float s = 0.f;
-            for (int c = kc0; c < kc1; c++) s += red[w][c][km];
-            GY[(long)e * 16 + lane] = s;
-        }
+        al_channel_sums<STD>(q, lane, ny, kc0, kc1, km, red[w], GY + (long)e * 16, false);
     }
 #pragma unroll
     for (int m = 0; m < 7; m++) genv[m] *= d.nu;
 #pragma unroll 2
     for (int e = e0; e < e1; e++) {
-        float q[7];
+        float q[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float ym[7];
+        al_lane_harm(Y + (long)e * 16, ch.l, ym);
         if (act) {
-            const float *ye = Y + (long)e * 16 + ch.m0;
             const float we = WV[(long)e * ldwv + NC + lane];
             float dot = 0.f;
 #pragma unroll
             for (int m = 0; m < 7; m++) {
-                const float ym = m < ch.nm ? ye[m] : 0.f;
-                dot = fmaf(genv[m], ym, dot);
+                dot = fmaf(genv[m], ym[m], dot);
                 q[m] = genv[m] * we;
             }
             GWV[(long)e * ldwv + NC + lane] = dot;
         }
-        __builtin_amdgcn_wave_barrier();
-        if (act)
-#pragma unroll
-            for (int m = 0; m < 7; m++) red[w][lane][m] = q[m];
-        __builtin_amdgcn_wave_barrier();
-        if (lane < ny) {
-            float s = 0.f;
-            for (int c = kc0; c < kc1; c++) s += red[w][c][km];
-            GY[(long)e * 16 + lane] += s;
-        }
+        al_channel_sums<STD>(q, lane, ny, kc0, kc1, km, red[w], GY + (long)e * 16, true);
     }
 }
 
@@ -746,7 +792,9 @@ int allegro_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, fl
         ProfScope ps(PK_GEMM, s);
         if (node_gemm_chain(s, P, c)) return fail(-5, "allegro latent adjoint GEMM failed");
     }
-    k_al_tp_bwd<<<nblk(n, 4), 256, 0, s>>>(rowc, n, d, Y, WV, ENV, LIN, X1, GWV, GY);
+    const bool std_layout = d.lmax == 3 && d.ch[0] == 32 && d.ch[1] == 16 && d.ch[2] == 8 && d.ch[3] == 8;
+    if (std_layout) k_al_tp_bwd<true><<<nblk(n, 4), 256, 0, s>>>(rowc, n, d, Y, WV, ENV, LIN, X1, GWV, GY);
+    else k_al_tp_bwd<false><<<nblk(n, 4), 256, 0, s>>>(rowc, n, d, Y, WV, ENV, LIN, X1, GWV, GY);
     if ((rc = gm(s, P, GE_ADD, GWV, 2 * d.NC, a.aVE, X1, D, ne, cnt, nullptr, nullptr, 0, X1, D))) return rc;
     k_al_x0_bwd<<<nblk(ne * 16, 256), 256, 0, s>>>(cnt, D, u, X1, Yo, GU);
     // the two-body MLP in reverse: dE/dy in Yo, pre-activation gradients over the activations
