@@ -26,7 +26,11 @@ struct MsgArgs {
     // are picked by species (device int32 per atom).
     bool layer0;
     const int *species;
+    // MSG_QUEUE_INTS device ints, zero on entry, used by this launch alone:
+    // the counters from which the waves take their atoms
+    int *queue;
 };
+constexpr int MSG_QUEUE_INTS = 2048;
 
 // Return 0, -1 (unsupported F, K) or -5 (launch error).
 int msg_forward(hipStream_t st, int precision, int F, int K, const MsgArgs &a);
@@ -60,10 +64,14 @@ __host__ __device__ constexpr int l0_block(int K) { return (K + 1 + 7) / 8 * 8; 
 int msg_l0_basis_sums(hipStream_t st, int K, int S, const L0Args &a);
 int msg_l0_edge_sums(hipStream_t st, int K, int S, const L0Args &a);
 
-// Feature passes of the adjoint (edge-sum slots per layer).
+// Feature passes of the adjoint.
 int msg_passes(int F);
+// Edge-sum slots of one evaluation: one per layer after the first (its
+// passes are summed in the kernel), then the first layer's (one when it is
+// factorised, else one per pass); slot q at S + q * s_stride.
+int msg_slots(int F, int T, bool l0_factorised);
 // G[e] over the pruned edges (count rowc[n], at most ne_max), assembled from
-// the nslot slots of S (slot q at S + q * s_stride; one per layer and pass).
+// the nslot slots of S (slot q at S + q * s_stride).
 int msg_assemble_G(hipStream_t st, const int *rowc, int n, long ne_max, const float4 *geom, const float4 *S,
                    long s_stride, int nslot, float4 *G);
 

@@ -194,20 +194,27 @@ struct Pass {
 
 // LDS image of the pass's rows of A' = [c | A]: local row q W + f holds the
 // global row q F + p W + f (part q = 0, 1, 2), in the layout the A operand
-// reads (reduction index contiguous).
-template <int P, int F, int K, int WM>
+// reads (reduction index contiguous).  Rows are padded against bank
+// conflicts (8 bf16 or one float), or, with SW (bf16 only), unpadded and
+// swizzled: a 64-byte row is four 16-byte pieces of 8 slots, and piece h of
+// row r sits at position h ^ wswz(r), which puts the 16 rows that one
+// A-operand read touches (same piece, rows 16 t .. 16 t + 15) on distinct
+// 16-byte bank groups for 32 or 64 banks, in 20 % less LDS.
+template <int P, int F, int K, int WM, bool SW = false>
 struct WStage {
+    static constexpr bool SWZ = SW && P >= 1;
     static constexpr int KP = Basis<P, K>::KP;
     static constexpr int ROWS = 3 * Pass<F, WM>::W;
-    static constexpr int LD = P >= 1 ? KP + 8 : KP + 1;          // padded row stride (elements)
-    static constexpr int ELEMS = ROWS * LD * (P == 2 ? 2 : 1);   // split mode: hi table, then lo table
+    static constexpr int LD = SWZ ? KP : (P >= 1 ? KP + 8 : KP + 1);   // row stride (elements)
+    static constexpr int ELEMS = ROWS * LD * (P == 2 ? 2 : 1);         // split mode: hi table, then lo table
     static constexpr int BYTES = ELEMS * (P >= 1 ? 2 : 4);
 };
+__device__ __forceinline__ int wswz(int r) { return (((r >> 2) & 1) << 1) | (((r >> 1) ^ (r >> 3)) & 1); }
 
-template <int P, int F, int K, int WM>
+template <int P, int F, int K, int WM, bool SW = false>
 __device__ __forceinline__ void stage_pass(const float *__restrict__ A, const float *__restrict__ c, int p,
                                            void *lds) {
-    using WS = WStage<P, F, K, WM>;
+    using WS = WStage<P, F, K, WM, SW>;
     constexpr int W = Pass<F, WM>::W;
     for (int idx = threadIdx.x; idx < WS::ROWS * WS::KP; idx += blockDim.x) {
         const int lr = idx / WS::KP, k = idx % WS::KP;
@@ -217,8 +224,9 @@ __device__ __forceinline__ void stage_pass(const float *__restrict__ A, const fl
         else if (k <= K) v = A[(long)f * K + (k - 1)];
         if (P >= 1) {
             const __bf16 h = (__bf16)v;
-            reinterpret_cast<__bf16 *>(lds)[lr * WS::LD + k] = h;
-            if (P == 2) reinterpret_cast<__bf16 *>(lds)[WS::ROWS * WS::LD + lr * WS::LD + k] = (__bf16)(v - (float)h);
+            const int at = lr * WS::LD + (WS::SWZ ? ((((k >> 3) ^ wswz(lr)) << 3) | (k & 7)) : k);
+            reinterpret_cast<__bf16 *>(lds)[at] = h;
+            if (P == 2) reinterpret_cast<__bf16 *>(lds)[WS::ROWS * WS::LD + at] = (__bf16)(v - (float)h);
         } else {
             reinterpret_cast<float *>(lds)[lr * WS::LD + k] = v;
         }
@@ -228,16 +236,19 @@ __device__ __forceinline__ void stage_pass(const float *__restrict__ A, const fl
 
 // Filter values of local tile t (rows 16t .. 16t+15): lane (e, g) receives
 // features 4g .. 4g+3 of the tile for its edge e.
-template <int P, int F, int K, int WM>
+template <int P, int F, int K, int WM, bool SW = false>
 __device__ __forceinline__ v4f filter_tile(const void *lds, int t, const BOp<P, K> &b, int lane) {
-    using WS = WStage<P, F, K, WM>;
+    using WS = WStage<P, F, K, WM, SW>;
     v4f acc = {0.f, 0.f, 0.f, 0.f};
     const int row = 16 * t + (lane & 15), g = lane >> 4;
+    // the swizzled piece position depends on the lane only (16 t leaves bits
+    // 1-3 of the row alone)
+    const int col = 8 * (WS::SWZ ? g ^ wswz(lane & 15) : g);
     if constexpr (P == 1) {
-        const v8bf a = *reinterpret_cast<const v8bf *>(reinterpret_cast<const __bf16 *>(lds) + row * WS::LD + 8 * g);
+        const v8bf a = *reinterpret_cast<const v8bf *>(reinterpret_cast<const __bf16 *>(lds) + row * WS::LD + col);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.v, acc, 0, 0, 0);
     } else if constexpr (P == 2) {
-        const __bf16 *t0 = reinterpret_cast<const __bf16 *>(lds) + row * WS::LD + 8 * g;
+        const __bf16 *t0 = reinterpret_cast<const __bf16 *>(lds) + row * WS::LD + col;
         const v8bf a = *reinterpret_cast<const v8bf *>(t0);
         const v8bf al = *reinterpret_cast<const v8bf *>(t0 + WS::ROWS * WS::LD);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b.v, acc, 0, 0, 0);
@@ -339,25 +350,46 @@ constexpr int MW = MSG_MW;   // waves per workgroup
 #define BWD_WAVES 2
 #endif
 
-// Atoms handled by this wave.  Workgroups are dispatched round-robin over the
-// XCDs, each with its own L2; with gridDim.x a multiple of 8, XCD x runs the
-// workgroups with blockIdx.x % 8 == x and gets the contiguous slice
-// [x n / 8, (x+1) n / 8) of the cell-sorted atoms; the waves of its workgroups
-// interleave over that slice, so neighbour rows gathered by one XCD stay in
-// its L2.  The slices partition [0, n) whatever the grid size.
-struct XcdRange {
-    int first, end, stride;
-    __device__ __forceinline__ explicit XcdRange(int n) {
+// Atoms for each wave, from a work queue per XCD slice.  Workgroups are
+// dispatched round-robin over the XCDs, each with its own L2; with gridDim.x
+// a multiple of 8, XCD x runs the workgroups with blockIdx.x % 8 == x and
+// works on the contiguous slice [x n / 8, (x+1) n / 8) of the cell-sorted
+// atoms.  The waves of a slice take its atoms in order, MSG_QB at a time, from
+// one counter, so the atoms in flight on an XCD are always a compact window of
+// the slice, whose neighbour rows the XCD's L2 holds (with a fixed
+// interleaving the waves drift apart over the slice and the rows in use
+// outgrow the L2).  Each counter has its own 128-byte line and starts at
+// zero.  The slices partition [0, n) whatever the grid size; every wave leaves
+// its loop once its slice's counter has passed the end.
+#ifndef MSG_QB
+#define MSG_QB 1
+#endif
+struct AtomQueue {
+    int lo, hi;
+    int *ctr;
+    __device__ __forceinline__ AtomQueue(int n, int *queue, int pass) {
         const int nx = gridDim.x < 8 ? (int)gridDim.x : 8;
-        const int x = blockIdx.x % nx, b = blockIdx.x / nx;
-        const int nb = ((int)gridDim.x - x + nx - 1) / nx;   // workgroups with blockIdx % nx == x
-        const int lo = (int)((long)n * x / nx), hi = (int)((long)n * (x + 1) / nx);
-        const int wpb = blockDim.x >> 6;
-        first = lo + b * wpb + (int)(threadIdx.x >> 6);
-        end = hi;
-        stride = nb * wpb;
+        const int x = blockIdx.x % nx;
+        lo = (int)((long)n * x / nx);
+        hi = (int)((long)n * (x + 1) / nx);
+        ctr = queue + (pass * 8 + x) * 32;
+    }
+    // first atom of the wave's next batch (wave-uniform), >= hi once the slice is drained
+    __device__ __forceinline__ int take() const {
+        int t = 0;
+        if ((threadIdx.x & 63) == 0)
+            t = __hip_atomic_fetch_add(ctr, MSG_QB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return lo + __builtin_amdgcn_readfirstlane(t);
     }
 };
+// for (each atom I of the wave, in queue order)
+#if MSG_QB == 1
+#define MSG_ATOMS(Q, I) for (int I = (Q).take(); I < (Q).hi; I = (Q).take())
+#else
+#define MSG_ATOMS(Q, I)                                           \
+    for (int I##_b = (Q).take(); I##_b < (Q).hi; I##_b = (Q).take()) \
+        for (int I = I##_b; I < I##_b + MSG_QB && I < (Q).hi; I++)
+#endif
 
 // ---------------------------------------------------------------------------
 // Forward message pass, one feature pass (blockIdx.y) per workgroup.
@@ -370,7 +402,7 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
                                                      const float *__restrict__ Aw,
                                                      const float *__restrict__ cw, float rc,
                                                      const int8_t *__restrict__ hop, int hop_max,
-                                                     const int *__restrict__ zsp,
+                                                     const int *__restrict__ zsp, int *__restrict__ queue,
                                                      float *__restrict__ sn, float *__restrict__ v1) {
     constexpr int WM = FWD_W;
     constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F, WM>::W, TU = Pass<F, WM>::TU;
@@ -384,9 +416,9 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
     const int fo = p * W + 4 * g;   // first feature of this lane (tile u adds 16 u)
     const Xch xc(g, e);
     v4f(*xw)[64] = xch[threadIdx.x >> 6];
-    const XcdRange xr(n);
+    const AtomQueue aq(n, queue, p);
     const float pirc = 3.14159265358979f / rc;
-    for (int i = xr.first; i < xr.end; i += xr.stride) {
+    MSG_ATOMS(aq, i) {
         const int e0 = rowc[i], e1 = rowc[i + 1];
         const int deg = hop[i] <= hop_max ? e1 - e0 : 0;
         v4f as[TU], av[3][TU];
@@ -498,172 +530,278 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint of the message pass, one feature pass (blockIdx.y) per workgroup.
+// Adjoint of the message pass.
 // Per chunk of 16 in-edges (j <- i) of the source atom j: the filter tiles and
 // their radial derivatives on MFMA, the destinations' gradient pieces
 // gathered per lane, dE/dphi_j and dE/dv_j accumulated in registers, and the
 // edge sums S = (dE/dr, dE/drhat) of the pass stored in the pass's slot.
+//
+// Two arrangements of the feature passes:
+//   * PIW (the layers after the first, more than one pass): every wave runs
+//     all passes of its atom, one after the other, with the weight images of
+//     every pass in LDS.  The radial basis and its derivative of a chunk, in
+//     the MFMA operand form (the split conversion included), are evaluated
+//     in the first pass and kept in the wave's LDS for the later ones (for
+//     the first BWD_CACHE chunks of the atom; later chunks are re-evaluated).
+//     The edge sums of the passes are added up in the wave, in pass order
+//     (in LDS for the cached chunks, in the slot itself for the others: the
+//     lane that adds is the lane that stored), so the layer has one slot.
+//     The workgroups fill the GPU once (one per compute unit).
+//   * otherwise blockIdx.y is the pass and the basis is evaluated per pass;
+//     pass p stores its sums in slot p.
 // ---------------------------------------------------------------------------
-template <int P, int F, int K, bool V0>
-__global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0 ? BWD_WAVES0 : BWD_WAVES))) k_msg_bwd(const int *__restrict__ rowc, const int *__restrict__ colc,
+#ifndef BWD_PIW_WAVES
+#define BWD_PIW_WAVES 8
+#endif
+#ifndef BWD_CACHE
+#define BWD_CACHE 3
+#endif
+
+// The two B operands of a chunk as 16-byte words per lane (FP32 mode: 4-byte
+// words), stored lane-contiguously so that the writes and reads are
+// conflict-free.  Each lane reads back only what it wrote itself.
+template <int P, int K>
+struct BCache {
+    static constexpr int WORDS = P >= 1 ? (P == 2 ? 4 : 2) : 2 * Basis<P, K>::NS;   // words per lane
+    static constexpr int WBYTES = P >= 1 ? 16 : 4;
+    static constexpr int BYTES = WORDS * WBYTES * 64;                                 // per chunk and wave
+};
+template <int P, int K>
+__device__ __forceinline__ void bcache_put(char *slot, int lane, const BOp<P, K> &b, const BOp<P, K> &d) {
+    if constexpr (P == 2) {
+        v4f *q = reinterpret_cast<v4f *>(slot) + lane;
+        q[0] = __builtin_bit_cast(v4f, b.v);
+        q[64] = __builtin_bit_cast(v4f, b.lo);
+        q[128] = __builtin_bit_cast(v4f, d.v);
+        q[192] = __builtin_bit_cast(v4f, d.lo);
+    } else if constexpr (P == 1) {
+        v4f *q = reinterpret_cast<v4f *>(slot) + lane;
+        q[0] = __builtin_bit_cast(v4f, b.v);
+        q[64] = __builtin_bit_cast(v4f, d.v);
+    } else {
+        float *q = reinterpret_cast<float *>(slot) + lane;
+#pragma unroll
+        for (int s = 0; s < Basis<P, K>::NS; s++) {
+            q[64 * s] = b.v[s];
+            q[64 * (Basis<P, K>::NS + s)] = d.v[s];
+        }
+    }
+}
+template <int P, int K>
+__device__ __forceinline__ void bcache_get(const char *slot, int lane, BOp<P, K> &b, BOp<P, K> &d) {
+    if constexpr (P == 2) {
+        const v4f *q = reinterpret_cast<const v4f *>(slot) + lane;
+        b.v = __builtin_bit_cast(v8bf, q[0]);
+        b.lo = __builtin_bit_cast(v8bf, q[64]);
+        d.v = __builtin_bit_cast(v8bf, q[128]);
+        d.lo = __builtin_bit_cast(v8bf, q[192]);
+    } else if constexpr (P == 1) {
+        const v4f *q = reinterpret_cast<const v4f *>(slot) + lane;
+        b.v = __builtin_bit_cast(v8bf, q[0]);
+        d.v = __builtin_bit_cast(v8bf, q[64]);
+    } else {
+        const float *q = reinterpret_cast<const float *>(slot) + lane;
+#pragma unroll
+        for (int s = 0; s < Basis<P, K>::NS; s++) {
+            b.v[s] = q[64 * s];
+            d.v[s] = q[64 * (Basis<P, K>::NS + s)];
+        }
+    }
+}
+
+template <int P, int F, int K, bool V0, bool PIW>
+__global__ void __launch_bounds__(64 * (PIW ? BWD_PIW_WAVES : MW)) __attribute__((amdgpu_waves_per_eu(V0 ? BWD_WAVES0 : BWD_WAVES))) k_msg_bwd(const int *__restrict__ rowc, const int *__restrict__ colc,
                                                      const float4 *__restrict__ geom, int n,
                                                      const float *__restrict__ phi, const float *__restrict__ v,
                                                      const float *__restrict__ gs1, const float *__restrict__ gv1,
                                                      const float *__restrict__ Aw, const float *__restrict__ cw,
                                                      float rc, const int8_t *__restrict__ hop, int hop_max,
-                                                     const int *__restrict__ zsp,
+                                                     const int *__restrict__ zsp, int *__restrict__ queue,
                                                      float *__restrict__ gv_in, float *__restrict__ gphi,
                                                      float4 *__restrict__ S, long s_stride) {
     constexpr int WM = BWD_W;
     constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F, WM>::W, TU = Pass<F, WM>::TU;
-    __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K, WM>::BYTES];
-    __shared__ v4f xch[MW][4][64];
-    const int p = blockIdx.y;
-    stage_pass<P, F, K, WM>(Aw, cw, p, lds);
-    float4 *Sp = S + (long)p * s_stride;
+    constexpr int NW = PIW ? BWD_PIW_WAVES : MW;        // waves per workgroup
+    constexpr int NPL = PIW ? Pass<F, WM>::N : 1;       // passes per workgroup
+    constexpr int NC = PIW ? BWD_CACHE : 0;             // chunks whose basis a wave keeps
+    constexpr int WB = WStage<P, F, K, WM, PIW>::BYTES;
+    constexpr int CB = BCache<P, K>::BYTES;
+    static_assert(!PIW || !V0, "the first layer runs one pass per workgroup");
+    __shared__ __attribute__((aligned(16))) char lds[NPL * WB];
+    __shared__ v4f xch[NW][PIW ? 1 : 4][64];
+    __shared__ __attribute__((aligned(16))) char bcache[PIW ? NW * NC * CB : 16];
+    __shared__ float4 sacc[PIW ? NW : 1][PIW ? NC : 1][16];   // edge sums of the cached chunks
+#pragma unroll 1
+    for (int q = 0; q < NPL; q++) stage_pass<P, F, K, WM, PIW>(Aw, cw, PIW ? q : (int)blockIdx.y, lds + q * WB);
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
-    const int fo = p * W + 4 * g;
     const Xch xc(g, e);
     v4f(*xw)[64] = xch[threadIdx.x >> 6];
-    const XcdRange xr(n);
+    char *bc = bcache + (PIW ? (threadIdx.x >> 6) * NC * CB : 0);
+    const AtomQueue aq(n, queue, PIW ? 0 : (int)blockIdx.y);
     const float pirc = 3.14159265358979f / rc;
-    for (int j = xr.first; j < xr.end; j += xr.stride) {
+    MSG_ATOMS(aq, j) {
         const int e0 = rowc[j], e1 = rowc[j + 1];
         const int deg = hop[j] <= hop_max ? e1 - e0 : 0;
-        // first layer: v_j = 0 and no node gradient, so phi_vv, v_j, dE/dphi_j
-        // and dE/dv_j drop out and only the edge sums remain.
-        // Later layers accumulate Y_d = sum_e dE/dv1_d(i) w_vv (from which both
-        // dE/dv_j = phi_vv Y_d and dE/dphi_vv = sum_d v_jd Y_d follow once per
-        // atom), dE/dphi_s and dE/dphi_vs; the v_j term of dE/dr enters through
-        // c_d = v_jd phi_vv.
-        v4f ph[3][TU], cv[3][TU], Y[3][TU], ap[2][TU];
-#pragma unroll
-        for (int u = 0; u < TU; u++) {
-#pragma unroll
-            for (int q = V0 ? 1 : 0; q < 3; q++) ph[q][u] = ld4(phi + (V0 ? (long)zsp[j] : (long)j) * F3 + q * F + fo + 16 * u);
-            if constexpr (!V0) {
-#pragma unroll
-                for (int d = 0; d < 3; d++) {
-                    cv[d][u] = ld4(v + (long)j * F3 + d * F + fo + 16 * u) * ph[0][u];
-                    Y[d][u] = v4f{0.f, 0.f, 0.f, 0.f};
-                }
-                ap[0][u] = v4f{0.f, 0.f, 0.f, 0.f};
-                ap[1][u] = v4f{0.f, 0.f, 0.f, 0.f};
-            }
-        }
         // edges of an atom beyond the hop range carry no gradient in this layer
+        float4 *Sp = S + (long)(PIW ? 0 : (int)blockIdx.y) * s_stride;
         if (hop[j] > hop_max)
-            for (int q = e0 + lane; q < e1; q += 64) Sp[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-        float4 gm_n = make_float4(0.f, 0.f, 0.f, rc);
-        int i_n = j;
-        if (e < deg) {
-            gm_n = geom[e0 + e];
-            i_n = colc[e0 + e];
-        }
-        for (int cb = 0; cb < deg; cb += 16) {
-            const char *wl = lds_chunk(lds);
-            const bool valid = cb + e < deg;
-            const float4 gm = gm_n;
-            const int i = i_n;
-            gm_n = make_float4(0.f, 0.f, 0.f, rc);
-            i_n = j;
-            if (cb + 16 + e < deg) {
-                gm_n = geom[e0 + cb + 16 + e];
-                i_n = colc[e0 + cb + 16 + e];
-            }
-            // the destinations' gradient rows, gathered quarter-contiguously and
-            // moved to the accumulator layout
-            const int iq = __shfl(i, xc.src, 64);
-            v4f gs[TU], gv[3][TU];
+            for (int t = e0 + lane; t < e1; t += 64) Sp[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 1
+        for (int pi = 0; pi < NPL; pi++) {
+            const int p = PIW ? pi : (int)blockIdx.y;
+            const int fo = p * W + 4 * g;   // first feature of this lane (tile u adds 16 u)
+            // first layer: v_j = 0 and no node gradient, so phi_vv, v_j, dE/dphi_j
+            // and dE/dv_j drop out and only the edge sums remain.
+            // Later layers accumulate Y_d = sum_e dE/dv1_d(i) w_vv (from which both
+            // dE/dv_j = phi_vv Y_d and dE/dphi_vv = sum_d v_jd Y_d follow once per
+            // atom), dE/dphi_s and dE/dphi_vs; the v_j term of dE/dr enters through
+            // c_d = v_jd phi_vv.
+            v4f ph[3][TU], cv[3][TU], Y[3][TU], ap[2][TU];
 #pragma unroll
             for (int u = 0; u < TU; u++) {
-                gs[u] = ld4(gs1 + (long)iq * F + p * W + xc.fo + 16 * u);
 #pragma unroll
-                for (int d = 0; d < 3; d++) gv[d][u] = ld4(gv1 + (long)iq * F3 + d * F + p * W + xc.fo + 16 * u);
-            }
-#pragma unroll
-            for (int u = 0; u < TU; u++) {
-                gs[u] = xc.move(xw[0], gs[u]);
-#pragma unroll
-                for (int d = 0; d < 3; d++) gv[d][u] = xc.move(xw[1 + d], gv[d][u]);
-            }
-            const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
-            float eb[SL], db[SL];
-            basis_slots<P, K, true>(gm.w, ir, pirc, valid, g, eb, db);
-            BOp<P, K> bop, dop;
-            bop.set(eb);
-            dop.set(db);
-            // direction of the message edge (i <- j) is x_j - x_i = -(x_i - x_j)
-            const float rx = -gm.x * ir, ry = -gm.y * ir, rz = -gm.z * ir;
-            float sr = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
-#pragma unroll
-            for (int u = 0; u < TU; u++) {
-                v4f w0, w1, d0;
+                for (int q = V0 ? 1 : 0; q < 3; q++)
+                    ph[q][u] = ld4(phi + (V0 ? (long)zsp[j] : (long)j) * F3 + q * F + fo + 16 * u);
                 if constexpr (!V0) {
-                    w0 = filter_tile<P, F, K, WM>(wl, u, bop, lane);
-                    w1 = filter_tile<P, F, K, WM>(wl, TU + u, bop, lane);
+#pragma unroll
+                    for (int d = 0; d < 3; d++) {
+                        cv[d][u] = ld4(v + (long)j * F3 + d * F + fo + 16 * u) * ph[0][u];
+                        Y[d][u] = v4f{0.f, 0.f, 0.f, 0.f};
+                    }
+                    ap[0][u] = v4f{0.f, 0.f, 0.f, 0.f};
+                    ap[1][u] = v4f{0.f, 0.f, 0.f, 0.f};
                 }
-                const v4f w2 = filter_tile<P, F, K, WM>(wl, 2 * TU + u, bop, lane);
-                if constexpr (!V0) d0 = filter_tile<P, F, K, WM>(wl, u, dop, lane);
-                const v4f d1 = filter_tile<P, F, K, WM>(wl, TU + u, dop, lane);
-                const v4f d2 = filter_tile<P, F, K, WM>(wl, 2 * TU + u, dop, lane);
+            }
+            float4 gm_n = make_float4(0.f, 0.f, 0.f, rc);
+            int i_n = j;
+            if (e < deg) {
+                gm_n = geom[e0 + e];
+                i_n = colc[e0 + e];
+            }
+            for (int cb = 0; cb < deg; cb += 16) {
+                const char *wl = lds_chunk(lds + pi * WB);
+                const bool valid = cb + e < deg;
+                const float4 gm = gm_n;
+                const int i = i_n;
+                gm_n = make_float4(0.f, 0.f, 0.f, rc);
+                i_n = j;
+                if (cb + 16 + e < deg) {
+                    gm_n = geom[e0 + cb + 16 + e];
+                    i_n = colc[e0 + cb + 16 + e];
+                }
+                // the destinations' gradient rows, gathered quarter-contiguously and
+                // moved to the accumulator layout
+                const int iq = __shfl(i, xc.src, 64);
+                v4f gs[TU], gv[3][TU];
+#pragma unroll
+                for (int u = 0; u < TU; u++) {
+                    gs[u] = ld4(gs1 + (long)iq * F + p * W + xc.fo + 16 * u);
+#pragma unroll
+                    for (int d = 0; d < 3; d++) gv[d][u] = ld4(gv1 + (long)iq * F3 + d * F + p * W + xc.fo + 16 * u);
+                }
+#pragma unroll
+                for (int u = 0; u < TU; u++) {
+                    gs[u] = xc.move(xw[0], gs[u]);
+#pragma unroll
+                    for (int d = 0; d < 3; d++) gv[d][u] = xc.move(xw[PIW ? 0 : 1 + d], gv[d][u]);
+                }
+                const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
+                BOp<P, K> bop, dop;
+                const int c = cb >> 4;
+                if (PIW && pi > 0 && c < NC) {
+                    bcache_get<P, K>(bc + c * CB, lane, bop, dop);
+                } else {
+                    float eb[SL], db[SL];
+                    basis_slots<P, K, true>(gm.w, ir, pirc, valid, g, eb, db);
+                    bop.set(eb);
+                    dop.set(db);
+                    if (PIW && pi == 0 && c < NC) bcache_put<P, K>(bc + c * CB, lane, bop, dop);
+                }
+                // direction of the message edge (i <- j) is x_j - x_i = -(x_i - x_j)
+                const float rx = -gm.x * ir, ry = -gm.y * ir, rz = -gm.z * ir;
+                float sr = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+                for (int u = 0; u < TU; u++) {
+                    v4f w0, w1, d0;
+                    if constexpr (!V0) {
+                        w0 = filter_tile<P, F, K, WM, PIW>(wl, u, bop, lane);
+                        w1 = filter_tile<P, F, K, WM, PIW>(wl, TU + u, bop, lane);
+                    }
+                    const v4f w2 = filter_tile<P, F, K, WM, PIW>(wl, 2 * TU + u, bop, lane);
+                    if constexpr (!V0) d0 = filter_tile<P, F, K, WM, PIW>(wl, u, dop, lane);
+                    const v4f d1 = filter_tile<P, F, K, WM, PIW>(wl, TU + u, dop, lane);
+                    const v4f d2 = filter_tile<P, F, K, WM, PIW>(wl, 2 * TU + u, dop, lane);
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const float ga = gv[0][u][r], gb = gv[1][u][r], gc = gv[2][u][r], gsr = gs[u][r];
+                        const float gxvs = fmaf(ga, rx, fmaf(gb, ry, gc * rz));
+                        const float xvs = ph[2][u][r] * w2[r];
+                        sx = fmaf(ga, xvs, sx);
+                        sy = fmaf(gb, xvs, sy);
+                        sz = fmaf(gc, xvs, sz);
+                        if constexpr (V0) {
+                            sr = fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr));
+                            continue;
+                        }
+                        const float gc0 = fmaf(ga, cv[0][u][r], fmaf(gb, cv[1][u][r], gc * cv[2][u][r]));
+                        Y[0][u][r] = fmaf(ga, w0[r], Y[0][u][r]);
+                        Y[1][u][r] = fmaf(gb, w0[r], Y[1][u][r]);
+                        Y[2][u][r] = fmaf(gc, w0[r], Y[2][u][r]);
+                        ap[0][u][r] = fmaf(gsr, w1[r], ap[0][u][r]);
+                        ap[1][u][r] = fmaf(gxvs, w2[r], ap[1][u][r]);
+                        sr = fmaf(gc0, d0[r], fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr)));
+                    }
+                }
+                // sum over the four lane rows (all features of the pass)
+                sr += __shfl_xor(sr, 16, 64);
+                sx += __shfl_xor(sx, 16, 64);
+                sy += __shfl_xor(sy, 16, 64);
+                sz += __shfl_xor(sz, 16, 64);
+                sr += __shfl_xor(sr, 32, 64);
+                sx += __shfl_xor(sx, 32, 64);
+                sy += __shfl_xor(sy, 32, 64);
+                sz += __shfl_xor(sz, 32, 64);
+                if (g == 0 && valid) {
+                    float4 o = make_float4(sr, sx, sy, sz);
+                    if constexpr (PIW) {
+                        float4 *acc = c < NC ? &sacc[threadIdx.x >> 6][c][e] : Sp + e0 + cb + e;
+                        if (pi > 0) {
+                            const float4 a = *acc;
+                            o = make_float4(a.x + o.x, a.y + o.y, a.z + o.z, a.w + o.w);
+                        }
+                        if (c < NC && pi + 1 < NPL) *acc = o;
+                        else Sp[e0 + cb + e] = o;
+                    } else {
+                        Sp[e0 + cb + e] = o;
+                    }
+                }
+            }
+            if constexpr (V0) continue;
+            // sum over the 16 edge lanes of each row
+#pragma unroll
+            for (int u = 0; u < TU; u++)
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const float ga = gv[0][u][r], gb = gv[1][u][r], gc = gv[2][u][r], gsr = gs[u][r];
-                    const float gxvs = fmaf(ga, rx, fmaf(gb, ry, gc * rz));
-                    const float xvs = ph[2][u][r] * w2[r];
-                    sx = fmaf(ga, xvs, sx);
-                    sy = fmaf(gb, xvs, sy);
-                    sz = fmaf(gc, xvs, sz);
-                    if constexpr (V0) {
-                        sr = fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr));
-                        continue;
+#pragma unroll
+                    for (int d = 0; d < 3; d++) Y[d][u][r] = row_sum16(Y[d][u][r]);
+                    ap[0][u][r] = row_sum16(ap[0][u][r]);
+                    ap[1][u][r] = row_sum16(ap[1][u][r]);
+                }
+            if (e == 0) {
+#pragma unroll
+                for (int u = 0; u < TU; u++) {
+                    const long b = (long)j * F3 + fo + 16 * u;
+                    const v4f pvv = ld4(phi + b);
+                    v4f gvv = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int d = 0; d < 3; d++) {
+                        gvv += ld4(v + b + d * F) * Y[d][u];
+                        st4(gv_in + b + d * F, ld4(gv1 + b + d * F) + pvv * Y[d][u]);
                     }
-                    const float gc0 = fmaf(ga, cv[0][u][r], fmaf(gb, cv[1][u][r], gc * cv[2][u][r]));
-                    Y[0][u][r] = fmaf(ga, w0[r], Y[0][u][r]);
-                    Y[1][u][r] = fmaf(gb, w0[r], Y[1][u][r]);
-                    Y[2][u][r] = fmaf(gc, w0[r], Y[2][u][r]);
-                    ap[0][u][r] = fmaf(gsr, w1[r], ap[0][u][r]);
-                    ap[1][u][r] = fmaf(gxvs, w2[r], ap[1][u][r]);
-                    sr = fmaf(gc0, d0[r], fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr)));
+                    st4(gphi + b, gvv);
+                    st4(gphi + b + F, ap[0][u]);
+                    st4(gphi + b + 2 * F, ap[1][u]);
                 }
-            }
-            // sum over the four lane rows (all features of the pass)
-            sr += __shfl_xor(sr, 16, 64);
-            sx += __shfl_xor(sx, 16, 64);
-            sy += __shfl_xor(sy, 16, 64);
-            sz += __shfl_xor(sz, 16, 64);
-            sr += __shfl_xor(sr, 32, 64);
-            sx += __shfl_xor(sx, 32, 64);
-            sy += __shfl_xor(sy, 32, 64);
-            sz += __shfl_xor(sz, 32, 64);
-            if (g == 0 && valid) Sp[e0 + cb + e] = make_float4(sr, sx, sy, sz);
-        }
-        if constexpr (V0) continue;
-        // sum over the 16 edge lanes of each row
-#pragma unroll
-        for (int u = 0; u < TU; u++)
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-#pragma unroll
-                for (int d = 0; d < 3; d++) Y[d][u][r] = row_sum16(Y[d][u][r]);
-                ap[0][u][r] = row_sum16(ap[0][u][r]);
-                ap[1][u][r] = row_sum16(ap[1][u][r]);
-            }
-        if (e == 0) {
-#pragma unroll
-            for (int u = 0; u < TU; u++) {
-                const long b = (long)j * F3 + fo + 16 * u;
-                const v4f pvv = ld4(phi + b);
-                v4f gvv = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int d = 0; d < 3; d++) {
-                    gvv += ld4(v + b + d * F) * Y[d][u];
-                    st4(gv_in + b + d * F, ld4(gv1 + b + d * F) + pvv * Y[d][u]);
-                }
-                st4(gphi + b, gvv);
-                st4(gphi + b + F, ap[0][u]);
-                st4(gphi + b + 2 * F, ap[1][u]);
             }
         }
     }
@@ -890,16 +1028,43 @@ static int launch_fwd(hipStream_t st, const MsgArgs &a) {
     dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F, FWD_W>::N);
     auto kern = a.layer0 ? k_msg_fwd<P, F, K, true> : k_msg_fwd<P, F, K, false>;
     kern<<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.u, a.s, a.v, a.A, a.c, a.rc, a.hop,
-                                   a.hop_max, a.species, a.sn, a.v1);
+                                   a.hop_max, a.species, a.queue, a.sn, a.v1);
     return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+// Workgroups of kern (with the given block size) that the current device
+// holds at once: compute units times the workgroups per compute unit.
+template <class KERN>
+static int resident_grid(KERN kern, int block) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, 0) != hipSuccess || per <= 0) per = 1;
+    return cus * per;
 }
 
 template <int P, int F, int K>
 static int launch_bwd(hipStream_t st, const MsgArgs &a) {
+    constexpr bool piw = Pass<F, BWD_W>::N > 1;
+    if constexpr (piw) {
+        if (!a.layer0) {
+            auto kern = k_msg_bwd<P, F, K, false, true>;
+            constexpr int block = 64 * BWD_PIW_WAVES;
+            static const int resident = resident_grid(kern, block);   // per process: one device type
+            int b = std::min(resident, (a.n + BWD_PIW_WAVES - 1) / BWD_PIW_WAVES);
+            if (b >= 8) b -= b % 8;
+            kern<<<dim3((unsigned)std::max(1, b)), block, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.v, a.gs1,
+                                                                   a.gv1, a.A, a.c, a.rc, a.hop, a.hop_max,
+                                                                   a.species, a.queue, a.gv_in, a.gphi, a.S,
+                                                                   a.s_stride);
+            return hipGetLastError() == hipSuccess ? 0 : -5;
+        }
+    }
     dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F, BWD_W>::N);
-    auto kern = a.layer0 ? k_msg_bwd<P, F, K, true> : k_msg_bwd<P, F, K, false>;
+    auto kern = a.layer0 ? k_msg_bwd<P, F, K, true, false> : k_msg_bwd<P, F, K, false, false>;
     kern<<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.v, a.gs1, a.gv1, a.A, a.c, a.rc, a.hop,
-                                   a.hop_max, a.species, a.gv_in, a.gphi, a.S, a.s_stride);
+                                   a.hop_max, a.species, a.queue, a.gv_in, a.gphi, a.S, a.s_stride);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
@@ -949,6 +1114,8 @@ int msg_l0_edge_sums(hipStream_t st, int K, int S, const L0Args &a) {
 }
 
 int msg_passes(int F) { return F < BWD_W ? 1 : F / BWD_W; }
+
+int msg_slots(int F, int T, bool l0_factorised) { return T - 1 + (l0_factorised ? 1 : msg_passes(F)); }
 
 static unsigned edge_blocks(long ne_max) { return (unsigned)std::max(1L, std::min((ne_max + 255) / 256, 8192L)); }
 

@@ -322,13 +322,15 @@ struct Act {
     float *gs, *gv, *gs1, *gv1, *gphi, *ga, *gh3, *gsn, *gUV, *ga1, *tmpF, *h5, *g5, *U;
     float *u;   // v * phi_vv of the current forward layer (shares gUV: the adjoint starts after the forward)
     double *epart;
+    int *queue;   // the message launches' atom counters, MSG_QUEUE_INTS per launch
 };
+constexpr long QUEUE_INTS = 2L * MLP_MAX_LAYERS * MSG_QUEUE_INTS;
 
 static size_t act_floats(long N, int F, int T) {
     long per_layer = (long)N * F * (1 + 3 + 1 + 3 + 2 + 3 + 3 + 3 + 1 + 3);
     long io = (long)N * F * 4;  // s, v of the final layer
     long bwd = (long)N * F * (1 + 3 + 1 + 3 + 3 + 3 + 1 + 2 + 3 + 3 + 1 + 1) + (long)N * F;  // + h5, g5
-    return (size_t)(T * per_layer + io + bwd + N + 64 * (12 * T + 32) + 4096);
+    return (size_t)(T * per_layer + io + bwd + N + 64 * (12 * T + 32) + 4096 + QUEUE_INTS);
 }
 
 static void carve(float *base, long N, int F, int T, Act &A) {
@@ -367,6 +369,7 @@ static void carve(float *base, long N, int F, int T, Act &A) {
     A.g5 = take(NF / 2 + 64);
     A.U = take(N + 64);
     A.epart = reinterpret_cast<double *>(take(2 * 1024));
+    A.queue = reinterpret_cast<int *>(take(QUEUE_INTS));
 }
 
 static MsgArgs msg_args(mlp_nbr *g, mlp_model *m, const LayerW &L, int hop_max) {
@@ -502,7 +505,7 @@ void eval_model_needs(const mlp_model *m, const mlp_nbr *g, size_t *act, size_t 
     }
     *act = act_floats(g->n_atoms, m->F, m->T) * sizeof(float);
     *G = sizeof(float4) * ne + 64;
-    *Gs = sizeof(float4) * ne * (size_t)msg_passes(m->F) * (size_t)m->T + 64;
+    *Gs = sizeof(float4) * ne * (size_t)msg_slots(m->F, m->T, m->l0f) + 64;
 }
 
 int launch_energy(hipStream_t s, const float *U, const int *perm, int n, int n_local, double *energy,
@@ -534,16 +537,19 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     size_t need_act, need_G, need_Gs;
     eval_model_needs(m, g, &need_act, &need_G, &need_Gs);
     if ((rc = g->act.ensure(need_act, 1.2, Gr))) return rc;
-    const int npass = msg_passes(F);
     const long ne = g->n_edges_skin;
     if ((rc = g->G.ensure(need_G, 1.2, Gr))) return rc;
     if ((rc = g->Gs.ensure(need_Gs, 1.2, Gr))) return rc;
     Act A;
     carve(g->act.as<float>(), n, F, T, A);
+    // every message launch takes its own zeroed atom counters
+    fill_zero(s, reinterpret_cast<float *>(A.queue), QUEUE_INTS);
+    int nq = 0;
+    auto next_queue = [&]() { return A.queue + (long)(nq++) * MSG_QUEUE_INTS; };
     const int *perm = g->perm.as<int>();
-    // edge-sum slots: layers 1 .. T-1 take npass each, from slot 0; the first
-    // layer's come last (one slot when it is factorised)
-    const int slot0 = (T - 1) * npass, nslot = slot0 + (m->l0f ? 1 : npass);
+    // edge-sum slots: layers 1 .. T-1 take one each, from slot 0; the first
+    // layer's come last (one when it is factorised, else one per pass)
+    const int slot0 = T - 1, nslot = msg_slots(F, T, m->l0f);
     // factorised first layer: its matrices live in the adjoint's dUV rows
     // (free in the first layer's forward, and again once dv1 is formed)
     const L0Layout l0 = l0_layout(F, K, m->S);
@@ -592,6 +598,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             ma.v = A.v[t];
             ma.sn = A.sn[t];
             ma.v1 = A.v1[t];
+            ma.queue = next_queue();
             ProfScope ps(PK_MSG_FWD, s);
             if ((rc = msg_forward(s, PF, F, K, ma))) return fail(rc, "message kernel launch failed");
         }
@@ -682,8 +689,9 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             ma.gv1 = A.gv1;
             ma.gv_in = A.gv;
             ma.gphi = A.gphi;
-            ma.S = g->Gs.as<float4>() + (size_t)(t == 0 ? slot0 : (t - 1) * npass) * ne;
+            ma.S = g->Gs.as<float4>() + (size_t)(t == 0 ? slot0 : t - 1) * ne;
             ma.layer0 = t == 0;
+            ma.queue = next_queue();
             ProfScope ps(PK_MSG_BWD, s);
             if ((rc = msg_adjoint(s, PF, F, K, ma))) return fail(rc, "adjoint message kernel launch failed");
         }
