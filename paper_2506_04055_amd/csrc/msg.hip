@@ -391,11 +391,57 @@ struct AtomQueue {
         for (int I = I##_b; I < I##_b + MSG_QB && I < (Q).hi; I++)
 #endif
 
+// A chunk's B operand kept in LDS between passes: 16-byte words per lane
+// (FP32 mode: 4-byte words), stored lane-contiguously so that the writes
+// and reads are conflict-free.  Each lane reads back only what it wrote
+// itself, so no barrier is needed.
+template <int P, int K>
+struct BOpStore {
+    static constexpr int WBYTES = P >= 1 ? 16 : 4;                            // bytes per word
+    static constexpr int WORDS = P == 2 ? 2 : (P == 1 ? 1 : Basis<P, K>::NS); // words per lane
+    static constexpr int BYTES = WORDS * WBYTES * 64;                         // per operand and wave
+};
+template <int P, int K>
+__device__ __forceinline__ void bop_put(char *slot, int lane, const BOp<P, K> &b) {
+    if constexpr (P >= 1) {
+        v4f *q = reinterpret_cast<v4f *>(slot) + lane;
+        q[0] = __builtin_bit_cast(v4f, b.v);
+        if constexpr (P == 2) q[64] = __builtin_bit_cast(v4f, b.lo);
+    } else {
+        float *q = reinterpret_cast<float *>(slot) + lane;
+#pragma unroll
+        for (int s = 0; s < Basis<P, K>::NS; s++) q[64 * s] = b.v[s];
+    }
+}
+template <int P, int K>
+__device__ __forceinline__ void bop_get(const char *slot, int lane, BOp<P, K> &b) {
+    if constexpr (P >= 1) {
+        const v4f *q = reinterpret_cast<const v4f *>(slot) + lane;
+        b.v = __builtin_bit_cast(v8bf, q[0]);
+        if constexpr (P == 2) b.lo = __builtin_bit_cast(v8bf, q[64]);
+    } else {
+        const float *q = reinterpret_cast<const float *>(slot) + lane;
+#pragma unroll
+        for (int s = 0; s < Basis<P, K>::NS; s++) b.v[s] = q[64 * s];
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Forward message pass, one feature pass (blockIdx.y) per workgroup.
+// Forward message pass.  Two arrangements of the feature passes, as in the
+// adjoint below: with PIW (the layers after the first, more than one pass)
+// every wave runs all passes of its atom with the weight images of every
+// pass in LDS, and the radial basis of a chunk, in MFMA operand form, is
+// evaluated in the first pass and kept in the wave's LDS for the later ones
+// (the first FWD_CACHE chunks of the atom); otherwise blockIdx.y is the pass.
 // ---------------------------------------------------------------------------
-template <int P, int F, int K, bool V0>
-__global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0 ? FWD_WAVES0 : FWD_WAVES))) k_msg_fwd(const int *__restrict__ rowc, const int *__restrict__ colc,
+#ifndef FWD_PIW_WAVES
+#define FWD_PIW_WAVES 16
+#endif
+#ifndef FWD_CACHE
+#define FWD_CACHE 3
+#endif
+template <int P, int F, int K, bool V0, bool PIW>
+__global__ void __launch_bounds__(64 * (PIW ? FWD_PIW_WAVES : MW)) __attribute__((amdgpu_waves_per_eu(V0 ? FWD_WAVES0 : FWD_WAVES))) k_msg_fwd(const int *__restrict__ rowc, const int *__restrict__ colc,
                                                      const float4 *__restrict__ geom, int n,
                                                      const float *__restrict__ phi, const float *__restrict__ uvp,
                                                      const float *__restrict__ s, const float *__restrict__ v,
@@ -406,123 +452,141 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
                                                      float *__restrict__ sn, float *__restrict__ v1) {
     constexpr int WM = FWD_W;
     constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F, WM>::W, TU = Pass<F, WM>::TU;
-    __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K, WM>::BYTES];
+    constexpr int NW = PIW ? FWD_PIW_WAVES : MW;        // waves per workgroup
+    constexpr int NPL = PIW ? Pass<F, WM>::N : 1;       // passes per workgroup
+    constexpr int NC = PIW ? FWD_CACHE : 0;             // chunks whose basis a wave keeps
+    constexpr int WB = WStage<P, F, K, WM, PIW>::BYTES;
+    constexpr int CB = BOpStore<P, K>::BYTES;
+    static_assert(!PIW || !V0, "the first layer runs one pass per workgroup");
+    __shared__ __attribute__((aligned(16))) char lds[NPL * WB];
     // first layer: phi and s are per-species tables (rows by zsp), a few rows
     // that every gather hits in L1, read directly in the accumulator layout
-    __shared__ v4f xch[MW][V0 ? 1 : 5][64];
-    const int p = blockIdx.y;
-    stage_pass<P, F, K, WM>(Aw, cw, p, lds);
+    __shared__ v4f xch[NW][(V0 || PIW) ? 1 : 5][64];
+    __shared__ __attribute__((aligned(16))) char bcache[PIW ? NW * NC * CB : 16];
+#pragma unroll 1
+    for (int q = 0; q < NPL; q++) stage_pass<P, F, K, WM, PIW>(Aw, cw, PIW ? q : (int)blockIdx.y, lds + q * WB);
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
-    const int fo = p * W + 4 * g;   // first feature of this lane (tile u adds 16 u)
     const Xch xc(g, e);
     v4f(*xw)[64] = xch[threadIdx.x >> 6];
-    const AtomQueue aq(n, queue, p);
+    char *bc = bcache + (PIW ? (threadIdx.x >> 6) * NC * CB : 0);
+    const AtomQueue aq(n, queue, PIW ? 0 : (int)blockIdx.y);
     const float pirc = 3.14159265358979f / rc;
     MSG_ATOMS(aq, i) {
         const int e0 = rowc[i], e1 = rowc[i + 1];
         const int deg = hop[i] <= hop_max ? e1 - e0 : 0;
-        v4f as[TU], av[3][TU];
-#pragma unroll
-        for (int u = 0; u < TU; u++) {
-            as[u] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int d = 0; d < 3; d++) av[d][u] = v4f{0.f, 0.f, 0.f, 0.f};
-        }
-        // edge records of the next chunk are loaded one chunk ahead
-        float4 gm_n = make_float4(0.f, 0.f, 0.f, rc);
-        int j_n = i;
-        if (e < deg) {
-            gm_n = geom[e0 + e];
-            j_n = colc[e0 + e];
-        }
-        for (int cb = 0; cb < deg; cb += 16) {
-            const char *wl = lds_chunk(lds);
-            const bool valid = cb + e < deg;
-            const float4 gm = gm_n;
-            const int j = j_n;
-            gm_n = make_float4(0.f, 0.f, 0.f, rc);
-            j_n = i;
-            if (cb + 16 + e < deg) {
-                gm_n = geom[e0 + cb + 16 + e];
-                j_n = colc[e0 + cb + 16 + e];
-            }
-            // gathered: phi_s, phi_vs and (after the first layer) u = v * phi_vv
-            // of the source (5 row slices, quarter-contiguously, then moved to
-            // the accumulator layout; the first layer's 2 from the table)
-            v4f ph[2][TU], uu[3][TU];
-            if constexpr (V0) {
-                const float *pj = phi + (long)zsp[j] * F3 + fo;
-#pragma unroll
-                for (int u = 0; u < TU; u++) {
-                    ph[0][u] = ld4(pj + F + 16 * u);
-                    ph[1][u] = ld4(pj + 2 * F + 16 * u);
-                }
-            } else {
-                const int jq = __shfl(j, xc.src, 64);
-                const float *pj = phi + (long)jq * F3 + p * W + xc.fo;
-                const float *uj = uvp + (long)jq * F3 + p * W + xc.fo;
-#pragma unroll
-                for (int u = 0; u < TU; u++) {
-                    ph[0][u] = ld4(pj + F + 16 * u);
-                    ph[1][u] = ld4(pj + 2 * F + 16 * u);
-#pragma unroll
-                    for (int d = 0; d < 3; d++) uu[d][u] = ld4(uj + d * F + 16 * u);
-                }
-#pragma unroll
-                for (int u = 0; u < TU; u++) {
-                    ph[0][u] = xc.move(xw[0], ph[0][u]);
-                    ph[1][u] = xc.move(xw[1], ph[1][u]);
-#pragma unroll
-                    for (int d = 0; d < 3; d++) uu[d][u] = xc.move(xw[2 + d], uu[d][u]);
-                }
-            }
-            const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
-            float eb[SL];
-            basis_slots<P, K, false>(gm.w, ir, pirc, valid, g, eb, nullptr);
-            BOp<P, K> bop;
-            bop.set(eb);
-            const float rx = gm.x * ir, ry = gm.y * ir, rz = gm.z * ir;
+#pragma unroll 1
+        for (int pi = 0; pi < NPL; pi++) {
+            const int p = PIW ? pi : (int)blockIdx.y;
+            const int fo = p * W + 4 * g;   // first feature of this lane (tile u adds 16 u)
+            v4f as[TU], av[3][TU];
 #pragma unroll
             for (int u = 0; u < TU; u++) {
-                v4f wvv;
-                if constexpr (!V0) wvv = filter_tile<P, F, K, WM>(wl, u, bop, lane);
-                const v4f ws = filter_tile<P, F, K, WM>(wl, TU + u, bop, lane);
-                const v4f wvs = filter_tile<P, F, K, WM>(wl, 2 * TU + u, bop, lane);
+                as[u] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const float xvs = ph[1][u][r] * wvs[r];
-                    as[u][r] = fmaf(ph[0][u][r], ws[r], as[u][r]);
-                    if constexpr (V0) {
-                        av[0][u][r] = fmaf(rx, xvs, av[0][u][r]);
-                        av[1][u][r] = fmaf(ry, xvs, av[1][u][r]);
-                        av[2][u][r] = fmaf(rz, xvs, av[2][u][r]);
-                    } else {
-                        av[0][u][r] = fmaf(uu[0][u][r], wvv[r], fmaf(rx, xvs, av[0][u][r]));
-                        av[1][u][r] = fmaf(uu[1][u][r], wvv[r], fmaf(ry, xvs, av[1][u][r]));
-                        av[2][u][r] = fmaf(uu[2][u][r], wvv[r], fmaf(rz, xvs, av[2][u][r]));
+                for (int d = 0; d < 3; d++) av[d][u] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+            // edge records of the next chunk are loaded one chunk ahead
+            float4 gm_n = make_float4(0.f, 0.f, 0.f, rc);
+            int j_n = i;
+            if (e < deg) {
+                gm_n = geom[e0 + e];
+                j_n = colc[e0 + e];
+            }
+            for (int cb = 0; cb < deg; cb += 16) {
+                const char *wl = lds_chunk(lds + pi * WB);
+                const bool valid = cb + e < deg;
+                const float4 gm = gm_n;
+                const int j = j_n;
+                gm_n = make_float4(0.f, 0.f, 0.f, rc);
+                j_n = i;
+                if (cb + 16 + e < deg) {
+                    gm_n = geom[e0 + cb + 16 + e];
+                    j_n = colc[e0 + cb + 16 + e];
+                }
+                // gathered: phi_s, phi_vs and (after the first layer) u = v * phi_vv
+                // of the source (5 row slices, quarter-contiguously, then moved to
+                // the accumulator layout; the first layer's 2 from the table)
+                v4f ph[2][TU], uu[3][TU];
+                if constexpr (V0) {
+                    const float *pj = phi + (long)zsp[j] * F3 + fo;
+#pragma unroll
+                    for (int u = 0; u < TU; u++) {
+                        ph[0][u] = ld4(pj + F + 16 * u);
+                        ph[1][u] = ld4(pj + 2 * F + 16 * u);
+                    }
+                } else {
+                    const int jq = __shfl(j, xc.src, 64);
+                    const float *pj = phi + (long)jq * F3 + p * W + xc.fo;
+                    const float *uj = uvp + (long)jq * F3 + p * W + xc.fo;
+#pragma unroll
+                    for (int u = 0; u < TU; u++) {
+                        ph[0][u] = ld4(pj + F + 16 * u);
+                        ph[1][u] = ld4(pj + 2 * F + 16 * u);
+#pragma unroll
+                        for (int d = 0; d < 3; d++) uu[d][u] = ld4(uj + d * F + 16 * u);
+                    }
+#pragma unroll
+                    for (int u = 0; u < TU; u++) {
+                        ph[0][u] = xc.move(xw[0], ph[0][u]);
+                        ph[1][u] = xc.move(xw[PIW ? 0 : 1], ph[1][u]);
+#pragma unroll
+                        for (int d = 0; d < 3; d++) uu[d][u] = xc.move(xw[PIW ? 0 : 2 + d], uu[d][u]);
+                    }
+                }
+                const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
+                BOp<P, K> bop;
+                const int c = cb >> 4;
+                if (PIW && pi > 0 && c < NC) {
+                    bop_get<P, K>(bc + c * CB, lane, bop);
+                } else {
+                    float eb[SL];
+                    basis_slots<P, K, false>(gm.w, ir, pirc, valid, g, eb, nullptr);
+                    bop.set(eb);
+                    if (PIW && pi == 0 && c < NC) bop_put<P, K>(bc + c * CB, lane, bop);
+                }
+                const float rx = gm.x * ir, ry = gm.y * ir, rz = gm.z * ir;
+#pragma unroll
+                for (int u = 0; u < TU; u++) {
+                    v4f wvv;
+                    if constexpr (!V0) wvv = filter_tile<P, F, K, WM, PIW>(wl, u, bop, lane);
+                    const v4f ws = filter_tile<P, F, K, WM, PIW>(wl, TU + u, bop, lane);
+                    const v4f wvs = filter_tile<P, F, K, WM, PIW>(wl, 2 * TU + u, bop, lane);
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const float xvs = ph[1][u][r] * wvs[r];
+                        as[u][r] = fmaf(ph[0][u][r], ws[r], as[u][r]);
+                        if constexpr (V0) {
+                            av[0][u][r] = fmaf(rx, xvs, av[0][u][r]);
+                            av[1][u][r] = fmaf(ry, xvs, av[1][u][r]);
+                            av[2][u][r] = fmaf(rz, xvs, av[2][u][r]);
+                        } else {
+                            av[0][u][r] = fmaf(uu[0][u][r], wvv[r], fmaf(rx, xvs, av[0][u][r]));
+                            av[1][u][r] = fmaf(uu[1][u][r], wvv[r], fmaf(ry, xvs, av[1][u][r]));
+                            av[2][u][r] = fmaf(uu[2][u][r], wvv[r], fmaf(rz, xvs, av[2][u][r]));
+                        }
                     }
                 }
             }
-        }
-        // sum over the 16 edge lanes of each row
+            // sum over the 16 edge lanes of each row
 #pragma unroll
-        for (int u = 0; u < TU; u++)
+            for (int u = 0; u < TU; u++)
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                as[u][r] = row_sum16(as[u][r]);
+                for (int r = 0; r < 4; r++) {
+                    as[u][r] = row_sum16(as[u][r]);
 #pragma unroll
-                for (int d = 0; d < 3; d++) av[d][u][r] = row_sum16(av[d][u][r]);
-            }
-        if (e == 0) {
+                    for (int d = 0; d < 3; d++) av[d][u][r] = row_sum16(av[d][u][r]);
+                }
+            if (e == 0) {
 #pragma unroll
-            for (int u = 0; u < TU; u++) {
-                const int f = fo + 16 * u;
-                const long si = V0 ? (long)zsp[i] : (long)i;
-                st4(sn + (long)i * 2 * F + f, ld4(s + si * F + f) + as[u]);
+                for (int u = 0; u < TU; u++) {
+                    const int f = fo + 16 * u;
+                    const long si = V0 ? (long)zsp[i] : (long)i;
+                    st4(sn + (long)i * 2 * F + f, ld4(s + si * F + f) + as[u]);
 #pragma unroll
-                for (int d = 0; d < 3; d++) {
-                    if constexpr (V0) st4(v1 + (long)i * F3 + d * F + f, av[d][u]);
-                    else st4(v1 + (long)i * F3 + d * F + f, ld4(v + (long)i * F3 + d * F + f) + av[d][u]);
+                    for (int d = 0; d < 3; d++) {
+                        if constexpr (V0) st4(v1 + (long)i * F3 + d * F + f, av[d][u]);
+                        else st4(v1 + (long)i * F3 + d * F + f, ld4(v + (long)i * F3 + d * F + f) + av[d][u]);
+                    }
                 }
             }
         }
@@ -557,58 +621,6 @@ __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0
 #define BWD_CACHE 3
 #endif
 
-// The two B operands of a chunk as 16-byte words per lane (FP32 mode: 4-byte
-// words), stored lane-contiguously so that the writes and reads are
-// conflict-free.  Each lane reads back only what it wrote itself.
-template <int P, int K>
-struct BCache {
-    static constexpr int WORDS = P >= 1 ? (P == 2 ? 4 : 2) : 2 * Basis<P, K>::NS;   // words per lane
-    static constexpr int WBYTES = P >= 1 ? 16 : 4;
-    static constexpr int BYTES = WORDS * WBYTES * 64;                                 // per chunk and wave
-};
-template <int P, int K>
-__device__ __forceinline__ void bcache_put(char *slot, int lane, const BOp<P, K> &b, const BOp<P, K> &d) {
-    if constexpr (P == 2) {
-        v4f *q = reinterpret_cast<v4f *>(slot) + lane;
-        q[0] = __builtin_bit_cast(v4f, b.v);
-        q[64] = __builtin_bit_cast(v4f, b.lo);
-        q[128] = __builtin_bit_cast(v4f, d.v);
-        q[192] = __builtin_bit_cast(v4f, d.lo);
-    } else if constexpr (P == 1) {
-        v4f *q = reinterpret_cast<v4f *>(slot) + lane;
-        q[0] = __builtin_bit_cast(v4f, b.v);
-        q[64] = __builtin_bit_cast(v4f, d.v);
-    } else {
-        float *q = reinterpret_cast<float *>(slot) + lane;
-#pragma unroll
-        for (int s = 0; s < Basis<P, K>::NS; s++) {
-            q[64 * s] = b.v[s];
-            q[64 * (Basis<P, K>::NS + s)] = d.v[s];
-        }
-    }
-}
-template <int P, int K>
-__device__ __forceinline__ void bcache_get(const char *slot, int lane, BOp<P, K> &b, BOp<P, K> &d) {
-    if constexpr (P == 2) {
-        const v4f *q = reinterpret_cast<const v4f *>(slot) + lane;
-        b.v = __builtin_bit_cast(v8bf, q[0]);
-        b.lo = __builtin_bit_cast(v8bf, q[64]);
-        d.v = __builtin_bit_cast(v8bf, q[128]);
-        d.lo = __builtin_bit_cast(v8bf, q[192]);
-    } else if constexpr (P == 1) {
-        const v4f *q = reinterpret_cast<const v4f *>(slot) + lane;
-        b.v = __builtin_bit_cast(v8bf, q[0]);
-        d.v = __builtin_bit_cast(v8bf, q[64]);
-    } else {
-        const float *q = reinterpret_cast<const float *>(slot) + lane;
-#pragma unroll
-        for (int s = 0; s < Basis<P, K>::NS; s++) {
-            b.v[s] = q[64 * s];
-            d.v[s] = q[64 * (Basis<P, K>::NS + s)];
-        }
-    }
-}
-
 template <int P, int F, int K, bool V0, bool PIW>
 __global__ void __launch_bounds__(64 * (PIW ? BWD_PIW_WAVES : MW)) __attribute__((amdgpu_waves_per_eu(V0 ? BWD_WAVES0 : BWD_WAVES))) k_msg_bwd(const int *__restrict__ rowc, const int *__restrict__ colc,
                                                      const float4 *__restrict__ geom, int n,
@@ -625,7 +637,7 @@ __global__ void __launch_bounds__(64 * (PIW ? BWD_PIW_WAVES : MW)) __attribute__
     constexpr int NPL = PIW ? Pass<F, WM>::N : 1;       // passes per workgroup
     constexpr int NC = PIW ? BWD_CACHE : 0;             // chunks whose basis a wave keeps
     constexpr int WB = WStage<P, F, K, WM, PIW>::BYTES;
-    constexpr int CB = BCache<P, K>::BYTES;
+    constexpr int CB = 2 * BOpStore<P, K>::BYTES;       // basis and derivative of a chunk
     static_assert(!PIW || !V0, "the first layer runs one pass per workgroup");
     __shared__ __attribute__((aligned(16))) char lds[NPL * WB];
     __shared__ v4f xch[NW][PIW ? 1 : 4][64];
@@ -709,13 +721,17 @@ __global__ void __launch_bounds__(64 * (PIW ? BWD_PIW_WAVES : MW)) __attribute__
                 BOp<P, K> bop, dop;
                 const int c = cb >> 4;
                 if (PIW && pi > 0 && c < NC) {
-                    bcache_get<P, K>(bc + c * CB, lane, bop, dop);
+                    bop_get<P, K>(bc + c * CB, lane, bop);
+                    bop_get<P, K>(bc + c * CB + CB / 2, lane, dop);
                 } else {
                     float eb[SL], db[SL];
                     basis_slots<P, K, true>(gm.w, ir, pirc, valid, g, eb, db);
                     bop.set(eb);
                     dop.set(db);
-                    if (PIW && pi == 0 && c < NC) bcache_put<P, K>(bc + c * CB, lane, bop, dop);
+                    if (PIW && pi == 0 && c < NC) {
+                        bop_put<P, K>(bc + c * CB, lane, bop);
+                        bop_put<P, K>(bc + c * CB + CB / 2, lane, dop);
+                    }
                 }
                 // direction of the message edge (i <- j) is x_j - x_i = -(x_i - x_j)
                 const float rx = -gm.x * ir, ry = -gm.y * ir, rz = -gm.z * ir;
@@ -1023,15 +1039,6 @@ static int grid_x(int n) {
     return std::max(1, b);
 }
 
-template <int P, int F, int K>
-static int launch_fwd(hipStream_t st, const MsgArgs &a) {
-    dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F, FWD_W>::N);
-    auto kern = a.layer0 ? k_msg_fwd<P, F, K, true> : k_msg_fwd<P, F, K, false>;
-    kern<<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.u, a.s, a.v, a.A, a.c, a.rc, a.hop,
-                                   a.hop_max, a.species, a.queue, a.sn, a.v1);
-    return hipGetLastError() == hipSuccess ? 0 : -5;
-}
-
 // Workgroups of kern (with the given block size) that the current device
 // holds at once: compute units times the workgroups per compute unit.
 template <class KERN>
@@ -1042,6 +1049,29 @@ static int resident_grid(KERN kern, int block) {
         cus = 256;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, 0) != hipSuccess || per <= 0) per = 1;
     return cus * per;
+}
+
+template <int P, int F, int K>
+static int launch_fwd(hipStream_t st, const MsgArgs &a) {
+    constexpr bool piw = Pass<F, FWD_W>::N > 1;
+    if constexpr (piw) {
+        if (!a.layer0) {
+            auto kern = k_msg_fwd<P, F, K, false, true>;
+            constexpr int block = 64 * FWD_PIW_WAVES;
+            static const int resident = resident_grid(kern, block);   // per process: one device type
+            int b = std::min(resident, (a.n + FWD_PIW_WAVES - 1) / FWD_PIW_WAVES);
+            if (b >= 8) b -= b % 8;
+            kern<<<dim3((unsigned)std::max(1, b)), block, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.u, a.s, a.v,
+                                                                   a.A, a.c, a.rc, a.hop, a.hop_max, a.species,
+                                                                   a.queue, a.sn, a.v1);
+            return hipGetLastError() == hipSuccess ? 0 : -5;
+        }
+    }
+    dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F, FWD_W>::N);
+    auto kern = a.layer0 ? k_msg_fwd<P, F, K, true, false> : k_msg_fwd<P, F, K, false, false>;
+    kern<<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.u, a.s, a.v, a.A, a.c, a.rc, a.hop,
+                                   a.hop_max, a.species, a.queue, a.sn, a.v1);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
 template <int P, int F, int K>
