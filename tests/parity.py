@@ -4,8 +4,13 @@ Tolerances per precision mode (operand forms of the node GEMMs / the radial
 filter; every accumulation FP32, energy sums FP64):
 
 * fp32 (FP32 / FP32): forces 1e-5 relative RMS, the target for this path;
-  energy 2e-6 relative (per-atom FP32 energies, ~1e-7 rounding each, summed
-  in FP64).
+  energy 5e-6 relative, half of it.  The energy is summed in FP64, but each
+  per-atom energy is the output of the FP32 network and carries the rounding
+  of its activations (hundreds of FP32 terms per product, three layers), the
+  same rounding that the forces carry: measured 1.2e-6 to 2.1e-6 for the
+  128-feature water models, depending on the order of the sums in the
+  message kernels.  One dropped edge term moves a 192-atom box's energy by
+  about 1e-4, so the bound still sees it.
 * bf16 = bf16x3 (split bf16 / split bf16): each operand is hi + lo with
   |x - hi - lo| <= 2^-18 |x| and the dropped lo*lo product is <= 2^-18 of the
   product, so a product carries ~2^-17 (7.6e-6) relative error against
@@ -43,7 +48,7 @@ from __future__ import annotations
 import numpy as np
 
 TOL = {  # mode: (energy relative to |E_ref|, force relative RMS)
-    "fp32": (2e-6, 1e-5),
+    "fp32": (5e-6, 1e-5),
     "bf16": (1e-4, 5e-4),
     "bf16x3": (1e-4, 5e-4),
     "bf16_fast": (5e-2, 5e-2),
