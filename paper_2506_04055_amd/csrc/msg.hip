@@ -235,8 +235,10 @@ __device__ __forceinline__ void stage_pass(const float *__restrict__ A, const fl
 }
 
 // Filter values of local tile t (rows 16t .. 16t+15): lane (e, g) receives
-// features 4g .. 4g+3 of the tile for its edge e.
-template <int P, int F, int K, int WM, bool SW = false>
+// features 4g .. 4g+3 of the tile for its edge e; with TR (the operands
+// swapped, the same products) lane (f, g) receives feature f of the tile for
+// the edges 4g .. 4g+3.
+template <int P, int F, int K, int WM, bool SW = false, bool TR = false>
 __device__ __forceinline__ v4f filter_tile(const void *lds, int t, const BOp<P, K> &b, int lane) {
     using WS = WStage<P, F, K, WM, SW>;
     v4f acc = {0.f, 0.f, 0.f, 0.f};
@@ -246,19 +248,28 @@ __device__ __forceinline__ v4f filter_tile(const void *lds, int t, const BOp<P, 
     const int col = 8 * (WS::SWZ ? g ^ wswz(lane & 15) : g);
     if constexpr (P == 1) {
         const v8bf a = *reinterpret_cast<const v8bf *>(reinterpret_cast<const __bf16 *>(lds) + row * WS::LD + col);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.v, acc, 0, 0, 0);
+        if constexpr (TR) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b.v, a, acc, 0, 0, 0);
+        else acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.v, acc, 0, 0, 0);
     } else if constexpr (P == 2) {
         const __bf16 *t0 = reinterpret_cast<const __bf16 *>(lds) + row * WS::LD + col;
         const v8bf a = *reinterpret_cast<const v8bf *>(t0);
         const v8bf al = *reinterpret_cast<const v8bf *>(t0 + WS::ROWS * WS::LD);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b.v, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.lo, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.v, acc, 0, 0, 0);
+        if constexpr (TR) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b.v, al, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b.lo, a, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b.v, a, acc, 0, 0, 0);
+        } else {
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b.v, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.lo, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.v, acc, 0, 0, 0);
+        }
     } else {
         const float *w = reinterpret_cast<const float *>(lds) + row * WS::LD;
 #pragma unroll
-        for (int s = 0; s < Basis<P, K>::NS; s++)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w[4 * s + g], b.v[s], acc, 0, 0, 0);
+        for (int s = 0; s < Basis<P, K>::NS; s++) {
+            if constexpr (TR) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(b.v[s], w[4 * s + g], acc, 0, 0, 0);
+            else acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w[4 * s + g], b.v[s], acc, 0, 0, 0);
+        }
     }
     return acc;
 }
@@ -427,21 +438,11 @@ __device__ __forceinline__ void bop_get(const char *slot, int lane, BOp<P, K> &b
 }
 
 // ---------------------------------------------------------------------------
-// Forward message pass.  Two arrangements of the feature passes, as in the
-// adjoint below: with PIW (the layers after the first, more than one pass)
-// every wave runs all passes of its atom with the weight images of every
-// pass in LDS, and the radial basis of a chunk, in MFMA operand form, is
-// evaluated in the first pass and kept in the wave's LDS for the later ones
-// (the first FWD_CACHE chunks of the atom); otherwise blockIdx.y is the pass.
+// Forward message pass, one feature pass (blockIdx.y) per workgroup: the
+// first layer, and models with a single pass.
 // ---------------------------------------------------------------------------
-#ifndef FWD_PIW_WAVES
-#define FWD_PIW_WAVES 16
-#endif
-#ifndef FWD_CACHE
-#define FWD_CACHE 3
-#endif
-template <int P, int F, int K, bool V0, bool PIW>
-__global__ void __launch_bounds__(64 * (PIW ? FWD_PIW_WAVES : MW)) __attribute__((amdgpu_waves_per_eu(V0 ? FWD_WAVES0 : FWD_WAVES))) k_msg_fwd(const int *__restrict__ rowc, const int *__restrict__ colc,
+template <int P, int F, int K, bool V0>
+__global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0 ? FWD_WAVES0 : FWD_WAVES))) k_msg_fwd(const int *__restrict__ rowc, const int *__restrict__ colc,
                                                      const float4 *__restrict__ geom, int n,
                                                      const float *__restrict__ phi, const float *__restrict__ uvp,
                                                      const float *__restrict__ s, const float *__restrict__ v,
@@ -452,40 +453,187 @@ __global__ void __launch_bounds__(64 * (PIW ? FWD_PIW_WAVES : MW)) __attribute__
                                                      float *__restrict__ sn, float *__restrict__ v1) {
     constexpr int WM = FWD_W;
     constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F, WM>::W, TU = Pass<F, WM>::TU;
-    constexpr int NW = PIW ? FWD_PIW_WAVES : MW;        // waves per workgroup
-    constexpr int NPL = PIW ? Pass<F, WM>::N : 1;       // passes per workgroup
-    constexpr int NC = PIW ? FWD_CACHE : 0;             // chunks whose basis a wave keeps
-    constexpr int WB = WStage<P, F, K, WM, PIW>::BYTES;
-    constexpr int CB = BOpStore<P, K>::BYTES;
-    static_assert(!PIW || !V0, "the first layer runs one pass per workgroup");
-    __shared__ __attribute__((aligned(16))) char lds[NPL * WB];
+    __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K, WM>::BYTES];
     // first layer: phi and s are per-species tables (rows by zsp), a few rows
     // that every gather hits in L1, read directly in the accumulator layout
-    __shared__ v4f xch[NW][(V0 || PIW) ? 1 : 5][64];
-    __shared__ __attribute__((aligned(16))) char bcache[PIW ? NW * NC * CB : 16];
-#pragma unroll 1
-    for (int q = 0; q < NPL; q++) stage_pass<P, F, K, WM, PIW>(Aw, cw, PIW ? q : (int)blockIdx.y, lds + q * WB);
+    __shared__ v4f xch[MW][V0 ? 1 : 5][64];
+    const int p = blockIdx.y;
+    stage_pass<P, F, K, WM>(Aw, cw, p, lds);
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
+    const int fo = p * W + 4 * g;   // first feature of this lane (tile u adds 16 u)
     const Xch xc(g, e);
     v4f(*xw)[64] = xch[threadIdx.x >> 6];
-    char *bc = bcache + (PIW ? (threadIdx.x >> 6) * NC * CB : 0);
-    const AtomQueue aq(n, queue, PIW ? 0 : (int)blockIdx.y);
+    const AtomQueue aq(n, queue, p);
+    const float pirc = 3.14159265358979f / rc;
+    MSG_ATOMS(aq, i) {
+        const int e0 = rowc[i], e1 = rowc[i + 1];
+        const int deg = hop[i] <= hop_max ? e1 - e0 : 0;
+        v4f as[TU], av[3][TU];
+#pragma unroll
+        for (int u = 0; u < TU; u++) {
+            as[u] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int d = 0; d < 3; d++) av[d][u] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+        // edge records of the next chunk are loaded one chunk ahead
+        float4 gm_n = make_float4(0.f, 0.f, 0.f, rc);
+        int j_n = i;
+        if (e < deg) {
+            gm_n = geom[e0 + e];
+            j_n = colc[e0 + e];
+        }
+        for (int cb = 0; cb < deg; cb += 16) {
+            const char *wl = lds_chunk(lds);
+            const bool valid = cb + e < deg;
+            const float4 gm = gm_n;
+            const int j = j_n;
+            gm_n = make_float4(0.f, 0.f, 0.f, rc);
+            j_n = i;
+            if (cb + 16 + e < deg) {
+                gm_n = geom[e0 + cb + 16 + e];
+                j_n = colc[e0 + cb + 16 + e];
+            }
+            // gathered: phi_s, phi_vs and (after the first layer) u = v * phi_vv
+            // of the source (5 row slices, quarter-contiguously, then moved to
+            // the accumulator layout; the first layer's 2 from the table)
+            v4f ph[2][TU], uu[3][TU];
+            if constexpr (V0) {
+                const float *pj = phi + (long)zsp[j] * F3 + fo;
+#pragma unroll
+                for (int u = 0; u < TU; u++) {
+                    ph[0][u] = ld4(pj + F + 16 * u);
+                    ph[1][u] = ld4(pj + 2 * F + 16 * u);
+                }
+            } else {
+                const int jq = __shfl(j, xc.src, 64);
+                const float *pj = phi + (long)jq * F3 + p * W + xc.fo;
+                const float *uj = uvp + (long)jq * F3 + p * W + xc.fo;
+#pragma unroll
+                for (int u = 0; u < TU; u++) {
+                    ph[0][u] = ld4(pj + F + 16 * u);
+                    ph[1][u] = ld4(pj + 2 * F + 16 * u);
+#pragma unroll
+                    for (int d = 0; d < 3; d++) uu[d][u] = ld4(uj + d * F + 16 * u);
+                }
+#pragma unroll
+                for (int u = 0; u < TU; u++) {
+                    ph[0][u] = xc.move(xw[0], ph[0][u]);
+                    ph[1][u] = xc.move(xw[1], ph[1][u]);
+#pragma unroll
+                    for (int d = 0; d < 3; d++) uu[d][u] = xc.move(xw[2 + d], uu[d][u]);
+                }
+            }
+            const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
+            float eb[SL];
+            basis_slots<P, K, false>(gm.w, ir, pirc, valid, g, eb, nullptr);
+            BOp<P, K> bop;
+            bop.set(eb);
+            const float rx = gm.x * ir, ry = gm.y * ir, rz = gm.z * ir;
+#pragma unroll
+            for (int u = 0; u < TU; u++) {
+                v4f wvv;
+                if constexpr (!V0) wvv = filter_tile<P, F, K, WM>(wl, u, bop, lane);
+                const v4f ws = filter_tile<P, F, K, WM>(wl, TU + u, bop, lane);
+                const v4f wvs = filter_tile<P, F, K, WM>(wl, 2 * TU + u, bop, lane);
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const float xvs = ph[1][u][r] * wvs[r];
+                    as[u][r] = fmaf(ph[0][u][r], ws[r], as[u][r]);
+                    if constexpr (V0) {
+                        av[0][u][r] = fmaf(rx, xvs, av[0][u][r]);
+                        av[1][u][r] = fmaf(ry, xvs, av[1][u][r]);
+                        av[2][u][r] = fmaf(rz, xvs, av[2][u][r]);
+                    } else {
+                        av[0][u][r] = fmaf(uu[0][u][r], wvv[r], fmaf(rx, xvs, av[0][u][r]));
+                        av[1][u][r] = fmaf(uu[1][u][r], wvv[r], fmaf(ry, xvs, av[1][u][r]));
+                        av[2][u][r] = fmaf(uu[2][u][r], wvv[r], fmaf(rz, xvs, av[2][u][r]));
+                    }
+                }
+            }
+        }
+        // sum over the 16 edge lanes of each row
+#pragma unroll
+        for (int u = 0; u < TU; u++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                as[u][r] = row_sum16(as[u][r]);
+#pragma unroll
+                for (int d = 0; d < 3; d++) av[d][u][r] = row_sum16(av[d][u][r]);
+            }
+        if (e == 0) {
+#pragma unroll
+            for (int u = 0; u < TU; u++) {
+                const int f = fo + 16 * u;
+                const long si = V0 ? (long)zsp[i] : (long)i;
+                st4(sn + (long)i * 2 * F + f, ld4(s + si * F + f) + as[u]);
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    if constexpr (V0) st4(v1 + (long)i * F3 + d * F + f, av[d][u]);
+                    else st4(v1 + (long)i * F3 + d * F + f, ld4(v + (long)i * F3 + d * F + f) + av[d][u]);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward message pass of the layers after the first with more than one
+// feature pass: every wave runs all passes of its atom, with the weight
+// images of every pass in LDS, and the radial basis of a chunk, in MFMA
+// operand form, is evaluated in the first pass and kept in the wave's LDS for
+// the later ones (the first FWD_CACHE chunks of the atom).  The filter tiles
+// come out transposed (filter_tile with TR): lane (f, g) holds feature f of
+// the tile for the edges 4g .. 4g+3, so it gathers 16 consecutive features
+// of one source row per quarter-wave and register (no exchange), adds its
+// four edges in registers, and the sums over the atom's edges need only a
+// sum over the four lane rows at the end.  The basis is evaluated in the
+// layout the MFMA operand takes (lane (e, g): slots of edge e); the source
+// index and direction of the edges 4g + r move to the vector layout by lane
+// shuffles.
+// ---------------------------------------------------------------------------
+#ifndef FWD_PIW_WAVES
+#define FWD_PIW_WAVES 16
+#endif
+#ifndef FWD_CACHE
+#define FWD_CACHE 3
+#endif
+template <int P, int F, int K>
+__global__ void __launch_bounds__(64 * FWD_PIW_WAVES) __attribute__((amdgpu_waves_per_eu(FWD_WAVES))) k_msg_fwd_pw(const int *__restrict__ rowc, const int *__restrict__ colc,
+                                                     const float4 *__restrict__ geom, int n,
+                                                     const float *__restrict__ phi, const float *__restrict__ uvp,
+                                                     const float *__restrict__ s, const float *__restrict__ v,
+                                                     const float *__restrict__ Aw,
+                                                     const float *__restrict__ cw, float rc,
+                                                     const int8_t *__restrict__ hop, int hop_max,
+                                                     int *__restrict__ queue,
+                                                     float *__restrict__ sn, float *__restrict__ v1) {
+    constexpr int WM = FWD_W;
+    constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F, WM>::W, TU = Pass<F, WM>::TU;
+    constexpr int NP = Pass<F, WM>::N, NC = FWD_CACHE;
+    constexpr int WB = WStage<P, F, K, WM, true>::BYTES;
+    constexpr int CB = BOpStore<P, K>::BYTES;
+    __shared__ __attribute__((aligned(16))) char lds[NP * WB];
+    __shared__ __attribute__((aligned(16))) char bcache[FWD_PIW_WAVES * NC * CB];
+#pragma unroll 1
+    for (int q = 0; q < NP; q++) stage_pass<P, F, K, WM, true>(Aw, cw, q, lds + q * WB);
+    const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
+    char *bc = bcache + (threadIdx.x >> 6) * NC * CB;
+    const AtomQueue aq(n, queue, 0);
     const float pirc = 3.14159265358979f / rc;
     MSG_ATOMS(aq, i) {
         const int e0 = rowc[i], e1 = rowc[i + 1];
         const int deg = hop[i] <= hop_max ? e1 - e0 : 0;
 #pragma unroll 1
-        for (int pi = 0; pi < NPL; pi++) {
-            const int p = PIW ? pi : (int)blockIdx.y;
-            const int fo = p * W + 4 * g;   // first feature of this lane (tile u adds 16 u)
-            v4f as[TU], av[3][TU];
+        for (int p = 0; p < NP; p++) {
+            const int fl = p * W + e;   // this lane's feature (tile u adds 16 u)
+            float as[TU], av[3][TU];
 #pragma unroll
             for (int u = 0; u < TU; u++) {
-                as[u] = v4f{0.f, 0.f, 0.f, 0.f};
+                as[u] = 0.f;
 #pragma unroll
-                for (int d = 0; d < 3; d++) av[d][u] = v4f{0.f, 0.f, 0.f, 0.f};
+                for (int d = 0; d < 3; d++) av[d][u] = 0.f;
             }
-            // edge records of the next chunk are loaded one chunk ahead
+            // edge records (edge e of the chunk) are loaded one chunk ahead
             float4 gm_n = make_float4(0.f, 0.f, 0.f, rc);
             int j_n = i;
             if (e < deg) {
@@ -493,7 +641,7 @@ __global__ void __launch_bounds__(64 * (PIW ? FWD_PIW_WAVES : MW)) __attribute__
                 j_n = colc[e0 + e];
             }
             for (int cb = 0; cb < deg; cb += 16) {
-                const char *wl = lds_chunk(lds + pi * WB);
+                const char *wl = lds_chunk(lds + p * WB);
                 const bool valid = cb + e < deg;
                 const float4 gm = gm_n;
                 const int j = j_n;
@@ -503,90 +651,77 @@ __global__ void __launch_bounds__(64 * (PIW ? FWD_PIW_WAVES : MW)) __attribute__
                     gm_n = geom[e0 + cb + 16 + e];
                     j_n = colc[e0 + cb + 16 + e];
                 }
-                // gathered: phi_s, phi_vs and (after the first layer) u = v * phi_vv
-                // of the source (5 row slices, quarter-contiguously, then moved to
-                // the accumulator layout; the first layer's 2 from the table)
-                v4f ph[2][TU], uu[3][TU];
-                if constexpr (V0) {
-                    const float *pj = phi + (long)zsp[j] * F3 + fo;
+                const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
+                const float rx = gm.x * ir, ry = gm.y * ir, rz = gm.z * ir;
+                // source rows and directions of this lane's edges 4g + r (padding
+                // edges: the atom's own row and a zero direction; their filter is 0)
+                int jr[4];
+                float hx[4], hy[4], hz[4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int src = 4 * g + r;
+                    jr[r] = __shfl(j, src, 64);
+                    hx[r] = __shfl(rx, src, 64);
+                    hy[r] = __shfl(ry, src, 64);
+                    hz[r] = __shfl(rz, src, 64);
+                }
+                float ps[TU][4], pv[TU][4], uu[3][TU][4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const float *pj = phi + (long)jr[r] * F3 + fl;
+                    const float *uj = uvp + (long)jr[r] * F3 + fl;
 #pragma unroll
                     for (int u = 0; u < TU; u++) {
-                        ph[0][u] = ld4(pj + F + 16 * u);
-                        ph[1][u] = ld4(pj + 2 * F + 16 * u);
-                    }
-                } else {
-                    const int jq = __shfl(j, xc.src, 64);
-                    const float *pj = phi + (long)jq * F3 + p * W + xc.fo;
-                    const float *uj = uvp + (long)jq * F3 + p * W + xc.fo;
+                        ps[u][r] = pj[F + 16 * u];
+                        pv[u][r] = pj[2 * F + 16 * u];
 #pragma unroll
-                    for (int u = 0; u < TU; u++) {
-                        ph[0][u] = ld4(pj + F + 16 * u);
-                        ph[1][u] = ld4(pj + 2 * F + 16 * u);
-#pragma unroll
-                        for (int d = 0; d < 3; d++) uu[d][u] = ld4(uj + d * F + 16 * u);
-                    }
-#pragma unroll
-                    for (int u = 0; u < TU; u++) {
-                        ph[0][u] = xc.move(xw[0], ph[0][u]);
-                        ph[1][u] = xc.move(xw[PIW ? 0 : 1], ph[1][u]);
-#pragma unroll
-                        for (int d = 0; d < 3; d++) uu[d][u] = xc.move(xw[PIW ? 0 : 2 + d], uu[d][u]);
+                        for (int d = 0; d < 3; d++) uu[d][u][r] = uj[d * F + 16 * u];
                     }
                 }
-                const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
                 BOp<P, K> bop;
                 const int c = cb >> 4;
-                if (PIW && pi > 0 && c < NC) {
+                if (p > 0 && c < NC) {
                     bop_get<P, K>(bc + c * CB, lane, bop);
                 } else {
                     float eb[SL];
                     basis_slots<P, K, false>(gm.w, ir, pirc, valid, g, eb, nullptr);
                     bop.set(eb);
-                    if (PIW && pi == 0 && c < NC) bop_put<P, K>(bc + c * CB, lane, bop);
+                    if (p == 0 && c < NC) bop_put<P, K>(bc + c * CB, lane, bop);
                 }
-                const float rx = gm.x * ir, ry = gm.y * ir, rz = gm.z * ir;
 #pragma unroll
                 for (int u = 0; u < TU; u++) {
-                    v4f wvv;
-                    if constexpr (!V0) wvv = filter_tile<P, F, K, WM, PIW>(wl, u, bop, lane);
-                    const v4f ws = filter_tile<P, F, K, WM, PIW>(wl, TU + u, bop, lane);
-                    const v4f wvs = filter_tile<P, F, K, WM, PIW>(wl, 2 * TU + u, bop, lane);
+                    const v4f wvv = filter_tile<P, F, K, WM, true, true>(wl, u, bop, lane);
+                    const v4f ws = filter_tile<P, F, K, WM, true, true>(wl, TU + u, bop, lane);
+                    const v4f wvs = filter_tile<P, F, K, WM, true, true>(wl, 2 * TU + u, bop, lane);
 #pragma unroll
                     for (int r = 0; r < 4; r++) {
-                        const float xvs = ph[1][u][r] * wvs[r];
-                        as[u][r] = fmaf(ph[0][u][r], ws[r], as[u][r]);
-                        if constexpr (V0) {
-                            av[0][u][r] = fmaf(rx, xvs, av[0][u][r]);
-                            av[1][u][r] = fmaf(ry, xvs, av[1][u][r]);
-                            av[2][u][r] = fmaf(rz, xvs, av[2][u][r]);
-                        } else {
-                            av[0][u][r] = fmaf(uu[0][u][r], wvv[r], fmaf(rx, xvs, av[0][u][r]));
-                            av[1][u][r] = fmaf(uu[1][u][r], wvv[r], fmaf(ry, xvs, av[1][u][r]));
-                            av[2][u][r] = fmaf(uu[2][u][r], wvv[r], fmaf(rz, xvs, av[2][u][r]));
-                        }
+                        const float xvs = pv[u][r] * wvs[r];
+                        as[u] = fmaf(ps[u][r], ws[r], as[u]);
+                        av[0][u] = fmaf(uu[0][u][r], wvv[r], fmaf(hx[r], xvs, av[0][u]));
+                        av[1][u] = fmaf(uu[1][u][r], wvv[r], fmaf(hy[r], xvs, av[1][u]));
+                        av[2][u] = fmaf(uu[2][u][r], wvv[r], fmaf(hz[r], xvs, av[2][u]));
                     }
                 }
             }
-            // sum over the 16 edge lanes of each row
+            // sum over the four lane rows (edges 4g .. 4g+3 of every chunk)
 #pragma unroll
-            for (int u = 0; u < TU; u++)
+            for (int u = 0; u < TU; u++) {
+                as[u] += __shfl_xor(as[u], 16, 64);
+                as[u] += __shfl_xor(as[u], 32, 64);
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    as[u][r] = row_sum16(as[u][r]);
-#pragma unroll
-                    for (int d = 0; d < 3; d++) av[d][u][r] = row_sum16(av[d][u][r]);
+                for (int d = 0; d < 3; d++) {
+                    av[d][u] += __shfl_xor(av[d][u], 16, 64);
+                    av[d][u] += __shfl_xor(av[d][u], 32, 64);
                 }
-            if (e == 0) {
+            }
+            if (g == 0) {
 #pragma unroll
                 for (int u = 0; u < TU; u++) {
-                    const int f = fo + 16 * u;
-                    const long si = V0 ? (long)zsp[i] : (long)i;
-                    st4(sn + (long)i * 2 * F + f, ld4(s + si * F + f) + as[u]);
+                    const int f = fl + 16 * u;
+                    sn[(long)i * 2 * F + f] = s[(long)i * F + f] + as[u];
 #pragma unroll
-                    for (int d = 0; d < 3; d++) {
-                        if constexpr (V0) st4(v1 + (long)i * F3 + d * F + f, av[d][u]);
-                        else st4(v1 + (long)i * F3 + d * F + f, ld4(v + (long)i * F3 + d * F + f) + av[d][u]);
-                    }
+                    for (int d = 0; d < 3; d++)
+                        v1[(long)i * F3 + d * F + f] = v[(long)i * F3 + d * F + f] + av[d][u];
                 }
             }
         }
@@ -1056,19 +1191,19 @@ static int launch_fwd(hipStream_t st, const MsgArgs &a) {
     constexpr bool piw = Pass<F, FWD_W>::N > 1;
     if constexpr (piw) {
         if (!a.layer0) {
-            auto kern = k_msg_fwd<P, F, K, false, true>;
+            auto kern = k_msg_fwd_pw<P, F, K>;
             constexpr int block = 64 * FWD_PIW_WAVES;
             static const int resident = resident_grid(kern, block);   // per process: one device type
             int b = std::min(resident, (a.n + FWD_PIW_WAVES - 1) / FWD_PIW_WAVES);
             if (b >= 8) b -= b % 8;
             kern<<<dim3((unsigned)std::max(1, b)), block, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.u, a.s, a.v,
-                                                                   a.A, a.c, a.rc, a.hop, a.hop_max, a.species,
-                                                                   a.queue, a.sn, a.v1);
+                                                                   a.A, a.c, a.rc, a.hop, a.hop_max, a.queue, a.sn,
+                                                                   a.v1);
             return hipGetLastError() == hipSuccess ? 0 : -5;
         }
     }
     dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F, FWD_W>::N);
-    auto kern = a.layer0 ? k_msg_fwd<P, F, K, true, false> : k_msg_fwd<P, F, K, false, false>;
+    auto kern = a.layer0 ? k_msg_fwd<P, F, K, true> : k_msg_fwd<P, F, K, false>;
     kern<<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.u, a.s, a.v, a.A, a.c, a.rc, a.hop,
                                    a.hop_max, a.species, a.queue, a.sn, a.v1);
     return hipGetLastError() == hipSuccess ? 0 : -5;
