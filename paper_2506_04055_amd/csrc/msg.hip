@@ -729,35 +729,15 @@ __global__ void __launch_bounds__(64 * FWD_PIW_WAVES) __attribute__((amdgpu_wave
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint of the message pass.
+// Adjoint of the message pass, one feature pass (blockIdx.y) per workgroup:
+// the first layer, and models with a single pass.
 // Per chunk of 16 in-edges (j <- i) of the source atom j: the filter tiles and
 // their radial derivatives on MFMA, the destinations' gradient pieces
 // gathered per lane, dE/dphi_j and dE/dv_j accumulated in registers, and the
 // edge sums S = (dE/dr, dE/drhat) of the pass stored in the pass's slot.
-//
-// Two arrangements of the feature passes:
-//   * PIW (the layers after the first, more than one pass): every wave runs
-//     all passes of its atom, one after the other, with the weight images of
-//     every pass in LDS.  The radial basis and its derivative of a chunk, in
-//     the MFMA operand form (the split conversion included), are evaluated
-//     in the first pass and kept in the wave's LDS for the later ones (for
-//     the first BWD_CACHE chunks of the atom; later chunks are re-evaluated).
-//     The edge sums of the passes are added up in the wave, in pass order
-//     (in LDS for the cached chunks, in the slot itself for the others: the
-//     lane that adds is the lane that stored), so the layer has one slot.
-//     The workgroups fill the GPU once (one per compute unit).
-//   * otherwise blockIdx.y is the pass and the basis is evaluated per pass;
-//     pass p stores its sums in slot p.
 // ---------------------------------------------------------------------------
-#ifndef BWD_PIW_WAVES
-#define BWD_PIW_WAVES 8
-#endif
-#ifndef BWD_CACHE
-#define BWD_CACHE 3
-#endif
-
-template <int P, int F, int K, bool V0, bool PIW>
-__global__ void __launch_bounds__(64 * (PIW ? BWD_PIW_WAVES : MW)) __attribute__((amdgpu_waves_per_eu(V0 ? BWD_WAVES0 : BWD_WAVES))) k_msg_bwd(const int *__restrict__ rowc, const int *__restrict__ colc,
+template <int P, int F, int K, bool V0>
+__global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(V0 ? BWD_WAVES0 : BWD_WAVES))) k_msg_bwd(const int *__restrict__ rowc, const int *__restrict__ colc,
                                                      const float4 *__restrict__ geom, int n,
                                                      const float *__restrict__ phi, const float *__restrict__ v,
                                                      const float *__restrict__ gs1, const float *__restrict__ gv1,
@@ -768,56 +748,256 @@ __global__ void __launch_bounds__(64 * (PIW ? BWD_PIW_WAVES : MW)) __attribute__
                                                      float4 *__restrict__ S, long s_stride) {
     constexpr int WM = BWD_W;
     constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F, WM>::W, TU = Pass<F, WM>::TU;
-    constexpr int NW = PIW ? BWD_PIW_WAVES : MW;        // waves per workgroup
-    constexpr int NPL = PIW ? Pass<F, WM>::N : 1;       // passes per workgroup
-    constexpr int NC = PIW ? BWD_CACHE : 0;             // chunks whose basis a wave keeps
-    constexpr int WB = WStage<P, F, K, WM, PIW>::BYTES;
-    constexpr int CB = 2 * BOpStore<P, K>::BYTES;       // basis and derivative of a chunk
-    static_assert(!PIW || !V0, "the first layer runs one pass per workgroup");
-    __shared__ __attribute__((aligned(16))) char lds[NPL * WB];
-    __shared__ v4f xch[NW][PIW ? 1 : 4][64];
-    __shared__ __attribute__((aligned(16))) char bcache[PIW ? NW * NC * CB : 16];
-    __shared__ float4 sacc[PIW ? NW : 1][PIW ? NC : 1][16];   // edge sums of the cached chunks
-#pragma unroll 1
-    for (int q = 0; q < NPL; q++) stage_pass<P, F, K, WM, PIW>(Aw, cw, PIW ? q : (int)blockIdx.y, lds + q * WB);
+    __shared__ __attribute__((aligned(16))) char lds[WStage<P, F, K, WM>::BYTES];
+    __shared__ v4f xch[MW][4][64];
+    const int p = blockIdx.y;
+    stage_pass<P, F, K, WM>(Aw, cw, p, lds);
+    float4 *Sp = S + (long)p * s_stride;
     const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
+    const int fo = p * W + 4 * g;
     const Xch xc(g, e);
     v4f(*xw)[64] = xch[threadIdx.x >> 6];
-    char *bc = bcache + (PIW ? (threadIdx.x >> 6) * NC * CB : 0);
-    const AtomQueue aq(n, queue, PIW ? 0 : (int)blockIdx.y);
+    const AtomQueue aq(n, queue, p);
+    const float pirc = 3.14159265358979f / rc;
+    MSG_ATOMS(aq, j) {
+        const int e0 = rowc[j], e1 = rowc[j + 1];
+        const int deg = hop[j] <= hop_max ? e1 - e0 : 0;
+        // first layer: v_j = 0 and no node gradient, so phi_vv, v_j, dE/dphi_j
+        // and dE/dv_j drop out and only the edge sums remain.
+        // Later layers accumulate Y_d = sum_e dE/dv1_d(i) w_vv (from which both
+        // dE/dv_j = phi_vv Y_d and dE/dphi_vv = sum_d v_jd Y_d follow once per
+        // atom), dE/dphi_s and dE/dphi_vs; the v_j term of dE/dr enters through
+        // c_d = v_jd phi_vv.
+        v4f ph[3][TU], cv[3][TU], Y[3][TU], ap[2][TU];
+#pragma unroll
+        for (int u = 0; u < TU; u++) {
+#pragma unroll
+            for (int q = V0 ? 1 : 0; q < 3; q++) ph[q][u] = ld4(phi + (V0 ? (long)zsp[j] : (long)j) * F3 + q * F + fo + 16 * u);
+            if constexpr (!V0) {
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    cv[d][u] = ld4(v + (long)j * F3 + d * F + fo + 16 * u) * ph[0][u];
+                    Y[d][u] = v4f{0.f, 0.f, 0.f, 0.f};
+                }
+                ap[0][u] = v4f{0.f, 0.f, 0.f, 0.f};
+                ap[1][u] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+        // edges of an atom beyond the hop range carry no gradient in this layer
+        if (hop[j] > hop_max)
+            for (int q = e0 + lane; q < e1; q += 64) Sp[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 gm_n = make_float4(0.f, 0.f, 0.f, rc);
+        int i_n = j;
+        if (e < deg) {
+            gm_n = geom[e0 + e];
+            i_n = colc[e0 + e];
+        }
+        for (int cb = 0; cb < deg; cb += 16) {
+            const char *wl = lds_chunk(lds);
+            const bool valid = cb + e < deg;
+            const float4 gm = gm_n;
+            const int i = i_n;
+            gm_n = make_float4(0.f, 0.f, 0.f, rc);
+            i_n = j;
+            if (cb + 16 + e < deg) {
+                gm_n = geom[e0 + cb + 16 + e];
+                i_n = colc[e0 + cb + 16 + e];
+            }
+            // the destinations' gradient rows, gathered quarter-contiguously and
+            // moved to the accumulator layout
+            const int iq = __shfl(i, xc.src, 64);
+            v4f gs[TU], gv[3][TU];
+#pragma unroll
+            for (int u = 0; u < TU; u++) {
+                gs[u] = ld4(gs1 + (long)iq * F + p * W + xc.fo + 16 * u);
+#pragma unroll
+                for (int d = 0; d < 3; d++) gv[d][u] = ld4(gv1 + (long)iq * F3 + d * F + p * W + xc.fo + 16 * u);
+            }
+#pragma unroll
+            for (int u = 0; u < TU; u++) {
+                gs[u] = xc.move(xw[0], gs[u]);
+#pragma unroll
+                for (int d = 0; d < 3; d++) gv[d][u] = xc.move(xw[1 + d], gv[d][u]);
+            }
+            const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
+            float eb[SL], db[SL];
+            basis_slots<P, K, true>(gm.w, ir, pirc, valid, g, eb, db);
+            BOp<P, K> bop, dop;
+            bop.set(eb);
+            dop.set(db);
+            // direction of the message edge (i <- j) is x_j - x_i = -(x_i - x_j)
+            const float rx = -gm.x * ir, ry = -gm.y * ir, rz = -gm.z * ir;
+            float sr = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+            for (int u = 0; u < TU; u++) {
+                v4f w0, w1, d0;
+                if constexpr (!V0) {
+                    w0 = filter_tile<P, F, K, WM>(wl, u, bop, lane);
+                    w1 = filter_tile<P, F, K, WM>(wl, TU + u, bop, lane);
+                }
+                const v4f w2 = filter_tile<P, F, K, WM>(wl, 2 * TU + u, bop, lane);
+                if constexpr (!V0) d0 = filter_tile<P, F, K, WM>(wl, u, dop, lane);
+                const v4f d1 = filter_tile<P, F, K, WM>(wl, TU + u, dop, lane);
+                const v4f d2 = filter_tile<P, F, K, WM>(wl, 2 * TU + u, dop, lane);
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const float ga = gv[0][u][r], gb = gv[1][u][r], gc = gv[2][u][r], gsr = gs[u][r];
+                    const float gxvs = fmaf(ga, rx, fmaf(gb, ry, gc * rz));
+                    const float xvs = ph[2][u][r] * w2[r];
+                    sx = fmaf(ga, xvs, sx);
+                    sy = fmaf(gb, xvs, sy);
+                    sz = fmaf(gc, xvs, sz);
+                    if constexpr (V0) {
+                        sr = fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr));
+                        continue;
+                    }
+                    const float gc0 = fmaf(ga, cv[0][u][r], fmaf(gb, cv[1][u][r], gc * cv[2][u][r]));
+                    Y[0][u][r] = fmaf(ga, w0[r], Y[0][u][r]);
+                    Y[1][u][r] = fmaf(gb, w0[r], Y[1][u][r]);
+                    Y[2][u][r] = fmaf(gc, w0[r], Y[2][u][r]);
+                    ap[0][u][r] = fmaf(gsr, w1[r], ap[0][u][r]);
+                    ap[1][u][r] = fmaf(gxvs, w2[r], ap[1][u][r]);
+                    sr = fmaf(gc0, d0[r], fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr)));
+                }
+            }
+            // sum over the four lane rows (all features of the pass)
+            sr += __shfl_xor(sr, 16, 64);
+            sx += __shfl_xor(sx, 16, 64);
+            sy += __shfl_xor(sy, 16, 64);
+            sz += __shfl_xor(sz, 16, 64);
+            sr += __shfl_xor(sr, 32, 64);
+            sx += __shfl_xor(sx, 32, 64);
+            sy += __shfl_xor(sy, 32, 64);
+            sz += __shfl_xor(sz, 32, 64);
+            if (g == 0 && valid) Sp[e0 + cb + e] = make_float4(sr, sx, sy, sz);
+        }
+        if constexpr (V0) continue;
+        // sum over the 16 edge lanes of each row
+#pragma unroll
+        for (int u = 0; u < TU; u++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+#pragma unroll
+                for (int d = 0; d < 3; d++) Y[d][u][r] = row_sum16(Y[d][u][r]);
+                ap[0][u][r] = row_sum16(ap[0][u][r]);
+                ap[1][u][r] = row_sum16(ap[1][u][r]);
+            }
+        if (e == 0) {
+#pragma unroll
+            for (int u = 0; u < TU; u++) {
+                const long b = (long)j * F3 + fo + 16 * u;
+                const v4f pvv = ld4(phi + b);
+                v4f gvv = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    gvv += ld4(v + b + d * F) * Y[d][u];
+                    st4(gv_in + b + d * F, ld4(gv1 + b + d * F) + pvv * Y[d][u]);
+                }
+                st4(gphi + b, gvv);
+                st4(gphi + b + F, ap[0][u]);
+                st4(gphi + b + 2 * F, ap[1][u]);
+            }
+        }
+    }
+}
+
+// One stage of a reduce-scatter over the 16 lanes of a row: lane e keeps the
+// half of x[0 .. 2H) its bit selects (U) and adds the partner's copy of it,
+// which the DPP pattern CTRL brings (the partner's bit is the opposite one).
+template <int CTRL, int H>
+__device__ __forceinline__ void rs_half(float *x, bool U) {
+#pragma unroll
+    for (int k = 0; k < H; k++) {
+        const float send = U ? x[k] : x[k + H], keep = U ? x[k + H] : x[k];
+        x[k] = keep + dpp<CTRL>(send);
+    }
+}
+// Sums of x[0 .. 16) over the 16 lanes of each row; lane e of the row
+// receives the sum of x[e].
+__device__ __forceinline__ float row_reduce_scatter16(float *x, int e) {
+    rs_half<0x140, 8>(x, e & 8);   // row_mirror: e <-> 15 - e
+    rs_half<0x141, 4>(x, e & 4);   // row_half_mirror: e <-> 7 - e inside each half
+    rs_half<0x1B, 2>(x, e & 2);    // quad_perm [3,2,1,0]: e <-> e ^ 3
+    rs_half<0xB1, 1>(x, e & 1);    // quad_perm [1,0,3,2]: e <-> e ^ 1
+    return x[0];
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the message pass of the layers after the first with more than
+// one feature pass, organised like k_msg_fwd_pw: every wave runs all passes
+// of its source atom j with the weight images of every pass in LDS; the
+// radial basis and its derivative of a chunk, in MFMA operand form, are
+// evaluated in the first pass and kept in the wave's LDS for the later ones
+// (the first BWD_CACHE chunks); the filter tiles come out transposed, so
+// lane (f, g) works on feature f of the tile for the in-edges 4g .. 4g+3:
+// it gathers the destinations' gradient rows 16 consecutive features per
+// quarter-wave, accumulates dE/dphi_j and dE/dv_j over its edges in
+// registers (summed over the four lane rows once per atom and pass), and
+// holds per-edge partial sums over its feature, which a reduce-scatter over
+// the 16 lanes of the row turns into the 16 values (4 edges x (dE/dr,
+// dE/drhat)) that the row stores as 64 contiguous bytes.  The edge sums of
+// the passes are added up in the wave, in pass order (in LDS for the cached
+// chunks, in the slot itself for the others: the lane that adds is the lane
+// that stored), so the layer has one slot.
+// ---------------------------------------------------------------------------
+#ifndef BWD_PIW_WAVES
+#define BWD_PIW_WAVES 8
+#endif
+#ifndef BWD_PIW_EU
+#define BWD_PIW_EU 2
+#endif
+#ifndef BWD_CACHE
+#define BWD_CACHE 3
+#endif
+template <int P, int F, int K>
+__global__ void __launch_bounds__(64 * BWD_PIW_WAVES) __attribute__((amdgpu_waves_per_eu(BWD_PIW_EU))) k_msg_bwd_pw(const int *__restrict__ rowc, const int *__restrict__ colc,
+                                                     const float4 *__restrict__ geom, int n,
+                                                     const float *__restrict__ phi, const float *__restrict__ v,
+                                                     const float *__restrict__ gs1, const float *__restrict__ gv1,
+                                                     const float *__restrict__ Aw, const float *__restrict__ cw,
+                                                     float rc, const int8_t *__restrict__ hop, int hop_max,
+                                                     int *__restrict__ queue,
+                                                     float *__restrict__ gv_in, float *__restrict__ gphi,
+                                                     float4 *__restrict__ S) {
+    constexpr int WM = BWD_W;
+    constexpr int F3 = 3 * F, SL = Basis<P, K>::SLOTS, W = Pass<F, WM>::W, TU = Pass<F, WM>::TU;
+    constexpr int NP = Pass<F, WM>::N, NC = BWD_CACHE;
+    constexpr int WB = WStage<P, F, K, WM, true>::BYTES;
+    constexpr int CB = 2 * BOpStore<P, K>::BYTES;       // basis and derivative of a chunk
+    __shared__ __attribute__((aligned(16))) char lds[NP * WB];
+    __shared__ __attribute__((aligned(16))) char bcache[BWD_PIW_WAVES * NC * CB];
+    __shared__ float sacc[BWD_PIW_WAVES][NC][64];       // edge sums of the cached chunks
+#pragma unroll 1
+    for (int q = 0; q < NP; q++) stage_pass<P, F, K, WM, true>(Aw, cw, q, lds + q * WB);
+    const int lane = threadIdx.x & 63, e = lane & 15, g = lane >> 4;
+    char *bc = bcache + (threadIdx.x >> 6) * NC * CB;
+    float *Sf = reinterpret_cast<float *>(S);
+    const AtomQueue aq(n, queue, 0);
     const float pirc = 3.14159265358979f / rc;
     MSG_ATOMS(aq, j) {
         const int e0 = rowc[j], e1 = rowc[j + 1];
         const int deg = hop[j] <= hop_max ? e1 - e0 : 0;
         // edges of an atom beyond the hop range carry no gradient in this layer
-        float4 *Sp = S + (long)(PIW ? 0 : (int)blockIdx.y) * s_stride;
         if (hop[j] > hop_max)
-            for (int t = e0 + lane; t < e1; t += 64) Sp[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int t = e0 + lane; t < e1; t += 64) S[t] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll 1
-        for (int pi = 0; pi < NPL; pi++) {
-            const int p = PIW ? pi : (int)blockIdx.y;
-            const int fo = p * W + 4 * g;   // first feature of this lane (tile u adds 16 u)
-            // first layer: v_j = 0 and no node gradient, so phi_vv, v_j, dE/dphi_j
-            // and dE/dv_j drop out and only the edge sums remain.
-            // Later layers accumulate Y_d = sum_e dE/dv1_d(i) w_vv (from which both
-            // dE/dv_j = phi_vv Y_d and dE/dphi_vv = sum_d v_jd Y_d follow once per
-            // atom), dE/dphi_s and dE/dphi_vs; the v_j term of dE/dr enters through
-            // c_d = v_jd phi_vv.
-            v4f ph[3][TU], cv[3][TU], Y[3][TU], ap[2][TU];
+        for (int p = 0; p < NP; p++) {
+            const int fl = p * W + e;   // this lane's feature (tile u adds 16 u)
+            // Y_d = sum_e dE/dv1_d(i) w_vv (dE/dv_j = phi_vv Y_d and dE/dphi_vv =
+            // sum_d v_jd Y_d follow once per atom), dE/dphi_s, dE/dphi_vs; the v_j
+            // term of dE/dr enters through c_d = v_jd phi_vv
+            float ph[3][TU], cv[3][TU], Y[3][TU], ap[2][TU];
 #pragma unroll
             for (int u = 0; u < TU; u++) {
 #pragma unroll
-                for (int q = V0 ? 1 : 0; q < 3; q++)
-                    ph[q][u] = ld4(phi + (V0 ? (long)zsp[j] : (long)j) * F3 + q * F + fo + 16 * u);
-                if constexpr (!V0) {
+                for (int q = 0; q < 3; q++) ph[q][u] = phi[(long)j * F3 + q * F + fl + 16 * u];
 #pragma unroll
-                    for (int d = 0; d < 3; d++) {
-                        cv[d][u] = ld4(v + (long)j * F3 + d * F + fo + 16 * u) * ph[0][u];
-                        Y[d][u] = v4f{0.f, 0.f, 0.f, 0.f};
-                    }
-                    ap[0][u] = v4f{0.f, 0.f, 0.f, 0.f};
-                    ap[1][u] = v4f{0.f, 0.f, 0.f, 0.f};
+                for (int d = 0; d < 3; d++) {
+                    cv[d][u] = v[(long)j * F3 + d * F + fl + 16 * u] * ph[0][u];
+                    Y[d][u] = 0.f;
                 }
+                ap[0][u] = 0.f;
+                ap[1][u] = 0.f;
             }
             float4 gm_n = make_float4(0.f, 0.f, 0.f, rc);
             int i_n = j;
@@ -826,7 +1006,7 @@ __global__ void __launch_bounds__(64 * (PIW ? BWD_PIW_WAVES : MW)) __attribute__
                 i_n = colc[e0 + e];
             }
             for (int cb = 0; cb < deg; cb += 16) {
-                const char *wl = lds_chunk(lds + pi * WB);
+                const char *wl = lds_chunk(lds + p * WB);
                 const bool valid = cb + e < deg;
                 const float4 gm = gm_n;
                 const int i = i_n;
@@ -836,26 +1016,36 @@ __global__ void __launch_bounds__(64 * (PIW ? BWD_PIW_WAVES : MW)) __attribute__
                     gm_n = geom[e0 + cb + 16 + e];
                     i_n = colc[e0 + cb + 16 + e];
                 }
-                // the destinations' gradient rows, gathered quarter-contiguously and
-                // moved to the accumulator layout
-                const int iq = __shfl(i, xc.src, 64);
-                v4f gs[TU], gv[3][TU];
-#pragma unroll
-                for (int u = 0; u < TU; u++) {
-                    gs[u] = ld4(gs1 + (long)iq * F + p * W + xc.fo + 16 * u);
-#pragma unroll
-                    for (int d = 0; d < 3; d++) gv[d][u] = ld4(gv1 + (long)iq * F3 + d * F + p * W + xc.fo + 16 * u);
-                }
-#pragma unroll
-                for (int u = 0; u < TU; u++) {
-                    gs[u] = xc.move(xw[0], gs[u]);
-#pragma unroll
-                    for (int d = 0; d < 3; d++) gv[d][u] = xc.move(xw[PIW ? 0 : 1 + d], gv[d][u]);
-                }
                 const float ir = valid ? __builtin_amdgcn_rcpf(gm.w) : 0.f;
+                // direction of the message edge (i <- j) is x_j - x_i = -(x_i - x_j)
+                const float rx = -gm.x * ir, ry = -gm.y * ir, rz = -gm.z * ir;
+                // destinations and directions of this lane's edges 4g + r (padding
+                // edges: the atom itself and a zero direction; their filter is 0)
+                int ir_[4];
+                float hx[4], hy[4], hz[4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int src = 4 * g + r;
+                    ir_[r] = __shfl(i, src, 64);
+                    hx[r] = __shfl(rx, src, 64);
+                    hy[r] = __shfl(ry, src, 64);
+                    hz[r] = __shfl(rz, src, 64);
+                }
+                float gs[TU][4], gv[3][TU][4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const float *gsi = gs1 + (long)ir_[r] * F + fl;
+                    const float *gvi = gv1 + (long)ir_[r] * F3 + fl;
+#pragma unroll
+                    for (int u = 0; u < TU; u++) {
+                        gs[u][r] = gsi[16 * u];
+#pragma unroll
+                        for (int d = 0; d < 3; d++) gv[d][u][r] = gvi[d * F + 16 * u];
+                    }
+                }
                 BOp<P, K> bop, dop;
                 const int c = cb >> 4;
-                if (PIW && pi > 0 && c < NC) {
+                if (p > 0 && c < NC) {
                     bop_get<P, K>(bc + c * CB, lane, bop);
                     bop_get<P, K>(bc + c * CB + CB / 2, lane, dop);
                 } else {
@@ -863,95 +1053,77 @@ __global__ void __launch_bounds__(64 * (PIW ? BWD_PIW_WAVES : MW)) __attribute__
                     basis_slots<P, K, true>(gm.w, ir, pirc, valid, g, eb, db);
                     bop.set(eb);
                     dop.set(db);
-                    if (PIW && pi == 0 && c < NC) {
+                    if (p == 0 && c < NC) {
                         bop_put<P, K>(bc + c * CB, lane, bop);
                         bop_put<P, K>(bc + c * CB + CB / 2, lane, dop);
                     }
                 }
-                // direction of the message edge (i <- j) is x_j - x_i = -(x_i - x_j)
-                const float rx = -gm.x * ir, ry = -gm.y * ir, rz = -gm.z * ir;
-                float sr = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+                // per edge r: (dE/dr, dE/drhat_x, _y, _z) of this lane's feature
+                float es[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) es[k] = 0.f;
 #pragma unroll
                 for (int u = 0; u < TU; u++) {
-                    v4f w0, w1, d0;
-                    if constexpr (!V0) {
-                        w0 = filter_tile<P, F, K, WM, PIW>(wl, u, bop, lane);
-                        w1 = filter_tile<P, F, K, WM, PIW>(wl, TU + u, bop, lane);
-                    }
-                    const v4f w2 = filter_tile<P, F, K, WM, PIW>(wl, 2 * TU + u, bop, lane);
-                    if constexpr (!V0) d0 = filter_tile<P, F, K, WM, PIW>(wl, u, dop, lane);
-                    const v4f d1 = filter_tile<P, F, K, WM, PIW>(wl, TU + u, dop, lane);
-                    const v4f d2 = filter_tile<P, F, K, WM, PIW>(wl, 2 * TU + u, dop, lane);
+                    const v4f w0 = filter_tile<P, F, K, WM, true, true>(wl, u, bop, lane);
+                    const v4f w1 = filter_tile<P, F, K, WM, true, true>(wl, TU + u, bop, lane);
+                    const v4f w2 = filter_tile<P, F, K, WM, true, true>(wl, 2 * TU + u, bop, lane);
+                    const v4f d0 = filter_tile<P, F, K, WM, true, true>(wl, u, dop, lane);
+                    const v4f d1 = filter_tile<P, F, K, WM, true, true>(wl, TU + u, dop, lane);
+                    const v4f d2 = filter_tile<P, F, K, WM, true, true>(wl, 2 * TU + u, dop, lane);
 #pragma unroll
                     for (int r = 0; r < 4; r++) {
                         const float ga = gv[0][u][r], gb = gv[1][u][r], gc = gv[2][u][r], gsr = gs[u][r];
-                        const float gxvs = fmaf(ga, rx, fmaf(gb, ry, gc * rz));
-                        const float xvs = ph[2][u][r] * w2[r];
-                        sx = fmaf(ga, xvs, sx);
-                        sy = fmaf(gb, xvs, sy);
-                        sz = fmaf(gc, xvs, sz);
-                        if constexpr (V0) {
-                            sr = fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr));
-                            continue;
-                        }
-                        const float gc0 = fmaf(ga, cv[0][u][r], fmaf(gb, cv[1][u][r], gc * cv[2][u][r]));
-                        Y[0][u][r] = fmaf(ga, w0[r], Y[0][u][r]);
-                        Y[1][u][r] = fmaf(gb, w0[r], Y[1][u][r]);
-                        Y[2][u][r] = fmaf(gc, w0[r], Y[2][u][r]);
-                        ap[0][u][r] = fmaf(gsr, w1[r], ap[0][u][r]);
-                        ap[1][u][r] = fmaf(gxvs, w2[r], ap[1][u][r]);
-                        sr = fmaf(gc0, d0[r], fmaf(gsr * ph[1][u][r], d1[r], fmaf(gxvs * ph[2][u][r], d2[r], sr)));
+                        const float gxvs = fmaf(ga, hx[r], fmaf(gb, hy[r], gc * hz[r]));
+                        const float xvs = ph[2][u] * w2[r];
+                        es[4 * r + 1] = fmaf(ga, xvs, es[4 * r + 1]);
+                        es[4 * r + 2] = fmaf(gb, xvs, es[4 * r + 2]);
+                        es[4 * r + 3] = fmaf(gc, xvs, es[4 * r + 3]);
+                        const float gc0 = fmaf(ga, cv[0][u], fmaf(gb, cv[1][u], gc * cv[2][u]));
+                        Y[0][u] = fmaf(ga, w0[r], Y[0][u]);
+                        Y[1][u] = fmaf(gb, w0[r], Y[1][u]);
+                        Y[2][u] = fmaf(gc, w0[r], Y[2][u]);
+                        ap[0][u] = fmaf(gsr, w1[r], ap[0][u]);
+                        ap[1][u] = fmaf(gxvs, w2[r], ap[1][u]);
+                        es[4 * r] = fmaf(gc0, d0[r], fmaf(gsr * ph[1][u], d1[r], fmaf(gxvs * ph[2][u], d2[r], es[4 * r])));
                     }
                 }
-                // sum over the four lane rows (all features of the pass)
-                sr += __shfl_xor(sr, 16, 64);
-                sx += __shfl_xor(sx, 16, 64);
-                sy += __shfl_xor(sy, 16, 64);
-                sz += __shfl_xor(sz, 16, 64);
-                sr += __shfl_xor(sr, 32, 64);
-                sx += __shfl_xor(sx, 32, 64);
-                sy += __shfl_xor(sy, 32, 64);
-                sz += __shfl_xor(sz, 32, 64);
-                if (g == 0 && valid) {
-                    float4 o = make_float4(sr, sx, sy, sz);
-                    if constexpr (PIW) {
-                        float4 *acc = c < NC ? &sacc[threadIdx.x >> 6][c][e] : Sp + e0 + cb + e;
-                        if (pi > 0) {
-                            const float4 a = *acc;
-                            o = make_float4(a.x + o.x, a.y + o.y, a.z + o.z, a.w + o.w);
-                        }
-                        if (c < NC && pi + 1 < NPL) *acc = o;
-                        else Sp[e0 + cb + e] = o;
-                    } else {
-                        Sp[e0 + cb + e] = o;
-                    }
+                // lane e of row g receives component e & 3 of edge 4g + (e >> 2),
+                // summed over the pass's features
+                float o = row_reduce_scatter16(es, e);
+                const int ke = cb + 4 * g + (e >> 2);   // the edge this lane stores
+                if (ke < deg) {
+                    float *acc = c < NC ? &sacc[threadIdx.x >> 6][c][lane] : Sf + 4L * (e0 + cb + 4 * g) + e;
+                    if (p > 0) o += *acc;
+                    if (c < NC && p + 1 < NP) *acc = o;
+                    else Sf[4L * (e0 + cb + 4 * g) + e] = o;
                 }
             }
-            if constexpr (V0) continue;
-            // sum over the 16 edge lanes of each row
+            // sum over the four lane rows
 #pragma unroll
-            for (int u = 0; u < TU; u++)
+            for (int u = 0; u < TU; u++) {
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-#pragma unroll
-                    for (int d = 0; d < 3; d++) Y[d][u][r] = row_sum16(Y[d][u][r]);
-                    ap[0][u][r] = row_sum16(ap[0][u][r]);
-                    ap[1][u][r] = row_sum16(ap[1][u][r]);
+                for (int d = 0; d < 3; d++) {
+                    Y[d][u] += __shfl_xor(Y[d][u], 16, 64);
+                    Y[d][u] += __shfl_xor(Y[d][u], 32, 64);
                 }
-            if (e == 0) {
+                ap[0][u] += __shfl_xor(ap[0][u], 16, 64);
+                ap[0][u] += __shfl_xor(ap[0][u], 32, 64);
+                ap[1][u] += __shfl_xor(ap[1][u], 16, 64);
+                ap[1][u] += __shfl_xor(ap[1][u], 32, 64);
+            }
+            if (g == 0) {
 #pragma unroll
                 for (int u = 0; u < TU; u++) {
-                    const long b = (long)j * F3 + fo + 16 * u;
-                    const v4f pvv = ld4(phi + b);
-                    v4f gvv = v4f{0.f, 0.f, 0.f, 0.f};
+                    const long b = (long)j * F3 + fl + 16 * u;
+                    float gvv = 0.f;
 #pragma unroll
                     for (int d = 0; d < 3; d++) {
-                        gvv += ld4(v + b + d * F) * Y[d][u];
-                        st4(gv_in + b + d * F, ld4(gv1 + b + d * F) + pvv * Y[d][u]);
+                        gvv = fmaf(v[b + d * F], Y[d][u], gvv);
+                        gv_in[b + d * F] = fmaf(ph[0][u], Y[d][u], gv1[b + d * F]);
                     }
-                    st4(gphi + b, gvv);
-                    st4(gphi + b + F, ap[0][u]);
-                    st4(gphi + b + 2 * F, ap[1][u]);
+                    gphi[b] = gvv;
+                    gphi[b + F] = ap[0][u];
+                    gphi[b + 2 * F] = ap[1][u];
                 }
             }
         }
@@ -1214,20 +1386,19 @@ static int launch_bwd(hipStream_t st, const MsgArgs &a) {
     constexpr bool piw = Pass<F, BWD_W>::N > 1;
     if constexpr (piw) {
         if (!a.layer0) {
-            auto kern = k_msg_bwd<P, F, K, false, true>;
+            auto kern = k_msg_bwd_pw<P, F, K>;
             constexpr int block = 64 * BWD_PIW_WAVES;
             static const int resident = resident_grid(kern, block);   // per process: one device type
             int b = std::min(resident, (a.n + BWD_PIW_WAVES - 1) / BWD_PIW_WAVES);
             if (b >= 8) b -= b % 8;
             kern<<<dim3((unsigned)std::max(1, b)), block, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.v, a.gs1,
-                                                                   a.gv1, a.A, a.c, a.rc, a.hop, a.hop_max,
-                                                                   a.species, a.queue, a.gv_in, a.gphi, a.S,
-                                                                   a.s_stride);
+                                                                   a.gv1, a.A, a.c, a.rc, a.hop, a.hop_max, a.queue,
+                                                                   a.gv_in, a.gphi, a.S);
             return hipGetLastError() == hipSuccess ? 0 : -5;
         }
     }
     dim3 grid((unsigned)grid_x(a.n), (unsigned)Pass<F, BWD_W>::N);
-    auto kern = a.layer0 ? k_msg_bwd<P, F, K, true, false> : k_msg_bwd<P, F, K, false, false>;
+    auto kern = a.layer0 ? k_msg_bwd<P, F, K, true> : k_msg_bwd<P, F, K, false>;
     kern<<<grid, 64 * MW, 0, st>>>(a.rowc, a.colc, a.geom, a.n, a.phi, a.v, a.gs1, a.gv1, a.A, a.c, a.rc, a.hop,
                                    a.hop_max, a.species, a.queue, a.gv_in, a.gphi, a.S, a.s_stride);
     return hipGetLastError() == hipSuccess ? 0 : -5;
