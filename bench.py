@@ -573,6 +573,8 @@ def main():
                     help="skip the water MD, slab, NVT, capacity and Allegro timings")
     ap.add_argument("--allegro-only", action="store_true", help="time only the Allegro workload (a quick check)")
     ap.add_argument("--mace-only", action="store_true", help="time only the MACE workload (a quick check)")
+    ap.add_argument("--water-only", action="store_true",
+                    help="time only the 24,000-atom water MD workload (100 velocity-Verlet steps)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device to device (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -586,18 +588,21 @@ def main():
     import torch
     from paper_2506_04055_amd import mlp, synth
 
-    if args.allegro_only:
-        print(json.dumps({p: measure_allegro(mlp, synth, torch, p) for p in (args.precision, "fp32")}), flush=True)
-        return
-    if args.mace_only:
-        print(json.dumps({p: measure_mace(mlp, synth, torch, p) for p in (args.precision, "fp32")}), flush=True)
-        return
     if args.copy_probe:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.allegro_only:
+        print(json.dumps({p: measure_allegro(mlp, synth, torch, p) for p in (args.precision, "fp32")}), flush=True)
+        return
+    if args.mace_only:
+        print(json.dumps({p: measure_mace(mlp, synth, torch, p) for p in (args.precision, "fp32")}), flush=True)
+        return
+    if args.water_only:
+        print(json.dumps({args.precision: run_md(mlp, synth, torch, args.precision, 100, 10)}), flush=True)
+        return
     dom, hdr, w = synth.workload("fcc1m_ghost")
     print(f"bench: headline fcc domain, {dom.n_local} locals, {dom.n_atoms} rows, {args.precision}", file=sys.stderr,
           flush=True)
