@@ -4,26 +4,32 @@
 // contraction with A' = [c | A] and e~ = [fc, e_1 fc, ..., e_K fc],
 // e_k = sin(k pi r / rc) / r.  A wave owns one atom and takes its edges 16 at
 // a time.  The filter of a chunk is computed as 16 x 16 MFMA tiles (16
-// features x 16 edges):
-//   A operand = 16 rows of A' (staged in LDS once per workgroup),
-//   B operand = e~ of the 16 edges (each lane evaluates the basis slots it
-//               holds; the slots of padding edges are zero, so they
-//               contribute nothing).
-// The accumulator of a tile leaves lane l = 16 g + e holding features
-// 4g .. 4g+3 of the tile for edge e.  That is the layout the rest of the pass
-// works in: lane (e, g) gathers the matching 16-byte pieces of its edge's
-// neighbour rows, forms the products in registers, and
-//   * sums over the features of an edge stay inside the lane, plus one
-//     exchange across the four lane rows;
-//   * sums over the edges of the atom stay inside the lane over the chunks,
-//     plus one 16-lane DPP row reduction per atom.
-// No LDS round trip sits between the matrix cores and the vector ALUs.
+// features x 16 edges) from two operands: 16 rows of A' (staged in LDS once
+// per workgroup) and e~ of the 16 edges (each lane evaluates the basis slots
+// it holds; the slots of padding edges are zero, so they contribute nothing).
+// The vector phase works in the accumulator layout of the tiles; no LDS round
+// trip sits between the matrix cores and the vector ALUs.  Features are
+// processed in passes of W = min(F, 32).  Two arrangements:
 //
-// Features are processed in passes of W = min(F, 32): blockIdx.y is the pass.
-// Workgroups are dispatched in linear order, so the workgroups of pass p are
-// issued before those of pass p + 1 and the rows gathered at any time are
-// W-feature slices (6 W floats per neighbour), a working set the per-XCD L2
-// holds.  The basis is re-evaluated per pass.
+// * One pass per workgroup (k_msg_fwd, k_msg_bwd: the first layer when it is
+//   not factorised, and models with a single pass).  blockIdx.y is the pass;
+//   A' is the first MFMA operand, so lane l = 16 g + e holds features
+//   4g .. 4g+3 of the tile for edge e: it gathers the matching 16-byte pieces
+//   of its edge's neighbour rows (quarter-contiguously, then moved through
+//   LDS), sums over the features of an edge stay inside the lane (plus one
+//   exchange across the four lane rows), sums over the edges of the atom stay
+//   inside the lane over the chunks (plus one 16-lane DPP row reduction per
+//   atom).  The basis is evaluated per pass.
+// * All passes in the wave (k_msg_fwd_pw, k_msg_bwd_pw: the layers after the
+//   first with more than one pass).  The weight images of every pass are in
+//   LDS; the basis of a chunk, in MFMA operand form, is evaluated in the first
+//   pass and kept in the wave's LDS for the later ones.  e~ is the first MFMA
+//   operand, so the tile comes out transposed: lane (f, g) holds feature f of
+//   the tile for the edges 4g .. 4g+3.  It gathers 16 consecutive features of
+//   a row per quarter-wave (no exchange), adds its four edges in registers,
+//   and the sums over an atom's edges reduce over the four lane rows once per
+//   atom and pass; the adjoint's sums over the features of an edge go through
+//   a reduce-scatter over the 16 lanes of a row.
 //
 // Precision P = 0: FP32 operands (v_mfma_f32_16x16x4_f32); P = 1: bfloat16
 // operands (v_mfma_f32_16x16x32_bf16); P = 2: split bfloat16 operands
@@ -34,10 +40,10 @@
 // The adjoint is organised by source atom j over its in-edges (j <- i), the
 // reverses of the edges (i <- j) that carried j's messages; it gathers the
 // destination gradients and accumulates dE/dphi_j and dE/dv_j.  For every edge
-// it also forms S = (dE/dr, dE/drhat) summed over the pass's features (dE/dr
-// through dw/dr = A' de~/dr, a second MFMA) and stores it in the slot of its
-// (layer, pass): every slot is written exactly once, so no two launches or
-// passes touch the same memory and nothing is read back.  The edge gradient
+// it also forms S = (dE/dr, dE/drhat) summed over the features (dE/dr through
+// dw/dr = A' de~/dr, a second MFMA): one slot per layer (the all-pass kernel
+// adds the passes up in the wave) or per layer and pass (one pass per
+// workgroup), each written by one lane only.  The edge gradient
 // G = dE/d(x_j - x_i) = (dE/dr) rhat + (I - rhat rhat^T) dE/drhat / r is linear
 // in S and is assembled once after the last layer.
 #include "internal.h"
@@ -1130,7 +1136,7 @@ __global__ void __launch_bounds__(64 * BWD_PIW_WAVES) __attribute__((amdgpu_wave
     }
 }
 
-// G of each pruned edge from the per-pass sums: G = dE/dr rhat + (g - (g . rhat) rhat) / r,
+// G of each pruned edge from its edge-sum slots: G = dE/dr rhat + (g - (g . rhat) rhat) / r,
 // with rhat the direction of the message edge, the reverse of the stored one.
 // The pruned edge count is rowc[n], read on the device.
 __global__ void k_assemble_G(const int *__restrict__ rowc, int n, const float4 *__restrict__ geom,
