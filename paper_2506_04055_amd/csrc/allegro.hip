@@ -506,7 +506,7 @@ __global__ void k_al_geom_bwd(const int *__restrict__ rowc, int n, const float4 
 
 // Offsets (floats) of the per-evaluation arrays in the arena.
 struct AlArena {
-    long H0, u, GL, Y, P[6], A[6], Yo, LIN, WV, PL, M, X1, PO, HO, GU, GWV, GY, GB, ENV, Uat, total;
+    long H0, u, GL, Y, P[6], A[6], Yo, LIN, WV, PL, M, X1, PO, HO, GU, GWV, GY, GB, ENV, Uat, EP, total;
 };
 
 static AlArena al_layout(const AlModel &a, long N, long E) {
@@ -541,6 +541,7 @@ static AlArena al_layout(const AlModel &a, long N, long E) {
     L.GB = take(E * a.NBP);
     L.ENV = take(N * d.NC * 8);
     L.Uat = take(N + 64);
+    L.EP = take(2 * energy_part_doubles(N));   // the energy sums' chunk partials (doubles)
     L.total = o + 4096;
     return L;
 }
@@ -768,7 +769,9 @@ int allegro_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, fl
     k_al_x1<<<nblk(ne * (D / 4), 256), 256, 0, s>>>(LIN, ldl, u, M, cnt, D, X1);
     if ((rc = gm(s, P, GE_BIAS_SILU, X1, D, a.fO1, PO, d.OH, ne, cnt, a.out_b1, HO, d.OH))) return rc;
     k_al_energy<<<nblk(n, 4), 256, 0, s>>>(rowc, n, d.OH, HO, u, a.out_w2, a.out_b2_host, Uat);
-    if ((rc = launch_energy(s, Uat, perm, n, g->n_local, energy, atom_energy_user, n_seg, seg_dev))) return rc;
+    if ((rc = launch_energy(s, Uat, perm, n, g->n_local, energy, atom_energy_user, n_seg, seg_dev,
+                            reinterpret_cast<double *>(base + L.EP))))
+        return rc;
     if (!forces_user) return 0;
 
     // adjoint

@@ -209,8 +209,10 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
 void eval_model_needs(const mlp_model *m, const mlp_nbr *g, size_t *act, size_t *G, size_t *Gs);
 // Energy of each segment (FP64, fixed order) from per-atom energies U in
 // internal order, and U scattered to the caller's order if atom_energy_user.
+// part: device scratch of at least energy_part_doubles(n) doubles (n_seg <= n).
 int launch_energy(hipStream_t s, const float *U, const int *perm, int n, int n_local, double *energy,
-                  float *atom_energy_user, int n_seg, const int *seg_dev);
+                  float *atom_energy_user, int n_seg, const int *seg_dev, double *part);
+inline long energy_part_doubles(long n) { return n + 1024; }
 // F_k = sum over in-edges e of (G at rev(e)) - (G at e), G_e = dE/d(x_dst - x_src),
 // written to the caller's order (SoA).
 int launch_forces(hipStream_t s, const int *rowc, const int *revc, const float4 *G, const int *perm, int n,

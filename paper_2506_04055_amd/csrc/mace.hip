@@ -932,7 +932,7 @@ __global__ void k_mc_species(int S, const float *__restrict__ Wemb, const float 
 // Host side
 // ---------------------------------------------------------------------------
 struct McArena {
-    long X0, Y, P[2][4], A[2][4], R[2], GY, GX0, MSG, AR[2], AP[2], GAP, H1, HB1, H2, GH1S, U, total;
+    long X0, Y, P[2][4], A[2][4], R[2], GY, GX0, MSG, AR[2], AP[2], GAP, H1, HB1, H2, GH1S, U, EP, total;
 };
 
 static McArena mc_layout(const McModel &a, long N, long E) {
@@ -967,6 +967,7 @@ static McArena mc_layout(const McModel &a, long N, long E) {
     L.H2 = take(N * MK);
     L.GH1S = take(N * MK);
     L.U = take(N + 64);
+    L.EP = take(2 * energy_part_doubles(N));   // the energy sums' chunk partials (doubles)
     L.total = o + 4096;
     return L;
 }
@@ -1273,7 +1274,9 @@ int mace_evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float
         else k_mc_node<1><<<nblk(nd, APB), 256, 0, s>>>(nd, zsp, na);
     }
     HIP_TRY(hipGetLastError());
-    if ((rc = launch_energy(s, U, perm, n, g->n_local, energy, atom_energy_user, n_seg, seg_dev))) return rc;
+    if ((rc = launch_energy(s, U, perm, n, g->n_local, energy, atom_energy_user, n_seg, seg_dev,
+                            reinterpret_cast<double *>(base + L.EP))))
+        return rc;
     if (!forces_user) return 0;
 
     // adjoint

@@ -231,31 +231,38 @@ __global__ void k_readout(const float *__restrict__ h5, int n, int Fh, const flo
     if (q == 0 && i < n) U[i] = u + b6[0];
 }
 
-constexpr int ERED = 1024;
+constexpr int ERED = 512;      // threads per block of the energy sums
+constexpr int ECH = 16384;     // rows per chunk of a segment
 
 // E_b = sum of U_i over the local atoms of segment b (internal rows
 // [seg[b], seg[b+1]), or [0, n) without segments), in FP64 with a fixed
-// order: one block per segment, strided partial sums, a butterfly within each
-// wave, then the wave totals in order.  A
-// segment's energy is therefore the same whether it is evaluated alone or
-// packed into a batch.
-__global__ void __launch_bounds__(ERED) k_energy_seg(const float *__restrict__ U, const int *__restrict__ perm,
-                                                     const int *__restrict__ seg, int n, int n_local,
-                                                     double *__restrict__ E) {
+// order that depends on the segment alone: the segment is cut into chunks of
+// ECH rows from its first row; block (b, c) sums chunk c (strided partial
+// sums, a butterfly within each wave, then the wave totals in order) into
+// part[o_b + c], o_b = b + seg[b] / ECH (disjoint: segment b has
+// ceil(len / ECH) <= 1 + len / ECH chunks); k_energy_total adds the chunk
+// sums of each segment in order.  A segment's energy is therefore the same
+// whether it is evaluated alone or packed into a batch.
+__global__ void __launch_bounds__(ERED) k_energy_chunk(const float *__restrict__ U, const int *__restrict__ perm,
+                                                       const int *__restrict__ seg, int n, int n_local,
+                                                       double *__restrict__ part) {
     __shared__ double sh[ERED / 64];
-    const int b = blockIdx.x;
+    const int b = blockIdx.x, c = blockIdx.y;
     const int a = seg ? seg[b] : 0, e = seg ? seg[b + 1] : n;
+    const int ca = a + c * ECH;
+    if (ca >= e && !(c == 0 && a == e)) return;   // past the segment (an empty one keeps chunk 0)
+    const int ce = min(ca + ECH, e);
     // eight interleaved partial sums per thread; the row's energy and its
     // local flag are loaded together, so eight pairs of loads are in flight
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i0 = a + threadIdx.x; i0 < e; i0 += 8 * ERED) {
+    for (int i0 = ca + threadIdx.x; i0 < ce; i0 += 8 * ERED) {
         float u[8];
         int pm[8];
 #pragma unroll
         for (int q = 0; q < 8; q++) {
             const int i = i0 + q * ERED;
-            u[q] = i < e ? U[i] : 0.f;
-            pm[q] = i < e ? perm[i] : n_local;
+            u[q] = i < ce ? U[i] : 0.f;
+            pm[q] = i < ce ? perm[i] : n_local;
         }
 #pragma unroll
         for (int q = 0; q < 8; q++)
@@ -268,10 +275,21 @@ __global__ void __launch_bounds__(ERED) k_energy_seg(const float *__restrict__ U
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < ERED / 64; w++) s += sh[w];
-        E[b] = s;
+        double t = 0.0;
+        for (int w = 0; w < ERED / 64; w++) t += sh[w];
+        part[b + a / ECH + c] = t;
     }
+}
+__global__ void k_energy_total(const int *__restrict__ seg, int n, int n_seg, const double *__restrict__ part,
+                               double *__restrict__ E) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_seg) return;
+    const int a = seg ? seg[b] : 0, e = seg ? seg[b + 1] : n;
+    const int nc = e > a ? (e - a + ECH - 1) / ECH : 1;
+    const double *p = part + b + a / ECH;
+    double t = 0.0;
+    for (int c = 0; c < nc; c++) t += p[c];
+    E[b] = t;
 }
 
 // F_k = sum over in-edges e of (G at rev(e)) - (G at e), scattered to the
@@ -330,7 +348,8 @@ static size_t act_floats(long N, int F, int T) {
     long per_layer = (long)N * F * (1 + 3 + 1 + 3 + 2 + 3 + 3 + 3 + 1 + 3);
     long io = (long)N * F * 4;  // s, v of the final layer
     long bwd = (long)N * F * (1 + 3 + 1 + 3 + 3 + 3 + 1 + 2 + 3 + 3 + 1 + 1) + (long)N * F;  // + h5, g5
-    return (size_t)(T * per_layer + io + bwd + N + 64 * (12 * T + 32) + 4096 + QUEUE_INTS);
+    return (size_t)(T * per_layer + io + bwd + N + 64 * (12 * T + 32) + 4096 + QUEUE_INTS +
+                    2 * energy_part_doubles(N));
 }
 
 static void carve(float *base, long N, int F, int T, Act &A) {
@@ -368,7 +387,7 @@ static void carve(float *base, long N, int F, int T, Act &A) {
     A.h5 = take(NF / 2 + 64);
     A.g5 = take(NF / 2 + 64);
     A.U = take(N + 64);
-    A.epart = reinterpret_cast<double *>(take(2 * 1024));
+    A.epart = reinterpret_cast<double *>(take(2 * energy_part_doubles(N)));
     A.queue = reinterpret_cast<int *>(take(QUEUE_INTS));
 }
 
@@ -509,8 +528,11 @@ void eval_model_needs(const mlp_model *m, const mlp_nbr *g, size_t *act, size_t 
 }
 
 int launch_energy(hipStream_t s, const float *U, const int *perm, int n, int n_local, double *energy,
-                  float *atom_energy_user, int n_seg, const int *seg_dev) {
-    k_energy_seg<<<std::max(1, n_seg), ERED, 0, s>>>(U, perm, seg_dev, n, n_local, energy);
+                  float *atom_energy_user, int n_seg, const int *seg_dev, double *part) {
+    const int ns = std::max(1, n_seg);
+    const dim3 grid((unsigned)ns, (unsigned)std::max(1, (n + ECH - 1) / ECH));
+    k_energy_chunk<<<grid, ERED, 0, s>>>(U, perm, seg_dev, n, n_local, part);
+    k_energy_total<<<(unsigned)((ns + 63) / 64), 64, 0, s>>>(seg_dev, n, ns, part, energy);
     if (atom_energy_user) k_scatter_energy<<<nblk(n, 256), 256, 0, s>>>(U, perm, n, atom_energy_user);
     HIP_TRY(hipGetLastError());
     return 0;
@@ -632,7 +654,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
     k_readout<<<nblk(16L * nloc, 256), 256, 0, s>>>(A.h5, nloc, Fh, m->at(m->off_w6), m->at(m->off_b6), perm,
                                                     g->n_local, A.U, A.g5);
     fill_zero(s, A.U + nloc, (long)(n - nloc));
-    k_energy_seg<<<std::max(1, n_seg), ERED, 0, s>>>(A.U, perm, seg_dev, n, g->n_local, energy);
+    if ((rc = launch_energy(s, A.U, perm, n, g->n_local, energy, nullptr, n_seg, seg_dev, A.epart))) return rc;
     if (atom_energy_user) k_scatter_energy<<<nblk(n, 256), 256, 0, s>>>(A.U, perm, n, atom_energy_user);
     if (!forces_user) return 0;
 
