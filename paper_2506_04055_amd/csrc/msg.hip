@@ -391,17 +391,25 @@ struct AtomQueue {
         hi = (int)((long)n * (x + 1) / nx);
         ctr = queue + (pass * 8 + x) * 32;
     }
-    // first atom of the wave's next batch (wave-uniform), >= hi once the slice is drained
-    __device__ __forceinline__ int take() const {
+    // a ticket: the counter's old value in lane 0 (issue), and the first atom
+    // of the wave's batch it names (wave-uniform; >= hi once the slice is
+    // drained), read only when needed (resolve), so the atomic's latency can
+    // pass under other work
+    __device__ __forceinline__ int issue() const {
         int t = 0;
         if ((threadIdx.x & 63) == 0)
             t = __hip_atomic_fetch_add(ctr, MSG_QB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return lo + __builtin_amdgcn_readfirstlane(t);
+        return t;
     }
+    __device__ __forceinline__ int resolve(int t) const { return lo + __builtin_amdgcn_readfirstlane(t); }
+    __device__ __forceinline__ int take() const { return resolve(issue()); }
 };
 // for (each atom I of the wave, in queue order)
 #if MSG_QB == 1
-#define MSG_ATOMS(Q, I) for (int I = (Q).take(); I < (Q).hi; I = (Q).take())
+// (the next ticket is issued when an atom starts and resolved when it ends,
+// so its latency passes under the atom's work; the last one is not used)
+#define MSG_ATOMS(Q, I)                                                      \
+    for (int I = (Q).take(), I##_t = (Q).issue(); I < (Q).hi; I = (Q).resolve(I##_t), I##_t = (Q).issue())
 #else
 #define MSG_ATOMS(Q, I)                                           \
     for (int I##_b = (Q).take(); I##_b < (Q).hi; I##_b = (Q).take()) \
