@@ -406,14 +406,19 @@ struct AtomQueue {
 };
 // for (each atom I of the wave, in queue order)
 #if MSG_QB == 1
-// (the next ticket is issued when an atom starts and resolved when it ends,
-// so its latency passes under the atom's work; the last one is not used)
-#define MSG_ATOMS(Q, I)                                                      \
+#define MSG_ATOMS(Q, I) for (int I = (Q).take(); I < (Q).hi; I = (Q).take())
+// The same with the next ticket issued when an atom starts and resolved when
+// it ends, so the atomic's latency passes under the atom's work (the last
+// one is not used).  Each wave then holds two tickets, which doubles the
+// window of atoms in flight: worth it in the adjoint (2 waves per SIMD), not
+// in the forward, whose L2 then holds its window's rows less well.
+#define MSG_ATOMS_AHEAD(Q, I)                                                \
     for (int I = (Q).take(), I##_t = (Q).issue(); I < (Q).hi; I = (Q).resolve(I##_t), I##_t = (Q).issue())
 #else
 #define MSG_ATOMS(Q, I)                                           \
     for (int I##_b = (Q).take(); I##_b < (Q).hi; I##_b = (Q).take()) \
         for (int I = I##_b; I < I##_b + MSG_QB && I < (Q).hi; I++)
+#define MSG_ATOMS_AHEAD(Q, I) MSG_ATOMS(Q, I)
 #endif
 
 // A chunk's B operand kept in LDS between passes: 16-byte words per lane
@@ -988,7 +993,7 @@ __global__ void __launch_bounds__(64 * BWD_PIW_WAVES) __attribute__((amdgpu_wave
     float *Sf = reinterpret_cast<float *>(S);
     const AtomQueue aq(n, queue, 0);
     const float pirc = 3.14159265358979f / rc;
-    MSG_ATOMS(aq, j) {
+    MSG_ATOMS_AHEAD(aq, j) {
         const int e0 = rowc[j], e1 = rowc[j + 1];
         const int deg = hop[j] <= hop_max ? e1 - e0 : 0;
         // edges of an atom beyond the hop range carry no gradient in this layer
