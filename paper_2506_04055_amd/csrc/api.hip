@@ -228,6 +228,7 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
         int R, C;
         bool tr;
         mlp::PackedW *dst;
+        bool parts3 = false;
     };
     std::vector<Item> items;
     const int Fi = (int)F;
@@ -240,6 +241,7 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
             items.push_back({Wm[q], R[q], C[q], false, &m->pk[t][q]});
             items.push_back({Wm[q], R[q], C[q], true, &m->pk[t][5 + q]});
         }
+        if (Fi == 64 || Fi == 128) items.push_back({L.W4, 3 * Fi, Fi, true, &m->pk[t][mlp::WP_W4TP], true});
     }
     items.push_back({m->at(m->off_W5), Fi / 2, Fi, false, &m->pk_W5});
     items.push_back({m->at(m->off_W5), Fi / 2, Fi, true, &m->pk_W5t});
@@ -248,7 +250,8 @@ int mlp_model_create(const char *header_json, const float *weights, size_t n_wei
     int prc = hipMalloc(&m->pk_dev, pk_bytes) == hipSuccess ? 0 : MLP_ERR_OOM;
     for (size_t q = 0, o = 0; prc == 0 && q < items.size(); q++) {
         const Item &it = items[q];
-        if (mlp::pack_weight(nullptr, it.W, it.R, it.C, it.tr, (char *)m->pk_dev + o, it.dst)) prc = MLP_ERR_DEVICE;
+        if (mlp::pack_weight(nullptr, it.W, it.R, it.C, it.tr, (char *)m->pk_dev + o, it.dst, it.parts3))
+            prc = MLP_ERR_DEVICE;
         o += mlp::packed_bytes(it.R, it.C, it.tr);
     }
     // first-layer phi per species, followed by the scratch of its two GEMMs

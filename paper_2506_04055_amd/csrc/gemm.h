@@ -4,7 +4,7 @@
 
 namespace mlp {
 
-enum { GE_STORE = 0, GE_BIAS = 1, GE_BIAS_SILU = 2, GE_DSILU = 3, GE_ADD = 4, GE_UPDATE = 5, GE_NORM_ADJ = 6 };
+enum { GE_STORE = 0, GE_BIAS = 1, GE_BIAS_SILU = 2, GE_DSILU = 3, GE_ADD = 4, GE_UPDATE = 5, GE_UPDATE_ADJ = 6 };
 
 // One weight matrix packed as the B operand of C = A B: element (k, n) of B
 // at [n][k] (reduction index contiguous), zero-padded to Np x Kp
@@ -21,8 +21,12 @@ struct PackedW {
 size_t packed_bytes(int R, int C, bool transpose);
 // Pack W (row-major R x C, FP32, device) into `arena` (device, 256-byte
 // aligned, packed_bytes long): transpose = false gives B = W^T (forward, W
-// stored [out][in]), transpose = true gives B = W (adjoint).  Returns 0 or -5.
-int pack_weight(hipStream_t s, const float *W, int R, int C, bool transpose, void *arena, PackedW *out);
+// stored [out][in]), transpose = true gives B = W (adjoint).  parts3: the
+// reduction index (K = 3P, P a multiple of 32) taken in the order of the
+// GE_UPDATE_ADJ operand, block 3 b + p of 32 = rows p P + 32 b .. +31 of
+// part p.  Returns 0, -1 (parts3 with another K) or -5.
+int pack_weight(hipStream_t s, const float *W, int R, int C, bool transpose, void *arena, PackedW *out,
+                bool parts3 = false);
 
 // C = epilogue(A B) for A (M x K, row stride lda, FP32).  Mc (device, may be
 // null): a row count known only on the device; rows at or past it are not
@@ -45,9 +49,16 @@ int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, co
 //   GE_UPDATE (after bias2; the output is a = [a_vv | a_sv | a_ss]):
 //     C2 = a_vv, a_sv (a_ss is not stored), v2 = v1 + a_vv o Uv (if v2),
 //     s2 = s1 + a_sv o <Uv, Vv> + a_ss, with s1 = sn[:, :F];
-//   GE_NORM_ADJ (the output is [ds1 | dn]): C2 = R2 + ds1 (ds1 + ds2, with
-//     R2 = ds2), and dVv += (dn / n) o Vv in gUV, with n = sn[:, F:].
-// UV and gUV hold rows [Uv | Vv] of 2F per (atom, direction).
+//   GE_UPDATE_ADJ (with e1 = GE_DSILU; the whole adjoint of the update and
+//     of the norm; F = 64 or 128): the first product's A operand, da =
+//     [dE/da_vv | dE/da_sv | dE/da_ss] (K1 = 3F, B1 packed with parts3), is
+//     formed as it is needed from ds2 = R2, dv2 = gv (null: zero), UV and
+//     a = A (rows of lda floats, [a_vv | a_sv | ...]), and dUv = dv2 o a_vv +
+//     ds2 a_sv Vv goes to gUV on the way; the output is [ds1 | dn]: C2 =
+//     R2 + ds1, and dVv = ds2 a_sv Uv + (dn / n) o Vv to gUV, with
+//     n = sn[:, F:].
+// UV and gUV hold rows [Uv | Vv] of 2F per (atom, direction), v1, v2 and gv
+// rows of F per (atom, direction).
 struct GemmChain {
     int e1 = GE_BIAS_SILU, e2 = GE_BIAS;
     const float *A = nullptr;
@@ -64,6 +75,7 @@ struct GemmChain {
     int F = 0;                                    // feature width of the update epilogues
     const float *sn = nullptr, *v1 = nullptr, *UV = nullptr;
     float *s2 = nullptr, *v2 = nullptr, *gUV = nullptr;
+    const float *gv = nullptr;
     const int *Mc = nullptr;                      // device row count bounding M (may be null)
 };
 int node_gemm_chain(hipStream_t s, int precision, const GemmChain &c);

@@ -63,11 +63,13 @@ struct PackLayout {
 
 size_t packed_bytes(int R, int C, bool transpose) { return PackLayout(R, C, transpose).bytes; }
 
-__global__ void k_pack(const float *__restrict__ W, int C, bool tr, int N, int K, int Np, int Kp,
+__global__ void k_pack(const float *__restrict__ W, int C, bool tr, int N, int K, int Np, int Kp, bool parts3,
                        float *__restrict__ f, __bf16 *__restrict__ hi, __bf16 *__restrict__ lo) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)Np * Kp) return;
-    const int n = (int)(idx / Kp), k = (int)(idx % Kp);
+    const int n = (int)(idx / Kp), kp = (int)(idx % Kp);
+    // parts3: block 3 b + p of the packed k is block b of part p (K / 3 wide)
+    const int k = parts3 && kp < K ? (kp / 32) % 3 * (K / 3) + (kp / 96) * 32 + kp % 32 : kp;
     float v = 0.f;
     if (n < N && k < K) v = tr ? W[(long)k * C + n] : W[(long)n * C + k];
     f[idx] = v;
@@ -76,13 +78,16 @@ __global__ void k_pack(const float *__restrict__ W, int C, bool tr, int N, int K
     lo[idx] = (__bf16)(v - (float)h);
 }
 
-int pack_weight(hipStream_t s, const float *W, int R, int C, bool transpose, void *arena, PackedW *out) {
+int pack_weight(hipStream_t s, const float *W, int R, int C, bool transpose, void *arena, PackedW *out,
+                bool parts3) {
     const PackLayout L(R, C, transpose);
+    if (parts3 && (L.K % 96 || L.Kp != L.K)) return -1;
     char *b = reinterpret_cast<char *>(arena);
     float *f = reinterpret_cast<float *>(b);
     __bf16 *hi = reinterpret_cast<__bf16 *>(b + L.off_hi);
     __bf16 *lo = reinterpret_cast<__bf16 *>(b + L.off_lo);
-    k_pack<<<(unsigned)((L.cnt + 255) / 256), 256, 0, s>>>(W, C, transpose, L.N, L.K, L.Np, L.Kp, f, hi, lo);
+    k_pack<<<(unsigned)((L.cnt + 255) / 256), 256, 0, s>>>(W, C, transpose, L.N, L.K, L.Np, L.Kp, parts3, f, hi,
+                                                           lo);
     if (hipGetLastError() != hipSuccess) return -5;
     PackedW p;
     p.N = L.N;
@@ -152,6 +157,22 @@ struct AOp {
             }
         }
     }
+    // block s from the lane's two 4-value pieces: k = 32 s + koff(g, 0) and
+    // 32 s + koff(g, 1)
+    static __device__ __forceinline__ int koff(int g, int h) { return P >= 1 ? 8 * g + 4 * h : 16 * h + 4 * g; }
+    __device__ __forceinline__ void put(int s, v4f x, v4f y) {
+        if constexpr (P >= 1) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const float a = q < 4 ? x[q] : y[q - 4];
+                hi[s][q] = (__bf16)a;
+                if (P == 2) lo[s][q] = (__bf16)(a - (float)hi[s][q]);
+            }
+        } else {
+            f[s][0] = x;
+            f[s][1] = y;
+        }
+    }
 };
 
 // acc[t] (columns n0 + 16 t .. n0 + 16 t + 15) += A[16 rows][0 .. K) B[0 .. K)[n0 .. n0 + 127].
@@ -163,7 +184,7 @@ struct AOp {
 // whose B has at most 16 NT columns needs no more).
 template <int P, int KS, int NT = CT, int G = GW>
 __device__ __forceinline__ void mma_pass(char *lds, const PackedW &B, int n0, int K, const AOp<P, KS> &a,
-                                         v4f *acc) {
+                                         v4f *acc, int k0 = 0) {
     constexpr int KC = Stage<P>::KC, LDH = Stage<P>::LDH, LDF = Stage<P>::LDF;
     constexpr int VR = P >= 1 ? KC / 8 : KC / 4;   // 16-byte vectors per row of a stage
     constexpr int IT = NCH * VR / (64 * G);
@@ -172,13 +193,14 @@ __device__ __forceinline__ void mma_pass(char *lds, const PackedW &B, int n0, in
     const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
     v8bf sh[IT], sl[IT];
     v4f sf[IT];
+    // (k0: the operand's k = 0 is B's row k0)
     auto fetch = [&](int kc) {
-        const int kcl = min(KC, B.Kp - kc);
+        const int kcl = min(KC, B.Kp - k0 - kc);
 #pragma unroll
         for (int it = 0; it < IT; it++) {
             const int idx = threadIdx.x + 64 * G * it, n = idx / VR, q = idx % VR;
             if (EV * q < kcl) {
-                const long go = (long)(n0 + n) * B.Kp + kc + EV * q;
+                const long go = (long)(n0 + n) * B.Kp + k0 + kc + EV * q;
                 if constexpr (P >= 1) {
                     sh[it] = *reinterpret_cast<const v8bf *>(B.hi + go);
                     if (P == 2) sl[it] = *reinterpret_cast<const v8bf *>(B.lo + go);
@@ -189,7 +211,7 @@ __device__ __forceinline__ void mma_pass(char *lds, const PackedW &B, int n0, in
         }
     };
     auto park = [&](int kc) {
-        const int kcl = min(KC, B.Kp - kc);
+        const int kcl = min(KC, B.Kp - k0 - kc);
 #pragma unroll
         for (int it = 0; it < IT; it++) {
             const int idx = threadIdx.x + 64 * G * it, n = idx / VR, q = idx % VR;
@@ -363,10 +385,12 @@ __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(Ge
 // ---------------------------------------------------------------------------
 template <int P, int E1, int E2, int KS>
 __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(2)))
-k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *C1, int ldc1, const float *__restrict__ bias1,
-             const float *R1, int ldr1, PackedW B2, float *C2, int ldc2, const float *__restrict__ bias2,
-             const float *R2, int ldr2, int M, int Fu, const float *sn, const float *v1, const float *UV, float *s2,
-             float *v2, float *gUV, const int *Mc) {
+k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *__restrict__ C1, int ldc1,
+             const float *__restrict__ bias1, const float *__restrict__ R1, int ldr1, PackedW B2,
+             float *__restrict__ C2, int ldc2, const float *__restrict__ bias2, const float *__restrict__ R2, int ldr2,
+             int M, int Fu, const float *__restrict__ sn, const float *__restrict__ v1,
+             const float *__restrict__ UV, float *__restrict__ s2, float *__restrict__ v2, float *__restrict__ gUV,
+             const float *__restrict__ gv, const int *Mc) {
     __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
     if (Mc) M = min(M, *Mc);
     if ((long)blockIdx.x * GW * 16 >= M) return;   // the whole workgroup leaves
@@ -378,20 +402,75 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *C1, int ld
     const int K1 = B1.K, N1 = B1.N;
     float *ct;
     {
-        AOp<P, KS> a;
-        a.load(g, [&](int k) {
-            if (rowok && k + 4 <= K1) return gld4(Ar + k);
-            v4f z;
-#pragma unroll
-            for (int q = 0; q < 4; q++) z[q] = (rowok && k + q < K1) ? Ar[k + q] : 0.f;
-            return z;
-        });
         v4f rr[EIT];
-        if constexpr (E1 == GE_DSILU) fetch_rows(R1, ldr1, m0, 0, N1, M, rr);
         v4f acc[CT];
 #pragma unroll
         for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-        mma_pass<P, KS>(lds, B1, 0, K1, a, acc);
+        if constexpr (E2 == GE_UPDATE_ADJ) {
+            // da of the gated update (K1 = 3F = 32 KS), in pieces of two
+            // 32-feature blocks, each formed just before it is multiplied: B1
+            // is packed with the parts of a feature block adjacent (block
+            // 3 b + p = part p of features 32 b .. 32 b + 31), so a piece is
+            // six consecutive blocks of k.  All three parts of four features
+            // come from one set of loads, and dUv of those features is written
+            // on the way.
+            constexpr int SP = KS / 3;   // feature blocks: 2 (F = 64) or 4 (F = 128)
+            static_assert(3 * SP == KS && SP % 2 == 0, "pieces of two feature blocks");
+            const v4f z = v4f{0.f, 0.f, 0.f, 0.f};
+            // dv2 = 0 (gv null) reads UV (in bounds) scaled by zero, so no
+            // branch separates the loads
+            const float gsc = gv ? 1.f : 0.f;
+            const float *gvp = gv ? gv : UV;
+#pragma unroll
+            for (int pc = 0; pc < SP / 2; pc++) {
+                AOp<P, 6> a;
+                if (!rowok) {
+#pragma unroll
+                    for (int b = 0; b < 6; b++) a.put(b, z, z);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 2; i++) {
+                        v4f p0[2], p1[2], p2[2];
+#pragma unroll
+                        for (int h = 0; h < 2; h++) {
+                            const int f = 32 * (2 * pc + i) + AOp<P, 6>::koff(g, h);
+                            const v4f gs = gld4(R2 + arow * ldr2 + f);
+                            const v4f avv = gld4(Ar + f), gasv = gs * gld4(Ar + Fu + f);
+                            const float *uv = UV + arow * 6 * Fu + f;   // rows (3 m + d) of [Uv | Vv]
+                            v4f gavv = z, dot = z;
+#pragma unroll
+                            for (int d = 0; d < 3; d++) {
+                                const v4f u = gld4(uv + d * 2 * Fu), w = gld4(uv + d * 2 * Fu + Fu);
+                                const v4f gvd = gld4(gvp + (3 * arow + d) * Fu + f) * gsc;
+                                gavv += gvd * u;   // dE/da_vv = sum_d dv2_d o Uv_d
+                                dot += u * w;
+                                // dUv_d = dv2_d o a_vv + ds2 a_sv Vv_d
+                                *reinterpret_cast<v4f *>(gUV + (3 * arow + d) * 2 * Fu + f) = gvd * avv + gasv * w;
+                            }
+                            p0[h] = gavv;
+                            p1[h] = gs * dot;   // dE/da_sv = ds2 <Uv, Vv>
+                            p2[h] = gs;         // dE/da_ss = ds2
+                        }
+                        a.put(3 * i, p0[0], p0[1]);
+                        a.put(3 * i + 1, p1[0], p1[1]);
+                        a.put(3 * i + 2, p2[0], p2[1]);
+                    }
+                }
+                mma_pass<P, 6>(lds, B1, 0, 192, a, acc, 192 * pc);
+            }
+            fetch_rows(R1, ldr1, m0, 0, N1, M, rr);
+        } else {
+            AOp<P, KS> a;
+            a.load(g, [&](int k) {
+                if (rowok && k + 4 <= K1) return gld4(Ar + k);
+                v4f z;
+#pragma unroll
+                for (int q = 0; q < 4; q++) z[q] = (rowok && k + q < K1) ? Ar[k + q] : 0.f;
+                return z;
+            });
+            if constexpr (E1 == GE_DSILU) fetch_rows(R1, ldr1, m0, 0, N1, M, rr);
+            mma_pass<P, KS>(lds, B1, 0, K1, a, acc);
+        }
         ct = park_tile(lds, acc);
         // the activation, written back into the tile (zeros outside the valid
         // rows and columns, which the second product then reads as padding)
@@ -428,7 +507,7 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *C1, int ld
         for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
         mma_pass<P, 4>(lds, B2, n0, K2, a2, acc);
         const float *ct2 = park_tile(lds, acc);
-        if constexpr (E2 == GE_UPDATE || E2 == GE_NORM_ADJ) {
+        if constexpr (E2 == GE_UPDATE || E2 == GE_UPDATE_ADJ) {
             // the update epilogues load several operands per vector: a short
             // unroll keeps them from being hoisted all at once
 #pragma unroll 2
@@ -470,11 +549,14 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *C1, int ld
                     if (part == 0) {
                         *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = gld4(R2 + m * ldr2 + n) + o;
                     } else {
+                        // dVv_d = ds2 a_sv Uv_d + (dn / n) Vv_d
                         const v4f gn = o / gld4(sn + m * 2 * Fu + Fu + f);
+                        const v4f gasv = gld4(R2 + m * ldr2 + f) * gld4(A + m * lda + Fu + f);
 #pragma unroll
                         for (int d = 0; d < 3; d++) {
-                            const long b = (3 * m + d) * 2 * Fu + Fu + f;
-                            *reinterpret_cast<v4f *>(gUV + b) = gld4(gUV + b) + gn * gld4(UV + b);
+                            const long b = (3 * m + d) * 2 * Fu + f;
+                            const v4f gvu = gasv * gld4(UV + b);
+                            *reinterpret_cast<v4f *>(gUV + b + Fu) = gvu + gn * gld4(UV + b + Fu);
                         }
                     }
                 }
@@ -790,7 +872,7 @@ static void launch_chain(hipStream_t s, const GemmChain &c) {
     const unsigned bx = (unsigned)((c.M + 16 * GW - 1) / (16 * GW));
     k_gemm_chain<P, E1, E2, KS><<<bx, 64 * GW, 0, s>>>(c.A, c.lda, *c.B1, c.C1, c.ldc1, c.bias1, c.R1, c.ldr1, *c.B2,
                                                         c.C2, c.ldc2, c.bias2, c.R2, c.ldr2, c.M, c.F, c.sn, c.v1,
-                                                        c.UV, c.s2, c.v2, c.gUV, c.Mc);
+                                                        c.UV, c.s2, c.v2, c.gUV, c.gv, c.Mc);
 }
 
 template <int P>
@@ -809,7 +891,13 @@ static int chain_p(hipStream_t s, const GemmChain &c) {
     if (c.e1 == GE_BIAS_SILU && c.e2 == GE_UPDATE) CL(GE_BIAS_SILU, GE_UPDATE);
     if (c.e1 == GE_DSILU && c.e2 == GE_STORE) CL(GE_DSILU, GE_STORE);
     if (c.e1 == GE_DSILU && c.e2 == GE_ADD) CL(GE_DSILU, GE_ADD);
-    if (c.e1 == GE_DSILU && c.e2 == GE_NORM_ADJ) CL(GE_DSILU, GE_NORM_ADJ);
+    if (c.e1 == GE_DSILU && c.e2 == GE_UPDATE_ADJ) {
+        // K = 3F in whole blocks: F = 64 or 128
+        if (K == 192) launch_chain<P, GE_DSILU, GE_UPDATE_ADJ, 6>(s, c);
+        else if (K == 384) launch_chain<P, GE_DSILU, GE_UPDATE_ADJ, 12>(s, c);
+        else return -1;
+        return 0;
+    }
 #undef CL
     return -1;
 }
@@ -817,7 +905,8 @@ static int chain_p(hipStream_t s, const GemmChain &c) {
 int node_gemm_chain(hipStream_t s, int precision, const GemmChain &c) {
     if (c.M <= 0) return 0;
     if (c.B1->N > NCH || c.B2->K != c.B1->N) return -1;
-    if ((c.e2 == GE_UPDATE || c.e2 == GE_NORM_ADJ) && (c.F < 64 || c.F % 4 || c.B2->N % c.F)) return -1;
+    if ((c.e2 == GE_UPDATE || c.e2 == GE_UPDATE_ADJ) && (c.F < 64 || c.F % 4 || c.B2->N % c.F)) return -1;
+    if (c.e2 == GE_UPDATE_ADJ && (c.B1->K != 3 * c.F || c.lda < 2 * c.F || c.ldr2 < c.F)) return -1;
     const int rc = precision == 0 ? chain_p<0>(s, c) : (precision == 1 ? chain_p<1>(s, c) : chain_p<2>(s, c));
     if (rc) return rc;
     return hipGetLastError() == hipSuccess ? 0 : -5;

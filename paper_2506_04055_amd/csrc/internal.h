@@ -70,8 +70,10 @@ struct LayerW {
 };
 
 // Indices into mlp_model::pk[t]: forward (B = W^T) then adjoint (B = W);
-// UV is the stacked [U; V] (2F x F, adjacent in the weight layout).
-enum { WP_W1 = 0, WP_W2, WP_UV, WP_W3, WP_W4, WP_W1T, WP_W2T, WP_UVT, WP_W3T, WP_W4T, WP_COUNT };
+// UV is the stacked [U; V] (2F x F, adjacent in the weight layout).  WP_W4TP
+// is W4's adjoint operand with its reduction index in the order of the fused
+// update adjoint (F = 64 or 128 only).
+enum { WP_W1 = 0, WP_W2, WP_UV, WP_W3, WP_W4, WP_W1T, WP_W2T, WP_UVT, WP_W3T, WP_W4T, WP_W4TP, WP_COUNT };
 
 // Dimensions of a single-layer Allegro model (allegro.hip): species, radial
 // functions, envelope order, the two-body MLP widths, channel counts per

@@ -665,18 +665,21 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         const int hop_src = T - t;
         const bool last = t == T - 1;   // dE/dv of the last layer's output is zero
         const int ndst = NH(T - 1 - t), nsrc = NH(T - t), nfar = NH(T - t + 1);
-        k_update_bwd1<<<nblk((long)ndst * F, 256), 256, 0, s>>>(A.gs, last ? nullptr : A.gv, A.UV[t], A.a[t], ndst,
-                                                                F, A.ga, A.gUV);
-        if (F >= 64) {
-            // d[s1 | n] -> ds1 = ds2 + d s1 and dVv += (dn / n) Vv, in the epilogue
-            GemmChain c = mlp_bwd(A.ga, F3, m->pk[t][WP_W4T], A.h3[t], F, m->pk[t][WP_W3T], A.gs1, F, A.gs, ndst);
-            c.e2 = GE_NORM_ADJ;
+        if (F == 64 || F == 128) {
+            // one kernel: da (and dUv) formed from ds2, dv2, UV and a as the
+            // first product's operand is loaded, then d[s1 | n] -> ds1 = ds2 +
+            // d s1 and dVv in the epilogue
+            GemmChain c = mlp_bwd(A.a[t], F3, m->pk[t][WP_W4TP], A.h3[t], F, m->pk[t][WP_W3T], A.gs1, F, A.gs, ndst);
+            c.e2 = GE_UPDATE_ADJ;
             c.F = F;
             c.sn = A.sn[t];
             c.UV = A.UV[t];
             c.gUV = A.gUV;
+            c.gv = last ? nullptr : A.gv;
             gemm2(s, P, c);
         } else {
+            k_update_bwd1<<<nblk((long)ndst * F, 256), 256, 0, s>>>(A.gs, last ? nullptr : A.gv, A.UV[t], A.a[t],
+                                                                    ndst, F, A.ga, A.gUV);
             gemm2(s, P, mlp_bwd(A.ga, F3, m->pk[t][WP_W4T], A.h3[t], F, m->pk[t][WP_W3T], A.gsn, 2 * F, nullptr,
                                 ndst));
             k_update_bwd2<<<nblk((long)ndst * F, 256), 256, 0, s>>>(A.gsn, A.sn[t], A.UV[t], A.gs, ndst, F, A.gUV,
