@@ -4,7 +4,8 @@
 
 namespace mlp {
 
-enum { GE_STORE = 0, GE_BIAS = 1, GE_BIAS_SILU = 2, GE_DSILU = 3, GE_ADD = 4, GE_UPDATE = 5, GE_UPDATE_ADJ = 6 };
+enum { GE_STORE = 0, GE_BIAS = 1, GE_BIAS_SILU = 2, GE_DSILU = 3, GE_ADD = 4, GE_UPDATE = 5, GE_UPDATE_ADJ = 6,
+       GE_UPDATE_N = 7 };
 
 // One weight matrix packed as the B operand of C = A B: element (k, n) of B
 // at [n][k] (reduction index contiguous), zero-padded to Np x Kp
@@ -49,6 +50,9 @@ int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, co
 //   GE_UPDATE (after bias2; the output is a = [a_vv | a_sv | a_ss]):
 //     C2 = a_vv, a_sv (a_ss is not stored), v2 = v1 + a_vv o Uv (if v2),
 //     s2 = s1 + a_sv o <Uv, Vv> + a_ss, with s1 = sn[:, :F];
+//   GE_UPDATE_N: the same, with the first product's operand [s1 | n] formed
+//     as it is loaded (F = 64 or 128): s1 = A[:, :F], n = sqrt(eps + sum_d
+//     Vv_d^2) from UV (n is then not stored);
 //   GE_UPDATE_ADJ (with e1 = GE_DSILU; the whole adjoint of the update and
 //     of the norm; F = 64 or 128): the first product's A operand, da =
 //     [dE/da_vv | dE/da_sv | dE/da_ss] (K1 = 3F, B1 packed with parts3), is
@@ -56,7 +60,7 @@ int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, co
 //     a = A (rows of lda floats, [a_vv | a_sv | ...]), and dUv = dv2 o a_vv +
 //     ds2 a_sv Vv goes to gUV on the way; the output is [ds1 | dn]: C2 =
 //     R2 + ds1, and dVv = ds2 a_sv Uv + (dn / n) o Vv to gUV, with
-//     n = sn[:, F:].
+//     n = sqrt(eps + sum_d Vv_d^2) formed again from UV.
 // UV and gUV hold rows [Uv | Vv] of 2F per (atom, direction), v1, v2 and gv
 // rows of F per (atom, direction).
 struct GemmChain {
@@ -76,6 +80,7 @@ struct GemmChain {
     const float *sn = nullptr, *v1 = nullptr, *UV = nullptr;
     float *s2 = nullptr, *v2 = nullptr, *gUV = nullptr;
     const float *gv = nullptr;
+    float eps = 0.f;                              // the norm's epsilon (GE_UPDATE_N, GE_UPDATE_ADJ)
     const int *Mc = nullptr;                      // device row count bounding M (may be null)
 };
 int node_gemm_chain(hipStream_t s, int precision, const GemmChain &c);

@@ -157,6 +157,27 @@ struct AOp {
             }
         }
     }
+    // this lane's row of a row-major operand with K columns (zeros past K and
+    // on rows past the end).  With K a multiple of 4 each piece is one
+    // 16-byte load, its address clamped in bounds and its value selected
+    // away past K, so no branch separates the loads and they are all in
+    // flight together.
+    __device__ __forceinline__ void load_row(int g, const float *Ar, int K, bool rowok) {
+        if ((K & 3) == 0) {
+            load(g, [&](int k) {
+                const v4f x = *reinterpret_cast<const v4f *>(Ar + min(k, K - 4));
+                return (rowok && k < K) ? x : v4f{0.f, 0.f, 0.f, 0.f};
+            });
+        } else {
+            load(g, [&](int k) {
+                if (rowok && k + 4 <= K) return *reinterpret_cast<const v4f *>(Ar + k);
+                v4f z;
+#pragma unroll
+                for (int q = 0; q < 4; q++) z[q] = (rowok && k + q < K) ? Ar[k + q] : 0.f;
+                return z;
+            });
+        }
+    }
     // block s from the lane's two 4-value pieces: k = 32 s + koff(g, 0) and
     // 32 s + koff(g, 1)
     static __device__ __forceinline__ int koff(int g, int h) { return P >= 1 ? 8 * g + 4 * h : 16 * h + 4 * g; }
@@ -285,6 +306,16 @@ __device__ __forceinline__ float *park_tile(char *lds, const v4f *acc) {
 }
 constexpr int EIT = 16 * NCH / 4 / 64;   // epilogue vectors per lane
 
+// n = sqrt(eps + sum_d x_d^2) per component, the products added in d order
+// by fused multiply-adds
+__device__ __forceinline__ v4f norm4(v4f x0, v4f x1, v4f x2, float eps) {
+    v4f o;
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+        o[q] = sqrtf(__builtin_fmaf(x2[q], x2[q], __builtin_fmaf(x1[q], x1[q], __builtin_fmaf(x0[q], x0[q], eps))));
+    return o;
+}
+
 __device__ __forceinline__ v4f silu4(v4f h) {
     v4f o;
 #pragma unroll
@@ -335,13 +366,7 @@ __global__ void __launch_bounds__(64 * GW) __attribute__((amdgpu_waves_per_eu(Ge
     const int K = B.K;
     // the wave's 16 x K slice of A, loaded at once (all loads in flight together)
     AOp<P, KS> a;
-    a.load(g, [&](int k) {
-        if (rowok && k + 4 <= K) return gld4(Ar + k);
-        v4f z;
-#pragma unroll
-        for (int q = 0; q < 4; q++) z[q] = (rowok && k + q < K) ? Ar[k + q] : 0.f;
-        return z;
-    });
+    a.load_row(g, Ar, K, rowok);
     // the epilogue's second operand (R) is fetched now, so its latency
     // overlaps the products
     const int ncols = min(NCH, B.N - n0);   // a multiple of 4
@@ -390,7 +415,7 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *__restrict
              float *__restrict__ C2, int ldc2, const float *__restrict__ bias2, const float *__restrict__ R2, int ldr2,
              int M, int Fu, const float *__restrict__ sn, const float *__restrict__ v1,
              const float *__restrict__ UV, float *__restrict__ s2, float *__restrict__ v2, float *__restrict__ gUV,
-             const float *__restrict__ gv, const int *Mc) {
+             const float *__restrict__ gv, float eps, const int *Mc) {
     __shared__ __attribute__((aligned(16))) char lds[GemmLds<P>::BYTES];
     if (Mc) M = min(M, *Mc);
     if ((long)blockIdx.x * GW * 16 >= M) return;   // the whole workgroup leaves
@@ -459,15 +484,36 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *__restrict
                 mma_pass<P, 6>(lds, B1, 0, 192, a, acc, 192 * pc);
             }
             fetch_rows(R1, ldr1, m0, 0, N1, M, rr);
+        } else if constexpr (E2 == GE_UPDATE_N) {
+            // [s1 | n] (K1 = 2F = 32 KS): s1 from A, n from the Vv rows
+            constexpr int SP = KS / 2;
+            static_assert(2 * SP == KS, "two parts of whole blocks");
+            AOp<P, KS> a;
+            const v4f z = v4f{0.f, 0.f, 0.f, 0.f};
+            if (!rowok) {
+#pragma unroll
+                for (int b = 0; b < KS; b++) a.put(b, z, z);
+            } else {
+#pragma unroll
+                for (int b = 0; b < KS; b++) {
+                    v4f x[2];
+#pragma unroll
+                    for (int h = 0; h < 2; h++) {
+                        const int f = 32 * (b % SP) + AOp<P, KS>::koff(g, h);
+                        if (b < SP) {
+                            x[h] = gld4(Ar + f);
+                        } else {
+                            const float *vv = UV + arow * 6 * Fu + Fu + f;   // Vv of rows 3 m + d
+                            x[h] = norm4(gld4(vv), gld4(vv + 2 * Fu), gld4(vv + 4 * Fu), eps);
+                        }
+                    }
+                    a.put(b, x[0], x[1]);
+                }
+            }
+            mma_pass<P, KS>(lds, B1, 0, K1, a, acc);
         } else {
             AOp<P, KS> a;
-            a.load(g, [&](int k) {
-                if (rowok && k + 4 <= K1) return gld4(Ar + k);
-                v4f z;
-#pragma unroll
-                for (int q = 0; q < 4; q++) z[q] = (rowok && k + q < K1) ? Ar[k + q] : 0.f;
-                return z;
-            });
+            a.load_row(g, Ar, K1, rowok);
             if constexpr (E1 == GE_DSILU) fetch_rows(R1, ldr1, m0, 0, N1, M, rr);
             mma_pass<P, KS>(lds, B1, 0, K1, a, acc);
         }
@@ -507,7 +553,7 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *__restrict
         for (int t = 0; t < CT; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
         mma_pass<P, 4>(lds, B2, n0, K2, a2, acc);
         const float *ct2 = park_tile(lds, acc);
-        if constexpr (E2 == GE_UPDATE || E2 == GE_UPDATE_ADJ) {
+        if constexpr (E2 == GE_UPDATE || E2 == GE_UPDATE_N || E2 == GE_UPDATE_ADJ) {
             // the update epilogues load several operands per vector: a short
             // unroll keeps them from being hoisted all at once
 #pragma unroll 2
@@ -519,7 +565,7 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *__restrict
                 v4f o = *reinterpret_cast<const v4f *>(ct2 + row * LDC + c4);
                 // part of the output: F columns each, features f .. f+3
                 const int part = n / Fu, f = n - part * Fu;
-                if constexpr (E2 == GE_UPDATE) {
+                if constexpr (E2 == GE_UPDATE || E2 == GE_UPDATE_N) {
                     // part 0: a_vv, part 1: a_sv, part 2: a_ss
 #pragma unroll
                     for (int q = 0; q < 4; q++) o[q] += bias2[n + q];
@@ -550,13 +596,14 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *__restrict
                         *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = gld4(R2 + m * ldr2 + n) + o;
                     } else {
                         // dVv_d = ds2 a_sv Uv_d + (dn / n) Vv_d
-                        const v4f gn = o / gld4(sn + m * 2 * Fu + Fu + f);
+                        const float *uv = UV + m * 6 * Fu + f;   // rows (3 m + d) of [Uv | Vv]
+                        const v4f vv[3] = {gld4(uv + Fu), gld4(uv + 3 * Fu), gld4(uv + 5 * Fu)};
+                        const v4f gn = o / norm4(vv[0], vv[1], vv[2], eps);
                         const v4f gasv = gld4(R2 + m * ldr2 + f) * gld4(A + m * lda + Fu + f);
 #pragma unroll
                         for (int d = 0; d < 3; d++) {
-                            const long b = (3 * m + d) * 2 * Fu + f;
-                            const v4f gvu = gasv * gld4(UV + b);
-                            *reinterpret_cast<v4f *>(gUV + b + Fu) = gvu + gn * gld4(UV + b + Fu);
+                            const v4f gvu = gasv * gld4(uv + d * 2 * Fu);
+                            *reinterpret_cast<v4f *>(gUV + (3 * m + d) * 2 * Fu + Fu + f) = gvu + gn * vv[d];
                         }
                     }
                 }
@@ -697,13 +744,7 @@ k_mlp_bwd(const float *__restrict__ X, int ldx, EdgeMlp W, const float *__restri
     {
         const float *Gr = GC + (rowok ? arow : 0) * (long)ldgc;
         const int NO = W.f[NH].N;
-        ga.load(g, [&](int k) {
-            if (rowok && k + 4 <= NO) return gld4(Gr + k);
-            v4f z;
-#pragma unroll
-            for (int q = 0; q < 4; q++) z[q] = (rowok && k + q < NO) ? Gr[k + q] : 0.f;
-            return z;
-        });
+        ga.load_row(g, Gr, NO, rowok);
     }
     // forward recompute: pre-activations of every hidden layer
     v4f pre[NH][HT];
@@ -872,7 +913,7 @@ static void launch_chain(hipStream_t s, const GemmChain &c) {
     const unsigned bx = (unsigned)((c.M + 16 * GW - 1) / (16 * GW));
     k_gemm_chain<P, E1, E2, KS><<<bx, 64 * GW, 0, s>>>(c.A, c.lda, *c.B1, c.C1, c.ldc1, c.bias1, c.R1, c.ldr1, *c.B2,
                                                         c.C2, c.ldc2, c.bias2, c.R2, c.ldr2, c.M, c.F, c.sn, c.v1,
-                                                        c.UV, c.s2, c.v2, c.gUV, c.gv, c.Mc);
+                                                        c.UV, c.s2, c.v2, c.gUV, c.gv, c.eps, c.Mc);
 }
 
 template <int P>
@@ -889,6 +930,13 @@ static int chain_p(hipStream_t s, const GemmChain &c) {
     if (ks == 0) return -1;
     if (c.e1 == GE_BIAS_SILU && c.e2 == GE_BIAS) CL(GE_BIAS_SILU, GE_BIAS);
     if (c.e1 == GE_BIAS_SILU && c.e2 == GE_UPDATE) CL(GE_BIAS_SILU, GE_UPDATE);
+    if (c.e1 == GE_BIAS_SILU && c.e2 == GE_UPDATE_N) {
+        // K = 2F in whole blocks: F = 64 or 128
+        if (K == 128) launch_chain<P, GE_BIAS_SILU, GE_UPDATE_N, 4>(s, c);
+        else if (K == 256) launch_chain<P, GE_BIAS_SILU, GE_UPDATE_N, 8>(s, c);
+        else return -1;
+        return 0;
+    }
     if (c.e1 == GE_DSILU && c.e2 == GE_STORE) CL(GE_DSILU, GE_STORE);
     if (c.e1 == GE_DSILU && c.e2 == GE_ADD) CL(GE_DSILU, GE_ADD);
     if (c.e1 == GE_DSILU && c.e2 == GE_UPDATE_ADJ) {
@@ -905,7 +953,10 @@ static int chain_p(hipStream_t s, const GemmChain &c) {
 int node_gemm_chain(hipStream_t s, int precision, const GemmChain &c) {
     if (c.M <= 0) return 0;
     if (c.B1->N > NCH || c.B2->K != c.B1->N) return -1;
-    if ((c.e2 == GE_UPDATE || c.e2 == GE_UPDATE_ADJ) && (c.F < 64 || c.F % 4 || c.B2->N % c.F)) return -1;
+    if ((c.e2 == GE_UPDATE || c.e2 == GE_UPDATE_N || c.e2 == GE_UPDATE_ADJ) &&
+        (c.F < 64 || c.F % 4 || c.B2->N % c.F))
+        return -1;
+    if (c.e2 == GE_UPDATE_N && c.B1->K != 2 * c.F) return -1;
     if (c.e2 == GE_UPDATE_ADJ && (c.B1->K != 3 * c.F || c.lda < 2 * c.F || c.ldr2 < c.F)) return -1;
     const int rc = precision == 0 ? chain_p<0>(s, c) : (precision == 1 ? chain_p<1>(s, c) : chain_p<2>(s, c));
     if (rc) return rc;

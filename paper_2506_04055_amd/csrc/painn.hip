@@ -625,14 +625,18 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             if ((rc = msg_forward(s, PF, F, K, ma))) return fail(rc, "message kernel launch failed");
         }
         gemm<E_STORE>(s, P, A.v1[t], F, m->pk[t][WP_UV], A.UV[t], 2 * F, 3 * ndst);
-        k_norm<<<nblk((long)ndst * F, 256), 256, 0, s>>>(A.UV[t], ndst, F, m->eps, A.sn[t]);
+        // n = sqrt(eps + sum_d Vv_d^2): formed where it is used when F is 64
+        // or 128 (the update's operand load and the adjoint's epilogue)
+        const bool nfused = F == 64 || F == 128;
+        if (!nfused) k_norm<<<nblk((long)ndst * F, 256), 256, 0, s>>>(A.UV[t], ndst, F, m->eps, A.sn[t]);
         {
             GemmChain c = mlp_fwd(A.sn[t], 2 * F, m->pk[t][WP_W3], A.h3[t], F, L.b3, m->pk[t][WP_W4], A.a[t], F3, L.b4,
                                   ndst);
             if (F >= 64) {
                 // the gated update in the second product's epilogue (the last
                 // layer's v is not needed: the readout takes s only)
-                c.e2 = GE_UPDATE;
+                c.e2 = nfused ? GE_UPDATE_N : GE_UPDATE;
+                c.eps = m->eps;
                 c.F = F;
                 c.sn = A.sn[t];
                 c.v1 = A.v1[t];
@@ -676,6 +680,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             c.UV = A.UV[t];
             c.gUV = A.gUV;
             c.gv = last ? nullptr : A.gv;
+            c.eps = m->eps;
             gemm2(s, P, c);
         } else {
             k_update_bwd1<<<nblk((long)ndst * F, 256), 256, 0, s>>>(A.gs, last ? nullptr : A.gv, A.UV[t], A.a[t],
