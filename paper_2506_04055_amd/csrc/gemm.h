@@ -5,7 +5,7 @@
 namespace mlp {
 
 enum { GE_STORE = 0, GE_BIAS = 1, GE_BIAS_SILU = 2, GE_DSILU = 3, GE_ADD = 4, GE_UPDATE = 5, GE_UPDATE_ADJ = 6,
-       GE_UPDATE_N = 7 };
+       GE_UPDATE_N = 7, GE_BIAS_VPROD = 8 };
 
 // One weight matrix packed as the B operand of C = A B: element (k, n) of B
 // at [n][k] (reduction index contiguous), zero-padded to Np x Kp
@@ -42,7 +42,10 @@ int node_gemm(hipStream_t s, int precision, int epi, const float *A, int lda, co
 // Two chained products C2 = e2(act(A B1) B2) in one kernel, the intermediate
 // kept on chip.  e1 = GE_BIAS_SILU: act = SiLU(x + bias1), the pre-activation
 // x + bias1 also stored to C1; e1 = GE_DSILU: act = x * SiLU'(R1).  e2 =
-// GE_BIAS (+ bias2), GE_STORE or GE_ADD (+ R2).  B1 has at most 128 columns and
+// GE_BIAS (+ bias2), GE_STORE or GE_ADD (+ R2), or GE_BIAS_VPROD: GE_BIAS,
+// and of the first F output columns (phi_vv of a PaiNN message MLP) also
+// v2[(3 m + d) F + f] = v1[(3 m + d) F + f] C2[m][f] for d = 0, 1, 2 (the
+// rows a message pass gathers).  B1 has at most 128 columns and
 // B2 as many rows.  Returns 0, -1 (unsupported shape or combination) or -5.
 // Two further second-stage epilogues apply the gated update of a PaiNN layer
 // (F >= 64, so that the three F-column parts of the output fall in

@@ -556,7 +556,8 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *__restrict
         if constexpr (E2 == GE_UPDATE || E2 == GE_UPDATE_N || E2 == GE_UPDATE_ADJ) {
             // the update epilogues load several operands per vector: a short
             // unroll keeps them from being hoisted all at once
-#pragma unroll 2
+            constexpr int UPD_UNROLL = 2;
+#pragma unroll UPD_UNROLL
             for (int it = 0; it < EIT; it++) {
                 const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
                 const long m = m0 + row;
@@ -609,20 +610,30 @@ k_gemm_chain(const float *__restrict__ A, int lda, PackedW B1, float *__restrict
                 }
             }
         } else {
-#pragma unroll
+            // (three more loads per vector with the v o phi_vv rows: a shorter unroll)
+            constexpr int GEN_UNROLL = E2 == GE_BIAS_VPROD ? 4 : EIT;
+#pragma unroll GEN_UNROLL
             for (int it = 0; it < EIT; it++) {
                 const int idx = lane + 64 * it, row = idx / (NCH / 4), c4 = 4 * (idx % (NCH / 4));
                 const long m = m0 + row;
                 if (m >= M || c4 >= ncols) continue;
                 const int n = n0 + c4;
                 v4f o = *reinterpret_cast<const v4f *>(ct2 + row * LDC + c4);
-                if constexpr (E2 == GE_BIAS) {
+                if constexpr (E2 == GE_BIAS || E2 == GE_BIAS_VPROD) {
 #pragma unroll
                     for (int q = 0; q < 4; q++) o[q] += bias2[n + q];
                 } else if constexpr (E2 == GE_ADD) {
                     o += rr[it];
                 }
                 *reinterpret_cast<v4f *>(C2 + m * ldc2 + n) = o;
+                if constexpr (E2 == GE_BIAS_VPROD) {
+                    if (n < Fu)
+#pragma unroll
+                        for (int d = 0; d < 3; d++) {
+                            const long b = (3 * m + d) * Fu + n;
+                            *reinterpret_cast<v4f *>(v2 + b) = gld4(v1 + b) * o;
+                        }
+                }
             }
         }
     }
@@ -929,6 +940,7 @@ static int chain_p(hipStream_t s, const GemmChain &c) {
     } while (0)
     if (ks == 0) return -1;
     if (c.e1 == GE_BIAS_SILU && c.e2 == GE_BIAS) CL(GE_BIAS_SILU, GE_BIAS);
+    if (c.e1 == GE_BIAS_SILU && c.e2 == GE_BIAS_VPROD) CL(GE_BIAS_SILU, GE_BIAS_VPROD);
     if (c.e1 == GE_BIAS_SILU && c.e2 == GE_UPDATE) CL(GE_BIAS_SILU, GE_UPDATE);
     if (c.e1 == GE_BIAS_SILU && c.e2 == GE_UPDATE_N) {
         // K = 2F in whole blocks: F = 64 or 128
@@ -957,6 +969,7 @@ int node_gemm_chain(hipStream_t s, int precision, const GemmChain &c) {
         (c.F < 64 || c.F % 4 || c.B2->N % c.F))
         return -1;
     if (c.e2 == GE_UPDATE_N && c.B1->K != 2 * c.F) return -1;
+    if (c.e2 == GE_BIAS_VPROD && (c.F <= 0 || c.F % 4 || c.B2->N < c.F)) return -1;
     if (c.e2 == GE_UPDATE_ADJ && (c.B1->K != 3 * c.F || c.lda < 2 * c.F || c.ldr2 < c.F)) return -1;
     const int rc = precision == 0 ? chain_p<0>(s, c) : (precision == 1 ? chain_p<1>(s, c) : chain_p<2>(s, c));
     if (rc) return rc;

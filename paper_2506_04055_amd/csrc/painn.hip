@@ -101,20 +101,6 @@ static GemmChain mlp_bwd(const float *gout, int ldg, const PackedW &B1, const fl
 // Elementwise node kernels
 // ---------------------------------------------------------------------------
 
-// u[i][d][f] = v[i][d][f] phi[i][f] (phi_vv), four features per thread.
-__global__ void k_vprod(const float *__restrict__ v, const float *__restrict__ phi, int n, int F,
-                        float *__restrict__ u) {
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long)n * F / 4) return;
-    const long i = idx / (F / 4);
-    const int f = 4 * (int)(idx % (F / 4));
-    const float4 p = *reinterpret_cast<const float4 *>(phi + i * 3 * F + f);
-    for (int d = 0; d < 3; d++) {
-        const float4 x = *reinterpret_cast<const float4 *>(v + i * 3 * F + d * F + f);
-        *reinterpret_cast<float4 *>(u + i * 3 * F + d * F + f) = make_float4(x.x * p.x, x.y * p.y, x.z * p.z, x.w * p.w);
-    }
-}
-
 // p[0 .. count) = 0.
 __global__ void k_fill_zero(float *__restrict__ p, long count) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -594,10 +580,15 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         const int hop_dst = T - 1 - t;
         const int nsrc = NH(T - t), ndst = NH(T - 1 - t);
         if (t > 0) {
-            gemm2(s, P, mlp_fwd(A.s[t], F, m->pk[t][WP_W1], A.h1[t], F, L.b1, m->pk[t][WP_W2], A.phi[t], F3, L.b2,
-                                nsrc));
-            // u = v * phi_vv: the rows the message pass gathers together with phi_s and phi_vs
-            k_vprod<<<nblk((long)nsrc * F / 4, 256), 256, 0, s>>>(A.v[t], A.phi[t], nsrc, F, A.u);
+            // phi, and u = v * phi_vv in the same epilogue: the rows the
+            // message pass gathers together with phi_s and phi_vs
+            GemmChain c = mlp_fwd(A.s[t], F, m->pk[t][WP_W1], A.h1[t], F, L.b1, m->pk[t][WP_W2], A.phi[t], F3, L.b2,
+                                  nsrc);
+            c.e2 = GE_BIAS_VPROD;
+            c.F = F;
+            c.v1 = A.v[t];
+            c.v2 = A.u;
+            gemm2(s, P, c);
         }
         if (t == 0 && m->l0f) {
             // factorised first layer: basis sums per atom and species, then
