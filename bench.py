@@ -575,6 +575,8 @@ def main():
     ap.add_argument("--mace-only", action="store_true", help="time only the MACE workload (a quick check)")
     ap.add_argument("--water-only", action="store_true",
                     help="time only the 24,000-atom water MD workload (100 velocity-Verlet steps)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="time only the serving workload (closed loop and offered loads)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device to device (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -596,6 +598,9 @@ def main():
         del a, b
     if args.allegro_only:
         print(json.dumps({p: measure_allegro(mlp, synth, torch, p) for p in (args.precision, "fp32")}), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps(serve_bench(mlp, synth, args.precision, args.requests)), flush=True)
         return
     if args.mace_only:
         print(json.dumps({p: measure_mace(mlp, synth, torch, p) for p in (args.precision, "fp32")}), flush=True)
