@@ -9,8 +9,10 @@
 // batch (concatenated pruned CSR with atom and edge offsets, one energy
 // segment per system) and evaluated by a single pass of the kernels on the
 // compute stream, while the next arrivals are copied and built on the prep
-// stream.  Results are copied back into pinned memory; mlp_poll hands them
-// over.  The fixed-shape buffering of the paper (Results, "Runtime
+// stream.  A wave's energies and forces come back in one copy each into
+// pinned memory; when a wave completes, the next one is launched before
+// the completed one's rows are handed to its requests, so the device does
+// not wait on that host work.  mlp_poll hands the results over.  The fixed-shape buffering of the paper (Results, "Runtime
 // optimizations and buffering") becomes grow-only device buffers here: the
 // batch arena and the slots only grow.
 #include "../../include/mlp.h"
@@ -51,28 +53,53 @@ struct Req {
 };
 
 // A slot holds one admitted request: its graph, its device inputs and
-// pinned staging for the host <-> device copies (grown, never per request,
-// so no pinned allocation or release sits on the request path).
+// pinned staging for the upload (grown, never per request, so no pinned
+// allocation or release sits on the request path).
 struct Slot {
     mlp_nbr *nbr = nullptr;
     DevBuf pos, species;
-    float *h_pos = nullptr, *h_forces = nullptr;   // pinned, SoA 3 x cap
-    int *h_species = nullptr;                      // pinned, cap
+    float *h_pos = nullptr;      // pinned, SoA 3 x cap
+    int *h_species = nullptr;    // pinned, cap
     int h_cap = 0;
     bool busy = false;
 };
 
+// Host side of one wave: pinned buffers its results are copied into (one
+// copy each for the energies and the forces of the whole batch) and the atom
+// offsets of its systems.  Two alternate, so the next wave can be launched
+// before the finished one is unpacked.
+struct WaveHost {
+    double *energies = nullptr;
+    float *forces = nullptr;   // SoA 3 x nt, the batch's rows
+    size_t e_cap = 0, f_cap = 0;
+    std::vector<int> seg;      // B + 1 atom offsets
+    int64_t nt = 0;
+};
+
+int ensure_pinned(void **p, size_t *cap, size_t bytes) {
+    if (bytes <= *cap) return 0;
+    if (*p) hipHostFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    const size_t want = bytes + bytes / 4;
+    if (hipHostMalloc(p, want, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(MLP_ERR_OOM, "pinned allocation failed");
+    }
+    *cap = want;
+    return 0;
+}
+
 int ensure_staging(Slot &sl, int n) {
     if (n <= sl.h_cap) return 0;
     if (sl.h_pos) hipHostFree(sl.h_pos);
-    if (sl.h_forces) hipHostFree(sl.h_forces);
     if (sl.h_species) hipHostFree(sl.h_species);
-    sl.h_pos = sl.h_forces = nullptr;
+    sl.h_pos = nullptr;
     sl.h_species = nullptr;
     sl.h_cap = 0;
     const int cap = n + n / 4;
     if (hipHostMalloc((void **)&sl.h_pos, sizeof(float) * 3 * (size_t)cap, 0) != hipSuccess ||
-        hipHostMalloc((void **)&sl.h_forces, sizeof(float) * 3 * (size_t)cap, 0) != hipSuccess ||
         hipHostMalloc((void **)&sl.h_species, sizeof(int) * (size_t)cap, 0) != hipSuccess) {
         (void)hipGetLastError();
         return fail(MLP_ERR_OOM, "pinned staging allocation failed");
@@ -148,9 +175,8 @@ struct mlp_server {
     bool wave_in_flight = false;
     mlp_nbr batch;              // packed graph + activations of the running wave
     DevBuf seg, energies, forces;
-    double *h_energies = nullptr;
-    int h_energies_cap = 0;
-    std::vector<int> h_seg;
+    WaveHost wh[2];             // host side of the wave in flight (wh[cur]) and of the one before
+    int cur = 0;
     float skin = 0.0f;
 };
 
@@ -223,13 +249,15 @@ int launch_wave(mlp_server *S) {
         (rc = S->energies.ensure(sizeof(double) * B, 1.25, G)) ||
         (rc = S->forces.ensure(sizeof(float) * 3 * Nt, 1.25, G)))
         return rc;
-    if (S->h_energies_cap < B) {
-        if (S->h_energies) hipHostFree(S->h_energies);
-        S->h_energies_cap = std::max(B, 2 * S->h_energies_cap);
-        if (hipHostMalloc((void **)&S->h_energies, sizeof(double) * S->h_energies_cap, 0) != hipSuccess)
-            return fail(MLP_ERR_OOM, "pinned allocation failed");
-    }
-    S->h_seg.assign(B + 1, 0);
+    // this wave's host buffers: the other pair than the previous wave's,
+    // which may not be unpacked yet
+    S->cur ^= 1;
+    WaveHost &H = S->wh[S->cur];
+    if ((rc = ensure_pinned((void **)&H.energies, &H.e_cap, sizeof(double) * B)) ||
+        (rc = ensure_pinned((void **)&H.forces, &H.f_cap, sizeof(float) * 3 * (size_t)Nt)))
+        return rc;
+    H.seg.assign(B + 1, 0);
+    H.nt = Nt;
     int64_t aoff = 0, eoff = 0;
     for (int b = 0; b < B; b++) {
         Req *r = W[b];
@@ -242,7 +270,7 @@ int launch_wave(mlp_server *S) {
             k_pack_edges<<<(int)((r->n_edges + 255) / 256), 256, 0, S->s_comp>>>(
                 sg->colc.as<int>(), sg->revc.as<int>(), sg->geom.as<float4>(), (int)r->n_edges, (int)aoff, (int)eoff,
                 g.colc.as<int>(), g.revc.as<int>(), g.geom.as<float4>());
-        S->h_seg[b] = (int)aoff;
+        H.seg[b] = (int)aoff;
         aoff += r->n;
         eoff += r->n_edges;
     }
@@ -253,8 +281,8 @@ int launch_wave(mlp_server *S) {
             r->batch_size = B;
         }
     }
-    S->h_seg[B] = (int)aoff;
-    HIP_TRY(hipMemcpyAsync(S->seg.p, S->h_seg.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, S->s_comp));
+    H.seg[B] = (int)aoff;
+    HIP_TRY(hipMemcpyAsync(S->seg.p, H.seg.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, S->s_comp));
     g.n_atoms = (int)Nt;
     g.n_local = (int)Nt;
     g.n_edges_skin = Et;
@@ -262,35 +290,38 @@ int launch_wave(mlp_server *S) {
     if ((rc = evaluate(S->m, &g, S->s_comp, S->energies.as<double>(), S->forces.as<float>(), nullptr, B,
                        S->seg.as<int>())))
         return rc;
-    HIP_TRY(hipMemcpyAsync(S->h_energies, S->energies.p, sizeof(double) * B, hipMemcpyDeviceToHost, S->s_comp));
-    for (int b = 0; b < B; b++) {
-        Req *r = W[b];
-        const float *F = S->forces.as<float>();
-        for (int d = 0; d < 3; d++)
-            HIP_TRY(hipMemcpyAsync(S->slots[r->slot].h_forces + (size_t)d * r->n, F + (size_t)d * Nt + S->h_seg[b],
-                                   sizeof(float) * r->n, hipMemcpyDeviceToHost, S->s_comp));
-    }
+    // the results come back in two copies (the whole batch's energies and
+    // forces); each request's rows are taken out on the host
+    HIP_TRY(hipMemcpyAsync(H.energies, S->energies.p, sizeof(double) * B, hipMemcpyDeviceToHost, S->s_comp));
+    HIP_TRY(hipMemcpyAsync(H.forces, S->forces.p, sizeof(float) * 3 * (size_t)Nt, hipMemcpyDeviceToHost, S->s_comp));
     HIP_TRY(hipEventRecord(S->ev_wave, S->s_comp));
     S->wave_in_flight = true;
     return 0;
 }
 
-void finish_wave(mlp_server *S) {
+// Unpack a completed wave (its requests `done`, its host buffers `H`).
+void finish_wave(mlp_server *S, std::vector<Req *> &done, const WaveHost &H) {
     const auto now = clk::now();
+    // the rows of each request, out of the batch's SoA forces, before the lock
+    for (size_t b = 0; b < done.size(); b++) {
+        Req *r = done[b];
+        r->energy = H.energies[b];
+        r->forces.resize(3 * (size_t)r->n);
+        for (int d = 0; d < 3; d++) {
+            const float *hf = H.forces + (size_t)d * H.nt + H.seg[b];
+            std::copy(hf, hf + r->n, r->forces.begin() + (size_t)d * r->n);
+        }
+    }
     std::lock_guard<std::mutex> lk(S->mu);
-    for (size_t b = 0; b < S->running.size(); b++) {
-        Req *r = S->running[b];
-        r->energy = S->h_energies[b];
-        const float *hf = S->slots[r->slot].h_forces;
-        r->forces.assign(hf, hf + 3 * (size_t)r->n);
+    for (size_t b = 0; b < done.size(); b++) {
+        Req *r = done[b];
         r->t_done = now;
         r->state = 4;
         S->slots[r->slot].busy = false;
         S->reserved -= r->bytes;
         r->slot = -1;
     }
-    S->running.clear();
-    S->wave_in_flight = false;
+    done.clear();
     S->cv.notify_all();
 }
 
@@ -328,8 +359,27 @@ void prep_worker(mlp_server *S, int k) {
     }
 }
 
-// The scheduler: admission in arrival order, and waves.  A finished wave is
-// retired and the next one, of every request ready by then, launched.
+// Launch a wave of every ready request; if the launch fails, its requests
+// fail (and their slots are released).
+void start_wave(mlp_server *S) {
+    const int rc = launch_wave(S);
+    if (!rc) return;
+    // kernels of the partly launched wave may still read the slots
+    (void)hipStreamSynchronize(S->s_comp);
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (Req *r : S->running) {
+        fail_req(r, rc, mlp_last_error());
+        S->slots[r->slot].busy = false;
+        S->reserved -= r->bytes;
+        r->slot = -1;
+        r->t_done = clk::now();
+    }
+    S->running.clear();
+}
+
+// The scheduler: admission in arrival order, and waves.  When a wave
+// completes, the next one, of every request ready by then, is launched and
+// then the completed one is unpacked.
 void scheduler(mlp_server *S) {
     hipSetDevice(S->device);
     for (;;) {
@@ -366,7 +416,19 @@ void scheduler(mlp_server *S) {
         if (S->wave_in_flight) {
             const hipError_t q = hipEventQuery(S->ev_wave);
             if (q == hipSuccess) {
-                finish_wave(S);
+                // the next wave goes to the device before the finished one is
+                // unpacked on the host (it uses the other host buffers)
+                std::vector<Req *> done;
+                done.swap(S->running);
+                const int dcur = S->cur;
+                S->wave_in_flight = false;
+                {
+                    std::lock_guard<std::mutex> lk(S->mu);
+                    have_ready = !S->ready.empty();
+                }
+                if (have_ready) start_wave(S);
+                have_ready = false;
+                finish_wave(S, done, S->wh[dcur]);
             } else if (q != hipErrorNotReady) {
                 // the wave failed on the device: its requests fail instead of waiting forever
                 (void)hipStreamSynchronize(S->s_comp);
@@ -382,22 +444,7 @@ void scheduler(mlp_server *S) {
                 S->wave_in_flight = false;
             }
         }
-        if (!S->wave_in_flight && have_ready) {
-            int rc = launch_wave(S);
-            if (rc) {
-                // kernels of the partly launched wave may still read the slots
-                (void)hipStreamSynchronize(S->s_comp);
-                std::lock_guard<std::mutex> lk(S->mu);
-                for (Req *r : S->running) {
-                    fail_req(r, rc, mlp_last_error());
-                    S->slots[r->slot].busy = false;
-                    S->reserved -= r->bytes;
-                    r->slot = -1;
-                    r->t_done = clk::now();
-                }
-                S->running.clear();
-            }
-        }
+        if (!S->wave_in_flight && have_ready) start_wave(S);
         if (S->wave_in_flight) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
@@ -466,7 +513,6 @@ int mlp_server_destroy(mlp_server *S) {
         sl.pos.release();
         sl.species.release();
         if (sl.h_pos) hipHostFree(sl.h_pos);
-        if (sl.h_forces) hipHostFree(sl.h_forces);
         if (sl.h_species) hipHostFree(sl.h_species);
         mlp_nbr_destroy(sl.nbr);
     }
@@ -474,7 +520,10 @@ int mlp_server_destroy(mlp_server *S) {
                       &S->batch.revc, &S->batch.geom, &S->batch.act, &S->batch.G, &S->batch.Gs, &S->seg, &S->energies,
                       &S->forces};
     for (DevBuf *b : bufs) b->release();
-    if (S->h_energies) hipHostFree(S->h_energies);
+    for (WaveHost &H : S->wh) {
+        if (H.energies) hipHostFree(H.energies);
+        if (H.forces) hipHostFree(H.forces);
+    }
     hipEventDestroy(S->ev_wave);
     for (hipStream_t sp : S->s_preps)
         if (sp) hipStreamDestroy(sp);
