@@ -396,7 +396,7 @@ def measure_al_nvt(mlp, synth, torch, precision: str, n_cells: int = 35, equil: 
     return res
 
 
-def measure_capacity(mlp, synth, torch, n_cells: int = 110):
+def measure_capacity(mlp, synth, torch, n_cells: int = 114):
     """One energy + force evaluation of the largest fcc-Al PaiNN system
     (F = 64, T = 4, skin 2.0 A) that fits one MI355X: the analogue of the
     paper's "maximum atoms on one GPU" (Table 2)."""

@@ -323,17 +323,28 @@ struct Act {
     float *s[MLP_MAX_LAYERS + 1], *v[MLP_MAX_LAYERS + 1];
     float *h1[MLP_MAX_LAYERS], *phi[MLP_MAX_LAYERS], *sn[MLP_MAX_LAYERS], *v1[MLP_MAX_LAYERS],
         *UV[MLP_MAX_LAYERS], *h3[MLP_MAX_LAYERS], *a[MLP_MAX_LAYERS];
-    float *gs, *gv, *gs1, *gv1, *gphi, *ga, *gh3, *gsn, *gUV, *ga1, *tmpF, *h5, *g5, *U;
+    float *gs, *gv, *gs1, *gv1, *gphi, *ga, *gsn, *gUV, *h5, *g5, *U;
     float *u;   // v * phi_vv of the current forward layer (shares gUV: the adjoint starts after the forward)
     double *epart;
     int *queue;   // the message launches' atom counters, MSG_QUEUE_INTS per launch
 };
 constexpr long QUEUE_INTS = 2L * MLP_MAX_LAYERS * MSG_QUEUE_INTS;
 
+// The update and the norm (and their adjoint) are fused into the chained
+// GEMMs for these widths; other widths take the elementwise kernels, whose
+// work arrays (da, d[s1 | n]) the fused path does not need.
+static bool update_fused(int F) { return F == 64 || F == 128; }
+
+int adjoint_work_per_feature(int F) {
+    // gs 1, gv 3, gs1 1, gv1 3, gphi 3, gUV 6, h5 + g5 1; da 3 and
+    // d[s1 | n] 2 for the elementwise update adjoint
+    return 18 + (update_fused(F) ? 0 : 5);
+}
+
 static size_t act_floats(long N, int F, int T) {
     long per_layer = (long)N * F * (1 + 3 + 1 + 3 + 2 + 3 + 3 + 3 + 1 + 3);
     long io = (long)N * F * 4;  // s, v of the final layer
-    long bwd = (long)N * F * (1 + 3 + 1 + 3 + 3 + 3 + 1 + 2 + 3 + 3 + 1 + 1) + (long)N * F;  // + h5, g5
+    long bwd = (long)N * F * adjoint_work_per_feature(F);
     return (size_t)(T * per_layer + io + bwd + N + 64 * (12 * T + 32) + 4096 + QUEUE_INTS +
                     2 * energy_part_doubles(N));
 }
@@ -363,13 +374,10 @@ static void carve(float *base, long N, int F, int T, Act &A) {
     A.gs1 = take(NF);
     A.gv1 = take(3 * NF);
     A.gphi = take(3 * NF);
-    A.ga = take(3 * NF);
-    A.gh3 = take(NF);
-    A.gsn = take(2 * NF);
+    A.ga = update_fused(F) ? nullptr : take(3 * NF);
+    A.gsn = update_fused(F) ? nullptr : take(2 * NF);
     A.gUV = take(6 * NF);
     A.u = A.gUV;
-    A.ga1 = take(NF);
-    A.tmpF = take(NF);
     A.h5 = take(NF / 2 + 64);
     A.g5 = take(NF / 2 + 64);
     A.U = take(N + 64);
@@ -618,7 +626,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         gemm<E_STORE>(s, P, A.v1[t], F, m->pk[t][WP_UV], A.UV[t], 2 * F, 3 * ndst);
         // n = sqrt(eps + sum_d Vv_d^2): formed where it is used when F is 64
         // or 128 (the update's operand load and the adjoint's epilogue)
-        const bool nfused = F == 64 || F == 128;
+        const bool nfused = update_fused(F);
         if (!nfused) k_norm<<<nblk((long)ndst * F, 256), 256, 0, s>>>(A.UV[t], ndst, F, m->eps, A.sn[t]);
         {
             GemmChain c = mlp_fwd(A.sn[t], 2 * F, m->pk[t][WP_W3], A.h3[t], F, L.b3, m->pk[t][WP_W4], A.a[t], F3, L.b4,
@@ -660,7 +668,7 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         const int hop_src = T - t;
         const bool last = t == T - 1;   // dE/dv of the last layer's output is zero
         const int ndst = NH(T - 1 - t), nsrc = NH(T - t), nfar = NH(T - t + 1);
-        if (F == 64 || F == 128) {
+        if (update_fused(F)) {
             // one kernel: da (and dUv) formed from ds2, dv2, UV and a as the
             // first product's operand is loaded, then d[s1 | n] -> ds1 = ds2 +
             // d s1 and dVv in the epilogue
