@@ -64,6 +64,14 @@ struct Slot {
     bool busy = false;
 };
 
+// One request's part of a wave: its slot's pruned graph and its offsets in
+// the packed batch.
+struct PackDesc {
+    const int *rowc, *perm, *sp, *colc, *revc;
+    const float4 *geom;
+    int n, ne, aoff, eoff;
+};
+
 // Host side of one wave: pinned buffers its results are copied into (one
 // copy each for the energies and the forces of the whole batch) and the atom
 // offsets of its systems.  Two alternate, so the next wave can be launched
@@ -71,7 +79,8 @@ struct Slot {
 struct WaveHost {
     double *energies = nullptr;
     float *forces = nullptr;   // SoA 3 x nt, the batch's rows
-    size_t e_cap = 0, f_cap = 0;
+    PackDesc *desc = nullptr;  // the requests' pack descriptors (copied to the device)
+    size_t e_cap = 0, f_cap = 0, d_cap = 0;
     std::vector<int> seg;      // B + 1 atom offsets
     int64_t nt = 0;
 };
@@ -108,29 +117,31 @@ int ensure_staging(Slot &sl, int n) {
     return 0;
 }
 
-__global__ void k_pack_atoms(const int *__restrict__ rowc, const int *__restrict__ perm, const int *__restrict__ sp,
-                             int nb, int aoff, int eoff, int *__restrict__ browc, int *__restrict__ bperm,
-                             int *__restrict__ bsp, int8_t *__restrict__ bhop, int last) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > nb) return;
-    if (k == nb) {
-        if (last) browc[aoff + nb] = eoff + rowc[nb];
-        return;
+// Packs every request of a wave (blockIdx.y = request) in one launch:
+// atom rows (row offsets shifted by the request's edge offset, internal
+// order and species shifted by its atom offset), and edge rows (columns and
+// reverse indices shifted likewise, geometry copied).
+__global__ void k_pack_wave(const PackDesc *__restrict__ D, int *__restrict__ browc, int *__restrict__ bperm,
+                            int *__restrict__ bsp, int8_t *__restrict__ bhop, int *__restrict__ bcol,
+                            int *__restrict__ brev, float4 *__restrict__ bgeom) {
+    const PackDesc d = D[blockIdx.y];
+    const bool last = blockIdx.y == gridDim.y - 1;
+    const int span = max(d.n + 1, d.ne);
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < span; k += gridDim.x * blockDim.x) {
+        if (k < d.n) {
+            browc[d.aoff + k] = d.eoff + d.rowc[k];
+            bperm[d.aoff + k] = d.aoff + d.perm[k];
+            bsp[d.aoff + k] = d.sp[k];
+            bhop[d.aoff + k] = 0;
+        } else if (k == d.n && last) {
+            browc[d.aoff + d.n] = d.eoff + d.rowc[d.n];
+        }
+        if (k < d.ne) {
+            bcol[d.eoff + k] = d.aoff + d.colc[k];
+            brev[d.eoff + k] = d.eoff + d.revc[k];
+            bgeom[d.eoff + k] = d.geom[k];
+        }
     }
-    browc[aoff + k] = eoff + rowc[k];
-    bperm[aoff + k] = aoff + perm[k];
-    bsp[aoff + k] = sp[k];
-    bhop[aoff + k] = 0;
-}
-
-__global__ void k_pack_edges(const int *__restrict__ colc, const int *__restrict__ revc,
-                             const float4 *__restrict__ geom, int eb, int aoff, int eoff, int *__restrict__ bcol,
-                             int *__restrict__ brev, float4 *__restrict__ bgeom) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= eb) return;
-    bcol[eoff + e] = aoff + colc[e];
-    brev[eoff + e] = eoff + revc[e];
-    bgeom[eoff + e] = geom[e];
 }
 
 // Device bytes of one system of n atoms: activations of every layer, the
@@ -174,7 +185,7 @@ struct mlp_server {
     hipEvent_t ev_wave = nullptr;
     bool wave_in_flight = false;
     mlp_nbr batch;              // packed graph + activations of the running wave
-    DevBuf seg, energies, forces;
+    DevBuf seg, energies, forces, pdesc;
     WaveHost wh[2];             // host side of the wave in flight (wh[cur]) and of the one before
     int cur = 0;
     float skin = 0.0f;
@@ -246,6 +257,7 @@ int launch_wave(mlp_server *S) {
         (rc = g.colc.ensure(sizeof(int) * Et + 16, 1.25, G)) || (rc = g.revc.ensure(sizeof(int) * Et + 16, 1.25, G)) ||
         (rc = g.geom.ensure(sizeof(float4) * Et + 16, 1.25, G)) ||
         (rc = S->seg.ensure(sizeof(int) * (B + 1), 1.25, G)) ||
+        (rc = S->pdesc.ensure(sizeof(PackDesc) * B, 1.25, G)) ||
         (rc = S->energies.ensure(sizeof(double) * B, 1.25, G)) ||
         (rc = S->forces.ensure(sizeof(float) * 3 * Nt, 1.25, G)))
         return rc;
@@ -254,26 +266,28 @@ int launch_wave(mlp_server *S) {
     S->cur ^= 1;
     WaveHost &H = S->wh[S->cur];
     if ((rc = ensure_pinned((void **)&H.energies, &H.e_cap, sizeof(double) * B)) ||
-        (rc = ensure_pinned((void **)&H.forces, &H.f_cap, sizeof(float) * 3 * (size_t)Nt)))
+        (rc = ensure_pinned((void **)&H.forces, &H.f_cap, sizeof(float) * 3 * (size_t)Nt)) ||
+        (rc = ensure_pinned((void **)&H.desc, &H.d_cap, sizeof(PackDesc) * B)))
         return rc;
     H.seg.assign(B + 1, 0);
     H.nt = Nt;
-    int64_t aoff = 0, eoff = 0;
+    // one launch packs every request: its descriptor holds the slot's graph
+    // and its offsets in the batch
+    int64_t aoff = 0, eoff = 0, span = 1;
     for (int b = 0; b < B; b++) {
         Req *r = W[b];
         mlp_nbr *sg = S->slots[r->slot].nbr;
-        k_pack_atoms<<<(r->n + 256) / 256, 256, 0, S->s_comp>>>(sg->rowc.as<int>(), sg->perm.as<int>(),
-                                                                 sg->species.as<int>(), r->n, (int)aoff, (int)eoff,
-                                                                 g.rowc.as<int>(), g.perm.as<int>(),
-                                                                 g.species.as<int>(), g.hop.as<int8_t>(), b == B - 1);
-        if (r->n_edges > 0)
-            k_pack_edges<<<(int)((r->n_edges + 255) / 256), 256, 0, S->s_comp>>>(
-                sg->colc.as<int>(), sg->revc.as<int>(), sg->geom.as<float4>(), (int)r->n_edges, (int)aoff, (int)eoff,
-                g.colc.as<int>(), g.revc.as<int>(), g.geom.as<float4>());
+        H.desc[b] = PackDesc{sg->rowc.as<int>(), sg->perm.as<int>(), sg->species.as<int>(), sg->colc.as<int>(),
+                             sg->revc.as<int>(), sg->geom.as<float4>(), r->n, (int)r->n_edges, (int)aoff, (int)eoff};
+        span = std::max<int64_t>(span, std::max<int64_t>(r->n + 1, r->n_edges));
         H.seg[b] = (int)aoff;
         aoff += r->n;
         eoff += r->n_edges;
     }
+    HIP_TRY(hipMemcpyAsync(S->pdesc.p, H.desc, sizeof(PackDesc) * B, hipMemcpyHostToDevice, S->s_comp));
+    k_pack_wave<<<dim3((unsigned)std::min<int64_t>((span + 255) / 256, 1024), (unsigned)B), 256, 0, S->s_comp>>>(
+        S->pdesc.as<PackDesc>(), g.rowc.as<int>(), g.perm.as<int>(), g.species.as<int>(), g.hop.as<int8_t>(),
+        g.colc.as<int>(), g.revc.as<int>(), g.geom.as<float4>());
     {
         std::lock_guard<std::mutex> lk(S->mu);
         for (Req *r : W) {
@@ -445,7 +459,11 @@ void scheduler(mlp_server *S) {
             }
         }
         if (!S->wave_in_flight && have_ready) start_wave(S);
-        if (S->wave_in_flight) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        // a wave in flight: poll its event for a few tens of microseconds
+        // (yielding) before the next admission round; a sleep here overshot
+        // to 50-500 us and left the device idle between waves
+        if (S->wave_in_flight)
+            for (int k = 0; k < 64 && hipEventQuery(S->ev_wave) == hipErrorNotReady; k++) std::this_thread::yield();
     }
 }
 
@@ -518,11 +536,12 @@ int mlp_server_destroy(mlp_server *S) {
     }
     DevBuf *bufs[] = {&S->batch.rowc, &S->batch.perm, &S->batch.species, &S->batch.hop, &S->batch.colc,
                       &S->batch.revc, &S->batch.geom, &S->batch.act, &S->batch.G, &S->batch.Gs, &S->seg, &S->energies,
-                      &S->forces};
+                      &S->forces, &S->pdesc};
     for (DevBuf *b : bufs) b->release();
     for (WaveHost &H : S->wh) {
         if (H.energies) hipHostFree(H.energies);
         if (H.forces) hipHostFree(H.forces);
+        if (H.desc) hipHostFree(H.desc);
     }
     hipEventDestroy(S->ev_wave);
     for (hipStream_t sp : S->s_preps)
