@@ -396,7 +396,7 @@ def measure_al_nvt(mlp, synth, torch, precision: str, n_cells: int = 35, equil: 
     return res
 
 
-def measure_capacity(mlp, synth, torch, n_cells: int = 114):
+def measure_capacity(mlp, synth, torch, n_cells: int = 116):
     """One energy + force evaluation of the largest fcc-Al PaiNN system
     (F = 64, T = 4, skin 2.0 A) that fits one MI355X: the analogue of the
     paper's "maximum atoms on one GPU" (Table 2)."""
@@ -575,6 +575,8 @@ def main():
     ap.add_argument("--mace-only", action="store_true", help="time only the MACE workload (a quick check)")
     ap.add_argument("--water-only", action="store_true",
                     help="time only the 24,000-atom water MD workload (100 velocity-Verlet steps)")
+    ap.add_argument("--capacity-only", type=int, default=0, metavar="N",
+                    help="evaluate only the 4 N^3-atom fcc-Al PaiNN system (F=64, T=4) of the capacity point")
     ap.add_argument("--serving-only", action="store_true",
                     help="time only the serving workload (closed loop and offered loads)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -598,6 +600,9 @@ def main():
         del a, b
     if args.allegro_only:
         print(json.dumps({p: measure_allegro(mlp, synth, torch, p) for p in (args.precision, "fp32")}), flush=True)
+        return
+    if args.capacity_only:
+        print(json.dumps(measure_capacity(mlp, synth, torch, args.capacity_only)), flush=True)
         return
     if args.serving_only:
         print(json.dumps(serve_bench(mlp, synth, args.precision, args.requests)), flush=True)
