@@ -576,7 +576,9 @@ def main():
     ap.add_argument("--water-only", action="store_true",
                     help="time only the 24,000-atom water MD workload (100 velocity-Verlet steps)")
     ap.add_argument("--capacity-only", type=int, default=0, metavar="N",
-                    help="evaluate only the 4 N^3-atom fcc-Al PaiNN system (F=64, T=4) of the capacity point")
+                    help="evaluate only the 4 N^3-atom fcc-Al system of the capacity point (PaiNN F=64, T=4, or "
+                         "the model --capacity-model names)")
+    ap.add_argument("--capacity-model", default="painn", choices=["painn", "mace", "allegro"])
     ap.add_argument("--serving-only", action="store_true",
                     help="time only the serving workload (closed loop and offered loads)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -602,7 +604,11 @@ def main():
         print(json.dumps({p: measure_allegro(mlp, synth, torch, p) for p in (args.precision, "fp32")}), flush=True)
         return
     if args.capacity_only:
-        print(json.dumps(measure_capacity(mlp, synth, torch, args.capacity_only)), flush=True)
+        if args.capacity_model == "painn":
+            r = measure_capacity(mlp, synth, torch, args.capacity_only)
+        else:
+            r = measure_capacity_eq(mlp, synth, torch, args.capacity_model, args.capacity_only)
+        print(json.dumps(r), flush=True)
         return
     if args.serving_only:
         print(json.dumps(serve_bench(mlp, synth, args.precision, args.requests)), flush=True)
