@@ -202,7 +202,9 @@ int fold_ghosts(mlp_nbr *g, float *forces, hipStream_t s);
 int max_displacement_exceeds(mlp_nbr *g, const float *pos, float limit, hipStream_t s, bool *exceeds);
 
 // ---- model (painn.hip) ----
-// Floats per atom and feature of a PaiNN evaluation's adjoint work arrays.
+// Floats per atom and feature of a PaiNN evaluation's saved layer arrays
+// (per layer) and of its adjoint work arrays.
+int layer_work_per_feature(int F);
 int adjoint_work_per_feature(int F);
 // Energy of each of n_seg segments (seg_dev: device [n_seg + 1] internal row
 // offsets, or nullptr for one segment covering all rows), forces of all rows.

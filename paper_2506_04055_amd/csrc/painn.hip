@@ -335,6 +335,15 @@ constexpr long QUEUE_INTS = 2L * MLP_MAX_LAYERS * MSG_QUEUE_INTS;
 // work arrays (da, d[s1 | n]) the fused path does not need.
 static bool update_fused(int F) { return F == 64 || F == 128; }
 
+// Columns of the saved gate a of a layer: [a_vv | a_sv] when the update is
+// fused (a_ss is consumed in the epilogue that forms it), else all three.
+static int a_cols(int F) { return update_fused(F) ? 2 * F : 3 * F; }
+
+int layer_work_per_feature(int F) {
+    // s 1, v 3, h1 1, phi 3, [s1 | n] 2, v1 3, [Uv | Vv] 6, h3 1, a
+    return 20 + a_cols(F) / F;
+}
+
 int adjoint_work_per_feature(int F) {
     // gs 1, gv 3, gs1 1, gv1 3, gphi 3, gUV 6, h5 + g5 1; da 3 and
     // d[s1 | n] 2 for the elementwise update adjoint
@@ -342,7 +351,7 @@ int adjoint_work_per_feature(int F) {
 }
 
 static size_t act_floats(long N, int F, int T) {
-    long per_layer = (long)N * F * (1 + 3 + 1 + 3 + 2 + 3 + 3 + 3 + 1 + 3);
+    long per_layer = (long)N * F * layer_work_per_feature(F);
     long io = (long)N * F * 4;  // s, v of the final layer
     long bwd = (long)N * F * adjoint_work_per_feature(F);
     return (size_t)(T * per_layer + io + bwd + N + 64 * (12 * T + 32) + 4096 + QUEUE_INTS +
@@ -367,7 +376,7 @@ static void carve(float *base, long N, int F, int T, Act &A) {
         A.v1[t] = take(3 * NF);
         A.UV[t] = take(6 * NF);
         A.h3[t] = take(NF);
-        A.a[t] = take(3 * NF);
+        A.a[t] = take((long)a_cols(F) * N);
     }
     A.gs = take(NF);
     A.gv = take(3 * NF);
@@ -629,8 +638,8 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
         const bool nfused = update_fused(F);
         if (!nfused) k_norm<<<nblk((long)ndst * F, 256), 256, 0, s>>>(A.UV[t], ndst, F, m->eps, A.sn[t]);
         {
-            GemmChain c = mlp_fwd(A.sn[t], 2 * F, m->pk[t][WP_W3], A.h3[t], F, L.b3, m->pk[t][WP_W4], A.a[t], F3, L.b4,
-                                  ndst);
+            GemmChain c = mlp_fwd(A.sn[t], 2 * F, m->pk[t][WP_W3], A.h3[t], F, L.b3, m->pk[t][WP_W4], A.a[t],
+                                  a_cols(F), L.b4, ndst);
             if (F >= 64) {
                 // the gated update in the second product's epilogue (the last
                 // layer's v is not needed: the readout takes s only)
@@ -672,7 +681,8 @@ int evaluate(mlp_model *m, mlp_nbr *g, hipStream_t s, double *energy, float *for
             // one kernel: da (and dUv) formed from ds2, dv2, UV and a as the
             // first product's operand is loaded, then d[s1 | n] -> ds1 = ds2 +
             // d s1 and dVv in the epilogue
-            GemmChain c = mlp_bwd(A.a[t], F3, m->pk[t][WP_W4TP], A.h3[t], F, m->pk[t][WP_W3T], A.gs1, F, A.gs, ndst);
+            GemmChain c = mlp_bwd(A.a[t], a_cols(F), m->pk[t][WP_W4TP], A.h3[t], F, m->pk[t][WP_W3T], A.gs1, F, A.gs,
+                                  ndst);
             c.e2 = GE_UPDATE_ADJ;
             c.F = F;
             c.sn = A.sn[t];

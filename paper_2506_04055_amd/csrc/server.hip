@@ -149,7 +149,7 @@ __global__ void k_pack_wave(const PackDesc *__restrict__ D, int *__restrict__ br
 // rc + skin per atom.
 static size_t footprint(const mlp_model *m, int n) {
     const size_t F = m->F, T = m->T;
-    const size_t act = (23 * T + 4 + adjoint_work_per_feature((int)F) + 1) * F * 4 + 64;
+    const size_t act = (layer_work_per_feature((int)F) * T + 4 + adjoint_work_per_feature((int)F) + 1) * F * 4 + 64;
     const size_t nslot = (size_t)msg_slots((int)F, (int)T, false);   // the adjoint's edge sums (at most)
     const size_t graph = 120 * (60 + 16 * nslot) + 96;
     return (size_t)n * (act + graph) + (1u << 20);
